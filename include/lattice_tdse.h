@@ -1,0 +1,205 @@
+/*
+ * lattice_tdse.h -- C-ABI of the MI355X Strang-splitting library.
+ *
+ * Method: Suzuki, Suryanarayana, Nuyens, "Strang splitting in combination
+ * with rank-1 and rank-r lattices for the time-dependent Schroedinger
+ * equation" (arXiv:1808.06357).  The library advances
+ *
+ *     i gamma du/dt = -(gamma^2/2) lap u + v(x) u,   x in [0,1)^d periodic,
+ *
+ * (Sec. 1, eq. (TDSE)) on the points of a rank-1 or rank-2 lattice with the
+ * Strang scheme of eq. (StrangTDSE) / Algorithm 1, on one AMD GPU.
+ *
+ * Conventions shared by every call:
+ *   - A lattice (Def. 1) is given by r generating vectors z_1..z_r in Z^d,
+ *     stored row-wise: Z[i*d + j] = j-th component of z_i, and moduli
+ *     n_1..n_r with n_{i+1} | n_i.  N = n_1 * ... * n_r.
+ *   - Point index kappa = sum_i k_i prod_{j>i} n_j (Sec. 2.5, last index
+ *     fastest); point p_kappa = (sum_i z_i k_i / n_i) mod 1.
+ *   - Frequency key chi(h) = sum_i xi_i prod_{j>i} n_j with
+ *     xi_i = h.z_i mod n_i (Def. 2, Thm. 1(iii), Sec. 2.5).
+ *   - The state u is the vector of lattice values u(p_kappa) in kappa order
+ *     (equivalent to the coefficient vector of Algorithm 1 through the
+ *     unitary DFT of eqs. (Fnx)/(Fn): uhat = F u / sqrt(N)).
+ *   - Complex data are interleaved (re, im): LT_C64 = 2 x float,
+ *     LT_C128 = 2 x double (the layout of torch.complex64 / complex128).
+ *   - One step: u <- P u; U = F u; U <- K U; u = F^{-1} U; u <- P u with
+ *     P = diag(exp(-i dt v_kappa / (2 gamma))) and
+ *     K = diag(exp(-i 2 pi^2 gamma dt ||h_chi||^2)) (eqs. (Dn), (Vn),
+ *     (StrangTDSE)).  The phase arguments are formed and reduced mod 2 pi in
+ *     double precision in both precisions.
+ *
+ * Memory: every pointer documented "device" is device memory owned by the
+ * caller, who must keep it alive until the work queued on `stream` has
+ * finished.  The library never retains a caller pointer.  A plan owns its own
+ * host tables and device tables and frees them in lattice_plan_destroy.
+ * Streams are hipStream_t passed as void* (NULL = the default stream).
+ *
+ * Errors: argument and plan errors are detected on the host before anything
+ * is queued and reported through the return value; HIP failures return
+ * LT_E_HIP.  lt_last_error() gives a message for the calling thread's last
+ * non-OK status.  No call aborts the process or throws across the ABI.
+ */
+#ifndef LATTICE_TDSE_H
+#define LATTICE_TDSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lt_plan lt_plan;
+
+typedef enum { LT_C64 = 1, LT_C128 = 2 } lt_prec;
+
+typedef enum {
+    LT_OK = 0,
+    LT_E_ARG = 1,            /* bad argument (null pointer, size, value)          */
+    LT_E_NOT_CANONICAL = 2,  /* moduli not canonical (Def. 1: n_{i+1} | n_i)     */
+    LT_E_NOT_INJECTIVE = 3,  /* index set violates Def. 2                          */
+    LT_E_INCOMPLETE = 4,     /* not every key reachable: lattice points not distinct */
+    LT_E_NOMEM = 5,
+    LT_E_HIP = 6,            /* a HIP runtime call failed (or no GPU)              */
+    LT_E_UNSUPPORTED = 7     /* valid input outside what this build implements    */
+} lt_status;
+
+/* Read-only facts about a plan. */
+typedef struct {
+    int32_t d, r;
+    int64_t n[4];            /* moduli (first r used)                                */
+    int64_t N;               /* number of lattice points = number of keys            */
+    int64_t n_index;         /* size of the user index set I (0 if none given)       */
+    int64_t n_completed;     /* keys given minimal-l2 representatives (N - |I|)      */
+    int64_t max_s;           /* max ||h_chi||^2 over all keys                        */
+    int32_t bluestein;       /* 1: the length-N transform runs as a chirp-z convolution */
+    int32_t passes;          /* 1: whole run in one workgroup; 2: column + row passes  */
+    int64_t fft_len;         /* transform length L (N, or the convolution length)    */
+    int32_t L1, L2;          /* column / row lengths of the two-pass layout (L = L1*L2) */
+    int32_t cols;            /* columns per column-pass workgroup                     */
+    int32_t rows;            /* rows per row-pass workgroup                           */
+} lt_plan_info;
+
+/*
+ * lattice_plan -- host-side planning (no GPU needed).
+ *
+ * Builds the lattice of Def. 1 and its anti-aliasing set of full
+ * cardinality (Def. 2, Thm. 1):
+ *   - H (nh x d, row-major int32, may be NULL with nh = 0) is a user index
+ *     set; it must be injective under chi (LT_E_NOT_INJECTIVE otherwise) and
+ *     its elements own their keys;
+ *   - every key not owned by H gets its minimal-l2 representative
+ *     (Lemma 4, eq. (hrepresenter)), ties broken by h lexicographic
+ *     (h_1 first, signed ascending), found with the construction of Sec. 3.1
+ *     (enumerate a ball, sort by norm, first unseen key wins).
+ * Requirements: 1 <= r <= 2 for runs (planning accepts r <= 4), d >= 1,
+ * n_{i+1} | n_i (LT_E_NOT_CANONICAL), all N points distinct
+ * (LT_E_INCOMPLETE; for rank-1 this is gcd(N, z_1..z_d) = 1).
+ * Components of z_i sharing a factor with n_i are accepted when the points
+ * stay distinct, which is the property Thm. 1 uses.
+ * On success *out owns the plan; release it with lattice_plan_destroy.
+ */
+lt_status lattice_plan(int32_t d, int32_t r, const int64_t *Z, const int64_t *n,
+                       const int32_t *H, int64_t nh, lt_plan **out);
+
+/* Copy the plan's facts into *info. */
+lt_status lattice_plan_info(const lt_plan *p, lt_plan_info *info);
+
+/*
+ * Host copies of the plan's integer tables (for bit-exact checks); each
+ * output may be NULL.  key_of_h: chi(h) for each row of the H given at
+ * planning (nh entries); s_of_key: ||h_chi||^2 (N entries);
+ * h_of_key: h_chi (N x d, row-major).
+ */
+lt_status lattice_plan_keys(const lt_plan *p, int64_t *key_of_h, int64_t *s_of_key,
+                            int32_t *h_of_key);
+
+/*
+ * Lattice points (Def. 1) as exact integer numerators: for kappa in
+ * [first, first + count), num[(kappa-first)*d + j] = (sum_i z_{i,j} k_i N/n_i) mod N,
+ * so that p_kappa = num / N.  Host memory.
+ */
+lt_status lattice_plan_points(const lt_plan *p, int64_t first, int64_t count, int64_t *num);
+
+void lattice_plan_destroy(lt_plan *p);
+
+/*
+ * Bytes of device workspace strang_run needs for (p, prec, batch,
+ * shared_v) -- shared_v = 1 when v_stride == 0.  Written to *bytes.
+ */
+lt_status strang_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, int32_t shared_v,
+                                size_t *bytes);
+
+/*
+ * strang_run -- m Strang steps (eq. (StrangTDSE); Algorithm 1) for `batch`
+ * independent states on one lattice, in place.
+ *   v      device, double, N values per state in kappa order (the diagonal
+ *          of V_n, eq. (Vn)); state b uses v + b * v_stride (v_stride = 0
+ *          shares one potential).
+ *   u      device, batch x N complex of `prec`: in u(0), out u(m dt).
+ *   gamma  > 0, the scaled Planck constant of eq. (TDSE); dt any real (a
+ *          negative dt runs the scheme backwards: S(-dt) = S(dt)^{-1}).
+ *   steps  >= 0.
+ *   ckpt   optional (NULL with ckpt_every = 0): device, complex of `prec`,
+ *          ceil(steps / ckpt_every) x batch x N; receives u at steps
+ *          0, K, 2K, ... (K = ckpt_every), layout [c][b][kappa].
+ *   work   device workspace of at least strang_workspace_size bytes, or NULL
+ *          (then the call allocates and frees it stream-ordered).
+ * Successive half potential steps are merged into one full step, which
+ * equals the literal scheme within rounding.
+ */
+lt_status strang_run(const lt_plan *p, lt_prec prec, int32_t batch, const double *v,
+                     int64_t v_stride, void *u, double gamma, double dt, int64_t steps,
+                     void *ckpt, int64_t ckpt_every, void *work, size_t work_bytes, void *stream);
+
+/*
+ * strang_adjoint -- reverse-mode derivative of u(T) = S^m u(0) for a real
+ * loss J, for `batch` states sharing the plan (same v, dt, gamma convention
+ * as strang_run).  Gradients use g = dJ/dRe + i dJ/dIm.
+ *   uT     device, batch x N: u(T) from the forward run.
+ *   gT     device, batch x N: dJ/du(T).
+ *   ckpt   device, the forward checkpoints of strang_run (required,
+ *          ckpt_every >= 1).  The forward states are recomputed by running
+ *          the unitary step backwards (S^{-1} = S^H) and reset to the stored
+ *          checkpoint every ckpt_every steps to bound drift.
+ *   g0     device out, batch x N: dJ/du(0).
+ *   gv     device out, double: dJ/dv; N values if v_stride == 0 (summed
+ *          over the batch), batch x N otherwise.
+ *   work   device workspace of at least strang_adjoint_workspace_size
+ *          bytes, or NULL.
+ * Per step, with a = P u^{j-1}, b = F^{-1} K F a, y = conj(P) g_j and
+ * mu = F^{-1} conj(K) F y, the potential gradient collects
+ * dt/(2 gamma) [Im(conj(y) b) + Im(conj(mu) a)] and g_{j-1} = conj(P) mu.
+ */
+lt_status strang_adjoint_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch,
+                                        int32_t shared_v, size_t *bytes);
+lt_status strang_adjoint(const lt_plan *p, lt_prec prec, int32_t batch, const double *v,
+                         int64_t v_stride, const void *uT, const void *gT, double gamma, double dt,
+                         int64_t steps, const void *ckpt, int64_t ckpt_every, void *g0, double *gv,
+                         void *work, size_t work_bytes, void *stream);
+
+/*
+ * strang_run_batched -- B independent problems, each with its own plan,
+ * potential, state, gamma, dt and step count (eq. (StrangTDSE) for each),
+ * advanced together: problems small enough for one workgroup run their whole
+ * step loop inside one shared launch; the others are interleaved pass by
+ * pass in shared launches.  Arrays are host arrays of length B holding
+ * device pointers (v[b]: N_b doubles, u[b]: N_b complex of `prec`, in place).
+ *   work   device workspace of at least strang_batched_workspace_size bytes,
+ *          or NULL.
+ */
+lt_status strang_batched_workspace_size(int32_t B, const lt_plan *const *plans, lt_prec prec,
+                                        size_t *bytes);
+lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec prec,
+                             const double *const *v, void *const *u, const double *gamma,
+                             const double *dt, const int64_t *steps, void *work,
+                             size_t work_bytes, void *stream);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *lt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LATTICE_TDSE_H */

@@ -1,0 +1,17 @@
+"""Strang splitting on rank-1 / rank-2 lattices for the TDSE on MI355X.
+
+Python face of the HIP library (include/lattice_tdse.h): plans, runs,
+adjoints and batched runs, plus a torch.autograd.Function.  All arithmetic of
+a run happens in the library's HIP kernels.
+"""
+from ._capi import (LT_C64, LT_C128, LatticeError, Plan, lattice_plan, lattice_plan_info,
+                    lattice_plan_keys, lattice_plan_points, num_checkpoints, strang_adjoint,
+                    strang_adjoint_workspace_size, strang_batched_workspace_size, strang_run,
+                    strang_run_batched, strang_workspace_size)
+from .autograd import LatticeStrang, lattice_strang
+
+__all__ = ["LT_C64", "LT_C128", "LatticeError", "Plan", "lattice_plan", "lattice_plan_info",
+           "lattice_plan_keys", "lattice_plan_points", "num_checkpoints", "strang_run",
+           "strang_adjoint", "strang_run_batched", "strang_workspace_size",
+           "strang_adjoint_workspace_size", "strang_batched_workspace_size", "LatticeStrang",
+           "lattice_strang"]

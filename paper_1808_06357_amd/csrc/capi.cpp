@@ -1,0 +1,695 @@
+// C-ABI of the lattice Strang library: argument checks, device tables and the
+// launch sequences of a run (eq. (StrangTDSE) / Algorithm 1), its adjoint and
+// batches of unrelated problems.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "lt_internal.h"
+
+using namespace lt;
+
+namespace {
+
+constexpr long double kPiL = 3.141592653589793238462643383279502884L;
+
+size_t esz(int prec) { return prec == LT_C128 ? 16 : 8; }
+
+#define HIP_TRY(expr, what)                                                                    \
+    do {                                                                                       \
+        hipError_t e_ = (hipError_t)(expr);                                                    \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(LT_E_HIP, std::string(what) + ": " + hipGetErrorString(e_));           \
+    } while (0)
+
+// exp(-2 pi i q mult / L) for q < count, interleaved (re, im), computed in long
+// double from the exactly reduced integer q*mult mod L.
+template <typename T>
+std::vector<T> roots(int64_t L, int64_t count, int64_t mult)
+{
+    std::vector<T> out((size_t)(2 * count));
+    for (int64_t q = 0; q < count; ++q) {
+        const int64_t m = (int64_t)(((__int128)q * mult) % L);
+        const long double a = 2.0L * kPiL * (long double)m / (long double)L;
+        out[(size_t)(2 * q)] = (T)cosl(a);
+        out[(size_t)(2 * q + 1)] = (T)(-sinl(a));
+    }
+    return out;
+}
+
+template <typename T>
+lt_status upload(void **dst, const std::vector<T> &src, const char *what)
+{
+    HIP_TRY(hipMalloc(dst, std::max<size_t>(src.size() * sizeof(T), 16)), what);
+    HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice), what);
+    return LT_OK;
+}
+
+lt_status bind_device(lt_plan &p)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (p.device < 0) p.device = dev;
+    if (p.device != dev) return fail(LT_E_ARG, "plan was first used on another device");
+    kernels_init();
+    return LT_OK;
+}
+
+lt_status build_twiddles(lt_plan &p, int which, int prec)
+{
+    DevTables &D = p.dev[which][prec];
+    const Sched &s = p.sched[which][prec];
+    if (D.twa) return LT_OK;
+    int64_t La, Lb;
+    if (s.passes == 1) {
+        La = s.rank2 ? s.L1 : s.L;
+        Lb = s.rank2 ? s.L2 : 1;
+    } else {
+        La = s.L1;
+        Lb = s.L2;
+    }
+    lt_status st;
+    if (prec == LT_C128) {
+        if ((st = upload(&D.twa, roots<double>(La, La, 1), "twiddles"))) return st;
+        if ((st = upload(&D.twb, roots<double>(Lb, Lb, 1), "twiddles"))) return st;
+    } else {
+        if ((st = upload(&D.twa, roots<float>(La, La, 1), "twiddles"))) return st;
+        if ((st = upload(&D.twb, roots<float>(Lb, Lb, 1), "twiddles"))) return st;
+    }
+    if (s.passes == 2 && !s.rank2) {
+        if ((st = upload((void **)&D.tw4hi, roots<double>(s.L, s.L1, s.L2), "twiddles"))) return st;
+        if ((st = upload((void **)&D.tw4lo, roots<double>(s.L, s.L2, 1), "twiddles"))) return st;
+    }
+    std::vector<int32_t> sk((size_t)p.N);
+    for (int64_t t = 0; t < p.N; ++t) sk[(size_t)t] = (int32_t)p.s_of_key[(size_t)t];
+    return upload((void **)&D.s_key, sk, "key norms");
+}
+
+ColArgs col_base(const Sched &s, const DevTables &D, int64_t N)
+{
+    ColArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.L1 = s.L1;
+    a.L2 = s.L2;
+    a.C = s.cols;
+    a.ntiles = (s.L2 + s.cols - 1) / s.cols;
+    a.Nvalid = N;
+    a.twiddle = s.rank2 ? 0 : 1;
+    a.tw4hi = D.tw4hi;
+    a.tw4lo = D.tw4lo;
+    a.twa = D.twa;
+    a.rad = s.ra;
+    a.scale = 1.0;
+    a.Nchirp = N;
+    return a;
+}
+
+RowArgs row_base(const Sched &s, const DevTables &D)
+{
+    RowArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.L1 = s.L1;
+    a.L2 = s.L2;
+    a.rows = s.rows;
+    a.nblk = (s.L1 + s.rows - 1) / s.rows;
+    a.twb = D.twb;
+    a.rad = s.rb;
+    return a;
+}
+
+// kernel spectrum of the chirp-z convolution, natural order, complex double
+lt_status bhat_natural(lt_plan &p, void *nat, void *tmp, hipStream_t st)
+{
+    const Sched &s = p.sched[0][LT_C128];
+    if (!s.ok) return fail(LT_E_UNSUPPORTED, "no double-precision schedule for the chirp-z kernel");
+    lt_status r = build_twiddles(p, 0, LT_C128);
+    if (r) return r;
+    const DevTables &D = p.dev[0][LT_C128];
+    HIP_TRY(launch_chirp_filter(tmp, p.N, s.L, st), "chirp filter");
+    if (s.passes == 1) {
+        HIP_TRY(launch_fft_single(LT_C128, s.ra, D.twa, tmp, s.L, st), "kernel spectrum");
+        HIP_TRY(hipMemcpyAsync(nat, tmp, (size_t)s.L * 16, hipMemcpyDeviceToDevice, st), "copy");
+        return LT_OK;
+    }
+    ColArgs c = col_base(s, D, s.L);
+    c.buf = tmp;
+    c.post_fwd = 1;
+    HIP_TRY(launch_col(LT_C128, s, c, 1, st), "kernel spectrum (columns)");
+    RowArgs rw = row_base(s, D);
+    rw.buf = tmp;
+    rw.fft_only = 1;
+    HIP_TRY(launch_row(LT_C128, s, rw, 1, st), "kernel spectrum (rows)");
+    HIP_TRY(launch_unpermute_c128(nat, tmp, s.L, s.L1, s.L2, st), "kernel spectrum (order)");
+    return LT_OK;
+}
+
+struct Work {
+    size_t kt = 0, p2 = 0, w = 0, w2 = 0, gacc = 0, total = 0;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Work run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool shared)
+{
+    Work w;
+    size_t off = 0;
+    w.kt = off;
+    off = align_up(off + (size_t)std::max<int64_t>(s.L, p.N) * esz(prec));
+    w.p2 = off;
+    off = align_up(off + (size_t)(shared ? 1 : batch) * p.N * esz(prec));
+    w.w = off;
+    if (s.bluestein && s.passes == 2) off = align_up(off + (size_t)batch * s.L * esz(prec));
+    w.total = off;
+    return w;
+}
+
+Work adj_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool shared)
+{
+    Work w;
+    size_t off = 0;
+    w.kt = off;
+    off = align_up(off + (size_t)std::max<int64_t>(s.L, p.N) * esz(prec));
+    w.p2 = off;
+    off = align_up(off + (size_t)(shared ? 1 : batch) * p.N * esz(prec));
+    w.w = off;
+    off = align_up(off + (size_t)2 * batch * s.L * esz(prec));   // state and cotangent
+    w.gacc = off;
+    off = align_up(off + (size_t)batch * p.N * sizeof(double));
+    w.total = off;
+    return w;
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+lt_status check_common(const lt_plan *p, lt_prec prec, int32_t batch, double gamma, double dt,
+                       int64_t steps)
+{
+    if (!p) return fail(LT_E_ARG, "plan is NULL");
+    if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "prec must be LT_C64 or LT_C128");
+    if (batch < 0) return fail(LT_E_ARG, "batch must be >= 0");
+    if (!(gamma > 0) || !finite(gamma)) return fail(LT_E_ARG, "gamma must be finite and > 0");
+    if (!finite(dt)) return fail(LT_E_ARG, "dt must be finite");
+    if (steps < 0) return fail(LT_E_ARG, "steps must be >= 0");
+    if (!p->sched[0][prec].ok)
+        return fail(LT_E_UNSUPPORTED, "no GPU schedule for this lattice in this precision");
+    return LT_OK;
+}
+
+struct Scratch {
+    void *ptr = nullptr;
+    hipStream_t st = nullptr;
+    bool owned = false;
+    ~Scratch()
+    {
+        if (owned && ptr) hipFreeAsync(ptr, st);
+    }
+};
+
+lt_status get_work(Scratch &sc, void *work, size_t work_bytes, size_t need, hipStream_t st)
+{
+    sc.st = st;
+    if (work) {
+        if (work_bytes < need)
+            return fail(LT_E_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
+        sc.ptr = work;
+        return LT_OK;
+    }
+    HIP_TRY(hipMallocAsync(&sc.ptr, std::max<size_t>(need, 256), st), "workspace allocation");
+    sc.owned = true;
+    return LT_OK;
+}
+
+inline char *at(void *base, size_t off) { return (char *)base + off; }
+
+// one state batch through the two-pass sequence (forward or backward in time)
+lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int prec, int batch,
+                           const double *v, int64_t v_stride, void *u, double gamma, double dt,
+                           int64_t steps, void *ckpt, int64_t ck_every, void *Kt, void *P2,
+                           int64_t p2_bs, void *W, hipStream_t st)
+{
+    const int64_t N = p.N;
+    const size_t S = esz(prec);
+    const double half = dt / (2.0 * gamma);
+    void *buf = s.bluestein ? W : u;
+    const int64_t buf_bs = s.bluestein ? s.L : N;
+    // first pass: half potential step (and chirp), column DFT
+    ColArgs c = col_base(s, D, N);
+    c.buf = buf;
+    c.buf_bs = buf_bs;
+    c.in = u;
+    c.in_bs = N;
+    c.post_fwd = 1;
+    c.v = v;
+    c.v_bs = v_stride;
+    c.phase = half;
+    c.chirp = s.bluestein ? 1 : 0;
+    HIP_TRY(launch_col(prec, s, c, batch, st), "column pass");
+    RowArgs r = row_base(s, D);
+    r.buf = buf;
+    r.buf_bs = buf_bs;
+    r.tab = s.bluestein ? D.bhat : Kt;
+    ColArgs mid = col_base(s, D, N);
+    mid.buf = buf;
+    mid.buf_bs = buf_bs;
+    mid.pre_inv = 1;
+    mid.post_fwd = 1;
+    ColArgs kin = mid;
+    kin.tab = Kt;  // chirp-z: K at the natural spectral index
+    for (int64_t t = 0; t < steps; ++t) {
+        r.conj_tab = 0;
+        HIP_TRY(launch_row(prec, s, r, batch, st), "row pass");
+        if (s.bluestein) {
+            HIP_TRY(launch_col(prec, s, kin, batch, st), "column pass (kinetic)");
+            r.conj_tab = 1;
+            HIP_TRY(launch_row(prec, s, r, batch, st), "row pass");
+        }
+        if (t == steps - 1) break;
+        ColArgs m = mid;
+        m.tab = P2;
+        m.tab_bs = p2_bs;
+        const int64_t k = t + 1;  // state index at this merge point
+        if (ckpt && k % ck_every == 0) {
+            m.ck = at(ckpt, (size_t)(k / ck_every) * batch * N * S);
+            m.ck_bs = N;
+            m.ck_v = v;
+            m.v_bs = v_stride;
+            m.ck_phase = half;
+            m.ck_chirp = s.bluestein ? 1 : 0;
+        }
+        HIP_TRY(launch_col(prec, s, m, batch, st), "column pass (potential)");
+    }
+    ColArgs last = col_base(s, D, N);
+    last.buf = buf;
+    last.buf_bs = buf_bs;
+    last.pre_inv = 1;
+    last.out = u;
+    last.out_bs = N;
+    last.v = v;
+    last.v_bs = v_stride;
+    last.phase = half;
+    last.chirp = s.bluestein ? -1 : 0;
+    HIP_TRY(launch_col(prec, s, last, batch, st), "column pass (last)");
+    return LT_OK;
+}
+
+lt_status make_tables(lt_plan &p, const Sched &s, const DevTables &D, int prec, int batch,
+                      const double *v, int64_t v_stride, bool shared, double gamma, double dt,
+                      void *Kt, void *P2, hipStream_t st)
+{
+    const double kin = 2.0 * M_PI * M_PI * gamma * dt;
+    if (s.bluestein) {
+        HIP_TRY(launch_setup_kernel_table(prec, Kt, D.s_key, p.N, 0, 0, 0, kin, 1.0, st), "kinetic table");
+    } else {
+        const int transposed = (s.passes == 2 && !s.rank2) ? 1 : 0;
+        HIP_TRY(launch_setup_kernel_table(prec, Kt, D.s_key, p.N, s.L1, s.L2, transposed, kin,
+                                          1.0 / (double)s.L, st),
+                "kinetic table");
+    }
+    HIP_TRY(launch_setup_phase_table(prec, P2, v, v_stride, p.N, shared ? 1 : batch, dt / gamma, st),
+            "potential table");
+    return LT_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- device tables
+namespace lt {
+lt_status ensure_device_tables(lt_plan &p, int which, int prec, void *stream)
+{
+    std::lock_guard<std::mutex> lock(p.mu);
+    DevTables &D = p.dev[which][prec];
+    if (D.built) return LT_OK;
+    const Sched &s = p.sched[which][prec];
+    if (!s.ok) return fail(LT_E_UNSUPPORTED, "no GPU schedule for this lattice in this precision");
+    lt_status r = bind_device(p);
+    if (r) return r;
+    if ((r = build_twiddles(p, which, prec))) return r;
+    hipStream_t st = (hipStream_t)stream;
+    if (s.bluestein) {
+        void *nat = nullptr, *tmp = nullptr;
+        HIP_TRY(hipMalloc(&nat, (size_t)s.L * 16), "chirp-z tables");
+        HIP_TRY(hipMalloc(&tmp, (size_t)s.L * 16), "chirp-z tables");
+        HIP_TRY(hipMalloc(&D.bhat, (size_t)s.L * esz(prec)), "chirp-z tables");
+        r = bhat_natural(p, nat, tmp, st);
+        if (!r) {
+            const int transposed = s.passes == 2 ? 1 : 0;
+            const double scale = 1.0 / ((double)s.L * std::sqrt((double)p.N));
+            hipError_t e = (hipError_t)launch_convert_permute(prec, D.bhat, nat, s.L, s.L1, s.L2,
+                                                              transposed, scale, st);
+            if (e != hipSuccess) r = fail(LT_E_HIP, std::string("kernel spectrum: ") + hipGetErrorString(e));
+        }
+        hipError_t e = hipStreamSynchronize(st);
+        hipFree(nat);
+        hipFree(tmp);
+        if (r) return r;
+        if (e != hipSuccess) return fail(LT_E_HIP, std::string("table build: ") + hipGetErrorString(e));
+    }
+    D.built = true;
+    return LT_OK;
+}
+}  // namespace lt
+
+// ---------------------------------------------------------------- C-ABI
+extern "C" {
+
+lt_status lattice_plan(int32_t d, int32_t r, const int64_t *Z, const int64_t *n, const int32_t *H,
+                       int64_t nh, lt_plan **out)
+{
+    if (!out) return fail(LT_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (d < 1 || d > 64) return fail(LT_E_ARG, "d must be in [1, 64]");
+    if (r < 1 || r > 4) return fail(LT_E_ARG, "r must be in [1, 4]");
+    if (!Z || !n) return fail(LT_E_ARG, "Z and n must not be NULL");
+    if (nh < 0 || (nh > 0 && !H)) return fail(LT_E_ARG, "H must hold nh >= 0 rows");
+    __int128 N = 1;
+    for (int i = 0; i < r; ++i) {
+        if (n[i] < 1) return fail(LT_E_ARG, "moduli must be >= 1");
+        if (i > 0 && n[i - 1] % n[i] != 0)
+            return fail(LT_E_NOT_CANONICAL, "moduli must satisfy n_{i+1} | n_i (Def. 1)");
+        N *= n[i];
+        if (N > ((__int128)1 << 31) - 1) return fail(LT_E_UNSUPPORTED, "N must be below 2^31");
+    }
+    for (int64_t t = 0; t < nh * d; ++t)
+        if (H[t] < -(1 << 24) || H[t] > (1 << 24)) return fail(LT_E_ARG, "index set entries too large");
+    lt_plan *p = new (std::nothrow) lt_plan;
+    if (!p) return fail(LT_E_NOMEM, "plan allocation");
+    p->d = d;
+    p->r = r;
+    for (int i = 0; i < r; ++i) p->n[i] = n[i];
+    p->N = (int64_t)N;
+    try {
+        p->Z.assign(Z, Z + (size_t)r * d);
+        p->H.assign(H ? H : (const int32_t *)nullptr, H ? H + (size_t)nh * d : nullptr);
+        lt_status st = plan_index_set(*p);
+        if (st != LT_OK) {
+            delete p;
+            return st;
+        }
+        for (int prec : {LT_C64, LT_C128}) {
+            p->sched[0][prec] = make_schedule(*p, prec, false);
+            p->sched[1][prec] = p->sched[0][prec].passes == 2 ? p->sched[0][prec]
+                                                              : make_schedule(*p, prec, true);
+        }
+    } catch (const std::bad_alloc &) {
+        delete p;
+        return fail(LT_E_NOMEM, "out of host memory while planning");
+    }
+    *out = p;
+    return LT_OK;
+}
+
+lt_status lattice_plan_info(const lt_plan *p, lt_plan_info *info)
+{
+    if (!p || !info) return fail(LT_E_ARG, "NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    info->d = p->d;
+    info->r = p->r;
+    for (int i = 0; i < 4; ++i) info->n[i] = i < p->r ? p->n[i] : 0;
+    info->N = p->N;
+    info->n_index = p->n_index;
+    info->n_completed = p->n_completed;
+    info->max_s = p->max_s;
+    const Sched &s = p->sched[0][LT_C128].ok ? p->sched[0][LT_C128] : p->sched[0][LT_C64];
+    info->bluestein = s.bluestein ? 1 : 0;
+    info->passes = s.passes;
+    info->fft_len = s.L;
+    info->L1 = s.L1;
+    info->L2 = s.L2;
+    info->cols = s.cols;
+    info->rows = s.rows;
+    return LT_OK;
+}
+
+lt_status lattice_plan_keys(const lt_plan *p, int64_t *key_of_h, int64_t *s_of_key, int32_t *h_of_key)
+{
+    if (!p) return fail(LT_E_ARG, "plan is NULL");
+    if (key_of_h && !p->key_of_h.empty())
+        std::memcpy(key_of_h, p->key_of_h.data(), p->key_of_h.size() * sizeof(int64_t));
+    if (s_of_key) std::memcpy(s_of_key, p->s_of_key.data(), p->s_of_key.size() * sizeof(int64_t));
+    if (h_of_key) std::memcpy(h_of_key, p->h_of_key.data(), p->h_of_key.size() * sizeof(int32_t));
+    return LT_OK;
+}
+
+lt_status lattice_plan_points(const lt_plan *p, int64_t first, int64_t count, int64_t *num)
+{
+    if (!p || (!num && count > 0)) return fail(LT_E_ARG, "NULL argument");
+    if (first < 0 || count < 0 || first + count > p->N) return fail(LT_E_ARG, "point range out of bounds");
+    std::vector<int64_t> k(p->r);
+    for (int64_t kappa = first; kappa < first + count; ++kappa) {
+        int64_t rem = kappa;
+        for (int i = p->r - 1; i >= 0; --i) { k[i] = rem % p->n[i]; rem /= p->n[i]; }
+        for (int j = 0; j < p->d; ++j) {
+            __int128 acc = 0;
+            for (int i = 0; i < p->r; ++i) {
+                __int128 zi = p->Z[(size_t)i * p->d + j] % p->n[i];
+                if (zi < 0) zi += p->n[i];
+                acc += (zi * k[i] % p->n[i]) * (p->N / p->n[i]);
+            }
+            num[(kappa - first) * p->d + j] = (int64_t)(acc % p->N);
+        }
+    }
+    return LT_OK;
+}
+
+void lattice_plan_destroy(lt_plan *p)
+{
+    if (!p) return;
+    for (auto &row : p->dev)
+        for (auto &D : row) {
+            hipFree(D.twa);
+            hipFree(D.twb);
+            hipFree(D.tw4hi);
+            hipFree(D.tw4lo);
+            hipFree(D.s_key);
+            hipFree(D.bhat);
+        }
+    delete p;
+}
+
+lt_status strang_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, int32_t shared_v,
+                                size_t *bytes)
+{
+    if (!p || !bytes) return fail(LT_E_ARG, "NULL argument");
+    if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
+    if (batch < 0) return fail(LT_E_ARG, "batch must be >= 0");
+    *bytes = run_layout(*p, p->sched[0][prec], prec, batch, shared_v != 0).total;
+    return LT_OK;
+}
+
+lt_status strang_adjoint_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, int32_t shared_v,
+                                        size_t *bytes)
+{
+    if (!p || !bytes) return fail(LT_E_ARG, "NULL argument");
+    if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
+    if (batch < 0) return fail(LT_E_ARG, "batch must be >= 0");
+    *bytes = adj_layout(*p, p->sched[1][prec], prec, batch, shared_v != 0).total;
+    return LT_OK;
+}
+
+lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, int64_t v_stride,
+                     void *u, double gamma, double dt, int64_t steps, void *ckpt, int64_t ckpt_every,
+                     void *work, size_t work_bytes, void *stream)
+{
+    lt_status st = check_common(cp, prec, batch, gamma, dt, steps);
+    if (st) return st;
+    lt_plan &p = *const_cast<lt_plan *>(cp);
+    if (batch == 0 || steps == 0) return LT_OK;
+    if (!v || !u) return fail(LT_E_ARG, "v and u must not be NULL");
+    if (v_stride != 0 && v_stride < p.N) return fail(LT_E_ARG, "v_stride must be 0 or >= N");
+    if (ckpt && ckpt_every < 1) return fail(LT_E_ARG, "ckpt_every must be >= 1 with a checkpoint buffer");
+    hipStream_t hs = (hipStream_t)stream;
+    if ((st = ensure_device_tables(p, 0, prec, stream))) return st;
+    const Sched &s = p.sched[0][prec];
+    const DevTables &D = p.dev[0][prec];
+    const bool shared = v_stride == 0;
+    const Work L = run_layout(p, s, prec, batch, shared);
+    Scratch sc;
+    if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
+    void *Kt = at(sc.ptr, L.kt), *P2 = at(sc.ptr, L.p2), *W = at(sc.ptr, L.w);
+    if ((st = make_tables(p, s, D, prec, batch, v, v_stride, shared, gamma, dt, Kt, P2, hs))) return st;
+    const int64_t p2_bs = shared ? 0 : p.N;
+    if (s.passes == 1) {
+        ResArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.u = u;
+        a.u_bs = p.N;
+        a.N = p.N;
+        a.L = s.L;
+        a.rank2 = s.rank2 ? 1 : 0;
+        a.n1 = s.L1;
+        a.n2 = s.L2;
+        a.ra = s.ra;
+        a.rb = s.rb;
+        a.twa = D.twa;
+        a.twb = D.twb;
+        a.bluestein = s.bluestein ? 1 : 0;
+        a.tabK = Kt;
+        a.bhat = D.bhat;
+        a.tabP2 = P2;
+        a.p2_bs = p2_bs;
+        a.v = v;
+        a.v_bs = v_stride;
+        a.phase_half = dt / (2.0 * gamma);
+        a.steps = steps;
+        a.ck = ckpt;
+        a.ck_every = ckpt ? ckpt_every : 0;
+        a.ck_stride = (int64_t)batch * p.N;
+        a.batch = batch;
+        HIP_TRY(launch_resident(prec, s, a, batch, hs), "resident run");
+        return LT_OK;
+    }
+    if (ckpt)
+        HIP_TRY(hipMemcpyAsync(ckpt, u, (size_t)batch * p.N * esz(prec), hipMemcpyDeviceToDevice, hs),
+                "checkpoint 0");
+    return two_pass_forward(p, s, D, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every, Kt,
+                            P2, p2_bs, W, hs);
+}
+
+lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, int64_t v_stride,
+                         const void *uT, const void *gT, double gamma, double dt, int64_t steps,
+                         const void *ckpt, int64_t ckpt_every, void *g0, double *gv, void *work,
+                         size_t work_bytes, void *stream)
+{
+    lt_status st = check_common(cp, prec, batch, gamma, dt, steps);
+    if (st) return st;
+    lt_plan &p = *const_cast<lt_plan *>(cp);
+    if (batch == 0) return LT_OK;
+    if (!v || !uT || !gT || !g0 || !gv) return fail(LT_E_ARG, "NULL argument");
+    if (v_stride != 0 && v_stride < p.N) return fail(LT_E_ARG, "v_stride must be 0 or >= N");
+    const bool shared = v_stride == 0;
+    hipStream_t hs = (hipStream_t)stream;
+    const size_t S = esz(prec);
+    const int64_t N = p.N;
+    if (steps == 0) {
+        HIP_TRY(hipMemcpyAsync(g0, gT, (size_t)batch * N * S, hipMemcpyDeviceToDevice, hs), "copy");
+        HIP_TRY(hipMemsetAsync(gv, 0, (size_t)(shared ? 1 : batch) * N * sizeof(double), hs), "memset");
+        return LT_OK;
+    }
+    if (!ckpt || ckpt_every < 1) return fail(LT_E_ARG, "the adjoint needs the forward checkpoints");
+    if ((st = ensure_device_tables(p, 1, prec, stream))) return st;
+    const Sched &s = p.sched[1][prec];
+    const DevTables &D = p.dev[1][prec];
+    const Work L = adj_layout(p, s, prec, batch, shared);
+    Scratch sc;
+    if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
+    void *Kt = at(sc.ptr, L.kt), *P2 = at(sc.ptr, L.p2), *W = at(sc.ptr, L.w);
+    double *gacc = (double *)at(sc.ptr, L.gacc);
+    const double dtb = -dt;  // the backward sweep runs the scheme with -dt
+    if ((st = make_tables(p, s, D, prec, batch, v, v_stride, shared, gamma, dtb, Kt, P2, hs))) return st;
+    HIP_TRY(hipMemsetAsync(gacc, 0, (size_t)batch * N * sizeof(double), hs), "memset");
+    const double c = dt / (2.0 * gamma);
+    const int64_t p2_bs = shared ? 0 : N;
+    void *Wg = at(W, (size_t)batch * s.L * S);
+
+    ColArgs base = col_base(s, D, N);
+    base.C = std::max(1, s.cols / 2);
+    base.ntiles = (s.L2 + base.C - 1) / base.C;
+    base.buf = W;
+    base.buf_bs = s.L;
+    base.buf2 = Wg;
+    base.buf2_bs = s.L;
+    base.v = v;
+    base.v_bs = v_stride;
+    base.phase = dtb / (2.0 * gamma);
+    base.chirp = s.bluestein ? 1 : 0;
+    base.gacc = gacc;
+    base.gacc_bs = N;
+    base.reset_phase = c;
+    base.reset_bs = N;
+
+    ColArgs first = base;
+    first.adjoint = 1;
+    first.in = uT;
+    first.in_bs = N;
+    first.in2 = gT;
+    first.in2_bs = N;
+    first.post_fwd = 1;
+    first.gcoef = c;
+    HIP_TRY(launch_col(prec, s, first, batch, hs), "adjoint column pass");
+
+    RowArgs r = row_base(s, D);
+    r.buf = W;
+    r.buf_bs = s.L;
+    r.tab = s.bluestein ? D.bhat : Kt;
+    ColArgs kin = col_base(s, D, N);
+    kin.buf = W;
+    kin.buf_bs = s.L;
+    kin.pre_inv = 1;
+    kin.post_fwd = 1;
+    kin.tab = Kt;
+    for (int64_t j = steps; j >= 1; --j) {
+        r.conj_tab = 0;
+        HIP_TRY(launch_row(prec, s, r, 2 * batch, hs), "adjoint row pass");
+        if (s.bluestein) {
+            HIP_TRY(launch_col(prec, s, kin, 2 * batch, hs), "adjoint column pass (kinetic)");
+            r.conj_tab = 1;
+            HIP_TRY(launch_row(prec, s, r, 2 * batch, hs), "adjoint row pass");
+        }
+        const int64_t k = j - 1;  // state index at this merge point
+        ColArgs m = base;
+        m.pre_inv = 1;
+        if (k % ckpt_every == 0) m.reset = (const char *)ckpt + (size_t)(k / ckpt_every) * batch * N * S;
+        if (k > 0) {
+            m.adjoint = 2;
+            m.tab = P2;
+            m.tab_bs = p2_bs;
+            m.post_fwd = 1;
+            m.gcoef = 2.0 * c;
+        } else {
+            m.adjoint = 3;
+            m.out2 = g0;
+            m.out2_bs = N;
+            m.gcoef = c;
+        }
+        HIP_TRY(launch_col(prec, s, m, batch, hs), "adjoint column pass");
+    }
+    if (shared) {
+        HIP_TRY(launch_reduce_batch(gv, gacc, N, batch, hs), "gradient reduction");
+    } else {
+        HIP_TRY(hipMemcpyAsync(gv, gacc, (size_t)batch * N * sizeof(double), hipMemcpyDeviceToDevice, hs),
+                "copy");
+    }
+    return LT_OK;
+}
+
+lt_status strang_batched_workspace_size(int32_t B, const lt_plan *const *plans, lt_prec prec, size_t *bytes)
+{
+    if (B < 0 || (B > 0 && !plans) || !bytes) return fail(LT_E_ARG, "bad arguments");
+    if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
+    size_t tot = 0;
+    for (int i = 0; i < B; ++i) {
+        if (!plans[i]) return fail(LT_E_ARG, "plan is NULL");
+        tot += align_up(run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1, false).total);
+    }
+    *bytes = tot;
+    return LT_OK;
+}
+
+lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec prec, const double *const *v,
+                             void *const *u, const double *gamma, const double *dt, const int64_t *steps,
+                             void *work, size_t work_bytes, void *stream)
+{
+    if (B < 0) return fail(LT_E_ARG, "B must be >= 0");
+    if (B == 0) return LT_OK;
+    if (!plans || !v || !u || !gamma || !dt || !steps) return fail(LT_E_ARG, "NULL argument");
+    size_t need = 0;
+    lt_status st = strang_batched_workspace_size(B, plans, prec, &need);
+    if (st) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    Scratch sc;
+    if ((st = get_work(sc, work, work_bytes, need, hs))) return st;
+    size_t off = 0;
+    for (int i = 0; i < B; ++i) {
+        const size_t w = align_up(run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1, false).total);
+        st = strang_run(plans[i], prec, 1, v[i], plans[i]->N, u[i], gamma[i], dt[i], steps[i], nullptr, 0,
+                        at(sc.ptr, off), w, stream);
+        if (st) return st;
+        off += w;
+    }
+    return LT_OK;
+}
+
+}  // extern "C"

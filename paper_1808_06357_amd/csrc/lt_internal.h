@@ -1,0 +1,157 @@
+// Internal declarations shared by the host planner, the C-ABI layer and the
+// HIP kernels of the lattice Strang library.  Not part of the public ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/lattice_tdse.h"
+
+namespace lt {
+
+constexpr int kThreads = 256;           // workgroup size of every FFT kernel
+constexpr int kMaxStages = 24;
+constexpr size_t kTileBytes = 64 * 1024; // LDS tile budget per workgroup
+
+// Radix sequence of one sub-transform of length L (product of radices).
+struct Radices {
+    int L;
+    int n;
+    int r[kMaxStages];
+};
+
+// How one lattice transform is laid out on the GPU for one precision.
+struct Sched {
+    bool ok = false;
+    int passes = 0;          // 1: one workgroup holds the whole transform; 2: column + row passes
+    bool bluestein = false;  // the length-N DFT runs as a chirp-z convolution of length L
+    bool rank2 = false;      // 2-D transform over n1 x n2 (no four-step twiddle)
+    int64_t L = 0;           // transform length (N, or the convolution length)
+    int L1 = 0, L2 = 0;      // two-pass: column length, row length; single rank-2: n1, n2
+    int cols = 1;            // columns per column-pass workgroup
+    int rows = 1;            // rows per row-pass workgroup
+    int ept = 16;            // max complex elements per thread (register budget)
+    Radices ra{}, rb{};      // radices of L1 (or L) and of L2
+};
+
+// Device tables of a plan for one precision (built lazily, then immutable).
+struct DevTables {
+    bool built = false;
+    void *twa = nullptr;     // W_{La}^q, q < La (run precision), La = L1 or L
+    void *twb = nullptr;     // W_{L2}^q
+    double *tw4hi = nullptr; // W_L^{qa L2}, qa < L1   (double complex pairs)
+    double *tw4lo = nullptr; // W_L^{qb},    qb < L2
+    int32_t *s_key = nullptr;// ||h_chi||^2 per key
+    void *bhat = nullptr;    // chirp-z kernel spectrum, scaled by 1/(L sqrt N), schedule layout
+};
+
+// ---------------------------------------------------------------- kernel arguments
+struct ColArgs {
+    void *buf; int64_t buf_bs;        // transform buffer (L elements per batch item)
+    const void *in; int64_t in_bs;    // first pass: read lattice values from here (Nvalid)
+    void *out; int64_t out_bs;        // last pass: write lattice values here (Nvalid)
+    int L1, L2, C, ntiles;
+    int64_t Nvalid;                   // natural index >= Nvalid is zero / not stored
+    int pre_inv, post_fwd, twiddle;
+    const void *tab; int64_t tab_bs;  // mid multiplier (natural index), or null
+    const double *v; int64_t v_bs;    // on-the-fly phase exp(-i phase * v[n]) (first/last pass)
+    double phase;
+    int chirp;                        // +1: times c_n, -1: times conj(c_n), 0: none
+    int64_t Nchirp;                   // N of the chirp exp(-pi i (n^2 mod 2N)/N)
+    double scale;
+    const double *tw4hi, *tw4lo;
+    const void *twa;
+    Radices rad;
+    void *ck; int64_t ck_bs;          // optional checkpoint store of the point value
+    const double *ck_v;               // u = x * exp(-i ck_phase ck_v[n]) * conj(c_n)^[ck_chirp]
+    double ck_phase;
+    int ck_chirp;
+    // adjoint pairing: sequences of vector 0 (state) and vector 1 (cotangent)
+    int adjoint;                      // 0: off; 1: first; 2: middle; 3: last
+    void *buf2; int64_t buf2_bs;      // cotangent transform buffer
+    const void *in2; int64_t in2_bs;  // first adjoint pass: cotangent lattice values
+    void *out2; int64_t out2_bs;      // last adjoint pass: dJ/du0
+    double *gacc; int64_t gacc_bs;    // potential gradient accumulator (double, natural index)
+    double gcoef;                     // coefficient of Im(conj(mu) a) in the accumulator
+    const void *reset; int64_t reset_bs;  // checkpoint replacing the recomputed state, or null
+    double reset_phase;               // a = exp(-i reset_phase v) * ckpt (times c_n for chirp-z)
+};
+
+struct RowArgs {
+    void *buf; int64_t buf_bs;
+    int L1, L2, rows, nblk;
+    const void *tab; int64_t tab_bs; int conj_tab;
+    int fft_only;
+    const void *twb;
+    Radices rad;
+};
+
+struct ResArgs {
+    void *u; int64_t u_bs;
+    int64_t N, L;
+    int rank2, n1, n2;
+    Radices ra, rb;
+    const void *twa, *twb;
+    int bluestein;
+    const void *tabK;                  // natural order; smooth: K/L; chirp-z: K (index < N)
+    const void *bhat;                  // natural order, chirp-z only
+    const void *tabP2; int64_t p2_bs;
+    const double *v; int64_t v_bs;
+    double phase_half;                 // dt / (2 gamma)
+    int64_t steps;
+    void *ck; int64_t ck_every; int64_t ck_stride; // checkpoint c at ck + c*ck_stride + b*N
+    int64_t batch;
+};
+
+// ---------------------------------------------------------------- launchers (kernels.hip)
+// All launchers return 0 or a hipError_t value; they enqueue on `stream`.
+int launch_col(int prec, const Sched &s, const ColArgs &a, int batch, void *stream);
+int launch_row(int prec, const Sched &s, const RowArgs &a, int batch, void *stream);
+int launch_resident(int prec, const Sched &s, const ResArgs &a, int batch, void *stream);
+int launch_fft_single(int prec, const Radices &ra, const void *twa, void *buf, int64_t L,
+                      void *stream);
+int launch_setup_kernel_table(int prec, void *dst, const int32_t *s_key, int64_t N, int L1, int L2,
+                              int transposed, double kin, double scale, void *stream);
+int launch_setup_phase_table(int prec, void *dst, const double *v, int64_t v_bs, int64_t N,
+                             int batch, double phase, void *stream);
+int launch_convert_permute(int prec_dst, void *dst, const void *src_c128_nat, int64_t L, int L1,
+                           int L2, int transposed, double scale, void *stream);
+int launch_unpermute_c128(void *dst_nat, const void *src, int64_t L, int L1, int L2,
+                          void *stream);
+int launch_chirp_filter(void *dst_c128, int64_t N, int64_t L, void *stream);
+int launch_reduce_batch(double *dst, const double *src, int64_t N, int batch, void *stream);
+int kernels_init();  // raise dynamic LDS limits once
+
+}  // namespace lt
+
+// ---------------------------------------------------------------- the plan
+struct lt_plan {
+    int d = 0, r = 0;
+    int64_t n[4] = {1, 1, 1, 1};
+    int64_t N = 0;
+    std::vector<int64_t> Z;        // r x d
+    std::vector<int32_t> H;        // user index set, nh x d
+    std::vector<int64_t> key_of_h; // nh
+    std::vector<int64_t> s_of_key; // N
+    std::vector<int32_t> h_of_key; // N x d
+    int64_t n_index = 0, n_completed = 0, max_s = 0;
+    // [0]: the run schedule; [1]: a two-pass schedule (used by the adjoint,
+    // identical to [0] when [0] is already two-pass); inner index lt_prec
+    lt::Sched sched[2][3];
+    std::mutex mu;
+    lt::DevTables dev[2][3];
+    int device = -1;
+};
+
+namespace lt {
+void set_error(const std::string &msg);
+lt_status fail(lt_status st, const std::string &msg);
+Sched make_schedule(const lt_plan &p, int prec, bool force_two_pass);
+lt_status plan_index_set(lt_plan &p);
+lt_status ensure_device_tables(lt_plan &p, int which, int prec, void *stream);
+bool factor_radices(int64_t L, Radices &out);
+int64_t smooth7_at_least(int64_t x);
+}  // namespace lt

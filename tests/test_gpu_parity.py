@@ -1,0 +1,152 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle on the
+same seeded inputs.  Tolerances (relative L2 over all points): complex128
+1e-11, complex64 1e-4."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-11, "c64": 1e-4}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _dtype(prec):
+    torch = _torch()
+    return torch.complex128 if prec == "c128" else torch.complex64
+
+
+def gpu_run(lt, plan, v, u0, gamma, dt, steps, prec, **kw):
+    torch = _torch()
+    u = torch.tensor(np.asarray(u0), dtype=_dtype(prec), device="cuda")
+    vv = torch.tensor(np.asarray(v), dtype=torch.float64, device="cuda")
+    lt.strang_run(plan, vv, u, gamma, dt, steps, **kw)
+    torch.cuda.synchronize()
+    return u.cpu().numpy().astype(np.complex128)
+
+
+def korobov_case(N, d, seed, steps, gamma=0.05, dt=2e-3, batch=1, shared=True):
+    g = np.random.default_rng(seed)
+    z = W.korobov(N, d, g)
+    Z, n = z.reshape(1, -1), np.array([N])
+    num = W.point_numerators(Z, n)
+    if shared:
+        v = W.cosine_series(d, 16, g).at(num, N)
+    else:
+        v = np.stack([W.cosine_series(d, 16, g).at(num, N) for _ in range(batch)])
+    u0 = np.stack([W.seeded_packet(num, N, g) for _ in range(batch)])
+    if batch == 1:
+        u0 = u0[0]
+    return Z, n, v, u0, gamma, dt, steps
+
+
+def check_case(lt, Z, n, v, u0, gamma, dt, steps, precs=("c128", "c64"), I=None, tol_scale=1.0):
+    print(f"case N={int(np.prod(n))} r={len(n)} steps={steps} shape={np.shape(u0)}", flush=True)
+    plan = lt.lattice_plan(Z, n, I)
+    _, s, _ = O.index_set(Z, n, I)
+    ref = O.strang_run(n, s, v, u0, gamma, dt, steps)
+    for prec in precs:
+        got = gpu_run(lt, plan, v, u0, gamma, dt, steps, prec)
+        e = rel(got, ref)
+        print(f"  {prec} plan={plan.info['passes']}-pass bluestein={plan.info['bluestein']} "
+              f"L={plan.info['fft_len']} rel_l2={e:.3e}", flush=True)
+        assert e < TOL[prec] * tol_scale, (prec, e)
+    return plan
+
+
+def test_config0_resident(lt):
+    c = W.config0()
+    check_case(lt, c.Z, c.n, c.v, c.u0, c.gamma, c.dt, c.steps, I=c.I)
+
+
+def test_smooth_two_pass_composite(lt):
+    check_case(lt, *korobov_case(15360, 3, 1, 30))
+
+
+def test_power_of_two_two_pass(lt):
+    check_case(lt, *korobov_case(1 << 16, 4, 2, 20))
+
+
+def test_bluestein_two_pass(lt):
+    check_case(lt, *korobov_case(65521, 4, 3, 20))
+
+
+def test_bluestein_resident_small_prime(lt):
+    check_case(lt, *korobov_case(1999, 3, 4, 25))
+
+
+def test_tiny_lattices(lt):
+    check_case(lt, np.array([[1, 34]]), np.array([55]), *korobov_case(55, 2, 5, 7)[2:])
+    Z, n = np.array([[1]]), np.array([2])
+    check_case(lt, Z, n, np.array([0.3, -0.2]), np.array([1.0, 0.5j]), 0.2, 0.1, 3)
+
+
+def test_rank2_resident_and_two_pass(lt):
+    for n1, n2, d in [(64, 16, 4), (1024, 64, 5)]:
+        H = W.hyperbolic_cross(d, 1)
+        Z = W.cbc_rank2(H, n1, n2, np.random.default_rng(n1))
+        n = np.array([n1, n2])
+        num = W.point_numerators(Z, n)
+        N = n1 * n2
+        g = np.random.default_rng(7)
+        v = W.cosine_series(d, 8, g).at(num, N)
+        u0 = W.seeded_packet(num, N, g)
+        plan = check_case(lt, Z, n, v, u0, 0.05, 2e-3, 15, I=H)
+        assert plan.info["passes"] == (1 if N <= 4096 else 2)
+
+
+def test_batch_shared_and_per_state_potential(lt):
+    check_case(lt, *korobov_case(4096 * 3, 3, 8, 12, batch=3, shared=True))
+    check_case(lt, *korobov_case(65521, 3, 9, 6, batch=2, shared=False))
+    check_case(lt, *korobov_case(1031, 2, 10, 9, batch=4, shared=False))
+
+
+def test_zero_and_one_step(lt):
+    torch = _torch()
+    Z, n, v, u0, gamma, dt, _ = korobov_case(65521, 3, 11, 1)
+    plan = lt.lattice_plan(Z, n)
+    got = gpu_run(lt, plan, v, u0, gamma, dt, 0, "c128")
+    assert np.array_equal(got, u0)
+    _, s, _ = O.index_set(Z, n)
+    assert rel(gpu_run(lt, plan, v, u0, gamma, dt, 1, "c128"), O.strang_run(n, s, v, u0, gamma, dt, 1)) < 1e-12
+    del torch
+
+
+def test_reversibility_negative_dt(lt):
+    """S(-dt) S(dt) = I (symmetric scheme), on the GPU in complex128."""
+    torch = _torch()
+    for N in (1031, 65521, 1 << 16):
+        Z, n, v, u0, gamma, dt, _ = korobov_case(N, 3, 12, 40)
+        plan = lt.lattice_plan(Z, n)
+        u = torch.tensor(u0, dtype=torch.complex128, device="cuda")
+        vv = torch.tensor(v, device="cuda")
+        lt.strang_run(plan, vv, u, gamma, dt, 40)
+        lt.strang_run(plan, vv, u, gamma, -dt, 40)
+        assert rel(u.cpu().numpy(), u0) < 1e-12
+
+
+def test_checkpoints_match_shorter_runs(lt):
+    torch = _torch()
+    for N in (1031, 65521):
+        Z, n, v, u0, gamma, dt, _ = korobov_case(N, 3, 13, 1, batch=2, shared=False)
+        plan = lt.lattice_plan(Z, n)
+        steps, every = 23, 5
+        u = torch.tensor(u0, dtype=torch.complex128, device="cuda")
+        vv = torch.tensor(v, device="cuda")
+        ck = torch.empty(lt.num_checkpoints(steps, every) * 2 * N, dtype=torch.complex128, device="cuda")
+        lt.strang_run(plan, vv, u, gamma, dt, steps, ckpt=ck, ckpt_every=every)
+        ck = ck.view(-1, 2, N).cpu().numpy()
+        _, s, _ = O.index_set(Z, n)
+        for c in range(ck.shape[0]):
+            ref = O.strang_run(n, s, v, u0, gamma, dt, c * every)
+            assert rel(ck[c], ref) < 1e-11, (N, c)

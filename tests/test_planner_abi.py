@@ -1,0 +1,113 @@
+"""Host-side tests of the C-ABI library: exports, planner tables bit-exact
+against the oracle, argument and lattice errors.  No GPU call is made."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from paper_1808_06357_amd import _capi as C
+
+
+def test_library_exports_every_header_function():
+    names = C.header_functions()
+    assert "strang_run" in names and "lattice_plan" in names and len(names) >= 12
+    for name in names:
+        assert hasattr(C.lib, name), name
+
+
+def _planner_matches_oracle(Z, n, I=None):
+    p = C.lattice_plan(Z, n, I)
+    k, s, h = C.lattice_plan_keys(p)
+    ho, so, fromI = O.index_set(Z, n, I)
+    assert np.array_equal(s, so)
+    assert np.array_equal(h, ho)
+    if I is not None:
+        assert np.array_equal(k, O.keys(Z, n, I))
+        assert p.info["n_index"] == len(I) and p.info["n_completed"] == p.N - len(I)
+    assert p.info["max_s"] == so.max()
+    return p
+
+
+def test_planner_fig1_and_config0_bitexact():
+    _planner_matches_oracle(np.array([[1, 34]]), np.array([55]))
+    c = W.config0()
+    p = _planner_matches_oracle(c.Z, c.n, c.I)
+    assert p.N == 1031
+
+
+def test_planner_rank2_bitexact():
+    _planner_matches_oracle(np.array([[1, 5, 7], [0, 1, 3]]), np.array([12, 4]))
+    Z = W.cbc_rank2(W.hyperbolic_cross(4, 2), 64, 16, np.random.default_rng(3))
+    _planner_matches_oracle(Z, np.array([64, 16]), W.hyperbolic_cross(4, 2))
+
+
+def test_planner_config4_lattice_bitexact():
+    """d = 4, N = 65521, Korobov z, full minimal-l2 set (no user set)."""
+    z = W.korobov(65521, 4, W.rng(4, "z"))
+    _planner_matches_oracle(z.reshape(1, -1), np.array([65521]))
+
+
+@pytest.mark.slow
+def test_planner_config1_lattice_bitexact():
+    """The benchmark lattice: d = 6, N = 1048573, hyperbolic cross R = 10
+    completed with minimal-l2 representatives (bin map bit-exact)."""
+    c1 = W.config1(steps=1)
+    _planner_matches_oracle(c1.Z, c1.n, c1.I)
+
+
+def test_points_match_workload_numerators():
+    for Z, n in [(np.array([[1, 32]]), np.array([1031])), (np.array([[1, 5, 7], [0, 1, 3]]), np.array([12, 4]))]:
+        p = C.lattice_plan(Z, n)
+        assert np.array_equal(C.lattice_plan_points(p), W.point_numerators(Z, n))
+        assert np.array_equal(C.lattice_plan_points(p, 5, 3), W.point_numerators(Z, n)[5:8])
+
+
+def test_plan_errors():
+    with pytest.raises(C.LatticeError) as e:
+        C.lattice_plan(np.array([[1, 3], [1, 1]]), np.array([4, 8]))     # 8 does not divide 4
+    assert e.value.status == "LT_E_NOT_CANONICAL"
+    with pytest.raises(C.LatticeError) as e:
+        C.lattice_plan(np.array([[1, 3]]), np.array([7]), np.array([[0, 0], [7, 0]]))
+    assert e.value.status == "LT_E_NOT_INJECTIVE"
+    with pytest.raises(C.LatticeError) as e:
+        C.lattice_plan(np.array([[2, 4]]), np.array([8]))               # gcd 2: points repeat
+    assert e.value.status == "LT_E_INCOMPLETE"
+    with pytest.raises(C.LatticeError) as e:
+        C.lattice_plan(np.array([[1, 1, 1], [1, 1, 1]]), np.array([4, 4]))  # rank-2 all odd: repeats
+    assert e.value.status == "LT_E_INCOMPLETE"
+    out = ctypes.c_void_p()
+    assert C.lib.lattice_plan(0, 1, None, None, None, 0, ctypes.byref(out)) == 1
+    assert b"d must be" in C.lib.lt_last_error()
+
+
+def test_run_argument_errors_before_any_gpu_call():
+    p = C.lattice_plan(np.array([[1, 34]]), np.array([55]))
+    h = p.handle
+    # NULL buffers, bad gamma, bad precision, negative steps: rejected on the host
+    assert C.lib.strang_run(h, 1, 1, None, 0, None, 0.1, 0.01, 5, None, 0, None, 0, None) == 1
+    assert C.lib.strang_run(h, 1, 1, None, 0, None, -0.1, 0.01, 5, None, 0, None, 0, None) == 1
+    assert C.lib.strang_run(h, 3, 1, None, 0, None, 0.1, 0.01, 5, None, 0, None, 0, None) == 1
+    assert C.lib.strang_run(h, 1, 1, None, 0, None, 0.1, 0.01, -1, None, 0, None, 0, None) == 1
+    assert C.lib.strang_run(None, 1, 1, None, 0, None, 0.1, 0.01, 1, None, 0, None, 0, None) == 1
+    assert C.lib.strang_run(h, 1, 1, None, 0, None, 0.1, float("nan"), 1, None, 0, None, 0, None) == 1
+    # zero steps / zero batch are no-ops that touch nothing
+    assert C.lib.strang_run(h, 2, 0, None, 0, None, 0.1, 0.01, 5, None, 0, None, 0, None) == 0
+    assert C.lib.strang_run(h, 2, 1, None, 0, None, 0.1, 0.01, 0, None, 0, None, 0, None) == 0
+    assert C.lib.strang_adjoint(h, 2, 1, None, 0, None, None, 0.1, 0.01, 3, None, 0, None, None,
+                                None, 0, None) == 1
+
+
+def test_schedules():
+    """Transform layouts: chirp-z for prime N, two passes for long transforms."""
+    c = W.config0()
+    p = C.lattice_plan(c.Z, c.n, c.I)
+    assert p.info["bluestein"] == 1 and p.info["passes"] == 1 and p.info["fft_len"] >= 2 * 1031 - 1
+    p = C.lattice_plan(np.array([[1, 3]]), np.array([1 << 16]))
+    assert p.info["bluestein"] == 0 and p.info["passes"] == 2
+    assert p.info["L1"] * p.info["L2"] == 1 << 16
+    p = C.lattice_plan(np.array([[1, 5, 7], [0, 1, 3]]), np.array([12, 4]))
+    assert p.info["passes"] == 1 and p.info["fft_len"] == 48
+    for name, size in [("strang_workspace_size", 0), ("strang_adjoint_workspace_size", 0)]:
+        assert getattr(C, name)(p, C.LT_C128, 2, True) > size
