@@ -196,6 +196,17 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
                              const double *dt, const int64_t *steps, void *work,
                              size_t work_bytes, void *stream);
 
+/*
+ * Diagnostics: HIP-event timing of the library's own launches.  While
+ * enabled, every kernel launch is bracketed by two events recorded on its
+ * stream.  lt_timing_enable(on) also discards earlier records;
+ * lt_timing_summary waits for the recorded events of one kernel class and
+ * returns their count and summed elapsed milliseconds.
+ */
+typedef enum { LT_KIND_COLUMN = 0, LT_KIND_ROW = 1, LT_KIND_RESIDENT = 2 } lt_kernel_kind;
+lt_status lt_timing_enable(int32_t on);
+lt_status lt_timing_summary(int32_t kind, int64_t *launches, double *total_ms);
+
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *lt_last_error(void);
 

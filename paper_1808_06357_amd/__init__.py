@@ -4,8 +4,9 @@ Python face of the HIP library (include/lattice_tdse.h): plans, runs,
 adjoints and batched runs, plus a torch.autograd.Function.  All arithmetic of
 a run happens in the library's HIP kernels.
 """
-from ._capi import (LT_C64, LT_C128, LatticeError, Plan, lattice_plan, lattice_plan_info,
-                    lattice_plan_keys, lattice_plan_points, num_checkpoints, strang_adjoint,
+from ._capi import (LT_C64, LT_C128, LT_KIND_COLUMN, LT_KIND_RESIDENT, LT_KIND_ROW, LatticeError,
+                    Plan, lattice_plan, lattice_plan_info, lattice_plan_keys, lattice_plan_points,
+                    lt_timing_enable, lt_timing_summary, num_checkpoints, strang_adjoint,
                     strang_adjoint_workspace_size, strang_batched_workspace_size, strang_run,
                     strang_run_batched, strang_workspace_size)
 from .autograd import LatticeStrang, lattice_strang
@@ -14,4 +15,5 @@ __all__ = ["LT_C64", "LT_C128", "LatticeError", "Plan", "lattice_plan", "lattice
            "lattice_plan_keys", "lattice_plan_points", "num_checkpoints", "strang_run",
            "strang_adjoint", "strang_run_batched", "strang_workspace_size",
            "strang_adjoint_workspace_size", "strang_batched_workspace_size", "LatticeStrang",
-           "lattice_strang"]
+           "lattice_strang", "lt_timing_enable", "lt_timing_summary", "LT_KIND_COLUMN",
+           "LT_KIND_ROW", "LT_KIND_RESIDENT"]

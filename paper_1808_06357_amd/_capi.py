@@ -58,6 +58,8 @@ _SIGS = {
     "strang_adjoint": [_P, _i32, _i32, _P, _i64, _P, _P, _f64, _f64, _i64, _P, _i64, _P, _P, _P, _sz, _P],
     "strang_batched_workspace_size": [_i32, _P, _i32, ctypes.POINTER(_sz)],
     "strang_run_batched": [_i32, _P, _i32, _P, _P, _P, _P, _P, _P, _sz, _P],
+    "lt_timing_enable": [_i32],
+    "lt_timing_summary": [_i32, ctypes.POINTER(_i64), ctypes.POINTER(_f64)],
     "lt_last_error": [],
 }
 for _name, _args in _SIGS.items():
@@ -276,3 +278,17 @@ def strang_run_batched(plans: Sequence[Plan], vs, us, gammas, dts, steps, work=N
     _check(lib.strang_run_batched(B, parr, prec, varr, uarr, _np_ptr(g), _np_ptr(dtt), _np_ptr(st),
                                   _dev_ptr(work), wb, _stream(stream)), "strang_run_batched")
     return us
+
+
+LT_KIND_COLUMN, LT_KIND_ROW, LT_KIND_RESIDENT = 0, 1, 2
+
+
+def lt_timing_enable(on: bool) -> None:
+    _check(lib.lt_timing_enable(int(bool(on))), "lt_timing_enable")
+
+
+def lt_timing_summary(kind: int):
+    """(launches, total_ms) of the recorded launches of one kernel class."""
+    n, ms = _i64(), _f64()
+    _check(lib.lt_timing_summary(kind, ctypes.byref(n), ctypes.byref(ms)), "lt_timing_summary")
+    return n.value, ms.value

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "liblattice_tdse.so")
-SOURCES = ["planner.cpp", "capi.cpp", "kernels.hip"]
+SOURCES = ["planner.cpp", "capi.cpp", "timing.cpp", "kernels.hip", "kernels_fast.hip"]
 HEADERS = ["lt_internal.h", os.path.join("..", "..", "include", "lattice_tdse.h")]
 ARCH = os.environ.get("LT_OFFLOAD_ARCH", "gfx950")
 

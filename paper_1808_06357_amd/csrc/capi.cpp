@@ -25,17 +25,33 @@ size_t esz(int prec) { return prec == LT_C128 ? 16 : 8; }
             return fail(LT_E_HIP, std::string(what) + ": " + hipGetErrorString(e_));           \
     } while (0)
 
-// exp(-2 pi i q mult / L) for q < count, interleaved (re, im), computed in long
-// double from the exactly reduced integer q*mult mod L.
-template <typename T>
-std::vector<T> roots(int64_t L, int64_t count, int64_t mult)
+// exp(-2 pi i q mult / L) for q < count, computed in long double from the
+// exactly reduced integer q*mult mod L.  complex128 tables: (re, im) doubles;
+// complex64 tables: (hi.re, hi.im, lo.re, lo.im) floats with hi = fl(w) and
+// lo = fl(w - hi), so that products can carry the table value beyond FP32.
+std::vector<double> roots_d(int64_t L, int64_t count, int64_t mult)
 {
-    std::vector<T> out((size_t)(2 * count));
+    std::vector<double> out((size_t)(2 * count));
     for (int64_t q = 0; q < count; ++q) {
         const int64_t m = (int64_t)(((__int128)q * mult) % L);
         const long double a = 2.0L * kPiL * (long double)m / (long double)L;
-        out[(size_t)(2 * q)] = (T)cosl(a);
-        out[(size_t)(2 * q + 1)] = (T)(-sinl(a));
+        out[(size_t)(2 * q)] = (double)cosl(a);
+        out[(size_t)(2 * q + 1)] = (double)(-sinl(a));
+    }
+    return out;
+}
+
+std::vector<float> roots_f(int64_t L, int64_t count)
+{
+    std::vector<float> out((size_t)(4 * count));
+    for (int64_t q = 0; q < count; ++q) {
+        const long double a = 2.0L * kPiL * (long double)(q % L) / (long double)L;
+        const long double c = cosl(a), s = -sinl(a);
+        const float ch = (float)c, sh = (float)s;
+        out[(size_t)(4 * q)] = ch;
+        out[(size_t)(4 * q + 1)] = sh;
+        out[(size_t)(4 * q + 2)] = (float)(c - (long double)ch);
+        out[(size_t)(4 * q + 3)] = (float)(s - (long double)sh);
     }
     return out;
 }
@@ -58,6 +74,8 @@ lt_status bind_device(lt_plan &p)
     return LT_OK;
 }
 
+bool transposed_layout(const Sched &s) { return s.passes == 2 && !s.rank2; }
+
 lt_status build_twiddles(lt_plan &p, int which, int prec)
 {
     DevTables &D = p.dev[which][prec];
@@ -73,19 +91,33 @@ lt_status build_twiddles(lt_plan &p, int which, int prec)
     }
     lt_status st;
     if (prec == LT_C128) {
-        if ((st = upload(&D.twa, roots<double>(La, La, 1), "twiddles"))) return st;
-        if ((st = upload(&D.twb, roots<double>(Lb, Lb, 1), "twiddles"))) return st;
+        if ((st = upload(&D.twa, roots_d(La, La, 1), "twiddles"))) return st;
+        if ((st = upload(&D.twb, roots_d(Lb, Lb, 1), "twiddles"))) return st;
     } else {
-        if ((st = upload(&D.twa, roots<float>(La, La, 1), "twiddles"))) return st;
-        if ((st = upload(&D.twb, roots<float>(Lb, Lb, 1), "twiddles"))) return st;
+        if ((st = upload(&D.twa, roots_f(La, La), "twiddles"))) return st;
+        if ((st = upload(&D.twb, roots_f(Lb, Lb), "twiddles"))) return st;
     }
-    if (s.passes == 2 && !s.rank2) {
-        if ((st = upload((void **)&D.tw4hi, roots<double>(s.L, s.L1, s.L2), "twiddles"))) return st;
-        if ((st = upload((void **)&D.tw4lo, roots<double>(s.L, s.L2, 1), "twiddles"))) return st;
+    if (transposed_layout(s)) {
+        if ((st = upload((void **)&D.tw4hi, roots_d(s.L, s.L1, s.L2), "twiddles"))) return st;
+        if ((st = upload((void **)&D.tw4lo, roots_d(s.L, s.L2, 1), "twiddles"))) return st;
     }
     std::vector<int32_t> sk((size_t)p.N);
     for (int64_t t = 0; t < p.N; ++t) sk[(size_t)t] = (int32_t)p.s_of_key[(size_t)t];
-    return upload((void **)&D.s_key, sk, "key norms");
+    if ((st = upload((void **)&D.s_key, sk, "key norms"))) return st;
+    if (s.passes == 2 && !s.bluestein) {
+        // kinetic angles are read at the row-pass positions
+        std::vector<int32_t> sr((size_t)p.N);
+        for (int64_t pos = 0; pos < p.N; ++pos) {
+            int64_t chi = pos;
+            if (transposed_layout(s)) {
+                const int64_t k1 = pos / s.L2, k2 = pos - k1 * s.L2;
+                chi = k1 + (int64_t)s.L1 * k2;
+            }
+            sr[(size_t)pos] = sk[(size_t)chi];
+        }
+        if ((st = upload((void **)&D.s_row, sr, "key norms"))) return st;
+    }
+    return LT_OK;
 }
 
 ColArgs col_base(const Sched &s, const DevTables &D, int64_t N)
@@ -117,6 +149,7 @@ RowArgs row_base(const Sched &s, const DevTables &D)
     a.nblk = (s.L1 + s.rows - 1) / s.rows;
     a.twb = D.twb;
     a.rad = s.rb;
+    a.scale = 1.0;
     return a;
 }
 
@@ -130,7 +163,7 @@ lt_status bhat_natural(lt_plan &p, void *nat, void *tmp, hipStream_t st)
     const DevTables &D = p.dev[0][LT_C128];
     HIP_TRY(launch_chirp_filter(tmp, p.N, s.L, st), "chirp filter");
     if (s.passes == 1) {
-        HIP_TRY(launch_fft_single(LT_C128, s.ra, D.twa, tmp, s.L, st), "kernel spectrum");
+        HIP_TRY(launch_fft_single(s.ra, D.twa, tmp, s.L, st), "kernel spectrum");
         HIP_TRY(hipMemcpyAsync(nat, tmp, (size_t)s.L * 16, hipMemcpyDeviceToDevice, st), "copy");
         return LT_OK;
     }
@@ -146,34 +179,23 @@ lt_status bhat_natural(lt_plan &p, void *nat, void *tmp, hipStream_t st)
     return LT_OK;
 }
 
-struct Work {
-    size_t kt = 0, p2 = 0, w = 0, w2 = 0, gacc = 0, total = 0;
-};
-
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Work run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool shared)
+// forward runs: a transform buffer only for two-pass chirp-z (otherwise u itself)
+size_t run_bytes(const Sched &s, int prec, int batch)
 {
-    Work w;
-    size_t off = 0;
-    w.kt = off;
-    off = align_up(off + (size_t)std::max<int64_t>(s.L, p.N) * esz(prec));
-    w.p2 = off;
-    off = align_up(off + (size_t)(shared ? 1 : batch) * p.N * esz(prec));
-    w.w = off;
-    if (s.bluestein && s.passes == 2) off = align_up(off + (size_t)batch * s.L * esz(prec));
-    w.total = off;
-    return w;
+    if (s.bluestein && s.passes == 2) return align_up((size_t)batch * s.L * esz(prec));
+    return 0;
 }
 
-Work adj_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool shared)
+struct AdjWork {
+    size_t w = 0, gacc = 0, total = 0;
+};
+
+AdjWork adj_layout(const lt_plan &p, const Sched &s, int prec, int batch)
 {
-    Work w;
+    AdjWork w;
     size_t off = 0;
-    w.kt = off;
-    off = align_up(off + (size_t)std::max<int64_t>(s.L, p.N) * esz(prec));
-    w.p2 = off;
-    off = align_up(off + (size_t)(shared ? 1 : batch) * p.N * esz(prec));
     w.w = off;
     off = align_up(off + (size_t)2 * batch * s.L * esz(prec));   // state and cotangent
     w.gacc = off;
@@ -211,28 +233,31 @@ struct Scratch {
 lt_status get_work(Scratch &sc, void *work, size_t work_bytes, size_t need, hipStream_t st)
 {
     sc.st = st;
+    if (need == 0) return LT_OK;
     if (work) {
         if (work_bytes < need)
             return fail(LT_E_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
         sc.ptr = work;
         return LT_OK;
     }
-    HIP_TRY(hipMallocAsync(&sc.ptr, std::max<size_t>(need, 256), st), "workspace allocation");
+    HIP_TRY(hipMallocAsync(&sc.ptr, need, st), "workspace allocation");
     sc.owned = true;
     return LT_OK;
 }
 
 inline char *at(void *base, size_t off) { return (char *)base + off; }
 
-// one state batch through the two-pass sequence (forward or backward in time)
+double kinetic_angle(double gamma, double dt) { return 2.0 * M_PI * M_PI * gamma * dt; }
+
+// forward run of a state batch through the two-pass sequence
 lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int prec, int batch,
                            const double *v, int64_t v_stride, void *u, double gamma, double dt,
-                           int64_t steps, void *ckpt, int64_t ck_every, void *Kt, void *P2,
-                           int64_t p2_bs, void *W, hipStream_t st)
+                           int64_t steps, void *ckpt, int64_t ck_every, void *W, hipStream_t st)
 {
     const int64_t N = p.N;
     const size_t S = esz(prec);
     const double half = dt / (2.0 * gamma);
+    const double kin = kinetic_angle(gamma, dt);
     void *buf = s.bluestein ? W : u;
     const int64_t buf_bs = s.bluestein ? s.L : N;
     // first pass: half potential step (and chirp), column DFT
@@ -250,32 +275,40 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
     RowArgs r = row_base(s, D);
     r.buf = buf;
     r.buf_bs = buf_bs;
-    r.tab = s.bluestein ? D.bhat : Kt;
+    if (s.bluestein) {
+        r.bhat = D.bhat;
+    } else {
+        r.s = D.s_row;
+        r.kin = kin;
+        r.scale = 1.0 / (double)s.L;
+    }
     ColArgs mid = col_base(s, D, N);
     mid.buf = buf;
     mid.buf_bs = buf_bs;
     mid.pre_inv = 1;
     mid.post_fwd = 1;
-    ColArgs kin = mid;
-    kin.tab = Kt;  // chirp-z: K at the natural spectral index
+    ColArgs kinp = mid;  // chirp-z: kinetic phase at the natural spectral index
+    kinp.s = D.s_key;
+    kinp.kin = kin;
+    ColArgs pot = mid;   // merged potential step P^2
+    pot.v = v;
+    pot.v_bs = v_stride;
+    pot.phase = 2.0 * half;
     for (int64_t t = 0; t < steps; ++t) {
         r.conj_tab = 0;
         HIP_TRY(launch_row(prec, s, r, batch, st), "row pass");
         if (s.bluestein) {
-            HIP_TRY(launch_col(prec, s, kin, batch, st), "column pass (kinetic)");
+            HIP_TRY(launch_col(prec, s, kinp, batch, st), "column pass (kinetic)");
             r.conj_tab = 1;
             HIP_TRY(launch_row(prec, s, r, batch, st), "row pass");
         }
         if (t == steps - 1) break;
-        ColArgs m = mid;
-        m.tab = P2;
-        m.tab_bs = p2_bs;
+        ColArgs m = pot;
         const int64_t k = t + 1;  // state index at this merge point
         if (ckpt && k % ck_every == 0) {
             m.ck = at(ckpt, (size_t)(k / ck_every) * batch * N * S);
             m.ck_bs = N;
             m.ck_v = v;
-            m.v_bs = v_stride;
             m.ck_phase = half;
             m.ck_chirp = s.bluestein ? 1 : 0;
         }
@@ -292,24 +325,6 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
     last.phase = half;
     last.chirp = s.bluestein ? -1 : 0;
     HIP_TRY(launch_col(prec, s, last, batch, st), "column pass (last)");
-    return LT_OK;
-}
-
-lt_status make_tables(lt_plan &p, const Sched &s, const DevTables &D, int prec, int batch,
-                      const double *v, int64_t v_stride, bool shared, double gamma, double dt,
-                      void *Kt, void *P2, hipStream_t st)
-{
-    const double kin = 2.0 * M_PI * M_PI * gamma * dt;
-    if (s.bluestein) {
-        HIP_TRY(launch_setup_kernel_table(prec, Kt, D.s_key, p.N, 0, 0, 0, kin, 1.0, st), "kinetic table");
-    } else {
-        const int transposed = (s.passes == 2 && !s.rank2) ? 1 : 0;
-        HIP_TRY(launch_setup_kernel_table(prec, Kt, D.s_key, p.N, s.L1, s.L2, transposed, kin,
-                                          1.0 / (double)s.L, st),
-                "kinetic table");
-    }
-    HIP_TRY(launch_setup_phase_table(prec, P2, v, v_stride, p.N, shared ? 1 : batch, dt / gamma, st),
-            "potential table");
     return LT_OK;
 }
 
@@ -332,13 +347,12 @@ lt_status ensure_device_tables(lt_plan &p, int which, int prec, void *stream)
         void *nat = nullptr, *tmp = nullptr;
         HIP_TRY(hipMalloc(&nat, (size_t)s.L * 16), "chirp-z tables");
         HIP_TRY(hipMalloc(&tmp, (size_t)s.L * 16), "chirp-z tables");
-        HIP_TRY(hipMalloc(&D.bhat, (size_t)s.L * esz(prec)), "chirp-z tables");
+        HIP_TRY(hipMalloc((void **)&D.bhat, (size_t)s.L * 16), "chirp-z tables");
         r = bhat_natural(p, nat, tmp, st);
         if (!r) {
-            const int transposed = s.passes == 2 ? 1 : 0;
             const double scale = 1.0 / ((double)s.L * std::sqrt((double)p.N));
-            hipError_t e = (hipError_t)launch_convert_permute(prec, D.bhat, nat, s.L, s.L1, s.L2,
-                                                              transposed, scale, st);
+            hipError_t e = (hipError_t)launch_permute_c128(D.bhat, nat, s.L, s.L1, s.L2,
+                                                           transposed_layout(s) ? 1 : 0, scale, st);
             if (e != hipSuccess) r = fail(LT_E_HIP, std::string("kernel spectrum: ") + hipGetErrorString(e));
         }
         hipError_t e = hipStreamSynchronize(st);
@@ -382,7 +396,7 @@ lt_status lattice_plan(int32_t d, int32_t r, const int64_t *Z, const int64_t *n,
     p->N = (int64_t)N;
     try {
         p->Z.assign(Z, Z + (size_t)r * d);
-        p->H.assign(H ? H : (const int32_t *)nullptr, H ? H + (size_t)nh * d : nullptr);
+        if (H) p->H.assign(H, H + (size_t)nh * d);
         lt_status st = plan_index_set(*p);
         if (st != LT_OK) {
             delete p;
@@ -412,7 +426,7 @@ lt_status lattice_plan_info(const lt_plan *p, lt_plan_info *info)
     info->n_index = p->n_index;
     info->n_completed = p->n_completed;
     info->max_s = p->max_s;
-    const Sched &s = p->sched[0][LT_C128].ok ? p->sched[0][LT_C128] : p->sched[0][LT_C64];
+    const Sched &s = p->sched[0][LT_C64].ok ? p->sched[0][LT_C64] : p->sched[0][LT_C128];
     info->bluestein = s.bluestein ? 1 : 0;
     info->passes = s.passes;
     info->fft_len = s.L;
@@ -464,6 +478,7 @@ void lattice_plan_destroy(lt_plan *p)
             hipFree(D.tw4hi);
             hipFree(D.tw4lo);
             hipFree(D.s_key);
+            hipFree(D.s_row);
             hipFree(D.bhat);
         }
     delete p;
@@ -475,7 +490,8 @@ lt_status strang_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, i
     if (!p || !bytes) return fail(LT_E_ARG, "NULL argument");
     if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
     if (batch < 0) return fail(LT_E_ARG, "batch must be >= 0");
-    *bytes = run_layout(*p, p->sched[0][prec], prec, batch, shared_v != 0).total;
+    (void)shared_v;
+    *bytes = run_bytes(p->sched[0][prec], prec, batch);
     return LT_OK;
 }
 
@@ -485,7 +501,8 @@ lt_status strang_adjoint_workspace_size(const lt_plan *p, lt_prec prec, int32_t 
     if (!p || !bytes) return fail(LT_E_ARG, "NULL argument");
     if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
     if (batch < 0) return fail(LT_E_ARG, "batch must be >= 0");
-    *bytes = adj_layout(*p, p->sched[1][prec], prec, batch, shared_v != 0).total;
+    (void)shared_v;
+    *bytes = adj_layout(*p, p->sched[1][prec], prec, batch).total;
     return LT_OK;
 }
 
@@ -504,13 +521,8 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
     if ((st = ensure_device_tables(p, 0, prec, stream))) return st;
     const Sched &s = p.sched[0][prec];
     const DevTables &D = p.dev[0][prec];
-    const bool shared = v_stride == 0;
-    const Work L = run_layout(p, s, prec, batch, shared);
     Scratch sc;
-    if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
-    void *Kt = at(sc.ptr, L.kt), *P2 = at(sc.ptr, L.p2), *W = at(sc.ptr, L.w);
-    if ((st = make_tables(p, s, D, prec, batch, v, v_stride, shared, gamma, dt, Kt, P2, hs))) return st;
-    const int64_t p2_bs = shared ? 0 : p.N;
+    if ((st = get_work(sc, work, work_bytes, run_bytes(s, prec, batch), hs))) return st;
     if (s.passes == 1) {
         ResArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -526,10 +538,10 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
         a.twa = D.twa;
         a.twb = D.twb;
         a.bluestein = s.bluestein ? 1 : 0;
-        a.tabK = Kt;
+        a.s = D.s_key;
+        a.kin = kinetic_angle(gamma, dt);
+        a.scale = s.bluestein ? 1.0 : 1.0 / (double)s.L;
         a.bhat = D.bhat;
-        a.tabP2 = P2;
-        a.p2_bs = p2_bs;
         a.v = v;
         a.v_bs = v_stride;
         a.phase_half = dt / (2.0 * gamma);
@@ -544,8 +556,8 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
     if (ckpt)
         HIP_TRY(hipMemcpyAsync(ckpt, u, (size_t)batch * p.N * esz(prec), hipMemcpyDeviceToDevice, hs),
                 "checkpoint 0");
-    return two_pass_forward(p, s, D, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every, Kt,
-                            P2, p2_bs, W, hs);
+    return two_pass_forward(p, s, D, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every,
+                            sc.ptr, hs);
 }
 
 lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, int64_t v_stride,
@@ -572,16 +584,15 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
     if ((st = ensure_device_tables(p, 1, prec, stream))) return st;
     const Sched &s = p.sched[1][prec];
     const DevTables &D = p.dev[1][prec];
-    const Work L = adj_layout(p, s, prec, batch, shared);
+    const AdjWork L = adj_layout(p, s, prec, batch);
     Scratch sc;
     if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
-    void *Kt = at(sc.ptr, L.kt), *P2 = at(sc.ptr, L.p2), *W = at(sc.ptr, L.w);
+    void *W = at(sc.ptr, L.w);
     double *gacc = (double *)at(sc.ptr, L.gacc);
     const double dtb = -dt;  // the backward sweep runs the scheme with -dt
-    if ((st = make_tables(p, s, D, prec, batch, v, v_stride, shared, gamma, dtb, Kt, P2, hs))) return st;
+    const double halfb = dtb / (2.0 * gamma), kinb = kinetic_angle(gamma, dtb);
     HIP_TRY(hipMemsetAsync(gacc, 0, (size_t)batch * N * sizeof(double), hs), "memset");
     const double c = dt / (2.0 * gamma);
-    const int64_t p2_bs = shared ? 0 : N;
     void *Wg = at(W, (size_t)batch * s.L * S);
 
     ColArgs base = col_base(s, D, N);
@@ -593,7 +604,6 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
     base.buf2_bs = s.L;
     base.v = v;
     base.v_bs = v_stride;
-    base.phase = dtb / (2.0 * gamma);
     base.chirp = s.bluestein ? 1 : 0;
     base.gacc = gacc;
     base.gacc_bs = N;
@@ -602,6 +612,7 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
 
     ColArgs first = base;
     first.adjoint = 1;
+    first.phase = halfb;
     first.in = uT;
     first.in_bs = N;
     first.in2 = gT;
@@ -613,18 +624,25 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
     RowArgs r = row_base(s, D);
     r.buf = W;
     r.buf_bs = s.L;
-    r.tab = s.bluestein ? D.bhat : Kt;
-    ColArgs kin = col_base(s, D, N);
-    kin.buf = W;
-    kin.buf_bs = s.L;
-    kin.pre_inv = 1;
-    kin.post_fwd = 1;
-    kin.tab = Kt;
+    if (s.bluestein) {
+        r.bhat = D.bhat;
+    } else {
+        r.s = D.s_row;
+        r.kin = kinb;
+        r.scale = 1.0 / (double)s.L;
+    }
+    ColArgs kinp = col_base(s, D, N);
+    kinp.buf = W;
+    kinp.buf_bs = s.L;
+    kinp.pre_inv = 1;
+    kinp.post_fwd = 1;
+    kinp.s = D.s_key;
+    kinp.kin = kinb;
     for (int64_t j = steps; j >= 1; --j) {
         r.conj_tab = 0;
         HIP_TRY(launch_row(prec, s, r, 2 * batch, hs), "adjoint row pass");
         if (s.bluestein) {
-            HIP_TRY(launch_col(prec, s, kin, 2 * batch, hs), "adjoint column pass (kinetic)");
+            HIP_TRY(launch_col(prec, s, kinp, 2 * batch, hs), "adjoint column pass (kinetic)");
             r.conj_tab = 1;
             HIP_TRY(launch_row(prec, s, r, 2 * batch, hs), "adjoint row pass");
         }
@@ -634,12 +652,12 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
         if (k % ckpt_every == 0) m.reset = (const char *)ckpt + (size_t)(k / ckpt_every) * batch * N * S;
         if (k > 0) {
             m.adjoint = 2;
-            m.tab = P2;
-            m.tab_bs = p2_bs;
+            m.phase = 2.0 * halfb;
             m.post_fwd = 1;
             m.gcoef = 2.0 * c;
         } else {
             m.adjoint = 3;
+            m.phase = halfb;
             m.out2 = g0;
             m.out2_bs = N;
             m.gcoef = c;
@@ -662,7 +680,7 @@ lt_status strang_batched_workspace_size(int32_t B, const lt_plan *const *plans, 
     size_t tot = 0;
     for (int i = 0; i < B; ++i) {
         if (!plans[i]) return fail(LT_E_ARG, "plan is NULL");
-        tot += align_up(run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1, false).total);
+        tot += run_bytes(plans[i]->sched[0][prec], prec, 1);
     }
     *bytes = tot;
     return LT_OK;
@@ -683,9 +701,9 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
     if ((st = get_work(sc, work, work_bytes, need, hs))) return st;
     size_t off = 0;
     for (int i = 0; i < B; ++i) {
-        const size_t w = align_up(run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1, false).total);
+        const size_t w = run_bytes(plans[i]->sched[0][prec], prec, 1);
         st = strang_run(plans[i], prec, 1, v[i], plans[i]->N, u[i], gamma[i], dt[i], steps[i], nullptr, 0,
-                        at(sc.ptr, off), w, stream);
+                        w ? at(sc.ptr, off) : nullptr, w, stream);
         if (st) return st;
         off += w;
     }

@@ -1,0 +1,362 @@
+// Register-staged column / row passes for the lengths the benchmark and the
+// large lattices use (R^NS with R in {8, 16}: 64, 256, 512, 4096).
+//
+// Compared with the general kernels:
+//  * each thread owns E = 16 elements; every stage is one or two radix-R
+//    butterflies per thread, fully unrolled at compile time;
+//  * the first stage reads global memory straight into registers and the last
+//    stage's outputs stay in registers: the column pass goes
+//    [global -> inverse DFT -> point-domain phase -> forward DFT -> global] and
+//    the row pass [global -> DFT -> spectral multiplier -> inverse DFT ->
+//    global] with LDS used only for the NS-1 exchanges inside each DFT;
+//  * LDS indices are padded (one slot every 16 elements) so the strided
+//    Stockham writes do not pile onto a few banks;
+//  * column tiles are remapped so that neighbouring tiles, which share cache
+//    lines, run on the same XCD (workgroups are dealt round-robin to the 8
+//    XCDs, each with its own L2).
+// Both precisions: 256 threads x 16 elements (a 4096-element tile).
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "lt_internal.h"
+
+namespace lt {
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+
+// Stockham DFT over a tile of NT*E elements = SEQ sequences of length L = R^NS.
+// COLS: element e of sequence q at e*SEQ + q (interleaved columns);
+// otherwise at q*L + e (contiguous rows).  Butterfly bf = tid + j*NT handles
+// sequence q, index t; v[j][r] holds element t + r*L/R on entry (stage-1
+// inputs) and on exit (last-stage outputs).
+template <typename T, int R, int NS, int E, int NT, bool COLS>
+struct Fft {
+    static constexpr int L = ipow(R, NS);
+    static constexpr int TILE = NT * E;
+    static constexpr int SEQ = TILE / L;
+    static constexpr int J = E / R;
+    static constexpr int BPS = L / R;
+    static_assert(E % R == 0 && TILE % L == 0, "tile must hold whole sequences");
+
+    static __device__ __forceinline__ int q_of(int bf) { return COLS ? bf % SEQ : bf / BPS; }
+    static __device__ __forceinline__ int t_of(int bf) { return COLS ? bf / SEQ : bf % BPS; }
+    static __device__ __forceinline__ int addr(int q, int e) { return pidx(COLS ? e * SEQ + q : q * L + e); }
+
+    static __device__ __forceinline__ void run(cx<T> (&v)[J][R], cx<T> *s, const Tw<T> *__restrict__ tw,
+                                               bool sync_first)
+    {
+#pragma unroll
+        for (int j = 0; j < J; ++j) Dft<T, R>::run(v[j]);
+        int Ns = 1;
+#pragma unroll
+        for (int st = 1; st < NS; ++st) {
+            if (st > 1 || sync_first) __syncthreads();
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int bf = threadIdx.x + j * NT;
+                const int q = q_of(bf), t = t_of(bf);
+                const int jj = t % Ns;
+                const int ob = (t - jj) * R + jj;
+#pragma unroll
+                for (int r = 0; r < R; ++r) s[addr(q, ob + r * Ns)] = v[j][r];
+            }
+            __syncthreads();
+            Ns *= R;
+            const int twstep = L / (Ns * R);
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int bf = threadIdx.x + j * NT;
+                const int q = q_of(bf), t = t_of(bf);
+                const int jj = t % Ns;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[j][r] = s[addr(q, t + r * BPS)];
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[j][r] = twmul(v[j][r], tw[jj * r * twstep]);
+                Dft<T, R>::run(v[j]);
+            }
+        }
+    }
+};
+
+__device__ __forceinline__ int xcd_tile(int bid, int n)
+{
+    if (n % 8) return bid;
+    return (bid % 8) * (n / 8) + bid / 8;
+}
+
+// W_L^{n2 k} for k = t + r*BPS, r = 0..R-1: base W^{n2 t} and step W^{n2 BPS}
+// from the two-level tables, powers by recurrence in double (error ~1e-15).
+template <int R>
+__device__ __forceinline__ void tw4_series(double (&wr)[R], double (&wi)[R], int n2, int t, int BPS, int L2,
+                                           const double *hi, const double *lo)
+{
+    double br, bi, sr, si;
+    {
+        const cx<double> one = {1.0, 0.0};
+        const cx<double> b = tw4mul(one, n2, t, L2, hi, lo);
+        const cx<double> s = tw4mul(one, n2, BPS, L2, hi, lo);
+        br = b.x; bi = b.y; sr = s.x; si = s.y;
+    }
+    wr[0] = br;
+    wi[0] = bi;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        wr[r] = wr[r - 1] * sr - wi[r - 1] * si;
+        wi[r] = wr[r - 1] * si + wi[r - 1] * sr;
+    }
+}
+
+// Steady-state column pass: [inverse column DFT -> point-domain phase (and
+// chirp-z mask) -> forward column DFT], in place.  The phase is evaluated in
+// FP64 in a plain loop over the tile held in LDS, which keeps the unrolled
+// register FFT free of the sincos register pressure.
+template <typename T, int R, int NS, int E, int NT, int MINW>
+__global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
+{
+    using F = Fft<T, R, NS, E, NT, true>;
+    constexpr int C = F::SEQ, J = F::J, BPS = F::BPS, L1 = F::L, TILE = F::TILE;
+    extern __shared__ char smem_raw[];
+    cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
+    const int L2 = a.L2;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t b = blockIdx.y;
+    const int c0 = tile * C;
+    cx<T> *buf = (cx<T> *)a.buf + b * a.buf_bs;
+    const Tw<T> *tw = (const Tw<T> *)a.twa;
+    cx<T> v[J][R];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int bf = threadIdx.x + j * NT;
+        const int q = F::q_of(bf), t = F::t_of(bf);
+        const int n2 = c0 + q;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[j][r] = conjg(buf[(int64_t)(t + r * BPS) * L2 + n2]);
+        if (a.twiddle) {
+            double wr[R], wi[R];
+            tw4_series<R>(wr, wi, n2, t, BPS, L2, a.tw4hi, a.tw4lo);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[j][r] = cmul_d(v[j][r], wr[r], wi[r]);
+        }
+    }
+    F::run(v, s, tw, false);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int bf = threadIdx.x + j * NT;
+        const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[F::addr(q, t + r * BPS)] = conjg(v[j][r]);
+    }
+    __syncthreads();
+    const double *vb = a.v ? a.v + b * a.v_bs : nullptr;
+#pragma unroll 1
+    for (int i = threadIdx.x; i < TILE; i += NT) {
+        const int q = i % C, e = i / C;
+        const int64_t n = (int64_t)e * L2 + c0 + q;
+        const int at = F::addr(q, e);
+        s[at] = n < a.Nvalid ? col_mid(s[at], a, vb, n) : cx<T>{0, 0};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int bf = threadIdx.x + j * NT;
+        const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[j][r] = s[F::addr(q, t + r * BPS)];
+    }
+    F::run(v, s, tw, true);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int bf = threadIdx.x + j * NT;
+        const int q = F::q_of(bf), t = F::t_of(bf);
+        const int n2 = c0 + q;
+        if (a.twiddle) {
+            double wr[R], wi[R];
+            tw4_series<R>(wr, wi, n2, t, BPS, L2, a.tw4hi, a.tw4lo);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[j][r] = cmul_d(v[j][r], wr[r], wi[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[(int64_t)(t + r * BPS) * L2 + n2] = v[j][r];
+    }
+    (void)L1;
+}
+
+// Row pass: [DFT -> spectral multiplier -> inverse DFT], in place.  The
+// chirp-z kernel spectrum is a table product done in registers; kinetic
+// phases (FP64 sincos) go through one LDS round trip like the column pass.
+template <typename T, int R, int NS, int E, int NT, int MINW>
+__global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
+{
+    using F = Fft<T, R, NS, E, NT, false>;
+    constexpr int L2 = F::L, RW = F::SEQ, J = F::J, BPS = F::BPS, TILE = F::TILE;
+    extern __shared__ char smem_raw[];
+    cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
+    const int r0 = blockIdx.x * RW;
+    const int64_t b = blockIdx.y;
+    cx<T> *buf = (cx<T> *)a.buf + b * a.buf_bs + (int64_t)r0 * L2;
+    const Tw<T> *tw = (const Tw<T> *)a.twb;
+    const int64_t p0 = (int64_t)r0 * L2;
+    cx<T> v[J][R];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int bf = threadIdx.x + j * NT;
+        const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[j][r] = buf[q * L2 + t + r * BPS];
+    }
+    F::run(v, s, tw, false);
+    if (a.bhat) {
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int bf = threadIdx.x + j * NT;
+            const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t pos = p0 + q * L2 + t + r * BPS;
+                const double br = a.bhat[2 * pos], bi = a.bhat[2 * pos + 1];
+                v[j][r] = conjg(cmul_d(v[j][r], br, a.conj_tab ? -bi : bi));
+            }
+        }
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int bf = threadIdx.x + j * NT;
+            const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+            for (int r = 0; r < R; ++r) s[F::addr(q, t + r * BPS)] = v[j][r];
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int i = threadIdx.x; i < TILE; i += NT) {
+            const int at = pidx(i);
+            s[at] = conjg(row_mid(s[at], a, p0 + i));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int bf = threadIdx.x + j * NT;
+            const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[j][r] = s[F::addr(q, t + r * BPS)];
+        }
+    }
+    F::run(v, s, tw, true);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int bf = threadIdx.x + j * NT;
+        const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[q * L2 + t + r * BPS] = conjg(v[j][r]);
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+namespace {
+constexpr int kE = 16;
+template <typename T>
+struct Geo;
+template <>
+struct Geo<float> {
+    static constexpr int NT = 256, MINW = 2;
+};
+template <>
+struct Geo<double> {
+    static constexpr int NT = 256, MINW = 2;
+};
+
+template <typename T>
+constexpr int tile_elems() { return Geo<T>::NT * kE; }
+template <typename T>
+size_t lds_bytes() { return (size_t)(tile_elems<T>() + tile_elems<T>() / 16) * sizeof(cx<T>); }
+
+template <typename T, int R, int NS>
+int col_go(const ColArgs &a, int batch, void *stream)
+{
+    constexpr int NT = Geo<T>::NT, MINW = Geo<T>::MINW;
+    auto k = k_colf<T, R, NS, kE, NT, MINW>;
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    constexpr int C = tile_elems<T>() / ipow(R, NS);
+    dim3 grid(a.L2 / C, batch);
+    hipLaunchKernelGGL(k, grid, dim3(NT), lds_bytes<T>(), (hipStream_t)stream, a);
+    return (int)hipGetLastError();
+}
+
+template <typename T, int R, int NS>
+int row_go(const RowArgs &a, int batch, void *stream)
+{
+    constexpr int NT = Geo<T>::NT, MINW = Geo<T>::MINW;
+    auto k = k_rowf<T, R, NS, kE, NT, MINW>;
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    constexpr int RW = tile_elems<T>() / ipow(R, NS);
+    dim3 grid(a.L1 / RW, batch);
+    hipLaunchKernelGGL(k, grid, dim3(NT), lds_bytes<T>(), (hipStream_t)stream, a);
+    return (int)hipGetLastError();
+}
+
+template <typename T>
+int col_dispatch(const ColArgs &a, int batch, void *stream)
+{
+    switch (a.L1) {
+    case 64: return col_go<T, 8, 2>(a, batch, stream);
+    case 256: return col_go<T, 16, 2>(a, batch, stream);
+    case 512: return col_go<T, 8, 3>(a, batch, stream);
+    case 4096: return col_go<T, 16, 3>(a, batch, stream);
+    default: return -1;
+    }
+}
+
+template <typename T>
+int row_dispatch(const RowArgs &a, int batch, void *stream)
+{
+    switch (a.L2) {
+    case 64: return row_go<T, 8, 2>(a, batch, stream);
+    case 256: return row_go<T, 16, 2>(a, batch, stream);
+    case 512: return row_go<T, 8, 3>(a, batch, stream);
+    case 4096: return row_go<T, 16, 3>(a, batch, stream);
+    default: return -1;
+    }
+}
+
+bool fast_len(int L) { return L == 64 || L == 256 || L == 512 || L == 4096; }
+int tile_of(int prec) { return prec == LT_C128 ? tile_elems<double>() : tile_elems<float>(); }
+}  // namespace
+
+bool fast_col_fits(int prec, int L1, int L2, int C)
+{
+    return fast_len(L1) && C == tile_of(prec) / L1 && L2 % C == 0;
+}
+
+bool fast_row_fits(int prec, int L1, int L2, int rows)
+{
+    return fast_len(L2) && rows == tile_of(prec) / L2 && L1 % rows == 0;
+}
+
+int launch_col_fast(int prec, const ColArgs &a, int batch, void *stream)
+{
+    // steady-state passes only: the first / last / checkpoint passes of a run
+    // and the adjoint passes take the general kernel
+    const bool steady = a.pre_inv && a.post_fwd && !a.in && !a.out && !a.ck && !a.chirp &&
+                        a.scale == 1.0 && !a.adjoint;
+    if (!steady || !fast_col_fits(prec, a.L1, a.L2, a.C)) return -1;
+    return prec == LT_C128 ? col_dispatch<double>(a, batch, stream) : col_dispatch<float>(a, batch, stream);
+}
+
+int launch_row_fast(int prec, const RowArgs &a, int batch, void *stream)
+{
+    if (!fast_row_fits(prec, a.L1, a.L2, a.rows)) return -1;
+    return prec == LT_C128 ? row_dispatch<double>(a, batch, stream) : row_dispatch<float>(a, batch, stream);
+}
+
+}  // namespace lt

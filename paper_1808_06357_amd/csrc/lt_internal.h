@@ -14,7 +14,7 @@ namespace lt {
 
 constexpr int kThreads = 256;           // workgroup size of every FFT kernel
 constexpr int kMaxStages = 24;
-constexpr size_t kTileBytes = 64 * 1024; // LDS tile budget per workgroup
+constexpr int64_t kTileElems = 4096;     // complex elements per workgroup tile
 
 // Radix sequence of one sub-transform of length L (product of radices).
 struct Radices {
@@ -40,30 +40,34 @@ struct Sched {
 // Device tables of a plan for one precision (built lazily, then immutable).
 struct DevTables {
     bool built = false;
-    void *twa = nullptr;     // W_{La}^q, q < La (run precision), La = L1 or L
+    void *twa = nullptr;     // W_{La}^q, q < La (Tw<T> format), La = L1 or L
     void *twb = nullptr;     // W_{L2}^q
     double *tw4hi = nullptr; // W_L^{qa L2}, qa < L1   (double complex pairs)
     double *tw4lo = nullptr; // W_L^{qb},    qb < L2
-    int32_t *s_key = nullptr;// ||h_chi||^2 per key
-    void *bhat = nullptr;    // chirp-z kernel spectrum, scaled by 1/(L sqrt N), schedule layout
+    int32_t *s_key = nullptr;// ||h_chi||^2 per key, natural order
+    int32_t *s_row = nullptr;// ||h_chi||^2 at the row-pass positions (two-pass, no chirp-z)
+    double *bhat = nullptr;  // chirp-z kernel spectrum / (L sqrt N), complex double, schedule layout
 };
 
 // ---------------------------------------------------------------- kernel arguments
+// Point-domain multiplier of a column pass, at natural index n < Nvalid:
+//   w = exp(-i (phase * v[n] + kin * s[n])) * c_n^chirp * scale
+// (terms with a null pointer / zero flag are skipped; c_n is the chirp
+// exp(-pi i (n^2 mod 2N)/N)); indices n >= Nvalid are set to zero.
 struct ColArgs {
     void *buf; int64_t buf_bs;        // transform buffer (L elements per batch item)
     const void *in; int64_t in_bs;    // first pass: read lattice values from here (Nvalid)
     void *out; int64_t out_bs;        // last pass: write lattice values here (Nvalid)
     int L1, L2, C, ntiles;
-    int64_t Nvalid;                   // natural index >= Nvalid is zero / not stored
+    int64_t Nvalid;
     int pre_inv, post_fwd, twiddle;
-    const void *tab; int64_t tab_bs;  // mid multiplier (natural index), or null
-    const double *v; int64_t v_bs;    // on-the-fly phase exp(-i phase * v[n]) (first/last pass)
-    double phase;
+    const double *v; int64_t v_bs; double phase;
+    const int32_t *s; double kin;
     int chirp;                        // +1: times c_n, -1: times conj(c_n), 0: none
-    int64_t Nchirp;                   // N of the chirp exp(-pi i (n^2 mod 2N)/N)
+    int64_t Nchirp;
     double scale;
-    const double *tw4hi, *tw4lo;
-    const void *twa;
+    const double *tw4hi, *tw4lo;      // four-step twiddle tables (complex double)
+    const void *twa;                  // Tw<T> table of W_{L1}
     Radices rad;
     void *ck; int64_t ck_bs;          // optional checkpoint store of the point value
     const double *ck_v;               // u = x * exp(-i ck_phase ck_v[n]) * conj(c_n)^[ck_chirp]
@@ -80,12 +84,16 @@ struct ColArgs {
     double reset_phase;               // a = exp(-i reset_phase v) * ckpt (times c_n for chirp-z)
 };
 
+// Spectral multiplier of a row pass at row-pass position pos = k1 L2 + k2:
+// chirp-z: bhat[pos] (complex double, conjugated if conj_tab);
+// otherwise exp(-i kin * s[pos]) * scale.
 struct RowArgs {
     void *buf; int64_t buf_bs;
     int L1, L2, rows, nblk;
-    const void *tab; int64_t tab_bs; int conj_tab;
+    const double *bhat; int conj_tab;
+    const int32_t *s; double kin, scale;
     int fft_only;
-    const void *twb;
+    const void *twb;                  // Tw<T> table of W_{L2}
     Radices rad;
 };
 
@@ -96,9 +104,9 @@ struct ResArgs {
     Radices ra, rb;
     const void *twa, *twb;
     int bluestein;
-    const void *tabK;                  // natural order; smooth: K/L; chirp-z: K (index < N)
-    const void *bhat;                  // natural order, chirp-z only
-    const void *tabP2; int64_t p2_bs;
+    const int32_t *s;                  // ||h||^2 per key, natural order
+    double kin, scale;                 // kinetic angle per unit norm; 1/L (smooth) or 1
+    const double *bhat;                // natural order, chirp-z only (complex double)
     const double *v; int64_t v_bs;
     double phase_half;                 // dt / (2 gamma)
     int64_t steps;
@@ -111,19 +119,33 @@ struct ResArgs {
 int launch_col(int prec, const Sched &s, const ColArgs &a, int batch, void *stream);
 int launch_row(int prec, const Sched &s, const RowArgs &a, int batch, void *stream);
 int launch_resident(int prec, const Sched &s, const ResArgs &a, int batch, void *stream);
-int launch_fft_single(int prec, const Radices &ra, const void *twa, void *buf, int64_t L,
-                      void *stream);
-int launch_setup_kernel_table(int prec, void *dst, const int32_t *s_key, int64_t N, int L1, int L2,
-                              int transposed, double kin, double scale, void *stream);
-int launch_setup_phase_table(int prec, void *dst, const double *v, int64_t v_bs, int64_t N,
-                             int batch, double phase, void *stream);
-int launch_convert_permute(int prec_dst, void *dst, const void *src_c128_nat, int64_t L, int L1,
-                           int L2, int transposed, double scale, void *stream);
+int launch_fft_single(const Radices &ra, const void *twa_c128, void *buf, int64_t L, void *stream);
+int launch_permute_c128(void *dst, const void *src_nat, int64_t L, int L1, int L2, int transposed,
+                        double scale, void *stream);
 int launch_unpermute_c128(void *dst_nat, const void *src, int64_t L, int L1, int L2,
                           void *stream);
 int launch_chirp_filter(void *dst_c128, int64_t N, int64_t L, void *stream);
 int launch_reduce_batch(double *dst, const double *src, int64_t N, int batch, void *stream);
+// fast register-staged variants (kernels_fast.hip); return -1 when no variant fits
+int launch_col_fast(int prec, const ColArgs &a, int batch, void *stream);
+int launch_row_fast(int prec, const RowArgs &a, int batch, void *stream);
+bool fast_col_fits(int prec, int L1, int L2, int C);
+bool fast_row_fits(int prec, int L1, int L2, int rows);
 int kernels_init();  // raise dynamic LDS limits once
+
+// Event bracket around one launch when timing is enabled (timing.cpp).
+class KTimer {
+  public:
+    KTimer(int kind, void *stream);
+    ~KTimer();
+    KTimer(const KTimer &) = delete;
+    KTimer &operator=(const KTimer &) = delete;
+
+  private:
+    int kind_;
+    void *stream_;
+    void *a_ = nullptr;
+};
 
 }  // namespace lt
 

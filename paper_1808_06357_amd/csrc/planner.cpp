@@ -248,9 +248,9 @@ static bool split_two_pass(int64_t L, int64_t tile, int &L1, int &L2)
 Sched make_schedule(const lt_plan &p, int prec, bool force_two_pass)
 {
     Sched s;
-    const size_t esz = prec == LT_C128 ? 16 : 8;
-    const int64_t tile = (int64_t)(kTileBytes / esz);  // complex elements per tile
+    const int64_t tile = kTileElems;  // complex elements per workgroup tile
     s.ept = (int)(tile / kThreads);
+    (void)prec;
     if (p.r > 2) return s;
     if (p.r == 2) {
         if (!is_smooth7(p.n[0]) || !is_smooth7(p.n[1])) return s;

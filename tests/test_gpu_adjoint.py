@@ -1,0 +1,95 @@
+"""GPU adjoint (strang_adjoint, reverse-time recomputation with checkpoint
+resets) against the oracle's recompute-forward VJP, plus the autograd
+Function and a dot-product test."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def problem(N, d, seed, batch, shared, terms=16):
+    g = np.random.default_rng(seed)
+    z = W.korobov(N, d, g)
+    Z, n = z.reshape(1, -1), np.array([N])
+    num = W.point_numerators(Z, n)
+    if shared:
+        v = W.cosine_series(d, terms, g).at(num, N)
+    else:
+        v = np.stack([W.cosine_series(d, terms, g).at(num, N) for _ in range(batch)])
+    u0 = np.stack([W.seeded_packet(num, N, g) for _ in range(batch)])
+    tgt = np.stack([W.seeded_packet(num, N, g) for _ in range(batch)])
+    return Z, n, v, u0, tgt
+
+
+def gpu_grad(lt, plan, v, u0, tgt, gamma, dt, steps, every, dtype):
+    import torch
+    N = plan.N
+    u = torch.tensor(u0, dtype=dtype, device="cuda")
+    vv = torch.tensor(v, dtype=torch.float64, device="cuda")
+    batch = u0.shape[0]
+    ck = torch.empty(lt.num_checkpoints(steps, every) * batch * N, dtype=dtype, device="cuda")
+    lt.strang_run(plan, vv, u, gamma, dt, steps, ckpt=ck, ckpt_every=every)
+    gT = (2.0 / N) * (u - torch.tensor(tgt, dtype=dtype, device="cuda"))
+    g0, gv = lt.strang_adjoint(plan, vv, u, gT.contiguous(), gamma, dt, steps, ck, every)
+    torch.cuda.synchronize()
+    return g0.cpu().numpy().astype(np.complex128), gv.cpu().numpy()
+
+
+@pytest.mark.parametrize("N,d,shared", [(1031, 2, True), (12288, 3, False), (65521, 4, True),
+                                        (4096, 3, True), (97, 2, False)])
+def test_adjoint_matches_oracle(lt, N, d, shared):
+    import torch
+    batch, gamma, dt, steps, every = 2, 0.05, 2e-3, 37, 10
+    Z, n, v, u0, tgt = problem(N, d, N, batch, shared)
+    plan = lt.lattice_plan(Z, n)
+    _, s, _ = O.index_set(Z, n)
+    uT = O.strang_run(n, s, v, u0, gamma, dt, steps)
+    g0_ref, gv_ref = O.strang_vjp(n, s, v, u0, 2.0 * (uT - tgt) / N, gamma, dt, steps)
+    for dtype, tol in ((torch.complex128, 1e-10), (torch.complex64, 2e-4)):
+        g0, gv = gpu_grad(lt, plan, v, u0, tgt, gamma, dt, steps, every, dtype)
+        e0, ev = rel(g0, g0_ref), rel(gv, gv_ref)
+        print(f"N={N} {dtype} dJ/du0 rel={e0:.2e} dJ/dv rel={ev:.2e}", flush=True)
+        assert e0 < tol and ev < tol
+
+
+def test_autograd_function(lt):
+    import torch
+    N, d, batch, gamma, dt, steps = 65521, 4, 3, 0.05, 2e-3, 24
+    Z, n, v, u0, tgt = problem(N, d, 5, batch, True)
+    plan = lt.lattice_plan(Z, n)
+    vv = torch.tensor(v, dtype=torch.float64, device="cuda", requires_grad=True)
+    u = torch.tensor(u0, dtype=torch.complex128, device="cuda", requires_grad=True)
+    t = torch.tensor(tgt, dtype=torch.complex128, device="cuda")
+    uT = lt.lattice_strang(plan, vv, u, gamma, dt, steps, ckpt_every=8)
+    J = (uT - t).abs().pow(2).sum() / N
+    J.backward()
+    _, s, _ = O.index_set(Z, n)
+    uT_ref = O.strang_run(n, s, v, u0, gamma, dt, steps)
+    g0_ref, gv_ref = O.strang_vjp(n, s, v, u0, 2.0 * (uT_ref - tgt) / N, gamma, dt, steps)
+    assert rel(uT.detach().cpu().numpy(), uT_ref) < 1e-11
+    assert rel(u.grad.cpu().numpy(), g0_ref) < 1e-10
+    assert rel(vv.grad.cpu().numpy(), gv_ref) < 1e-10
+
+
+def test_dot_product_identity(lt):
+    """<S^m x, y> = <x, (S^m)^H y> with the GPU forward and GPU adjoint."""
+    import torch
+    N, d, steps, every = 65521, 3, 20, 7
+    Z, n, v, x, y = problem(N, d, 6, 1, True)
+    plan = lt.lattice_plan(Z, n)
+    vv = torch.tensor(v, device="cuda")
+    u = torch.tensor(x, dtype=torch.complex128, device="cuda")
+    ck = torch.empty(lt.num_checkpoints(steps, every) * N, dtype=torch.complex128, device="cuda")
+    lt.strang_run(plan, vv, u, 0.05, 2e-3, steps, ckpt=ck, ckpt_every=every)
+    yy = torch.tensor(y, dtype=torch.complex128, device="cuda")
+    g0, _ = lt.strang_adjoint(plan, vv, u, yy, 0.05, 2e-3, steps, ck, every)
+    lhs = np.vdot(y, u.cpu().numpy())
+    rhs = np.vdot(g0.cpu().numpy(), x)
+    assert abs(lhs - rhs) < 1e-11 * np.linalg.norm(x) * np.linalg.norm(y)
