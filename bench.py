@@ -118,6 +118,8 @@ def main():
             continue
         u = torch.tensor(inst.u0, dtype=dtype, device=dev)
         prec = lt.LT_C64 if name == "c64" else lt.LT_C128
+        kernels = lt.lattice_plan_autotune(plan, prec, reps=20)
+        log(f"{name}: autotuned kernel variants (column, row) = {kernels}")
         work = torch.empty(lt.strang_workspace_size(plan, prec, 1, True), dtype=torch.uint8, device=dev)
         # one run from u0 for the accuracy indicators
         lt.strang_run(plan, v, u, inst.gamma, inst.dt, m, work=work)
@@ -133,7 +135,7 @@ def main():
             per_kind[kname] = {"launches": launches, "total_ms": ms, "avg_us": avg_ms * 1e3,
                                "bytes_per_launch": avg_bytes,
                                "achieved_GBs": avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None}
-        results[name] = {"elapsed": elapsed, "kinds": per_kind, "uT": uT,
+        results[name] = {"elapsed": elapsed, "kinds": per_kind, "uT": uT, "kernels": kernels,
                          "value": N * m * args.steps / elapsed, "ms_per_step": elapsed / args.steps * 1e3}
         log(f"{name}: {results[name]['value']:.3e} pt-steps/s, {results[name]['ms_per_step']:.2f} ms/run; "
             + ", ".join(f"{k}: {v_['avg_us']:.1f} us/launch {v_['achieved_GBs'] or 0:.0f} GB/s"
@@ -174,6 +176,7 @@ def main():
                      "traffic": None, "avg_launch_us": dom["avg_us"],
                      "bytes_per_launch": dom["bytes_per_launch"]},
         "kernels_c64": head["kinds"],
+        "kernel_variants": {k: list(r_["kernels"]) for k, r_ in results.items()},
         "accuracy": acc,
     }
     if "c128" in results:

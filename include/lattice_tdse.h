@@ -197,6 +197,25 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
                              size_t work_bytes, void *stream);
 
 /*
+ * Kernel selection for two-pass schedules.  Each column / row pass can run
+ * on one of several kernels with identical results (within rounding):
+ *   0 = general LDS Stockham kernel (any 7-smooth length),
+ *   1 = register-staged kernel, 256 threads x 16 elements (radix 16 / 8),
+ *   2 = register-staged kernel, 512 threads x 8 elements (radix 8 / 4).
+ * Variants 1 and 2 exist for lengths 64, 256, 512 and 4096; elsewhere the
+ * general kernel runs whatever is selected.  The default is 1.
+ * lattice_plan_autotune times every applicable variant of the plan's
+ * steady-state column and row passes on `stream` (reps launches each, on a
+ * scratch buffer it allocates and frees) and keeps the fastest; it must not
+ * run concurrently with runs of the same plan.  One-workgroup schedules have
+ * nothing to tune.
+ */
+lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *stream);
+lt_status lattice_plan_set_kernels(lt_plan *p, lt_prec prec, int32_t col_variant, int32_t row_variant);
+lt_status lattice_plan_get_kernels(const lt_plan *p, lt_prec prec, int32_t *col_variant,
+                                   int32_t *row_variant);
+
+/*
  * Diagnostics: HIP-event timing of the library's own launches.  While
  * enabled, every kernel launch is bracketed by two events recorded on its
  * stream.  lt_timing_enable(on) also discards earlier records;

@@ -58,6 +58,9 @@ _SIGS = {
     "strang_adjoint": [_P, _i32, _i32, _P, _i64, _P, _P, _f64, _f64, _i64, _P, _i64, _P, _P, _P, _sz, _P],
     "strang_batched_workspace_size": [_i32, _P, _i32, ctypes.POINTER(_sz)],
     "strang_run_batched": [_i32, _P, _i32, _P, _P, _P, _P, _P, _P, _sz, _P],
+    "lattice_plan_autotune": [_P, _i32, _i32, _P],
+    "lattice_plan_set_kernels": [_P, _i32, _i32, _i32],
+    "lattice_plan_get_kernels": [_P, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
     "lt_timing_enable": [_i32],
     "lt_timing_summary": [_i32, ctypes.POINTER(_i64), ctypes.POINTER(_f64)],
     "lt_last_error": [],
@@ -292,3 +295,22 @@ def lt_timing_summary(kind: int):
     n, ms = _i64(), _f64()
     _check(lib.lt_timing_summary(kind, ctypes.byref(n), ctypes.byref(ms)), "lt_timing_summary")
     return n.value, ms.value
+
+
+def lattice_plan_autotune(plan: Plan, prec: int, reps: int = 10, stream=None):
+    """Time the kernel variants of the plan's passes and keep the fastest;
+    returns the chosen (column, row) variants."""
+    _check(lib.lattice_plan_autotune(plan.handle, prec, reps, _stream(stream)), "lattice_plan_autotune")
+    return lattice_plan_get_kernels(plan, prec)
+
+
+def lattice_plan_set_kernels(plan: Plan, prec: int, col_variant: int, row_variant: int) -> None:
+    _check(lib.lattice_plan_set_kernels(plan.handle, prec, col_variant, row_variant),
+           "lattice_plan_set_kernels")
+
+
+def lattice_plan_get_kernels(plan: Plan, prec: int):
+    cv, rv = _i32(), _i32()
+    _check(lib.lattice_plan_get_kernels(plan.handle, prec, ctypes.byref(cv), ctypes.byref(rv)),
+           "lattice_plan_get_kernels")
+    return cv.value, rv.value

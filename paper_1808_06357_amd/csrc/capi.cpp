@@ -149,7 +149,6 @@ RowArgs row_base(const Sched &s, const DevTables &D)
     a.nblk = (s.L1 + s.rows - 1) / s.rows;
     a.twb = D.twb;
     a.rad = s.rb;
-    a.scale = 1.0;
     return a;
 }
 
@@ -181,21 +180,32 @@ lt_status bhat_natural(lt_plan &p, void *nat, void *tmp, hipStream_t st)
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// forward runs: a transform buffer only for two-pass chirp-z (otherwise u itself)
-size_t run_bytes(const Sched &s, int prec, int batch)
+// forward runs: the kinetic table (one complex double per squared norm
+// 0..max_s) and, for two-pass chirp-z, a transform buffer (otherwise the
+// transform runs in u itself)
+struct RunWork {
+    size_t ktab = 0, w = 0, total = 0;
+};
+
+RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch)
 {
-    if (s.bluestein && s.passes == 2) return align_up((size_t)batch * s.L * esz(prec));
-    return 0;
+    RunWork w;
+    w.ktab = 0;
+    size_t off = align_up((size_t)(p.max_s + 1) * 16);
+    w.w = off;
+    if (s.bluestein && s.passes == 2) off = align_up(off + (size_t)batch * s.L * esz(prec));
+    w.total = off;
+    return w;
 }
 
 struct AdjWork {
-    size_t w = 0, gacc = 0, total = 0;
+    size_t ktab = 0, w = 0, gacc = 0, total = 0;
 };
 
 AdjWork adj_layout(const lt_plan &p, const Sched &s, int prec, int batch)
 {
     AdjWork w;
-    size_t off = 0;
+    size_t off = align_up((size_t)(p.max_s + 1) * 16);
     w.w = off;
     off = align_up(off + (size_t)2 * batch * s.L * esz(prec));   // state and cotangent
     w.gacc = off;
@@ -249,15 +259,23 @@ inline char *at(void *base, size_t off) { return (char *)base + off; }
 
 double kinetic_angle(double gamma, double dt) { return 2.0 * M_PI * M_PI * gamma * dt; }
 
+// exp(-i 2 pi^2 gamma dt m) * scale for every squared norm m of the plan
+lt_status make_ktab(const lt_plan &p, const Sched &s, double *ktab, double gamma, double dt, hipStream_t st)
+{
+    const double scale = s.bluestein ? 1.0 : 1.0 / (double)s.L;
+    HIP_TRY(launch_ktab(ktab, p.max_s + 1, kinetic_angle(gamma, dt), scale, st), "kinetic table");
+    return LT_OK;
+}
+
 // forward run of a state batch through the two-pass sequence
 lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int prec, int batch,
                            const double *v, int64_t v_stride, void *u, double gamma, double dt,
-                           int64_t steps, void *ckpt, int64_t ck_every, void *W, hipStream_t st)
+                           int64_t steps, void *ckpt, int64_t ck_every, const double *ktab, void *W,
+                           hipStream_t st)
 {
     const int64_t N = p.N;
     const size_t S = esz(prec);
     const double half = dt / (2.0 * gamma);
-    const double kin = kinetic_angle(gamma, dt);
     void *buf = s.bluestein ? W : u;
     const int64_t buf_bs = s.bluestein ? s.L : N;
     // first pass: half potential step (and chirp), column DFT
@@ -279,8 +297,7 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
         r.bhat = D.bhat;
     } else {
         r.s = D.s_row;
-        r.kin = kin;
-        r.scale = 1.0 / (double)s.L;
+        r.ktab = ktab;
     }
     ColArgs mid = col_base(s, D, N);
     mid.buf = buf;
@@ -289,7 +306,7 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
     mid.post_fwd = 1;
     ColArgs kinp = mid;  // chirp-z: kinetic phase at the natural spectral index
     kinp.s = D.s_key;
-    kinp.kin = kin;
+    kinp.ktab = ktab;
     ColArgs pot = mid;   // merged potential step P^2
     pot.v = v;
     pot.v_bs = v_stride;
@@ -491,7 +508,7 @@ lt_status strang_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, i
     if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
     if (batch < 0) return fail(LT_E_ARG, "batch must be >= 0");
     (void)shared_v;
-    *bytes = run_bytes(p->sched[0][prec], prec, batch);
+    *bytes = run_layout(*p, p->sched[0][prec], prec, batch).total;
     return LT_OK;
 }
 
@@ -521,8 +538,11 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
     if ((st = ensure_device_tables(p, 0, prec, stream))) return st;
     const Sched &s = p.sched[0][prec];
     const DevTables &D = p.dev[0][prec];
+    const RunWork L = run_layout(p, s, prec, batch);
     Scratch sc;
-    if ((st = get_work(sc, work, work_bytes, run_bytes(s, prec, batch), hs))) return st;
+    if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
+    double *ktab = (double *)at(sc.ptr, L.ktab);
+    if ((st = make_ktab(p, s, ktab, gamma, dt, hs))) return st;
     if (s.passes == 1) {
         ResArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -539,8 +559,7 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
         a.twb = D.twb;
         a.bluestein = s.bluestein ? 1 : 0;
         a.s = D.s_key;
-        a.kin = kinetic_angle(gamma, dt);
-        a.scale = s.bluestein ? 1.0 : 1.0 / (double)s.L;
+        a.ktab = ktab;
         a.bhat = D.bhat;
         a.v = v;
         a.v_bs = v_stride;
@@ -557,7 +576,7 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
         HIP_TRY(hipMemcpyAsync(ckpt, u, (size_t)batch * p.N * esz(prec), hipMemcpyDeviceToDevice, hs),
                 "checkpoint 0");
     return two_pass_forward(p, s, D, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every,
-                            sc.ptr, hs);
+                            ktab, at(sc.ptr, L.w), hs);
 }
 
 lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, int64_t v_stride,
@@ -589,8 +608,10 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
     if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
     void *W = at(sc.ptr, L.w);
     double *gacc = (double *)at(sc.ptr, L.gacc);
+    double *ktab = (double *)at(sc.ptr, L.ktab);
     const double dtb = -dt;  // the backward sweep runs the scheme with -dt
-    const double halfb = dtb / (2.0 * gamma), kinb = kinetic_angle(gamma, dtb);
+    const double halfb = dtb / (2.0 * gamma);
+    if ((st = make_ktab(p, s, ktab, gamma, dtb, hs))) return st;
     HIP_TRY(hipMemsetAsync(gacc, 0, (size_t)batch * N * sizeof(double), hs), "memset");
     const double c = dt / (2.0 * gamma);
     void *Wg = at(W, (size_t)batch * s.L * S);
@@ -628,8 +649,7 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
         r.bhat = D.bhat;
     } else {
         r.s = D.s_row;
-        r.kin = kinb;
-        r.scale = 1.0 / (double)s.L;
+        r.ktab = ktab;
     }
     ColArgs kinp = col_base(s, D, N);
     kinp.buf = W;
@@ -637,7 +657,7 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
     kinp.pre_inv = 1;
     kinp.post_fwd = 1;
     kinp.s = D.s_key;
-    kinp.kin = kinb;
+    kinp.ktab = ktab;
     for (int64_t j = steps; j >= 1; --j) {
         r.conj_tab = 0;
         HIP_TRY(launch_row(prec, s, r, 2 * batch, hs), "adjoint row pass");
@@ -680,7 +700,7 @@ lt_status strang_batched_workspace_size(int32_t B, const lt_plan *const *plans, 
     size_t tot = 0;
     for (int i = 0; i < B; ++i) {
         if (!plans[i]) return fail(LT_E_ARG, "plan is NULL");
-        tot += run_bytes(plans[i]->sched[0][prec], prec, 1);
+        tot += run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1).total;
     }
     *bytes = tot;
     return LT_OK;
@@ -701,13 +721,106 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
     if ((st = get_work(sc, work, work_bytes, need, hs))) return st;
     size_t off = 0;
     for (int i = 0; i < B; ++i) {
-        const size_t w = run_bytes(plans[i]->sched[0][prec], prec, 1);
+        const size_t w = run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1).total;
         st = strang_run(plans[i], prec, 1, v[i], plans[i]->N, u[i], gamma[i], dt[i], steps[i], nullptr, 0,
                         w ? at(sc.ptr, off) : nullptr, w, stream);
         if (st) return st;
         off += w;
     }
     return LT_OK;
+}
+
+lt_status lattice_plan_set_kernels(lt_plan *p, lt_prec prec, int32_t col_variant, int32_t row_variant)
+{
+    if (!p) return fail(LT_E_ARG, "plan is NULL");
+    if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
+    if (col_variant < 0 || col_variant > 2 || row_variant < 0 || row_variant > 2)
+        return fail(LT_E_ARG, "kernel variants are 0, 1 or 2");
+    std::lock_guard<std::mutex> lock(p->mu);
+    for (int w = 0; w < 2; ++w) {
+        if (p->sched[w][prec].passes != 2) continue;
+        p->sched[w][prec].col_var = col_variant;
+        p->sched[w][prec].row_var = row_variant;
+    }
+    return LT_OK;
+}
+
+lt_status lattice_plan_get_kernels(const lt_plan *p, lt_prec prec, int32_t *col_variant, int32_t *row_variant)
+{
+    if (!p || !col_variant || !row_variant) return fail(LT_E_ARG, "NULL argument");
+    if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
+    *col_variant = p->sched[0][prec].col_var;
+    *row_variant = p->sched[0][prec].row_var;
+    return LT_OK;
+}
+
+lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *stream)
+{
+    if (!p) return fail(LT_E_ARG, "plan is NULL");
+    if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
+    if (reps < 1) return fail(LT_E_ARG, "reps must be >= 1");
+    if (!p->sched[0][prec].ok) return fail(LT_E_UNSUPPORTED, "no GPU schedule for this precision");
+    if (p->sched[0][prec].passes != 2) return LT_OK;
+    lt_status st = ensure_device_tables(*p, 0, prec, stream);
+    if (st) return st;
+    Sched &s = p->sched[0][prec];
+    const DevTables &D = p->dev[0][prec];
+    hipStream_t hs = (hipStream_t)stream;
+    void *buf = nullptr, *v = nullptr, *kt = nullptr;
+    const size_t ktn = (size_t)(p->max_s + 1);
+    HIP_TRY(hipMalloc(&buf, (size_t)s.L * esz(prec)), "autotune buffer");
+    HIP_TRY(hipMalloc(&v, (size_t)p->N * sizeof(double)), "autotune buffer");
+    HIP_TRY(hipMalloc(&kt, ktn * 16), "autotune buffer");
+    HIP_TRY(hipMemsetAsync(buf, 0, (size_t)s.L * esz(prec), hs), "memset");
+    HIP_TRY(hipMemsetAsync(v, 0, (size_t)p->N * sizeof(double), hs), "memset");
+    HIP_TRY(launch_ktab((double *)kt, (int64_t)ktn, 0.0, 1.0, hs), "kinetic table");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "event");
+    HIP_TRY(hipEventCreate(&e1), "event");
+    ColArgs c = col_base(s, D, p->N);
+    c.buf = buf;
+    c.buf_bs = s.L;
+    c.pre_inv = 1;
+    c.post_fwd = 1;
+    c.v = (const double *)v;
+    c.phase = 1e-3;
+    RowArgs r = row_base(s, D);
+    r.buf = buf;
+    r.buf_bs = s.L;
+    if (s.bluestein) r.bhat = D.bhat;
+    else { r.s = D.s_row; r.ktab = (const double *)kt; }
+    auto time_it = [&](bool col, int var, float &ms) -> lt_status {
+        Sched t = s;
+        if (col) t.col_var = var; else t.row_var = var;
+        for (int i = 0; i < reps + 2; ++i) {
+            if (i == 2) HIP_TRY(hipEventRecord(e0, hs), "event");
+            HIP_TRY(col ? launch_col(prec, t, c, 1, hs) : launch_row(prec, t, r, 1, hs), "autotune launch");
+        }
+        HIP_TRY(hipEventRecord(e1, hs), "event");
+        HIP_TRY(hipEventSynchronize(e1), "event");
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "event");
+        return LT_OK;
+    };
+    int best_c = 0, best_r = 0;
+    float tc = 1e30f, tr = 1e30f;
+    for (int var = 0; var <= 2 && !st; ++var) {
+        float ms = 0.f;
+        if (var == 0 || fast_col_fits(prec, var, s.L1, s.L2, s.cols)) {
+            st = time_it(true, var, ms);
+            if (!st && ms < tc) { tc = ms; best_c = var; }
+        }
+        if (!st && (var == 0 || fast_row_fits(prec, var, s.L1, s.L2, s.rows))) {
+            st = time_it(false, var, ms);
+            if (!st && ms < tr) { tr = ms; best_r = var; }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(buf);
+    hipFree(v);
+    hipFree(kt);
+    if (st) return st;
+    return lattice_plan_set_kernels(p, prec, best_c, best_r);
 }
 
 }  // extern "C"

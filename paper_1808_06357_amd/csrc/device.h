@@ -350,13 +350,17 @@ __device__ __forceinline__ cx<T> mul_expm_i(cx<T> x, double a)
 template <typename T>
 __device__ __forceinline__ cx<T> col_mid(cx<T> x, const ColArgs &a, const double *vb, int64_t n)
 {
-    const bool any = vb || a.s || a.chirp || a.scale != 1.0;
+    const bool any = vb || a.ktab || a.chirp || a.scale != 1.0;
     if (!any) return x;
-    double ang = 0.0;
-    if (vb) ang += a.phase * vb[n];
-    if (a.s) ang += a.kin * (double)a.s[n];
-    double c, s;
-    expm_i(ang, c, s);
+    double c = 1.0, s = 0.0;
+    if (vb) expm_i(a.phase * vb[n], c, s);
+    if (a.ktab) {
+        const int m = a.s[n];
+        const double kr = a.ktab[2 * m], ki = a.ktab[2 * m + 1];
+        const double r = c * kr - s * ki, i = c * ki + s * kr;
+        c = r;
+        s = i;
+    }
     if (a.chirp) {
         double cc, cs;
         chirp(n, a.Nchirp, cc, cs);
@@ -392,9 +396,8 @@ __device__ __forceinline__ cx<T> row_mid(cx<T> x, const RowArgs &a, int64_t pos)
         const double br = a.bhat[2 * pos], bi = a.conj_tab ? -a.bhat[2 * pos + 1] : a.bhat[2 * pos + 1];
         return cmul_d(x, br, bi);
     }
-    double c, s;
-    expm_i(a.kin * (double)a.s[pos], c, s);
-    return cmul_d(x, c * a.scale, s * a.scale);
+    const int m = a.s[pos];
+    return cmul_d(x, a.ktab[2 * m], a.ktab[2 * m + 1]);
 }
 
 }  // namespace lt

@@ -323,9 +323,8 @@ __global__ void __launch_bounds__(kThreads) k_resident(ResArgs a)
             for (int n = threadIdx.x; n < L; n += kThreads) s[n] = conjg(cmul_d(s[n], B[2 * n], B[2 * n + 1]));
         } else {
             for (int n = threadIdx.x; n < L; n += kThreads) {
-                double c, sn;
-                expm_i(a.kin * (double)a.s[n], c, sn);
-                s[n] = conjg(cmul_d(s[n], c * a.scale, sn * a.scale));
+                const int m = a.s[n];
+                s[n] = conjg(cmul_d(s[n], a.ktab[2 * m], a.ktab[2 * m + 1]));
             }
         }
         __syncthreads();
@@ -334,9 +333,8 @@ __global__ void __launch_bounds__(kThreads) k_resident(ResArgs a)
             for (int n = threadIdx.x; n < L; n += kThreads) {
                 cx<T> x = {0, 0};
                 if (n < N) {
-                    double c, sn;
-                    expm_i(a.kin * (double)a.s[n], c, sn);
-                    x = cmul_d(conjg(s[n]), c, sn);
+                    const int m = a.s[n];
+                    x = cmul_d(conjg(s[n]), a.ktab[2 * m], a.ktab[2 * m + 1]);
                 }
                 s[n] = x;
             }
@@ -428,6 +426,18 @@ __global__ void k_chirp_filter(cx<double> *dst, int64_t N, int64_t L)
     }
 }
 
+// kinetic multipliers per squared norm m: exp(-i kin m) * scale, angle reduced in FP64
+__global__ void k_ktab(double *dst, int64_t count, double kin, double scale)
+{
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < count;
+         m += (int64_t)gridDim.x * blockDim.x) {
+        double c, s;
+        expm_i(kin * (double)m, c, s);
+        dst[2 * m] = c * scale;
+        dst[2 * m + 1] = s * scale;
+    }
+}
+
 __global__ void k_reduce_batch(double *dst, const double *src, int64_t N, int batch)
 {
     for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N;
@@ -466,8 +476,8 @@ int kernels_init()
 int launch_col(int prec, const Sched &s, const ColArgs &a, int batch, void *stream)
 {
     KTimer timer(LT_KIND_COLUMN, stream);
-    if (!a.adjoint) {
-        const int r = launch_col_fast(prec, a, batch, stream);
+    if (s.col_var > 0 && !a.adjoint) {
+        const int r = launch_col_fast(prec, s.col_var, a, batch, stream);
         if (r >= 0) return r;
     }
     const int nvec = a.adjoint ? 2 : 1;
@@ -477,15 +487,14 @@ int launch_col(int prec, const Sched &s, const ColArgs &a, int batch, void *stre
         hipLaunchKernelGGL((k_col<double, 16>), grid, dim3(kThreads), lds, (hipStream_t)stream, a);
     else
         hipLaunchKernelGGL((k_col<float, 32>), grid, dim3(kThreads), lds, (hipStream_t)stream, a);
-    (void)s;
     return (int)hipGetLastError();
 }
 
 int launch_row(int prec, const Sched &s, const RowArgs &a, int batch, void *stream)
 {
     KTimer timer(LT_KIND_ROW, stream);
-    if (!a.fft_only) {
-        const int r = launch_row_fast(prec, a, batch, stream);
+    if (s.row_var > 0 && !a.fft_only) {
+        const int r = launch_row_fast(prec, s.row_var, a, batch, stream);
         if (r >= 0) return r;
     }
     const size_t lds = (size_t)a.rows * a.L2 * esize(prec);
@@ -494,7 +503,6 @@ int launch_row(int prec, const Sched &s, const RowArgs &a, int batch, void *stre
         hipLaunchKernelGGL((k_row<double, 16>), grid, dim3(kThreads), lds, (hipStream_t)stream, a);
     else
         hipLaunchKernelGGL((k_row<float, 32>), grid, dim3(kThreads), lds, (hipStream_t)stream, a);
-    (void)s;
     return (int)hipGetLastError();
 }
 
@@ -538,6 +546,13 @@ int launch_chirp_filter(void *dst, int64_t N, int64_t L, void *stream)
 {
     hipLaunchKernelGGL(k_chirp_filter, dim3(grid1d(L)), dim3(256), 0, (hipStream_t)stream,
                        (cx<double> *)dst, N, L);
+    return (int)hipGetLastError();
+}
+
+int launch_ktab(double *dst, int64_t count, double kin, double scale, void *stream)
+{
+    hipLaunchKernelGGL(k_ktab, dim3(grid1d(count)), dim3(256), 0, (hipStream_t)stream, dst, count, kin,
+                       scale);
     return (int)hipGetLastError();
 }
 

@@ -14,7 +14,6 @@
 //  * column tiles are remapped so that neighbouring tiles, which share cache
 //    lines, run on the same XCD (workgroups are dealt round-robin to the 8
 //    XCDs, each with its own L2).
-// Both precisions: 256 threads x 16 elements (a 4096-element tile).
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -108,10 +107,8 @@ __device__ __forceinline__ void tw4_series(double (&wr)[R], double (&wi)[R], int
     }
 }
 
-// Steady-state column pass: [inverse column DFT -> point-domain phase (and
-// chirp-z mask) -> forward column DFT], in place.  The phase is evaluated in
-// FP64 in a plain loop over the tile held in LDS, which keeps the unrolled
-// register FFT free of the sincos register pressure.
+// Steady-state column pass: [inverse column DFT -> point-domain multiplier
+// (and chirp-z mask) -> forward column DFT], in place.
 template <typename T, int R, int NS, int E, int NT, int MINW>
 __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
 {
@@ -141,6 +138,9 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
         }
     }
     F::run(v, s, tw, false);
+    // point-domain multiplier (FP64 sincos or kinetic table) in a plain loop
+    // over the tile held in LDS, away from the unrolled register FFT
+    const double *vb = a.v ? a.v + b * a.v_bs : nullptr;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -150,7 +150,6 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
         for (int r = 0; r < R; ++r) s[F::addr(q, t + r * BPS)] = conjg(v[j][r]);
     }
     __syncthreads();
-    const double *vb = a.v ? a.v + b * a.v_bs : nullptr;
 #pragma unroll 1
     for (int i = threadIdx.x; i < TILE; i += NT) {
         const int q = i % C, e = i / C;
@@ -184,10 +183,9 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
     (void)L1;
 }
 
-// Row pass: [DFT -> spectral multiplier -> inverse DFT], in place.  The
-// chirp-z kernel spectrum is a table product done in registers; kinetic
-// phases (FP64 sincos) go through one LDS round trip like the column pass.
-template <typename T, int R, int NS, int E, int NT, int MINW>
+// Row pass: [DFT -> spectral multiplier -> inverse DFT], in place; the
+// multiplier (chirp-z kernel spectrum or kinetic table) is applied in registers.
+template <typename T, int R, int NS, int E, int NT, int MINW, int MID>
 __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
 {
     using F = Fft<T, R, NS, E, NT, false>;
@@ -208,7 +206,8 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
         for (int r = 0; r < R; ++r) v[j][r] = buf[q * L2 + t + r * BPS];
     }
     F::run(v, s, tw, false);
-    if (a.bhat) {
+    if constexpr (MID == 0) {
+        // chirp-z kernel spectrum: one complex-double load per element
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             const int bf = threadIdx.x + j * NT;
@@ -221,6 +220,7 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
             }
         }
     } else {
+        // kinetic table indexed by the squared norm: gather through LDS
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -255,108 +255,129 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
 }
 
 // ---------------------------------------------------------------- dispatch
+// Variant 1: 256 threads x 16 elements (radix 16 / 8); variant 2: 512 threads
+// x 8 elements (radix 8 / 4, twice the waves per CU).  Both hold a
+// 4096-element tile, so they share the plan's layout and are interchangeable.
 namespace {
-constexpr int kE = 16;
-template <typename T>
+template <int V>
 struct Geo;
 template <>
-struct Geo<float> {
-    static constexpr int NT = 256, MINW = 2;
+struct Geo<1> {
+    static constexpr int NT = 256, E = 16, MINW = 2;
 };
 template <>
-struct Geo<double> {
-    static constexpr int NT = 256, MINW = 2;
+struct Geo<2> {
+    static constexpr int NT = 512, E = 8, MINW = 4;
 };
 
-template <typename T>
-constexpr int tile_elems() { return Geo<T>::NT * kE; }
-template <typename T>
-size_t lds_bytes() { return (size_t)(tile_elems<T>() + tile_elems<T>() / 16) * sizeof(cx<T>); }
+template <typename T, int V>
+size_t lds_bytes()
+{
+    constexpr int tile = Geo<V>::NT * Geo<V>::E;
+    return (size_t)(tile + tile / 16) * sizeof(cx<T>);
+}
 
-template <typename T, int R, int NS>
+template <typename T, int V, int R, int NS>
 int col_go(const ColArgs &a, int batch, void *stream)
 {
-    constexpr int NT = Geo<T>::NT, MINW = Geo<T>::MINW;
-    auto k = k_colf<T, R, NS, kE, NT, MINW>;
+    constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW;
+    auto k = k_colf<T, R, NS, E, NT, MINW>;
     static bool attr = false;
     if (!attr) {
         hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    constexpr int C = tile_elems<T>() / ipow(R, NS);
+    constexpr int C = NT * E / ipow(R, NS);
     dim3 grid(a.L2 / C, batch);
-    hipLaunchKernelGGL(k, grid, dim3(NT), lds_bytes<T>(), (hipStream_t)stream, a);
+    const size_t lds = lds_bytes<T, V>();
+    hipLaunchKernelGGL(k, grid, dim3(NT), lds, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 
-template <typename T, int R, int NS>
+template <typename T, int V, int R, int NS>
 int row_go(const RowArgs &a, int batch, void *stream)
 {
-    constexpr int NT = Geo<T>::NT, MINW = Geo<T>::MINW;
-    auto k = k_rowf<T, R, NS, kE, NT, MINW>;
+    constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW;
+    auto k = a.bhat ? k_rowf<T, R, NS, E, NT, MINW, 0> : k_rowf<T, R, NS, E, NT, MINW, 1>;
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipFuncSetAttribute((const void *)k_rowf<T, R, NS, E, NT, MINW, 0>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipFuncSetAttribute((const void *)k_rowf<T, R, NS, E, NT, MINW, 1>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    constexpr int RW = tile_elems<T>() / ipow(R, NS);
+    constexpr int RW = NT * E / ipow(R, NS);
     dim3 grid(a.L1 / RW, batch);
-    hipLaunchKernelGGL(k, grid, dim3(NT), lds_bytes<T>(), (hipStream_t)stream, a);
+    const size_t lds = lds_bytes<T, V>();
+    hipLaunchKernelGGL(k, grid, dim3(NT), lds, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 
-template <typename T>
-int col_dispatch(const ColArgs &a, int batch, void *stream)
+template <typename T, int V, int R, int NS, bool COL, class A>
+int go1(const A &a, int batch, void *stream)
 {
-    switch (a.L1) {
-    case 64: return col_go<T, 8, 2>(a, batch, stream);
-    case 256: return col_go<T, 16, 2>(a, batch, stream);
-    case 512: return col_go<T, 8, 3>(a, batch, stream);
-    case 4096: return col_go<T, 16, 3>(a, batch, stream);
-    default: return -1;
-    }
+    if constexpr (COL) return col_go<T, V, R, NS>(a, batch, stream);
+    else return row_go<T, V, R, NS>(a, batch, stream);
 }
 
-template <typename T>
-int row_dispatch(const RowArgs &a, int batch, void *stream)
+// (radix, stages) of each supported length per variant
+template <typename T, int V, bool COL, class A>
+int go(int L, const A &a, int batch, void *stream)
 {
-    switch (a.L2) {
-    case 64: return row_go<T, 8, 2>(a, batch, stream);
-    case 256: return row_go<T, 16, 2>(a, batch, stream);
-    case 512: return row_go<T, 8, 3>(a, batch, stream);
-    case 4096: return row_go<T, 16, 3>(a, batch, stream);
-    default: return -1;
+    if constexpr (V == 1) {
+        switch (L) {
+        case 64: return go1<T, V, 8, 2, COL>(a, batch, stream);
+        case 256: return go1<T, V, 16, 2, COL>(a, batch, stream);
+        case 512: return go1<T, V, 8, 3, COL>(a, batch, stream);
+        case 4096: return go1<T, V, 16, 3, COL>(a, batch, stream);
+        default: return -1;
+        }
+    } else {
+        switch (L) {
+        case 64: return go1<T, V, 8, 2, COL>(a, batch, stream);
+        case 256: return go1<T, V, 4, 4, COL>(a, batch, stream);
+        case 512: return go1<T, V, 8, 3, COL>(a, batch, stream);
+        case 4096: return go1<T, V, 8, 4, COL>(a, batch, stream);
+        default: return -1;
+        }
     }
 }
 
 bool fast_len(int L) { return L == 64 || L == 256 || L == 512 || L == 4096; }
-int tile_of(int prec) { return prec == LT_C128 ? tile_elems<double>() : tile_elems<float>(); }
+constexpr int kTile = 4096;
 }  // namespace
 
-bool fast_col_fits(int prec, int L1, int L2, int C)
+bool fast_col_fits(int prec, int variant, int L1, int L2, int C)
 {
-    return fast_len(L1) && C == tile_of(prec) / L1 && L2 % C == 0;
+    (void)prec;
+    return (variant == 1 || variant == 2) && fast_len(L1) && C == kTile / L1 && L2 % C == 0;
 }
 
-bool fast_row_fits(int prec, int L1, int L2, int rows)
+bool fast_row_fits(int prec, int variant, int L1, int L2, int rows)
 {
-    return fast_len(L2) && rows == tile_of(prec) / L2 && L1 % rows == 0;
+    (void)prec;
+    return (variant == 1 || variant == 2) && fast_len(L2) && rows == kTile / L2 && L1 % rows == 0;
 }
 
-int launch_col_fast(int prec, const ColArgs &a, int batch, void *stream)
+int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *stream)
 {
     // steady-state passes only: the first / last / checkpoint passes of a run
     // and the adjoint passes take the general kernel
     const bool steady = a.pre_inv && a.post_fwd && !a.in && !a.out && !a.ck && !a.chirp &&
                         a.scale == 1.0 && !a.adjoint;
-    if (!steady || !fast_col_fits(prec, a.L1, a.L2, a.C)) return -1;
-    return prec == LT_C128 ? col_dispatch<double>(a, batch, stream) : col_dispatch<float>(a, batch, stream);
+    if (!steady || !fast_col_fits(prec, variant, a.L1, a.L2, a.C)) return -1;
+    if (prec == LT_C128)
+        return variant == 1 ? go<double, 1, true>(a.L1, a, batch, stream) : go<double, 2, true>(a.L1, a, batch, stream);
+    return variant == 1 ? go<float, 1, true>(a.L1, a, batch, stream) : go<float, 2, true>(a.L1, a, batch, stream);
 }
 
-int launch_row_fast(int prec, const RowArgs &a, int batch, void *stream)
+int launch_row_fast(int prec, int variant, const RowArgs &a, int batch, void *stream)
 {
-    if (!fast_row_fits(prec, a.L1, a.L2, a.rows)) return -1;
-    return prec == LT_C128 ? row_dispatch<double>(a, batch, stream) : row_dispatch<float>(a, batch, stream);
+    if (a.fft_only || !fast_row_fits(prec, variant, a.L1, a.L2, a.rows)) return -1;
+    if (prec == LT_C128)
+        return variant == 1 ? go<double, 1, false>(a.L2, a, batch, stream) : go<double, 2, false>(a.L2, a, batch, stream);
+    return variant == 1 ? go<float, 1, false>(a.L2, a, batch, stream) : go<float, 2, false>(a.L2, a, batch, stream);
 }
 
 }  // namespace lt

@@ -34,6 +34,8 @@ struct Sched {
     int cols = 1;            // columns per column-pass workgroup
     int rows = 1;            // rows per row-pass workgroup
     int ept = 16;            // max complex elements per thread (register budget)
+    int col_var = 1;         // column-pass kernel: 0 general, 1 fast 256x16, 2 fast 512x8
+    int row_var = 1;         // row-pass kernel (same codes)
     Radices ra{}, rb{};      // radices of L1 (or L) and of L2
 };
 
@@ -51,9 +53,10 @@ struct DevTables {
 
 // ---------------------------------------------------------------- kernel arguments
 // Point-domain multiplier of a column pass, at natural index n < Nvalid:
-//   w = exp(-i (phase * v[n] + kin * s[n])) * c_n^chirp * scale
+//   w = exp(-i phase v[n]) * ktab[s[n]] * c_n^chirp * scale
 // (terms with a null pointer / zero flag are skipped; c_n is the chirp
-// exp(-pi i (n^2 mod 2N)/N)); indices n >= Nvalid are set to zero.
+// exp(-pi i (n^2 mod 2N)/N); ktab[m] = exp(-i kin m) for the integer
+// squared norms m = ||h||^2); indices n >= Nvalid are set to zero.
 struct ColArgs {
     void *buf; int64_t buf_bs;        // transform buffer (L elements per batch item)
     const void *in; int64_t in_bs;    // first pass: read lattice values from here (Nvalid)
@@ -62,7 +65,7 @@ struct ColArgs {
     int64_t Nvalid;
     int pre_inv, post_fwd, twiddle;
     const double *v; int64_t v_bs; double phase;
-    const int32_t *s; double kin;
+    const int32_t *s; const double *ktab;
     int chirp;                        // +1: times c_n, -1: times conj(c_n), 0: none
     int64_t Nchirp;
     double scale;
@@ -86,12 +89,12 @@ struct ColArgs {
 
 // Spectral multiplier of a row pass at row-pass position pos = k1 L2 + k2:
 // chirp-z: bhat[pos] (complex double, conjugated if conj_tab);
-// otherwise exp(-i kin * s[pos]) * scale.
+// otherwise ktab[s[pos]] (kinetic phase per squared norm, 1/L folded in).
 struct RowArgs {
     void *buf; int64_t buf_bs;
     int L1, L2, rows, nblk;
     const double *bhat; int conj_tab;
-    const int32_t *s; double kin, scale;
+    const int32_t *s; const double *ktab;
     int fft_only;
     const void *twb;                  // Tw<T> table of W_{L2}
     Radices rad;
@@ -105,7 +108,7 @@ struct ResArgs {
     const void *twa, *twb;
     int bluestein;
     const int32_t *s;                  // ||h||^2 per key, natural order
-    double kin, scale;                 // kinetic angle per unit norm; 1/L (smooth) or 1
+    const double *ktab;                // exp(-i kin m) * (1/L smooth, 1 chirp-z), m = ||h||^2
     const double *bhat;                // natural order, chirp-z only (complex double)
     const double *v; int64_t v_bs;
     double phase_half;                 // dt / (2 gamma)
@@ -126,11 +129,12 @@ int launch_unpermute_c128(void *dst_nat, const void *src, int64_t L, int L1, int
                           void *stream);
 int launch_chirp_filter(void *dst_c128, int64_t N, int64_t L, void *stream);
 int launch_reduce_batch(double *dst, const double *src, int64_t N, int batch, void *stream);
-// fast register-staged variants (kernels_fast.hip); return -1 when no variant fits
-int launch_col_fast(int prec, const ColArgs &a, int batch, void *stream);
-int launch_row_fast(int prec, const RowArgs &a, int batch, void *stream);
-bool fast_col_fits(int prec, int L1, int L2, int C);
-bool fast_row_fits(int prec, int L1, int L2, int rows);
+int launch_ktab(double *dst, int64_t count, double kin, double scale, void *stream);
+// fast register-staged variants (kernels_fast.hip); return -1 when the variant does not fit
+int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *stream);
+int launch_row_fast(int prec, int variant, const RowArgs &a, int batch, void *stream);
+bool fast_col_fits(int prec, int variant, int L1, int L2, int C);
+bool fast_row_fits(int prec, int variant, int L1, int L2, int rows);
 int kernels_init();  // raise dynamic LDS limits once
 
 // Event bracket around one launch when timing is enabled (timing.cpp).

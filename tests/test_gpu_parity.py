@@ -150,3 +150,24 @@ def test_checkpoints_match_shorter_runs(lt):
         for c in range(ck.shape[0]):
             ref = O.strang_run(n, s, v, u0, gamma, dt, c * every)
             assert rel(ck[c], ref) < 1e-11, (N, c)
+
+
+@pytest.mark.parametrize("N,d", [(65521, 4), (1 << 16, 3), (4096 * 64, 3)])
+def test_every_kernel_variant(lt, N, d):
+    """All column/row kernel variants give the oracle's result (the autotuner
+    may pick any of them)."""
+    Z, n, v, u0, gamma, dt, steps = korobov_case(N, d, 21, 9)
+    plan = lt.lattice_plan(Z, n)
+    _, s, _ = O.index_set(Z, n)
+    ref = O.strang_run(n, s, v, u0, gamma, dt, steps)
+    for cv in (0, 1, 2):
+        for rv in (0, 1, 2):
+            for prec in ("c128", "c64"):
+                p = lt.LT_C128 if prec == "c128" else lt.LT_C64
+                lt.lattice_plan_set_kernels(plan, p, cv, rv)
+                e = rel(gpu_run(lt, plan, v, u0, gamma, dt, steps, prec), ref)
+                print(f"  N={N} col={cv} row={rv} {prec} rel_l2={e:.2e}", flush=True)
+                assert e < TOL[prec], (cv, rv, prec, e)
+    for prec in (lt.LT_C64, lt.LT_C128):
+        chosen = lt.lattice_plan_autotune(plan, prec, reps=3)
+        assert all(x in (0, 1, 2) for x in chosen)

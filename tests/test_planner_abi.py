@@ -109,8 +109,14 @@ def test_schedules():
     assert p.info["L1"] * p.info["L2"] == 1 << 16
     p = C.lattice_plan(np.array([[1, 5, 7], [0, 1, 3]]), np.array([12, 4]))
     assert p.info["passes"] == 1 and p.info["fft_len"] == 48
-    # forward runs need scratch only for two-pass chirp-z transforms; the adjoint always does
-    assert C.strang_workspace_size(p, C.LT_C128, 2, True) == 0
-    assert C.strang_adjoint_workspace_size(p, C.LT_C128, 2, True) > 0
+    # forward runs: a kinetic table, plus a transform buffer for two-pass chirp-z
+    small = C.strang_workspace_size(p, C.LT_C128, 2, True)
+    assert 0 < small <= 4096
+    assert C.strang_adjoint_workspace_size(p, C.LT_C128, 2, True) > small
     c1 = C.lattice_plan(np.array([[1, 3]]), np.array([65521]))
-    assert C.strang_workspace_size(c1, C.LT_C64, 3, True) == 3 * c1.info["fft_len"] * 8
+    assert C.strang_workspace_size(c1, C.LT_C64, 3, True) >= 3 * c1.info["fft_len"] * 8
+    # kernel selection is host state: set / get without a GPU
+    C.lattice_plan_set_kernels(c1, C.LT_C64, 2, 0)
+    assert C.lattice_plan_get_kernels(c1, C.LT_C64) == (2, 0)
+    with pytest.raises(C.LatticeError):
+        C.lattice_plan_set_kernels(c1, C.LT_C64, 3, 0)
