@@ -44,20 +44,30 @@ def pass_bytes(plan_info, N, m, S):
 
 
 def time_runs(lt, torch, plan, v, u, work, inst, K, W):
+    """Region A: K plain runs (the throughput).  Region B: K more runs with
+    every kernel launch bracketed by HIP events on the library's stream (the
+    per-kernel durations for the roofline); the event records add gaps between
+    launches, so region B's wall time is not used for the throughput."""
     for _ in range(W):
         lt.strang_run(plan, v, u, inst.gamma, inst.dt, inst.steps, work=work)
     torch.cuda.synchronize()
-    lt.lt_timing_enable(True)
     t0 = time.perf_counter()
     for i in range(K):
         lt.strang_run(plan, v, u, inst.gamma, inst.dt, inst.steps, work=work)
-        torch.cuda.synchronize()
-        log(f"timed run {i + 1}/{K} done")
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log(f"timed region: {K} runs in {t1 - t0:.3f}s")
+    lt.lt_timing_enable(True)
+    tb = time.perf_counter()
+    for i in range(K):
+        lt.strang_run(plan, v, u, inst.gamma, inst.dt, inst.steps, work=work)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - tb
     kinds = {"column": lt.lt_timing_summary(lt.LT_KIND_COLUMN),
              "row": lt.lt_timing_summary(lt.LT_KIND_ROW)}
     lt.lt_timing_enable(False)
-    return t1 - t0, kinds
+    log(f"event-instrumented region: {K} runs in {tb:.3f}s")
+    return t1 - t0, kinds, tb
 
 
 def cpu_baseline(inst, seconds):
@@ -89,7 +99,19 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c128", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB device to device (counter calibration for the traffic figure)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.complex64, device="cuda:0")
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": a.numel() * 8,
+                          "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(a single lattice state does not shard; see DESIGN.md)", file=sys.stderr)
@@ -125,7 +147,7 @@ def main():
         lt.strang_run(plan, v, u, inst.gamma, inst.dt, m, work=work)
         torch.cuda.synchronize()
         uT = u.cpu().numpy().astype(np.complex128)
-        elapsed, kinds = time_runs(lt, torch, plan, v, u, work, inst, args.steps, args.warmup)
+        elapsed, kinds, instrumented = time_runs(lt, torch, plan, v, u, work, inst, args.steps, args.warmup)
         col_b, row_b = pass_bytes(info, N, m, S)
         per_kind = {}
         for kname, bytes_list in (("column", col_b), ("row", row_b)):
@@ -136,6 +158,7 @@ def main():
                                "bytes_per_launch": avg_bytes,
                                "achieved_GBs": avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None}
         results[name] = {"elapsed": elapsed, "kinds": per_kind, "uT": uT, "kernels": kernels,
+                         "instrumented_ms_per_run": instrumented / args.steps * 1e3,
                          "value": N * m * args.steps / elapsed, "ms_per_step": elapsed / args.steps * 1e3}
         log(f"{name}: {results[name]['value']:.3e} pt-steps/s, {results[name]['ms_per_step']:.2f} ms/run; "
             + ", ".join(f"{k}: {v_['avg_us']:.1f} us/launch {v_['achieved_GBs'] or 0:.0f} GB/s"
@@ -174,7 +197,8 @@ def main():
                      "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom["achieved_GBs"] / HBM_PEAK_GBS if dom["achieved_GBs"] else None,
                      "traffic": None, "avg_launch_us": dom["avg_us"],
-                     "bytes_per_launch": dom["bytes_per_launch"]},
+                     "bytes_per_launch": dom["bytes_per_launch"],
+                     "instrumented_ms_per_run": head["instrumented_ms_per_run"]},
         "kernels_c64": head["kinds"],
         "kernel_variants": {k: list(r_["kernels"]) for k, r_ in results.items()},
         "accuracy": acc,

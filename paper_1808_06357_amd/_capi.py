@@ -22,6 +22,15 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                       "(python -c 'import __graft_entry__ as g; g.build()')")
 
+# PyTorch ships its own HIP runtime under the same soname as the system one.
+# Loading torch first lets the library bind to that runtime, so the process
+# holds one HIP/HSA runtime; loaded the other way round, torch maps a second
+# copy and the runtime that initialises second finds no device.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 lib = ctypes.CDLL(LIB_PATH)
 
 LT_C64, LT_C128 = 1, 2
@@ -104,7 +113,10 @@ class Plan:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib.lattice_plan_destroy(h)
+            try:
+                lib.lattice_plan_destroy(h)
+            except Exception:  # interpreter shutdown: ctypes may already be torn down
+                pass
             self._h = _P(0)
 
 

@@ -6,7 +6,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "lt_internal.h"
 
@@ -267,6 +269,64 @@ lt_status make_ktab(const lt_plan &p, const Sched &s, double *ktab, double gamma
     return LT_OK;
 }
 
+// launch arguments of the two-pass sequence, per role: the first column pass
+// (half potential step, chirp), the merged potential step P^2 between steps,
+// the chirp-z kinetic column pass, the last column pass, and the row pass
+struct Roles {
+    ColArgs first, pot, kin, last;
+    RowArgs row;
+};
+
+Roles two_pass_roles(const Sched &s, const DevTables &D, int64_t N, const double *v, int64_t v_stride, void *u,
+                     void *W, double half, const double *ktab)
+{
+    Roles R;
+    void *buf = s.bluestein ? W : u;
+    const int64_t buf_bs = s.bluestein ? s.L : N;
+    R.first = col_base(s, D, N);
+    R.first.buf = buf;
+    R.first.buf_bs = buf_bs;
+    R.first.in = u;
+    R.first.in_bs = N;
+    R.first.post_fwd = 1;
+    R.first.v = v;
+    R.first.v_bs = v_stride;
+    R.first.phase = half;
+    R.first.chirp = s.bluestein ? 1 : 0;
+    R.row = row_base(s, D);
+    R.row.buf = buf;
+    R.row.buf_bs = buf_bs;
+    if (s.bluestein) {
+        R.row.bhat = D.bhat;
+    } else {
+        R.row.s = D.s_row;
+        R.row.ktab = ktab;
+    }
+    ColArgs mid = col_base(s, D, N);
+    mid.buf = buf;
+    mid.buf_bs = buf_bs;
+    mid.pre_inv = 1;
+    mid.post_fwd = 1;
+    R.kin = mid;  // chirp-z: kinetic phase at the natural spectral index
+    R.kin.s = D.s_key;
+    R.kin.ktab = ktab;
+    R.pot = mid;
+    R.pot.v = v;
+    R.pot.v_bs = v_stride;
+    R.pot.phase = 2.0 * half;
+    R.last = col_base(s, D, N);
+    R.last.buf = buf;
+    R.last.buf_bs = buf_bs;
+    R.last.pre_inv = 1;
+    R.last.out = u;
+    R.last.out_bs = N;
+    R.last.v = v;
+    R.last.v_bs = v_stride;
+    R.last.phase = half;
+    R.last.chirp = s.bluestein ? -1 : 0;
+    return R;
+}
+
 // forward run of a state batch through the two-pass sequence
 lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int prec, int batch,
                            const double *v, int64_t v_stride, void *u, double gamma, double dt,
@@ -276,51 +336,18 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
     const int64_t N = p.N;
     const size_t S = esz(prec);
     const double half = dt / (2.0 * gamma);
-    void *buf = s.bluestein ? W : u;
-    const int64_t buf_bs = s.bluestein ? s.L : N;
-    // first pass: half potential step (and chirp), column DFT
-    ColArgs c = col_base(s, D, N);
-    c.buf = buf;
-    c.buf_bs = buf_bs;
-    c.in = u;
-    c.in_bs = N;
-    c.post_fwd = 1;
-    c.v = v;
-    c.v_bs = v_stride;
-    c.phase = half;
-    c.chirp = s.bluestein ? 1 : 0;
-    HIP_TRY(launch_col(prec, s, c, batch, st), "column pass");
-    RowArgs r = row_base(s, D);
-    r.buf = buf;
-    r.buf_bs = buf_bs;
-    if (s.bluestein) {
-        r.bhat = D.bhat;
-    } else {
-        r.s = D.s_row;
-        r.ktab = ktab;
-    }
-    ColArgs mid = col_base(s, D, N);
-    mid.buf = buf;
-    mid.buf_bs = buf_bs;
-    mid.pre_inv = 1;
-    mid.post_fwd = 1;
-    ColArgs kinp = mid;  // chirp-z: kinetic phase at the natural spectral index
-    kinp.s = D.s_key;
-    kinp.ktab = ktab;
-    ColArgs pot = mid;   // merged potential step P^2
-    pot.v = v;
-    pot.v_bs = v_stride;
-    pot.phase = 2.0 * half;
+    Roles R = two_pass_roles(s, D, N, v, v_stride, u, W, half, ktab);
+    HIP_TRY(launch_col(prec, s, R.first, batch, st), "column pass");
     for (int64_t t = 0; t < steps; ++t) {
-        r.conj_tab = 0;
-        HIP_TRY(launch_row(prec, s, r, batch, st), "row pass");
+        R.row.conj_tab = 0;
+        HIP_TRY(launch_row(prec, s, R.row, batch, st), "row pass");
         if (s.bluestein) {
-            HIP_TRY(launch_col(prec, s, kinp, batch, st), "column pass (kinetic)");
-            r.conj_tab = 1;
-            HIP_TRY(launch_row(prec, s, r, batch, st), "row pass");
+            HIP_TRY(launch_col(prec, s, R.kin, batch, st), "column pass (kinetic)");
+            R.row.conj_tab = 1;
+            HIP_TRY(launch_row(prec, s, R.row, batch, st), "row pass");
         }
         if (t == steps - 1) break;
-        ColArgs m = pot;
+        ColArgs m = R.pot;
         const int64_t k = t + 1;  // state index at this merge point
         if (ckpt && k % ck_every == 0) {
             m.ck = at(ckpt, (size_t)(k / ck_every) * batch * N * S);
@@ -331,17 +358,84 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
         }
         HIP_TRY(launch_col(prec, s, m, batch, st), "column pass (potential)");
     }
-    ColArgs last = col_base(s, D, N);
-    last.buf = buf;
-    last.buf_bs = buf_bs;
-    last.pre_inv = 1;
-    last.out = u;
-    last.out_bs = N;
-    last.v = v;
-    last.v_bs = v_stride;
-    last.phase = half;
-    last.chirp = s.bluestein ? -1 : 0;
-    HIP_TRY(launch_col(prec, s, last, batch, st), "column pass (last)");
+    HIP_TRY(launch_col(prec, s, R.last, batch, st), "column pass (last)");
+    return LT_OK;
+}
+
+// ---------------------------------------------------------------- batches
+// workspace of a batch: per problem its run workspace, then the descriptor
+// block (kinetic-table, resident and two-pass descriptors, block prefix sums)
+struct BatchLayout {
+    std::vector<size_t> off;
+    size_t desc = 0, d_ktab = 0, d_res = 0, d_two = 0, d_scol = 0, d_srow = 0, desc_bytes = 0, total = 0;
+};
+
+BatchLayout batch_layout(int32_t B, const lt_plan *const *plans, int prec)
+{
+    BatchLayout b;
+    size_t off = 0;
+    b.off.resize(B);
+    for (int i = 0; i < B; ++i) {
+        b.off[i] = off;
+        off += run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1).total;
+    }
+    b.desc = off;
+    size_t d = 0;
+    b.d_ktab = d;
+    d = align_up(d + (size_t)B * sizeof(KtabDesc));
+    b.d_res = d;
+    d = align_up(d + (size_t)B * sizeof(ResArgs));
+    b.d_two = d;
+    d = align_up(d + (size_t)B * sizeof(BatchDesc));
+    b.d_scol = d;
+    d = align_up(d + (size_t)(B + 1) * sizeof(int));
+    b.d_srow = d;
+    d = align_up(d + (size_t)(B + 1) * sizeof(int));
+    b.desc_bytes = d;
+    b.total = off + d;
+    return b;
+}
+
+// pinned staging buffer for descriptor uploads; the event of the last copy
+// guards its reuse
+struct Staging {
+    std::mutex mu;
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+Staging g_stage;
+
+lt_status upload_async(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g_stage.mu);
+    if (g_stage.done) HIP_TRY(hipEventSynchronize(g_stage.done), "staging wait");
+    if (bytes > g_stage.cap) {
+        if (g_stage.host) HIP_TRY(hipHostFree(g_stage.host), "staging free");
+        g_stage.host = nullptr;
+        g_stage.cap = 0;
+        HIP_TRY(hipHostMalloc(&g_stage.host, bytes, hipHostMallocDefault), "staging allocation");
+        g_stage.cap = bytes;
+    }
+    if (!g_stage.done) HIP_TRY(hipEventCreateWithFlags(&g_stage.done, hipEventDisableTiming), "event");
+    std::memcpy(g_stage.host, src, bytes);
+    HIP_TRY(hipMemcpyAsync(dst, g_stage.host, bytes, hipMemcpyHostToDevice, st), "descriptor upload");
+    HIP_TRY(hipEventRecord(g_stage.done, st), "event record");
+    return LT_OK;
+}
+
+// a second stream per device (default priority) for work that overlaps the
+// caller's stream
+lt_status side_stream(hipStream_t *out)
+{
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "device query");
+    if (dev < 0 || dev >= 64) return fail(LT_E_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!streams[dev]) HIP_TRY(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking), "stream");
+    *out = streams[dev];
     return LT_OK;
 }
 
@@ -697,12 +791,9 @@ lt_status strang_batched_workspace_size(int32_t B, const lt_plan *const *plans, 
 {
     if (B < 0 || (B > 0 && !plans) || !bytes) return fail(LT_E_ARG, "bad arguments");
     if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
-    size_t tot = 0;
-    for (int i = 0; i < B; ++i) {
+    for (int i = 0; i < B; ++i)
         if (!plans[i]) return fail(LT_E_ARG, "plan is NULL");
-        tot += run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1).total;
-    }
-    *bytes = tot;
+    *bytes = B ? batch_layout(B, plans, prec).total : 0;
     return LT_OK;
 }
 
@@ -713,20 +804,127 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
     if (B < 0) return fail(LT_E_ARG, "B must be >= 0");
     if (B == 0) return LT_OK;
     if (!plans || !v || !u || !gamma || !dt || !steps) return fail(LT_E_ARG, "NULL argument");
-    size_t need = 0;
-    lt_status st = strang_batched_workspace_size(B, plans, prec, &need);
-    if (st) return st;
-    hipStream_t hs = (hipStream_t)stream;
-    Scratch sc;
-    if ((st = get_work(sc, work, work_bytes, need, hs))) return st;
-    size_t off = 0;
+    lt_status st;
     for (int i = 0; i < B; ++i) {
-        const size_t w = run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1).total;
-        st = strang_run(plans[i], prec, 1, v[i], plans[i]->N, u[i], gamma[i], dt[i], steps[i], nullptr, 0,
-                        w ? at(sc.ptr, off) : nullptr, w, stream);
-        if (st) return st;
-        off += w;
+        if ((st = check_common(plans[i], prec, 1, gamma[i], dt[i], steps[i]))) return st;
+        if (steps[i] > 0 && (!v[i] || !u[i])) return fail(LT_E_ARG, "v and u must not be NULL");
     }
+    hipStream_t hs = (hipStream_t)stream;
+    const BatchLayout BL = batch_layout(B, plans, prec);
+    Scratch sc;
+    if ((st = get_work(sc, work, work_bytes, BL.total, hs))) return st;
+    const size_t S = esz(prec);
+    std::vector<KtabDesc> kd;
+    std::vector<ResArgs> res;
+    std::vector<BatchDesc> two;
+    size_t lds_res = 0, lds_col = 0, lds_row = 0;
+    int64_t max_ktab = 0;
+    for (int i = 0; i < B; ++i) {
+        if (steps[i] == 0) continue;
+        lt_plan &p = *const_cast<lt_plan *>(plans[i]);
+        if ((st = ensure_device_tables(p, 0, prec, stream))) return st;
+        const Sched &s = p.sched[0][prec];
+        const DevTables &D = p.dev[0][prec];
+        const RunWork L = run_layout(p, s, prec, 1);
+        char *w = at(sc.ptr, BL.off[i]);
+        double *ktab = (double *)(w + L.ktab);
+        kd.push_back({ktab, p.max_s + 1, kinetic_angle(gamma[i], dt[i]), s.bluestein ? 1.0 : 1.0 / (double)s.L});
+        max_ktab = std::max<int64_t>(max_ktab, p.max_s + 1);
+        const double half = dt[i] / (2.0 * gamma[i]);
+        if (s.passes == 1) {
+            ResArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.u = u[i];
+            a.u_bs = p.N;
+            a.N = p.N;
+            a.L = s.L;
+            a.rank2 = s.rank2 ? 1 : 0;
+            a.n1 = s.L1;
+            a.n2 = s.L2;
+            a.ra = s.ra;
+            a.rb = s.rb;
+            a.twa = D.twa;
+            a.twb = D.twb;
+            a.bluestein = s.bluestein ? 1 : 0;
+            a.s = D.s_key;
+            a.ktab = ktab;
+            a.bhat = D.bhat;
+            a.v = v[i];
+            a.phase_half = half;
+            a.steps = steps[i];
+            a.batch = 1;
+            res.push_back(a);
+            lds_res = std::max(lds_res, (size_t)s.L * S);
+            continue;
+        }
+        const Roles R = two_pass_roles(s, D, p.N, v[i], 0, u[i], w + L.w, half, ktab);
+        BatchDesc b;
+        std::memset(&b, 0, sizeof(b));
+        b.col[0] = R.first;
+        b.col[1] = R.pot;
+        b.col[2] = R.kin;
+        b.col[3] = R.last;
+        b.row[0] = R.row;
+        b.row[1] = R.row;
+        b.row[1].conj_tab = 1;
+        b.bluestein = s.bluestein ? 1 : 0;
+        b.npass = (s.bluestein ? 4 : 2) * steps[i] + 1;
+        two.push_back(b);
+        lds_col = std::max(lds_col, (size_t)R.first.L1 * R.first.C * S);
+        lds_row = std::max(lds_row, (size_t)R.row.rows * R.row.L2 * S);
+    }
+    if (kd.empty()) return LT_OK;
+    // longest schedules first: the problems still running at pass g are a prefix
+    std::stable_sort(two.begin(), two.end(),
+                     [](const BatchDesc &a, const BatchDesc &b) { return a.npass > b.npass; });
+    const int n2 = (int)two.size();
+    std::vector<int> scol(n2 + 1, 0), srow(n2 + 1, 0);
+    for (int i = 0; i < n2; ++i) {
+        scol[i + 1] = scol[i] + two[i].col[0].ntiles;
+        srow[i + 1] = srow[i] + two[i].row[0].nblk;
+    }
+    std::vector<char> blob(BL.desc_bytes, 0);
+    std::memcpy(blob.data() + BL.d_ktab, kd.data(), kd.size() * sizeof(KtabDesc));
+    if (!res.empty()) std::memcpy(blob.data() + BL.d_res, res.data(), res.size() * sizeof(ResArgs));
+    if (n2) std::memcpy(blob.data() + BL.d_two, two.data(), two.size() * sizeof(BatchDesc));
+    std::memcpy(blob.data() + BL.d_scol, scol.data(), scol.size() * sizeof(int));
+    std::memcpy(blob.data() + BL.d_srow, srow.data(), srow.size() * sizeof(int));
+    char *dd = at(sc.ptr, BL.desc);
+    if ((st = upload_async(dd, blob.data(), blob.size(), hs))) return st;
+    HIP_TRY(launch_ktab_multi((const KtabDesc *)(dd + BL.d_ktab), (int)kd.size(), max_ktab, hs),
+            "kinetic tables");
+    // problems that fit one workgroup: their whole step loop in one launch,
+    // overlapped with the pass-by-pass launches of the others
+    hipStream_t rs = hs;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    if (!res.empty() && n2) {
+        if ((st = side_stream(&rs))) return st;
+        HIP_TRY(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming), "event");
+        HIP_TRY(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming), "event");
+        HIP_TRY(hipEventRecord(ev_fork, hs), "event record");
+        HIP_TRY(hipStreamWaitEvent(rs, ev_fork, 0), "stream wait");
+    }
+    if (!res.empty())
+        HIP_TRY(launch_resident_multi(prec, (const ResArgs *)(dd + BL.d_res), (int)res.size(), lds_res, rs),
+                "resident batch");
+    const BatchDesc *dtwo = (const BatchDesc *)(dd + BL.d_two);
+    const int *dscol = (const int *)(dd + BL.d_scol), *dsrow = (const int *)(dd + BL.d_srow);
+    int act = n2;
+    const int64_t gmax = n2 ? two[0].npass : 0;
+    int herr = 0;
+    for (int64_t g = 0; g < gmax && !herr; ++g) {
+        while (act > 0 && two[act - 1].npass <= g) --act;
+        if (g & 1) herr = launch_row_multi(prec, dtwo, dsrow, act, srow[act], g, lds_row, hs);
+        else herr = launch_col_multi(prec, dtwo, dscol, act, scol[act], g, lds_col, hs);
+    }
+    if (ev_fork) {  // join even after a failed launch: the workspace must outlive the side stream's work
+        if (!herr) herr = (int)hipEventRecord(ev_join, rs);
+        if (!herr) herr = (int)hipStreamWaitEvent(hs, ev_join, 0);
+        else hipStreamSynchronize(rs);
+        hipEventDestroy(ev_fork);
+        hipEventDestroy(ev_join);
+    }
+    HIP_TRY(herr, "batched pass");
     return LT_OK;
 }
 

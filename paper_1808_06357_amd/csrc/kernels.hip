@@ -25,6 +25,7 @@
 //    each DFT becomes a length-L cyclic convolution with a precomputed kernel
 //    spectrum; the chirps of consecutive transforms cancel, so inside the step
 //    loop only the masked K and P^2 multiplies remain.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -119,15 +120,11 @@ __device__ __forceinline__ cx<T> ldc(const void *p, int64_t i) { return ((const 
 //   post_fwd: column DFT; x <- x W(n2,k1)                    (forward towards the rows)
 // In adjoint mode the tile also holds the cotangent columns (sequences C..2C-1).
 template <typename T, int EPT>
-__global__ void __launch_bounds__(kThreads) k_col(ColArgs a)
+__device__ void col_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
 {
-    extern __shared__ char smem_raw[];
-    cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
     const int L1 = a.L1, L2 = a.L2, C = a.C;
     const int nvec = a.adjoint ? 2 : 1;
     const int Cq = C * nvec;                  // sequences in the tile
-    const int tile = blockIdx.x;
-    const int64_t b = blockIdx.y;
     const int c0 = tile * C;
     const int cw = min(C, L2 - c0);           // valid columns in this tile
     const int tot = L1 * Cq;
@@ -241,18 +238,22 @@ __global__ void __launch_bounds__(kThreads) k_col(ColArgs a)
     }
 }
 
+template <typename T, int EPT>
+__global__ void __launch_bounds__(kThreads) k_col(ColArgs a)
+{
+    extern __shared__ char smem_raw[];
+    col_body<T, EPT>(a, blockIdx.x, blockIdx.y, reinterpret_cast<cx<T> *>(smem_raw));
+}
+
 // ---------------------------------------------------------------- row pass
 // `rows` contiguous rows of length L2 per workgroup: DFT; spectral multiplier;
 // inverse DFT.
 template <typename T, int EPT>
-__global__ void __launch_bounds__(kThreads) k_row(RowArgs a)
+__device__ void row_body(const RowArgs &a, int blk, int64_t b, cx<T> *s)
 {
-    extern __shared__ char smem_raw[];
-    cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
     const int L2 = a.L2;
-    const int r0 = blockIdx.x * a.rows;
+    const int r0 = blk * a.rows;
     const int rw = min(a.rows, a.L1 - r0);
-    const int64_t b = blockIdx.y;
     cx<T> *buf = (cx<T> *)a.buf + b * a.buf_bs + (int64_t)r0 * L2;
     const Tw<T> *twb = (const Tw<T> *)a.twb;
     const int tot = a.rows * L2;
@@ -271,6 +272,13 @@ __global__ void __launch_bounds__(kThreads) k_row(RowArgs a)
     for (int e = threadIdx.x; e < rw * L2; e += kThreads) buf[e] = conjg(s[e]);
 }
 
+template <typename T, int EPT>
+__global__ void __launch_bounds__(kThreads) k_row(RowArgs a)
+{
+    extern __shared__ char smem_raw[];
+    row_body<T, EPT>(a, blockIdx.x, blockIdx.y, reinterpret_cast<cx<T> *>(smem_raw));
+}
+
 // ---------------------------------------------------------------- resident run
 // Whole run of one state in one workgroup: the transform (1-D of length L,
 // or 2-D n1 x n2) and every step stay in LDS.
@@ -286,14 +294,12 @@ __device__ __forceinline__ void res_fft(cx<T> *s, const ResArgs &a)
 }
 
 template <typename T, int EPT>
-__global__ void __launch_bounds__(kThreads) k_resident(ResArgs a)
+__device__ void resident_body(const ResArgs &a, int64_t b, cx<T> *s)
 {
-    extern __shared__ char smem_raw[];
-    cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
-    const int64_t b = blockIdx.x;
     const int L = (int)a.L;
     const int N = (int)a.N;
     cx<T> *u = (cx<T> *)a.u + b * a.u_bs;
+    if (a.steps <= 0) return;
     const double *vb = a.v + b * a.v_bs;
     const double *B = a.bhat;
 
@@ -369,6 +375,64 @@ __global__ void __launch_bounds__(kThreads) k_resident(ResArgs a)
     }
 }
 
+template <typename T, int EPT>
+__global__ void __launch_bounds__(kThreads) k_resident(ResArgs a)
+{
+    extern __shared__ char smem_raw[];
+    resident_body<T, EPT>(a, blockIdx.x, reinterpret_cast<cx<T> *>(smem_raw));
+}
+
+// ---------------------------------------------------------------- batches of unrelated problems
+// One launch advances pass g of every two-pass problem of a batch.  Problem i
+// owns global blocks [start[i], start[i+1]) of the launch (column tiles or
+// row blocks); its role at pass g follows its schedule:
+//   smooth N:  g = 0 first, odd g row, other g potential P^2, last g last;
+//   chirp-z:   g = 0 first, g = 1, 3 mod 4 row (spectrum, conjugate spectrum),
+//              g = 2 mod 4 kinetic, g = 0 mod 4 potential, last g last.
+__device__ __forceinline__ int find_problem(const int *start, int ninst, int bid)
+{
+    int lo = 0, hi = ninst;  // start[lo] <= bid < start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (start[mid] <= bid) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T, int EPT>
+__global__ void __launch_bounds__(kThreads) k_col_multi(const BatchDesc *d, const int *start, int ninst, int64_t g)
+{
+    extern __shared__ char smem_raw[];
+    const int i = find_problem(start, ninst, blockIdx.x);
+    const BatchDesc &p = d[i];
+    if (g >= p.npass || (g & 1)) return;
+    int role;
+    if (g == 0) role = 0;
+    else if (g == p.npass - 1) role = 3;
+    else if (p.bluestein && (g % 4) == 2) role = 2;
+    else role = 1;
+    col_body<T, EPT>(p.col[role], blockIdx.x - start[i], 0, reinterpret_cast<cx<T> *>(smem_raw));
+}
+
+template <typename T, int EPT>
+__global__ void __launch_bounds__(kThreads) k_row_multi(const BatchDesc *d, const int *start, int ninst, int64_t g)
+{
+    extern __shared__ char smem_raw[];
+    const int i = find_problem(start, ninst, blockIdx.x);
+    const BatchDesc &p = d[i];
+    if (g >= p.npass || !(g & 1)) return;
+    const int role = (p.bluestein && (g % 4) == 3) ? 1 : 0;
+    row_body<T, EPT>(p.row[role], blockIdx.x - start[i], 0, reinterpret_cast<cx<T> *>(smem_raw));
+}
+
+template <typename T, int EPT>
+__global__ void __launch_bounds__(kThreads) k_resident_multi(const ResArgs *d)
+{
+    extern __shared__ char smem_raw[];
+    resident_body<T, EPT>(d[blockIdx.x], 0, reinterpret_cast<cx<T> *>(smem_raw));
+}
+
 // single forward DFT of one sequence in complex double (plan-time helper)
 __global__ void __launch_bounds__(kThreads) k_fft_single(Radices ra, const void *twa, void *buf)
 {
@@ -438,6 +502,19 @@ __global__ void k_ktab(double *dst, int64_t count, double kin, double scale)
     }
 }
 
+// one kinetic table per problem of a batch (blockIdx.y)
+__global__ void k_ktab_multi(const KtabDesc *d)
+{
+    const KtabDesc q = d[blockIdx.y];
+    for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < q.count;
+         m += (int64_t)gridDim.x * blockDim.x) {
+        double c, s;
+        expm_i(q.kin * (double)m, c, s);
+        q.dst[2 * m] = c * q.scale;
+        q.dst[2 * m + 1] = s * q.scale;
+    }
+}
+
 __global__ void k_reduce_batch(double *dst, const double *src, int64_t N, int batch)
 {
     for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N;
@@ -450,6 +527,20 @@ __global__ void k_reduce_batch(double *dst, const double *src, int64_t N, int ba
 
 // ---------------------------------------------------------------- launchers
 static inline size_t esize(int prec) { return prec == LT_C128 ? 16 : 8; }
+
+// launch with the kernel class's timing events when timing is enabled
+template <typename K, typename... A>
+static int timed_launch(int kind, K kernel, dim3 grid, dim3 block, size_t lds, void *stream, A... args)
+{
+    void *e0 = nullptr, *e1 = nullptr;
+    timing_events(kind, &e0, &e1);
+    if (e0)
+        hipExtLaunchKernelGGL(kernel, grid, block, lds, (hipStream_t)stream, (hipEvent_t)e0, (hipEvent_t)e1, 0,
+                              args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, (hipStream_t)stream, args...);
+    return (int)hipGetLastError();
+}
 
 static int grid1d(int64_t n)
 {
@@ -469,13 +560,18 @@ int kernels_init()
     hipFuncSetAttribute((const void *)k_row<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_resident<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_resident<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_col_multi<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_col_multi<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_row_multi<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_row_multi<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_resident_multi<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_resident_multi<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipGetLastError();
     return 0;
 }
 
 int launch_col(int prec, const Sched &s, const ColArgs &a, int batch, void *stream)
 {
-    KTimer timer(LT_KIND_COLUMN, stream);
     if (s.col_var > 0 && !a.adjoint) {
         const int r = launch_col_fast(prec, s.col_var, a, batch, stream);
         if (r >= 0) return r;
@@ -484,15 +580,12 @@ int launch_col(int prec, const Sched &s, const ColArgs &a, int batch, void *stre
     const size_t lds = (size_t)a.L1 * a.C * nvec * esize(prec);
     dim3 grid(a.ntiles, batch);
     if (prec == LT_C128)
-        hipLaunchKernelGGL((k_col<double, 16>), grid, dim3(kThreads), lds, (hipStream_t)stream, a);
-    else
-        hipLaunchKernelGGL((k_col<float, 32>), grid, dim3(kThreads), lds, (hipStream_t)stream, a);
-    return (int)hipGetLastError();
+        return timed_launch(LT_KIND_COLUMN, k_col<double, 16>, grid, dim3(kThreads), lds, stream, a);
+    return timed_launch(LT_KIND_COLUMN, k_col<float, 32>, grid, dim3(kThreads), lds, stream, a);
 }
 
 int launch_row(int prec, const Sched &s, const RowArgs &a, int batch, void *stream)
 {
-    KTimer timer(LT_KIND_ROW, stream);
     if (s.row_var > 0 && !a.fft_only) {
         const int r = launch_row_fast(prec, s.row_var, a, batch, stream);
         if (r >= 0) return r;
@@ -500,24 +593,55 @@ int launch_row(int prec, const Sched &s, const RowArgs &a, int batch, void *stre
     const size_t lds = (size_t)a.rows * a.L2 * esize(prec);
     dim3 grid(a.nblk, batch);
     if (prec == LT_C128)
-        hipLaunchKernelGGL((k_row<double, 16>), grid, dim3(kThreads), lds, (hipStream_t)stream, a);
-    else
-        hipLaunchKernelGGL((k_row<float, 32>), grid, dim3(kThreads), lds, (hipStream_t)stream, a);
-    return (int)hipGetLastError();
+        return timed_launch(LT_KIND_ROW, k_row<double, 16>, grid, dim3(kThreads), lds, stream, a);
+    return timed_launch(LT_KIND_ROW, k_row<float, 32>, grid, dim3(kThreads), lds, stream, a);
 }
 
 int launch_resident(int prec, const Sched &s, const ResArgs &a, int batch, void *stream)
 {
     const size_t lds = (size_t)a.L * esize(prec);
-    KTimer timer(LT_KIND_RESIDENT, stream);
-    if (prec == LT_C128)
-        hipLaunchKernelGGL((k_resident<double, 16>), dim3(batch), dim3(kThreads), lds,
-                           (hipStream_t)stream, a);
-    else
-        hipLaunchKernelGGL((k_resident<float, 32>), dim3(batch), dim3(kThreads), lds,
-                           (hipStream_t)stream, a);
     (void)s;
+    if (prec == LT_C128)
+        return timed_launch(LT_KIND_RESIDENT, k_resident<double, 16>, dim3(batch), dim3(kThreads), lds, stream, a);
+    return timed_launch(LT_KIND_RESIDENT, k_resident<float, 32>, dim3(batch), dim3(kThreads), lds, stream, a);
+}
+
+int launch_col_multi(int prec, const BatchDesc *d, const int *start, int ninst, int nblocks, int64_t g,
+                     size_t lds, void *stream)
+{
+    if (prec == LT_C128)
+        return timed_launch(LT_KIND_COLUMN, k_col_multi<double, 16>, dim3(nblocks), dim3(kThreads), lds, stream,
+                            d, start, ninst, g);
+    return timed_launch(LT_KIND_COLUMN, k_col_multi<float, 32>, dim3(nblocks), dim3(kThreads), lds, stream, d,
+                        start, ninst, g);
+}
+
+int launch_row_multi(int prec, const BatchDesc *d, const int *start, int ninst, int nblocks, int64_t g,
+                     size_t lds, void *stream)
+{
+    if (prec == LT_C128)
+        return timed_launch(LT_KIND_ROW, k_row_multi<double, 16>, dim3(nblocks), dim3(kThreads), lds, stream,
+                            d, start, ninst, g);
+    return timed_launch(LT_KIND_ROW, k_row_multi<float, 32>, dim3(nblocks), dim3(kThreads), lds, stream, d,
+                        start, ninst, g);
+}
+
+int launch_ktab_multi(const KtabDesc *d, int count, int64_t max_len, void *stream)
+{
+    if (count <= 0) return 0;
+    int gx = grid1d(max_len);
+    if (gx > 64) gx = 64;
+    hipLaunchKernelGGL(k_ktab_multi, dim3(gx, count), dim3(256), 0, (hipStream_t)stream, d);
     return (int)hipGetLastError();
+}
+
+int launch_resident_multi(int prec, const ResArgs *d, int ninst, size_t lds, void *stream)
+{
+    if (prec == LT_C128)
+        return timed_launch(LT_KIND_RESIDENT, k_resident_multi<double, 16>, dim3(ninst), dim3(kThreads), lds,
+                            stream, d);
+    return timed_launch(LT_KIND_RESIDENT, k_resident_multi<float, 32>, dim3(ninst), dim3(kThreads), lds, stream,
+                        d);
 }
 
 int launch_fft_single(const Radices &ra, const void *twa, void *buf, int64_t L, void *stream)

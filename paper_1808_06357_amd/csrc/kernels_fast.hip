@@ -14,6 +14,7 @@
 //  * column tiles are remapped so that neighbouring tiles, which share cache
 //    lines, run on the same XCD (workgroups are dealt round-robin to the 8
 //    XCDs, each with its own L2).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -25,11 +26,39 @@ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 
+// table entry as a double-precision complex (hi + lo for the float tables)
+__device__ __forceinline__ cx<double> tw_d(const Tw<double> &t) { return t.w; }
+__device__ __forceinline__ cx<double> tw_d(const Tw<float> &t)
+{
+    return {(double)t.hi.x + (double)t.lo.x, (double)t.hi.y + (double)t.lo.y};
+}
+
+// w^r for r = 0..R-1 in double by a balanced product tree
+// (w^r = w^(r/2) w^(r - r/2)): at most log2(R) rounding steps deep
+template <int R>
+__device__ __forceinline__ void powers(double wr, double wi, double (&pr)[R], double (&pi)[R])
+{
+    pr[0] = 1.0;
+    pi[0] = 0.0;
+    if constexpr (R > 1) {
+        pr[1] = wr;
+        pi[1] = wi;
+    }
+#pragma unroll
+    for (int r = 2; r < R; ++r) {
+        const int a = r / 2, b = r - r / 2;
+        pr[r] = pr[a] * pr[b] - pi[a] * pi[b];
+        pi[r] = pr[a] * pi[b] + pi[a] * pr[b];
+    }
+}
+
 // Stockham DFT over a tile of NT*E elements = SEQ sequences of length L = R^NS.
 // COLS: element e of sequence q at e*SEQ + q (interleaved columns);
 // otherwise at q*L + e (contiguous rows).  Butterfly bf = tid + j*NT handles
 // sequence q, index t; v[j][r] holds element t + r*L/R on entry (stage-1
-// inputs) and on exit (last-stage outputs).
+// inputs) and on exit (last-stage outputs).  The stage twiddles
+// W_{Ns R}^{(t mod Ns) r} are powers of one base per stage and butterfly; the
+// bases are loaded once (load_bases) and the powers formed in double.
 template <typename T, int R, int NS, int E, int NT, bool COLS>
 struct Fft {
     static constexpr int L = ipow(R, NS);
@@ -37,14 +66,35 @@ struct Fft {
     static constexpr int SEQ = TILE / L;
     static constexpr int J = E / R;
     static constexpr int BPS = L / R;
+    static constexpr int NB = NS > 1 ? NS - 1 : 1;
     static_assert(E % R == 0 && TILE % L == 0, "tile must hold whole sequences");
+
+    struct Bases {
+        double r[NB][J], i[NB][J];
+    };
 
     static __device__ __forceinline__ int q_of(int bf) { return COLS ? bf % SEQ : bf / BPS; }
     static __device__ __forceinline__ int t_of(int bf) { return COLS ? bf / SEQ : bf % BPS; }
     static __device__ __forceinline__ int addr(int q, int e) { return pidx(COLS ? e * SEQ + q : q * L + e); }
 
-    static __device__ __forceinline__ void run(cx<T> (&v)[J][R], cx<T> *s, const Tw<T> *__restrict__ tw,
-                                               bool sync_first)
+    static __device__ __forceinline__ void load_bases(Bases &B, const Tw<T> *__restrict__ tw)
+    {
+        int Ns = 1;
+#pragma unroll
+        for (int st = 1; st < NS; ++st) {
+            Ns *= R;
+            const int twstep = L / (Ns * R);
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int t = t_of(threadIdx.x + j * NT);
+                const cx<double> w = tw_d(tw[(t % Ns) * twstep]);
+                B.r[st - 1][j] = w.x;
+                B.i[st - 1][j] = w.y;
+            }
+        }
+    }
+
+    static __device__ __forceinline__ void run(cx<T> (&v)[J][R], cx<T> *s, const Bases &B, bool sync_first)
     {
 #pragma unroll
         for (int j = 0; j < J; ++j) Dft<T, R>::run(v[j]);
@@ -63,16 +113,16 @@ struct Fft {
             }
             __syncthreads();
             Ns *= R;
-            const int twstep = L / (Ns * R);
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 const int bf = threadIdx.x + j * NT;
                 const int q = q_of(bf), t = t_of(bf);
-                const int jj = t % Ns;
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[j][r] = s[addr(q, t + r * BPS)];
+                double pr[R], pi[R];
+                powers<R>(B.r[st - 1][j], B.i[st - 1][j], pr, pi);
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[j][r] = twmul(v[j][r], tw[jj * r * twstep]);
+                for (int r = 1; r < R; ++r) v[j][r] = cmul_d(v[j][r], pr[r], pi[r]);
                 Dft<T, R>::run(v[j]);
             }
         }
@@ -86,30 +136,27 @@ __device__ __forceinline__ int xcd_tile(int bid, int n)
 }
 
 // W_L^{n2 k} for k = t + r*BPS, r = 0..R-1: base W^{n2 t} and step W^{n2 BPS}
-// from the two-level tables, powers by recurrence in double (error ~1e-15).
+// from the two-level tables, W^{n2 k} = base * step^r with the powers from a
+// product tree, all in double.
 template <int R>
 __device__ __forceinline__ void tw4_series(double (&wr)[R], double (&wi)[R], int n2, int t, int BPS, int L2,
                                            const double *hi, const double *lo)
 {
-    double br, bi, sr, si;
-    {
-        const cx<double> one = {1.0, 0.0};
-        const cx<double> b = tw4mul(one, n2, t, L2, hi, lo);
-        const cx<double> s = tw4mul(one, n2, BPS, L2, hi, lo);
-        br = b.x; bi = b.y; sr = s.x; si = s.y;
-    }
-    wr[0] = br;
-    wi[0] = bi;
+    const cx<double> one = {1.0, 0.0};
+    const cx<double> b = tw4mul(one, n2, t, L2, hi, lo);
+    const cx<double> s = tw4mul(one, n2, BPS, L2, hi, lo);
+    double pr[R], pi[R];
+    powers<R>(s.x, s.y, pr, pi);
 #pragma unroll
-    for (int r = 1; r < R; ++r) {
-        wr[r] = wr[r - 1] * sr - wi[r - 1] * si;
-        wi[r] = wr[r - 1] * si + wi[r - 1] * sr;
+    for (int r = 0; r < R; ++r) {
+        wr[r] = b.x * pr[r] - b.y * pi[r];
+        wi[r] = b.x * pi[r] + b.y * pr[r];
     }
 }
 
 // Steady-state column pass: [inverse column DFT -> point-domain multiplier
 // (and chirp-z mask) -> forward column DFT], in place.
-template <typename T, int R, int NS, int E, int NT, int MINW>
+template <typename T, int R, int NS, int E, int NT, int MINW, int MID>
 __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
 {
     using F = Fft<T, R, NS, E, NT, true>;
@@ -121,7 +168,8 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
     const int64_t b = blockIdx.y;
     const int c0 = tile * C;
     cx<T> *buf = (cx<T> *)a.buf + b * a.buf_bs;
-    const Tw<T> *tw = (const Tw<T> *)a.twa;
+    typename F::Bases B;
+    F::load_bases(B, (const Tw<T> *)a.twa);
     cx<T> v[J][R];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -137,35 +185,43 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
             for (int r = 0; r < R; ++r) v[j][r] = cmul_d(v[j][r], wr[r], wi[r]);
         }
     }
-    F::run(v, s, tw, false);
-    // point-domain multiplier (FP64 sincos or kinetic table) in a plain loop
-    // over the tile held in LDS, away from the unrolled register FFT
-    const double *vb = a.v ? a.v + b * a.v_bs : nullptr;
-    __syncthreads();
+    F::run(v, s, B, false);
+    // point-domain multiplier: the inputs of all of this thread's elements are
+    // loaded in one batch (one exposed latency), then applied element by
+    // element.  The scheduling barriers keep the batch after the DFT and the
+    // FP64 temporaries of different elements apart (register pressure).
+    __builtin_amdgcn_sched_barrier(0);
+    double pin[J][R];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int bf = threadIdx.x + j * NT;
         const int q = F::q_of(bf), t = F::t_of(bf);
 #pragma unroll
-        for (int r = 0; r < R; ++r) s[F::addr(q, t + r * BPS)] = conjg(v[j][r]);
+        for (int r = 0; r < R; ++r) {
+            const int64_t n = (int64_t)(t + r * BPS) * L2 + c0 + q;
+            const bool ok = n < a.Nvalid;
+            if constexpr (MID == 0) pin[j][r] = ok ? a.v[b * a.v_bs + n] : 0.0;
+            else pin[j][r] = ok ? (double)a.s[n] : -1.0;
+        }
     }
-    __syncthreads();
-#pragma unroll 1
-    for (int i = threadIdx.x; i < TILE; i += NT) {
-        const int q = i % C, e = i / C;
-        const int64_t n = (int64_t)e * L2 + c0 + q;
-        const int at = F::addr(q, e);
-        s[at] = n < a.Nvalid ? col_mid(s[at], a, vb, n) : cx<T>{0, 0};
-    }
-    __syncthreads();
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        const int bf = threadIdx.x + j * NT;
-        const int q = F::q_of(bf), t = F::t_of(bf);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[j][r] = s[F::addr(q, t + r * BPS)];
+        for (int r = 0; r < R; ++r) {
+            cx<T> x = conjg(v[j][r]);
+            if constexpr (MID == 0) {
+                const int bf = threadIdx.x + j * NT;
+                const int64_t n = (int64_t)(F::t_of(bf) + r * BPS) * L2 + c0 + F::q_of(bf);
+                x = n < a.Nvalid ? mul_expm_i(x, a.phase * pin[j][r]) : cx<T>{0, 0};
+            } else {
+                const int m = (int)pin[j][r];
+                x = m >= 0 ? cmul_d(x, a.ktab[2 * m], a.ktab[2 * m + 1]) : cx<T>{0, 0};
+            }
+            v[j][r] = x;
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
-    F::run(v, s, tw, true);
+    F::run(v, s, B, true);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int bf = threadIdx.x + j * NT;
@@ -195,7 +251,8 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
     const int r0 = blockIdx.x * RW;
     const int64_t b = blockIdx.y;
     cx<T> *buf = (cx<T> *)a.buf + b * a.buf_bs + (int64_t)r0 * L2;
-    const Tw<T> *tw = (const Tw<T> *)a.twb;
+    typename F::Bases B;
+    F::load_bases(B, (const Tw<T> *)a.twb);
     const int64_t p0 = (int64_t)r0 * L2;
     cx<T> v[J][R];
 #pragma unroll
@@ -205,7 +262,7 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
 #pragma unroll
         for (int r = 0; r < R; ++r) v[j][r] = buf[q * L2 + t + r * BPS];
     }
-    F::run(v, s, tw, false);
+    F::run(v, s, B, false);
     if constexpr (MID == 0) {
         // chirp-z kernel spectrum: one complex-double load per element
 #pragma unroll
@@ -244,7 +301,7 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
             for (int r = 0; r < R; ++r) v[j][r] = s[F::addr(q, t + r * BPS)];
         }
     }
-    F::run(v, s, tw, true);
+    F::run(v, s, B, true);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int bf = threadIdx.x + j * NT;
@@ -270,6 +327,19 @@ struct Geo<2> {
     static constexpr int NT = 512, E = 8, MINW = 4;
 };
 
+template <typename K, typename A>
+int timed(int kind, K kernel, dim3 grid, dim3 block, size_t lds, void *stream, const A &args)
+{
+    void *e0 = nullptr, *e1 = nullptr;
+    timing_events(kind, &e0, &e1);
+    if (e0)
+        hipExtLaunchKernelGGL(kernel, grid, block, lds, (hipStream_t)stream, (hipEvent_t)e0, (hipEvent_t)e1, 0,
+                              args);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, (hipStream_t)stream, args);
+    return (int)hipGetLastError();
+}
+
 template <typename T, int V>
 size_t lds_bytes()
 {
@@ -281,17 +351,20 @@ template <typename T, int V, int R, int NS>
 int col_go(const ColArgs &a, int batch, void *stream)
 {
     constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW;
-    auto k = k_colf<T, R, NS, E, NT, MINW>;
+    // MID 0: potential phase exp(-i phase v) (FP64 sincos); MID 1: kinetic table
+    auto k = a.v ? k_colf<T, R, NS, E, NT, MINW, 0> : k_colf<T, R, NS, E, NT, MINW, 1>;
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipFuncSetAttribute((const void *)k_colf<T, R, NS, E, NT, MINW, 0>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipFuncSetAttribute((const void *)k_colf<T, R, NS, E, NT, MINW, 1>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
     constexpr int C = NT * E / ipow(R, NS);
     dim3 grid(a.L2 / C, batch);
     const size_t lds = lds_bytes<T, V>();
-    hipLaunchKernelGGL(k, grid, dim3(NT), lds, (hipStream_t)stream, a);
-    return (int)hipGetLastError();
+    return timed(LT_KIND_COLUMN, k, grid, dim3(NT), lds, stream, a);
 }
 
 template <typename T, int V, int R, int NS>
@@ -310,8 +383,7 @@ int row_go(const RowArgs &a, int batch, void *stream)
     constexpr int RW = NT * E / ipow(R, NS);
     dim3 grid(a.L1 / RW, batch);
     const size_t lds = lds_bytes<T, V>();
-    hipLaunchKernelGGL(k, grid, dim3(NT), lds, (hipStream_t)stream, a);
-    return (int)hipGetLastError();
+    return timed(LT_KIND_ROW, k, grid, dim3(NT), lds, stream, a);
 }
 
 template <typename T, int V, int R, int NS, bool COL, class A>
@@ -365,7 +437,7 @@ int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *st
     // steady-state passes only: the first / last / checkpoint passes of a run
     // and the adjoint passes take the general kernel
     const bool steady = a.pre_inv && a.post_fwd && !a.in && !a.out && !a.ck && !a.chirp &&
-                        a.scale == 1.0 && !a.adjoint;
+                        a.scale == 1.0 && !a.adjoint && ((a.v != nullptr) != (a.ktab != nullptr));
     if (!steady || !fast_col_fits(prec, variant, a.L1, a.L2, a.C)) return -1;
     if (prec == LT_C128)
         return variant == 1 ? go<double, 1, true>(a.L1, a, batch, stream) : go<double, 2, true>(a.L1, a, batch, stream);

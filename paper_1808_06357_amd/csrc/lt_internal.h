@@ -117,12 +117,35 @@ struct ResArgs {
     int64_t batch;
 };
 
+// One two-pass problem of a batch: its column / row arguments per role and
+// the number of passes of its schedule.
+struct BatchDesc {
+    ColArgs col[4];   // 0 first, 1 potential P^2, 2 kinetic (chirp-z), 3 last
+    RowArgs row[2];   // 0 spectral multiplier, 1 conjugated spectrum (chirp-z)
+    int64_t npass;    // 2m + 1 (smooth N) or 4m + 1 (chirp-z)
+    int bluestein;
+    int pad;
+};
+
+// kinetic table of one problem of a batch: dst[m] = exp(-i kin m) * scale, m < count
+struct KtabDesc {
+    double *dst;
+    int64_t count;
+    double kin, scale;
+};
+
 // ---------------------------------------------------------------- launchers (kernels.hip)
 // All launchers return 0 or a hipError_t value; they enqueue on `stream`.
 int launch_col(int prec, const Sched &s, const ColArgs &a, int batch, void *stream);
 int launch_row(int prec, const Sched &s, const RowArgs &a, int batch, void *stream);
 int launch_resident(int prec, const Sched &s, const ResArgs &a, int batch, void *stream);
 int launch_fft_single(const Radices &ra, const void *twa_c128, void *buf, int64_t L, void *stream);
+int launch_col_multi(int prec, const BatchDesc *d, const int *start, int ninst, int nblocks, int64_t g,
+                     size_t lds, void *stream);
+int launch_row_multi(int prec, const BatchDesc *d, const int *start, int ninst, int nblocks, int64_t g,
+                     size_t lds, void *stream);
+int launch_resident_multi(int prec, const ResArgs *d, int ninst, size_t lds, void *stream);
+int launch_ktab_multi(const KtabDesc *d, int count, int64_t max_len, void *stream);
 int launch_permute_c128(void *dst, const void *src_nat, int64_t L, int L1, int L2, int transposed,
                         double scale, void *stream);
 int launch_unpermute_c128(void *dst_nat, const void *src, int64_t L, int L1, int L2,
@@ -137,19 +160,11 @@ bool fast_col_fits(int prec, int variant, int L1, int L2, int C);
 bool fast_row_fits(int prec, int variant, int L1, int L2, int rows);
 int kernels_init();  // raise dynamic LDS limits once
 
-// Event bracket around one launch when timing is enabled (timing.cpp).
-class KTimer {
-  public:
-    KTimer(int kind, void *stream);
-    ~KTimer();
-    KTimer(const KTimer &) = delete;
-    KTimer &operator=(const KTimer &) = delete;
-
-  private:
-    int kind_;
-    void *stream_;
-    void *a_ = nullptr;
-};
+// Timing of one launch when timing is enabled (timing.cpp): a start / stop
+// event pair registered under a kernel class, to be passed to
+// hipExtLaunchKernelGGL so that the dispatch itself stamps them.  Both are
+// null when timing is off.
+void timing_events(int kind, void **start, void **stop);
 
 }  // namespace lt
 

@@ -8,6 +8,7 @@
 // the first vector that reaches it.  If the ball does not reach every key,
 // the next shell is visited, so the visiting order stays (norm, lex).
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -79,11 +80,16 @@ struct Shell {
     int d;
     int64_t lo, hi;
     std::vector<int32_t> h;
-    template <class F> void walk(F &&f) { h.assign(d, 0); rec(0, 0, f); }
+    int64_t limit = INT64_MAX, seen = 0;  // the walk stops after `limit` vectors
+    template <class F> void walk(F &&f) { h.assign(d, 0); seen = 0; rec(0, 0, f); }
     template <class F> void rec(int j, int64_t used, F &f)
     {
+        if (seen >= limit) return;
         if (j == d) {
-            if (used > lo) f(h.data(), used);
+            if (used > lo) {
+                f(h.data(), used);
+                ++seen;
+            }
             return;
         }
         int64_t rem = hi - used;
@@ -133,9 +139,15 @@ lt_status plan_index_set(lt_plan &p)
     int64_t hi = (int64_t)std::floor(std::exp(2.0 * lg / d));
     if (hi < 1) hi = 1;
     int64_t lo = -1;
+    // A lattice whose dual has short vectors leaves keys uncovered until the
+    // ball is far larger than N; bound the enumeration instead of exhausting
+    // host memory.
+    const int64_t budget = std::max<int64_t>(int64_t(1) << 26, 64 * N);
+    int64_t enumerated = 0;
     while (count < N) {
         // count the shell per norm, then place vectors in (norm, lex) order
         Shell sh{d, lo, hi, {}};
+        sh.limit = budget - enumerated + 1;
         std::vector<int64_t> per((size_t)(hi - (lo < 0 ? 0 : lo) + 2), 0);
         const int64_t base = lo < 0 ? 0 : lo + 1;
         int64_t total = 0;
@@ -145,6 +157,13 @@ lt_status plan_index_set(lt_plan &p)
             ++total;
             for (int j = 0; j < d; ++j) amax = std::max(amax, std::abs(h[j]));
         });
+        enumerated += total;
+        if (enumerated > budget)
+            return fail(LT_E_UNSUPPORTED,
+                        "minimal-l2 completion needs more than " + std::to_string(budget) +
+                            " frequency vectors (" + std::to_string(N - count) +
+                            " keys still uncovered at squared radius " + std::to_string(lo < 0 ? 0 : lo) +
+                            "): the generating vector has short dual vectors; choose a better lattice");
         std::vector<int64_t> off(per.size() + 1, 0);
         for (size_t t = 0; t < per.size(); ++t) off[t + 1] = off[t] + per[t];
         std::vector<int64_t> fill(off.begin(), off.end() - 1);

@@ -1,6 +1,8 @@
 // Per-kernel-class HIP-event timing of the launches the library makes.  When
-// enabled, every launch is bracketed by two events recorded on the launch
-// stream; lt_timing_summary waits for them and sums the elapsed times.
+// enabled, every launch gets a start / stop event pair that the kernel
+// dispatch itself stamps (hipExtLaunchKernelGGL), so the elapsed time is the
+// kernel's own duration without extra marker packets in the stream;
+// lt_timing_summary waits for them and sums the elapsed times.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -32,22 +34,16 @@ hipEvent_t take()
 }
 }  // namespace
 
-KTimer::KTimer(int kind, void *stream) : kind_(kind), stream_(stream)
+void timing_events(int kind, void **start, void **stop)
 {
+    *start = *stop = nullptr;
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return;
-    a_ = take();
-    if (a_) hipEventRecord((hipEvent_t)a_, (hipStream_t)stream_);
-}
-
-KTimer::~KTimer()
-{
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_on || !a_) return;
-    hipEvent_t b = take();
-    if (!b) return;
-    hipEventRecord(b, (hipStream_t)stream_);
-    g_recs.push_back({kind_, (hipEvent_t)a_, b});
+    hipEvent_t a = take(), b = take();
+    if (!a || !b) return;
+    g_recs.push_back({kind, a, b});
+    *start = a;
+    *stop = b;
 }
 
 }  // namespace lt

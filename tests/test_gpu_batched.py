@@ -1,0 +1,169 @@
+"""strang_run_batched: unrelated problems (own lattice, potential, state,
+gamma, dt and step count) advanced in shared launches, against the FP64
+oracle per problem and against single-problem runs, through the C-ABI."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-11, "c64": 1e-4}
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "config2_oracle_samples.npz")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def korobov_problem(N, d, seed, steps, gamma, dt):
+    g = np.random.default_rng(seed)
+    z = W.korobov(N, d, g)
+    Z, n = z.reshape(1, -1), np.array([N])
+    num = W.point_numerators(Z, n)
+    return dict(Z=Z, n=n, I=None, v=W.cosine_series(d, 16, g).at(num, N), u0=W.seeded_packet(num, N, g),
+                gamma=gamma, dt=dt, steps=steps)
+
+
+def rank2_problem(n1, n2, d, seed, steps, gamma, dt):
+    H = W.hyperbolic_cross(d, 1)
+    Z = W.cbc_rank2(H, n1, n2, np.random.default_rng(n1))
+    n = np.array([n1, n2])
+    num = W.point_numerators(Z, n)
+    g = np.random.default_rng(seed)
+    return dict(Z=Z, n=n, I=H, v=W.cosine_series(d, 8, g).at(num, n1 * n2),
+                u0=W.seeded_packet(num, n1 * n2, g), gamma=gamma, dt=dt, steps=steps)
+
+
+def mixed_problems():
+    """One-workgroup problems (smooth 2048, chirp-z 1031, rank-2 64 x 16) and
+    two-pass ones (smooth 15360, 2^16, chirp-z 8191 and 65521, rank-2
+    1024 x 64), with uneven step counts, a zero-step and a one-step problem."""
+    return [
+        korobov_problem(2048, 3, 1, 13, 0.07, 2e-3),
+        korobov_problem(15360, 4, 2, 9, 0.05, 3e-3),
+        korobov_problem(1031, 2, 3, 17, 0.1, 1e-2),
+        korobov_problem(8191, 5, 4, 6, 0.03, 4e-3),
+        korobov_problem(65521, 3, 5, 11, 0.12, 2e-3),
+        korobov_problem(1 << 16, 4, 6, 0, 0.05, 2e-3),
+        rank2_problem(64, 16, 4, 7, 8, 0.05, 2e-3),
+        korobov_problem(4099, 3, 8, 1, 0.2, 5e-3),
+        rank2_problem(1024, 64, 5, 9, 5, 0.08, 2e-3),
+    ]
+
+
+def run_batched(lt, plans, probs, prec):
+    import torch
+    dtype = torch.complex128 if prec == "c128" else torch.complex64
+    us = [torch.tensor(p["u0"], dtype=dtype, device="cuda") for p in probs]
+    vs = [torch.tensor(p["v"], dtype=torch.float64, device="cuda") for p in probs]
+    lt.strang_run_batched(plans, vs, us, [p["gamma"] for p in probs], [p["dt"] for p in probs],
+                          [p["steps"] for p in probs])
+    torch.cuda.synchronize()
+    return [u.cpu().numpy().astype(np.complex128) for u in us]
+
+
+@pytest.fixture(scope="module")
+def mixed(lt):
+    probs = mixed_problems()
+    plans = [lt.lattice_plan(p["Z"], p["n"], p["I"]) for p in probs]
+    refs = []
+    for p in probs:
+        _, s, _ = O.index_set(p["Z"], p["n"], p["I"])
+        refs.append(O.strang_run(p["n"], s, p["v"], p["u0"], p["gamma"], p["dt"], p["steps"]))
+    kinds = [(pl.info["passes"], pl.info["bluestein"]) for pl in plans]
+    assert (1, 0) in kinds and (1, 1) in kinds and (2, 0) in kinds and (2, 1) in kinds
+    return probs, plans, refs
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_mixed_batch_against_oracle(lt, mixed, prec):
+    probs, plans, refs = mixed
+    got = run_batched(lt, plans, probs, prec)
+    for i, (g, r, p) in enumerate(zip(got, refs, probs)):
+        e = rel(g, r)
+        print(f"  {prec} problem {i}: N={len(r)} steps={p['steps']} passes={plans[i].info['passes']} "
+              f"bluestein={plans[i].info['bluestein']} rel_l2={e:.2e}", flush=True)
+        if p["steps"] == 0:
+            assert np.array_equal(g, np.asarray(p["u0"]).astype(np.complex64 if prec == "c64" else np.complex128))
+        assert e < TOL[prec], (i, e)
+
+
+def test_batch_equals_single_runs(lt, mixed):
+    """Each problem of the batch gives what strang_run gives on its own with the
+    same (general) kernels."""
+    import torch
+    probs, plans, _ = mixed
+    got = run_batched(lt, plans, probs, "c128")
+    for i, (pl, p) in enumerate(zip(plans, probs)):
+        lt.lattice_plan_set_kernels(pl, lt.LT_C128, 0, 0)
+        u = torch.tensor(p["u0"], dtype=torch.complex128, device="cuda")
+        v = torch.tensor(p["v"], dtype=torch.float64, device="cuda")
+        lt.strang_run(pl, v, u, p["gamma"], p["dt"], p["steps"])
+        assert rel(got[i], u.cpu().numpy()) < 1e-14, i
+
+
+def test_single_problem_and_empty_batch(lt, mixed):
+    probs, plans, refs = mixed
+    assert lt.strang_run_batched([], [], [], [], [], []) == []
+    for i in (0, 4):
+        got = run_batched(lt, [plans[i]], [probs[i]], "c128")[0]
+        assert rel(got, refs[i]) < TOL["c128"]
+
+
+def test_batched_argument_errors(lt, mixed):
+    import torch
+    probs, plans, _ = mixed
+    u = torch.zeros(plans[0].N, dtype=torch.complex128, device="cuda")
+    v = torch.zeros(plans[0].N, dtype=torch.float64, device="cuda")
+    with pytest.raises(Exception):
+        lt.strang_run_batched([plans[0]], [v], [u], [-1.0], [1e-3], [3])   # gamma <= 0
+    with pytest.raises(Exception):
+        lt.strang_run_batched([plans[0]], [v], [u], [0.1], [1e-3], [-1])   # negative steps
+    with pytest.raises(Exception):
+        lt.strang_run_batched([plans[0]], [v], [u[:-1]], [0.1], [1e-3], [3])  # wrong length
+
+
+@pytest.fixture(scope="module")
+def config2(lt):
+    gold = np.load(GOLD)
+    insts = W.config2()
+    plans = [lt.lattice_plan(c.Z, c.n, c.I) for c in insts]
+    return insts, plans, gold
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_config2_full_batch(lt, config2, prec):
+    """All 256 problems, 200 steps, in the launch configuration the benchmark
+    times: the oracle's states at stored sample points of six problems, and the
+    norm of every problem (the scheme is unitary)."""
+    insts, plans, gold = config2
+    probs = [dict(u0=c.u0, v=c.v, gamma=c.gamma, dt=c.dt, steps=c.steps) for c in insts]
+    got = run_batched(lt, plans, probs, prec)
+    worst = 0.0
+    for i in gold["instances"]:
+        e = rel(got[i][gold[f"idx_{i}"]], gold[f"u_{i}"])
+        worst = max(worst, e)
+        print(f"  {prec} problem {i}: d={insts[i].d} N={insts[i].N} sampled rel_l2={e:.2e}", flush=True)
+        assert e < TOL[prec], (i, e)
+        assert abs(np.mean(np.abs(got[i]) ** 2) - float(gold[f"norm2_{i}"])) < 2 * TOL[prec]
+    for i, (g, c) in enumerate(zip(got, insts)):
+        n0 = np.mean(np.abs(c.u0) ** 2)
+        assert abs(np.mean(np.abs(g) ** 2) - n0) < 2 * TOL[prec] * n0, i
+
+
+def test_config2_reversible_c128(lt, config2):
+    """200 steps with dt, then 200 with -dt, batched: every problem returns to u0."""
+    import torch
+    insts, plans, _ = config2
+    us = [torch.tensor(c.u0, dtype=torch.complex128, device="cuda") for c in insts]
+    vs = [torch.tensor(c.v, dtype=torch.float64, device="cuda") for c in insts]
+    g = [c.gamma for c in insts]
+    st = [c.steps for c in insts]
+    lt.strang_run_batched(plans, vs, us, g, [c.dt for c in insts], st)
+    lt.strang_run_batched(plans, vs, us, g, [-c.dt for c in insts], st)
+    for u, c in zip(us, insts):
+        assert rel(u.cpu().numpy(), c.u0) < 1e-11

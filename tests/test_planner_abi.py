@@ -104,7 +104,7 @@ def test_schedules():
     c = W.config0()
     p = C.lattice_plan(c.Z, c.n, c.I)
     assert p.info["bluestein"] == 1 and p.info["passes"] == 1 and p.info["fft_len"] >= 2 * 1031 - 1
-    p = C.lattice_plan(np.array([[1, 3]]), np.array([1 << 16]))
+    p = C.lattice_plan(np.array([[1, 253]]), np.array([1 << 16]))
     assert p.info["bluestein"] == 0 and p.info["passes"] == 2
     assert p.info["L1"] * p.info["L2"] == 1 << 16
     p = C.lattice_plan(np.array([[1, 5, 7], [0, 1, 3]]), np.array([12, 4]))
@@ -113,10 +113,50 @@ def test_schedules():
     small = C.strang_workspace_size(p, C.LT_C128, 2, True)
     assert 0 < small <= 4096
     assert C.strang_adjoint_workspace_size(p, C.LT_C128, 2, True) > small
-    c1 = C.lattice_plan(np.array([[1, 3]]), np.array([65521]))
+    c1 = C.lattice_plan(np.array([[1, 253]]), np.array([65521]))
     assert C.strang_workspace_size(c1, C.LT_C64, 3, True) >= 3 * c1.info["fft_len"] * 8
     # kernel selection is host state: set / get without a GPU
     C.lattice_plan_set_kernels(c1, C.LT_C64, 2, 0)
     assert C.lattice_plan_get_kernels(c1, C.LT_C64) == (2, 0)
     with pytest.raises(C.LatticeError):
         C.lattice_plan_set_kernels(c1, C.LT_C64, 3, 0)
+
+
+def test_plan_poor_lattice_fails_within_budget():
+    """z = (1, ..., 1): keys are coordinate sums, so minimal-l2 representatives
+    of far keys lie far out; the planner stops at its enumeration budget with
+    a clear error instead of exhausting host memory."""
+    with pytest.raises(C.LatticeError) as e:
+        C.lattice_plan(np.ones((1, 6), dtype=np.int64), np.array([200003]))
+    assert e.value.status == "LT_E_UNSUPPORTED"
+    assert "short dual vectors" in str(e.value)
+
+
+def test_batched_argument_errors_on_host():
+    p = C.lattice_plan(np.array([[1, 34]]), np.array([55]))
+    arr = (ctypes.c_void_p * 1)(p.handle)
+    assert C.lib.strang_run_batched(-1, None, 1, None, None, None, None, None, None, 0, None) == 1
+    assert C.lib.strang_run_batched(1, None, 1, None, None, None, None, None, None, 0, None) == 1
+    assert C.lib.strang_run_batched(0, None, 1, None, None, None, None, None, None, 0, None) == 0
+    g = (ctypes.c_double * 1)(-0.1)
+    dt = (ctypes.c_double * 1)(0.01)
+    st = (ctypes.c_int64 * 1)(3)
+    nul = (ctypes.c_void_p * 1)(None)
+    assert C.lib.strang_run_batched(1, arr, 1, nul, nul, g, dt, st, None, 0, None) == 1  # gamma <= 0
+    g[0] = 0.1
+    assert C.lib.strang_run_batched(1, arr, 1, nul, nul, g, dt, st, None, 0, None) == 1  # NULL u, v
+    size = ctypes.c_size_t()
+    assert C.lib.strang_batched_workspace_size(1, arr, 1, ctypes.byref(size)) == 0 and size.value > 0
+
+
+@pytest.mark.slow
+def test_config2_lattices_bitexact_on_golden_instances():
+    """Planner bin maps of the batched workload's sampled problems (best-of-8
+    Korobov lattices, minimal-l2 full sets) equal the oracle's."""
+    import os
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "config2_oracle_samples.npz"))
+    sel = [int(i) for i in gold["instances"]]
+    shapes = W.config2_shapes()
+    insts = W.config2(shapes=shapes[: max(sel) + 1])
+    for i in sel:
+        _planner_matches_oracle(insts[i].Z, insts[i].n)

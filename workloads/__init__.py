@@ -147,6 +147,57 @@ def korobov(N: int, d: int, g: np.random.Generator) -> np.ndarray:
     return np.asarray(z, dtype=np.int64)
 
 
+def l2_ball_radius2(d: int, count: int) -> int:
+    """Smallest R^2 such that {h in Z^d : ||h||^2 <= R^2} holds >= count vectors
+    (counts per squared norm, one coordinate at a time)."""
+    smax = 4
+    while True:
+        c = np.zeros(smax + 1, dtype=np.int64)
+        c[0] = 1
+        for _ in range(d):
+            nxt = c.copy()
+            x = 1
+            while x * x <= smax:
+                nxt[x * x:] += 2 * c[: smax + 1 - x * x]
+                x += 1
+            c = nxt
+        hit = np.nonzero(np.cumsum(c) >= count)[0]
+        if hit.size:
+            return int(hit[0])
+        smax *= 2
+
+
+def l2_ball(d: int, r2: int) -> np.ndarray:
+    """All h in Z^d with ||h||^2 <= r2 (unordered)."""
+    a = math.isqrt(r2)
+    xs = np.arange(-a, a + 1, dtype=np.int64)
+    pts = np.zeros((1, 0), dtype=np.int64)
+    norms = np.zeros(1, dtype=np.int64)
+    for _ in range(d):
+        nn = norms[:, None] + xs[None, :] ** 2
+        i, j = np.nonzero(nn <= r2)
+        pts = np.concatenate([pts[i], xs[j, None]], axis=1)
+        norms = nn[i, j]
+    return pts
+
+
+def korobov_good(N: int, d: int, g: np.random.Generator, candidates: int = 8) -> np.ndarray:
+    """The best of `candidates` seeded Korobov vectors: the one whose keys
+    h.z mod N cover the most distinct values on the l2 ball of about N/2
+    frequencies.  Poor vectors (short dual vectors, e.g. a of small
+    multiplicative order) leave many keys uncovered there, which makes their
+    minimal-l2 completion reach far out and cost a large enumeration."""
+    ball = l2_ball(d, l2_ball_radius2(d, N // 2)).astype(np.float64)  # exact: |h.z| < 2^53
+    best, best_cov = None, -1
+    for _ in range(candidates):
+        z = korobov(N, d, g)
+        keys = np.mod(ball @ z.astype(np.float64), N).astype(np.int64)
+        cov = int(np.count_nonzero(np.bincount(keys, minlength=N)))
+        if cov > best_cov:
+            best, best_cov = z, cov
+    return best
+
+
 # ---------------------------------------------------------------- input functions
 def _cos2pi(num_mod: np.ndarray, N: int) -> np.ndarray:
     return np.cos(2.0 * np.pi * (num_mod % N).astype(np.float64) / N)
@@ -337,14 +388,15 @@ def config2_shapes(count: int = 256):
 
 
 def config2(count: int = 256, steps: int = 200, shapes=None) -> List[Instance]:
-    """Batched complex64: per instance Korobov z, minimal-l2 full index set,
+    """Batched complex64: per instance the best of 8 seeded Korobov vectors
+    (korobov_good), minimal-l2 full index set,
     16-term cosine potential (|h_j| <= 2, a ~ U(-1/2, 1/2)), gamma ~ U(0.02, 0.2),
     seeded packet, dt = 5e-3, 200 steps."""
     shapes = shapes if shapes is not None else config2_shapes(count)
     gz, gv, gu, gs = rng(2, "z"), rng(2, "v"), rng(2, "u0"), rng(2, "hidden_v")
     out = []
     for i, (d, N) in enumerate(shapes):
-        z = korobov(N, d, gz)
+        z = korobov_good(N, d, gz)
         Z = z.reshape(1, -1)
         n = np.array([N], dtype=np.int64)
         num = point_numerators(Z, n)
