@@ -10,7 +10,11 @@ one full strang_run (all 1000 time steps) with the state resident in HBM.
 
 The JSON line also carries the roofline of the dominant kernel (HIP-event
 timing of the library's own launches during the timed region), the complex128
-throughput, the FP64 oracle timed on the host, and accuracy indicators.
+throughput, the FP64 oracle timed on the host, accuracy indicators, and three
+companion workloads: 256 unrelated problems advanced by strang_run_batched in
+complex64 against the same problems run one by one in complex128; the d = 10
+rank-2 lattice 4096 x 256; and a forward run with checkpoints plus its adjoint
+(d = 4, N = 65521, 32 states).
 """
 from __future__ import annotations
 
@@ -32,15 +36,32 @@ def log(msg):
 
 
 def pass_bytes(plan_info, N, m, S):
-    """Algorithmic bytes of every column-pass and row-pass launch of one run
-    (two-pass chirp-z schedule): state read + write once per pass, plus the
-    tables the pass reads."""
+    """Algorithmic HBM bytes of every column-pass and row-pass launch of one
+    run (two-pass chirp-z schedule of length L): each pass reads and writes
+    the state once and reads the tables its step needs -- v (FP64, 8 B per
+    point) for potential steps, the key-norm index (int32, 4 B per key) for
+    the kinetic step, the kernel spectrum (complex double, 16 B per bin) in
+    the row pass."""
     L = plan_info["fft_len"]
     col = [N * S + 8 * N + L * S]                 # first: u, v in; transform out
-    col += [(2 * L + N) * S] * (2 * m - 1)        # merged P^2 and kinetic passes
-    col += [L * S + N * S + 8 * N]                # last: transform in, v, u out
-    row = [3 * L * S] * (2 * m)                   # state in/out + kernel spectrum
+    col += [2 * L * S + 4 * N] * m                # kinetic steps
+    col += [2 * L * S + 8 * N] * (m - 1)          # merged potential steps P^2
+    col += [L * S + 8 * N + N * S]                # last: transform in, v in, u out
+    row = [2 * L * S + 16 * L] * (2 * m)          # state in/out + kernel spectrum
     return col, row
+
+
+def pmc_traffic():
+    """Measured HBM bytes per steady-state column launch (complex64), from the
+    committed counter summary (FETCH_SIZE / WRITE_SIZE scaled by a plain
+    copy's readings); None when absent."""
+    path = os.path.join(ROOT, "profiles", "k_colf_k_rowf_c64_d6_N1048573_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if "column_c64_hbm_bytes_per_launch:" in line:
+            return float(line.split(":")[1])
+    return None
 
 
 def time_runs(lt, torch, plan, v, u, work, inst, K, W):
@@ -68,6 +89,163 @@ def time_runs(lt, torch, plan, v, u, work, inst, K, W):
     lt.lt_timing_enable(False)
     log(f"event-instrumented region: {K} runs in {tb:.3f}s")
     return t1 - t0, kinds, tb
+
+
+def kernel_summary(lt, fn, K):
+    """Per-kernel-class event times of K calls of fn (instrumented region)."""
+    import torch
+    torch.cuda.synchronize()
+    lt.lt_timing_enable(True)
+    for _ in range(K):
+        fn()
+    torch.cuda.synchronize()
+    out = {}
+    for name, kind in (("column", lt.LT_KIND_COLUMN), ("row", lt.LT_KIND_ROW),
+                       ("resident", lt.LT_KIND_RESIDENT)):
+        n, ms = lt.lt_timing_summary(kind)
+        if n:
+            out[name] = {"launches": n // K, "ms_per_call": ms / K, "avg_us": ms / n * 1e3}
+    lt.lt_timing_enable(False)
+    return out
+
+
+def wall(fn, K, W):
+    import torch
+    for _ in range(W):
+        fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(K):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / K
+
+
+def bench_batched(lt, torch, K, W):
+    """256 unrelated problems (d 2..10, N 2^12..2^18, 200 steps each):
+    strang_run_batched in complex64 vs. the single-state complex128 path
+    (strang_run per problem, one after another)."""
+    import numpy as np
+
+    import workloads as W_
+    t = time.perf_counter()
+    insts = W_.config2()
+    plans = [lt.lattice_plan(c.Z, c.n, c.I) for c in insts]
+    log(f"batched: inputs and {len(plans)} plans in {time.perf_counter() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    vs = [torch.tensor(c.v, dtype=torch.float64, device=dev) for c in insts]
+    gam = [c.gamma for c in insts]
+    dts = [c.dt for c in insts]
+    st = [c.steps for c in insts]
+    pt_steps = sum(c.N * c.steps for c in insts)
+    res = {}
+    for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
+        prec = lt.LT_C64 if name == "c64" else lt.LT_C128
+        us = [torch.tensor(c.u0, dtype=dtype, device=dev) for c in insts]
+        work = torch.empty(lt.strang_batched_workspace_size(plans, prec), dtype=torch.uint8, device=dev)
+        run = lambda: lt.strang_run_batched(plans, vs, us, gam, dts, st, work=work)  # noqa: E731
+        sec = wall(run, K, W)
+        res[f"batched_{name}"] = {"value": pt_steps / sec, "ms_per_call": sec * 1e3,
+                                  "kernels": kernel_summary(lt, run, 1)}
+        log(f"batched {name}: {pt_steps / sec:.3e} pt-steps/s, {sec * 1e3:.1f} ms per batch")
+        del us, work
+    # the plain single-state complex128 path over the same problems
+    us = [torch.tensor(c.u0, dtype=torch.complex128, device=dev) for c in insts]
+    wmax = max(lt.strang_workspace_size(p, lt.LT_C128, 1, True) for p in plans)
+    work = torch.empty(wmax, dtype=torch.uint8, device=dev)
+
+    def singles():
+        for p, v, u, c in zip(plans, vs, us, insts):
+            lt.strang_run(p, v, u, c.gamma, c.dt, c.steps, work=work)
+    sec = wall(singles, 1, 1)
+    res["single_c128"] = {"value": pt_steps / sec, "ms_per_call": sec * 1e3}
+    log(f"single-state c128: {pt_steps / sec:.3e} pt-steps/s, {sec * 1e3:.1f} ms")
+    # accuracy of the batched complex64 result against stored FP64 oracle samples
+    gold_path = os.path.join(ROOT, "tests", "golden", "config2_oracle_samples.npz")
+    acc = None
+    if os.path.exists(gold_path):
+        gold = np.load(gold_path)
+        us = [torch.tensor(c.u0, dtype=torch.complex64, device=dev) for c in insts]
+        lt.strang_run_batched(plans, vs, us, gam, dts, st)
+        errs = []
+        for i in gold["instances"]:
+            got = us[int(i)].cpu().numpy().astype(np.complex128)[gold[f"idx_{i}"]]
+            ref = gold[f"u_{i}"]
+            errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+        acc = {"c64_max_sampled_rel_l2_vs_oracle": max(errs), "problems_sampled": len(errs)}
+    Ns = [c.N for c in insts]
+    return {
+        "workload": f"{len(insts)} unrelated rank-1 problems, d in 2..10, N in [{min(Ns)}, {max(Ns)}] "
+                    f"(primes and 7-smooth composites, sum N = {sum(Ns)}), best-of-8 Korobov lattices, "
+                    "minimal-l2 index sets, 16-term cosine potentials, gamma in [0.02, 0.2], dt = 5e-3, "
+                    f"{insts[0].steps} steps each",
+        "unit": "lattice-point-steps/s",
+        "value_c64": res["batched_c64"]["value"],
+        "speedup_c64_batched_vs_single_state_c128": res["batched_c64"]["value"] / res["single_c128"]["value"],
+        **res, "accuracy": acc,
+    }
+
+
+def bench_rank2(lt, torch, K, W):
+    """d = 10 rank-2 lattice n = (4096, 256), 500 steps."""
+    import workloads as W_
+    c = W_.config3()
+    plan = lt.lattice_plan(c.Z, c.n, c.I)
+    dev = torch.device("cuda:0")
+    v = torch.tensor(c.v, dtype=torch.float64, device=dev)
+    out = {"workload": "rank-2 lattice d=10 n=(4096, 256), hyperbolic cross {-1,0,1}^10 + minimal-l2 "
+                       f"completion, gamma=0.05, dt=2e-3, {c.steps} steps per run",
+           "unit": "lattice-point-steps/s"}
+    for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
+        prec = lt.LT_C64 if name == "c64" else lt.LT_C128
+        kernels = lt.lattice_plan_autotune(plan, prec, reps=10)
+        u = torch.tensor(c.u0, dtype=dtype, device=dev)
+        work = torch.empty(lt.strang_workspace_size(plan, prec, 1, True), dtype=torch.uint8, device=dev)
+        run = lambda: lt.strang_run(plan, v, u, c.gamma, c.dt, c.steps, work=work)  # noqa: E731
+        sec = wall(run, K, W)
+        out[name] = {"value": c.N * c.steps / sec, "ms_per_run": sec * 1e3, "kernel_variants": list(kernels),
+                     "kernels": kernel_summary(lt, run, 1)}
+        log(f"rank-2 {name}: {c.N * c.steps / sec:.3e} pt-steps/s, {sec * 1e3:.1f} ms per run")
+    return out
+
+
+def bench_adjoint(lt, torch, K, W):
+    """Forward run with checkpoints every 50 steps plus strang_adjoint: d = 4,
+    N = 65521, 32 states sharing v, 500 steps."""
+    import workloads as W_
+    c = W_.config4()
+    plan = lt.lattice_plan(c.Z, c.n, c.I)
+    dev = torch.device("cuda:0")
+    v = torch.tensor(c.v, dtype=torch.float64, device=dev)
+    B, N, m, every = c.u0.shape[0], c.N, c.steps, c.meta["ckpt_every"]
+    out = {"workload": f"rank-1 d=4 N={N} (prime), {B} states sharing a 64-term cosine potential, "
+                       f"gamma=0.05, dt=2e-3, {m} steps, checkpoints every {every}",
+           "unit": "lattice-point-steps/s (forward + adjoint)"}
+    for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
+        prec = lt.LT_C64 if name == "c64" else lt.LT_C128
+        lt.lattice_plan_autotune(plan, prec, reps=10)
+        u0 = torch.tensor(c.u0, dtype=dtype, device=dev)
+        u = torch.empty_like(u0)
+        ck = torch.empty(lt.num_checkpoints(m, every) * B * N, dtype=dtype, device=dev)
+        tgt = torch.zeros_like(u0)
+        fw = torch.empty(lt.strang_workspace_size(plan, prec, B, True), dtype=torch.uint8, device=dev)
+        aw = torch.empty(lt.strang_adjoint_workspace_size(plan, prec, B, True), dtype=torch.uint8, device=dev)
+
+        def fwd():
+            u.copy_(u0)
+            lt.strang_run(plan, v, u, c.gamma, c.dt, m, ckpt=ck, ckpt_every=every, work=fw)
+        fwd()
+        gT = (2.0 / N) * (u - tgt)
+
+        def adj():
+            lt.strang_adjoint(plan, v, u, gT, c.gamma, c.dt, m, ck, every, work=aw)
+        tf = wall(fwd, K, W)
+        ta = wall(adj, K, W)
+        out[name] = {"value": B * N * m / (tf + ta), "forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3,
+                     "adjoint_kernels": kernel_summary(lt, adj, 1)}
+        log(f"adjoint {name}: fwd {tf * 1e3:.1f} ms, adj {ta * 1e3:.1f} ms, "
+            f"{B * N * m / (tf + ta):.3e} pt-steps/s")
+    return out
 
 
 def cpu_baseline(inst, seconds):
@@ -99,6 +277,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c128", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched, rank-2 and adjoint workloads")
+    ap.add_argument("--only", choices=["batched", "rank2", "adjoint"],
+                    help="run one companion workload alone (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device (counter calibration for the traffic figure)")
     args = ap.parse_args()
@@ -122,6 +304,11 @@ def main():
 
     import paper_1808_06357_amd as lt
     import workloads as W
+
+    extras = {"batched": bench_batched, "rank2": bench_rank2, "adjoint": bench_adjoint}
+    if args.only:
+        print(json.dumps({args.only: extras[args.only](lt, torch, args.steps, args.warmup)}), flush=True)
+        return
 
     t = time.perf_counter()
     inst = W.config1(steps=args.time_steps)
@@ -196,7 +383,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": f"k_{'row' if dom_name == 'row' else 'col'} (c64)",
                      "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom["achieved_GBs"] / HBM_PEAK_GBS if dom["achieved_GBs"] else None,
-                     "traffic": None, "avg_launch_us": dom["avg_us"],
+                     "traffic": pmc_traffic() if dom_name == "column" else None,
+                     "traffic_note": "HBM bytes per steady-state column launch from rocprofv3 FETCH_SIZE x2 + "
+                                     "WRITE_SIZE x1 (factors from a 256 MiB copy)",
+                     "avg_launch_us": dom["avg_us"],
                      "bytes_per_launch": dom["bytes_per_launch"],
                      "instrumented_ms_per_run": head["instrumented_ms_per_run"]},
         "kernels_c64": head["kinds"],
@@ -206,6 +396,10 @@ def main():
     if "c128" in results:
         c = results["c128"]
         out["c128"] = {"value": c["value"], "ms_per_step": c["ms_per_step"], "kernels": c["kinds"]}
+    if not args.no_extra:
+        for name, fn in extras.items():
+            out[name] = fn(lt, torch, args.steps, args.warmup)
+            torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     print(json.dumps(out), flush=True)
