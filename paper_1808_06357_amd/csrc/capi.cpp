@@ -43,11 +43,12 @@ std::vector<double> roots_d(int64_t L, int64_t count, int64_t mult)
     return out;
 }
 
-std::vector<float> roots_f(int64_t L, int64_t count)
+std::vector<float> roots_f(int64_t L, int64_t count, int64_t mult = 1)
 {
     std::vector<float> out((size_t)(4 * count));
     for (int64_t q = 0; q < count; ++q) {
-        const long double a = 2.0L * kPiL * (long double)(q % L) / (long double)L;
+        const int64_t m = (int64_t)(((__int128)q * mult) % L);
+        const long double a = 2.0L * kPiL * (long double)m / (long double)L;
         const long double c = cosl(a), s = -sinl(a);
         const float ch = (float)c, sh = (float)s;
         out[(size_t)(4 * q)] = ch;
@@ -183,19 +184,24 @@ lt_status bhat_natural(lt_plan &p, void *nat, void *tmp, hipStream_t st)
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // forward runs: the kinetic table (one complex double per squared norm
-// 0..max_s) and, for two-pass chirp-z, a transform buffer (otherwise the
-// transform runs in u itself)
+// 0..max_s), for two-pass chirp-z a transform buffer (otherwise the transform
+// runs in u itself), and for two-pass runs the merged potential multiplier
+// exp(-i dt v / gamma) per point (one table per distinct potential)
 struct RunWork {
-    size_t ktab = 0, w = 0, total = 0;
+    size_t ktab = 0, w = 0, ptab = 0, total = 0;
 };
 
-RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch)
+RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool shared_v = true,
+                   bool phase_table = true)
 {
     RunWork w;
     w.ktab = 0;
     size_t off = align_up((size_t)(p.max_s + 1) * 16);
     w.w = off;
     if (s.bluestein && s.passes == 2) off = align_up(off + (size_t)batch * s.L * esz(prec));
+    w.ptab = off;
+    if (s.passes == 2 && phase_table && prec == LT_C64)
+        off = align_up(off + (size_t)(shared_v ? 1 : batch) * p.N * 16);
     w.total = off;
     return w;
 }
@@ -278,7 +284,7 @@ struct Roles {
 };
 
 Roles two_pass_roles(const Sched &s, const DevTables &D, int64_t N, const double *v, int64_t v_stride, void *u,
-                     void *W, double half, const double *ktab)
+                     void *W, double half, const double *ktab, const void *ptab = nullptr)
 {
     Roles R;
     void *buf = s.bluestein ? W : u;
@@ -314,6 +320,8 @@ Roles two_pass_roles(const Sched &s, const DevTables &D, int64_t N, const double
     R.pot.v = v;
     R.pot.v_bs = v_stride;
     R.pot.phase = 2.0 * half;
+    R.pot.ptab = ptab;
+    R.pot.ptab_bs = v_stride ? N : 0;
     R.last = col_base(s, D, N);
     R.last.buf = buf;
     R.last.buf_bs = buf_bs;
@@ -331,12 +339,15 @@ Roles two_pass_roles(const Sched &s, const DevTables &D, int64_t N, const double
 lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int prec, int batch,
                            const double *v, int64_t v_stride, void *u, double gamma, double dt,
                            int64_t steps, void *ckpt, int64_t ck_every, const double *ktab, void *W,
-                           hipStream_t st)
+                           void *ptab, hipStream_t st)
 {
     const int64_t N = p.N;
     const size_t S = esz(prec);
     const double half = dt / (2.0 * gamma);
-    Roles R = two_pass_roles(s, D, N, v, v_stride, u, W, half, ktab);
+    if (ptab && steps > 1)
+        HIP_TRY(launch_phase_table(prec, ptab, v, v_stride, v_stride ? batch : 1, N, 2.0 * half, st),
+                "potential table");
+    Roles R = two_pass_roles(s, D, N, v, v_stride, u, W, half, ktab, ptab);
     HIP_TRY(launch_col(prec, s, R.first, batch, st), "column pass");
     for (int64_t t = 0; t < steps; ++t) {
         R.row.conj_tab = 0;
@@ -377,7 +388,7 @@ BatchLayout batch_layout(int32_t B, const lt_plan *const *plans, int prec)
     b.off.resize(B);
     for (int i = 0; i < B; ++i) {
         b.off[i] = off;
-        off += run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1).total;
+        off += run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1, true, false).total;
     }
     b.desc = off;
     size_t d = 0;
@@ -601,8 +612,7 @@ lt_status strang_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, i
     if (!p || !bytes) return fail(LT_E_ARG, "NULL argument");
     if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
     if (batch < 0) return fail(LT_E_ARG, "batch must be >= 0");
-    (void)shared_v;
-    *bytes = run_layout(*p, p->sched[0][prec], prec, batch).total;
+    *bytes = run_layout(*p, p->sched[0][prec], prec, batch, shared_v != 0).total;
     return LT_OK;
 }
 
@@ -632,7 +642,7 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
     if ((st = ensure_device_tables(p, 0, prec, stream))) return st;
     const Sched &s = p.sched[0][prec];
     const DevTables &D = p.dev[0][prec];
-    const RunWork L = run_layout(p, s, prec, batch);
+    const RunWork L = run_layout(p, s, prec, batch, v_stride == 0);
     Scratch sc;
     if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
     double *ktab = (double *)at(sc.ptr, L.ktab);
@@ -670,7 +680,7 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
         HIP_TRY(hipMemcpyAsync(ckpt, u, (size_t)batch * p.N * esz(prec), hipMemcpyDeviceToDevice, hs),
                 "checkpoint 0");
     return two_pass_forward(p, s, D, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every,
-                            ktab, at(sc.ptr, L.w), hs);
+                            ktab, at(sc.ptr, L.w), prec == LT_C64 ? at(sc.ptr, L.ptab) : nullptr, hs);
 }
 
 lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, int64_t v_stride,
@@ -825,7 +835,7 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
         if ((st = ensure_device_tables(p, 0, prec, stream))) return st;
         const Sched &s = p.sched[0][prec];
         const DevTables &D = p.dev[0][prec];
-        const RunWork L = run_layout(p, s, prec, 1);
+        const RunWork L = run_layout(p, s, prec, 1, true, false);
         char *w = at(sc.ptr, BL.off[i]);
         double *ktab = (double *)(w + L.ktab);
         kd.push_back({ktab, p.max_s + 1, kinetic_angle(gamma[i], dt[i]), s.bluestein ? 1.0 : 1.0 / (double)s.L});
@@ -964,14 +974,16 @@ lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *st
     Sched &s = p->sched[0][prec];
     const DevTables &D = p->dev[0][prec];
     hipStream_t hs = (hipStream_t)stream;
-    void *buf = nullptr, *v = nullptr, *kt = nullptr;
+    void *buf = nullptr, *v = nullptr, *kt = nullptr, *pt = nullptr;
     const size_t ktn = (size_t)(p->max_s + 1);
     HIP_TRY(hipMalloc(&buf, (size_t)s.L * esz(prec)), "autotune buffer");
     HIP_TRY(hipMalloc(&v, (size_t)p->N * sizeof(double)), "autotune buffer");
     HIP_TRY(hipMalloc(&kt, ktn * 16), "autotune buffer");
+    HIP_TRY(hipMalloc(&pt, (size_t)p->N * 16), "autotune buffer");
     HIP_TRY(hipMemsetAsync(buf, 0, (size_t)s.L * esz(prec), hs), "memset");
     HIP_TRY(hipMemsetAsync(v, 0, (size_t)p->N * sizeof(double), hs), "memset");
     HIP_TRY(launch_ktab((double *)kt, (int64_t)ktn, 0.0, 1.0, hs), "kinetic table");
+    HIP_TRY(launch_phase_table(prec, pt, (const double *)v, 0, 1, p->N, 1e-3, hs), "potential table");
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "event");
     HIP_TRY(hipEventCreate(&e1), "event");
@@ -982,6 +994,7 @@ lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *st
     c.post_fwd = 1;
     c.v = (const double *)v;
     c.phase = 1e-3;
+    c.ptab = pt;
     RowArgs r = row_base(s, D);
     r.buf = buf;
     r.buf_bs = s.L;
@@ -1017,6 +1030,7 @@ lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *st
     hipFree(buf);
     hipFree(v);
     hipFree(kt);
+    hipFree(pt);
     if (st) return st;
     return lattice_plan_set_kernels(p, prec, best_c, best_r);
 }

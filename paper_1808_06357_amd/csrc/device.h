@@ -107,6 +107,17 @@ __device__ __forceinline__ void expm_i(double a, double &c, double &s)
     s = -sn;
 }
 
+// floor(x / d) by a double reciprocal, for 0 <= x < 2^50 and d >= 1: the
+// quotient (x + 1/2) / d lies at least 1/(2d) from an integer, far beyond the
+// relative error 2^-52 of the two roundings
+struct FDiv {
+    int d;
+    double r;
+};
+__device__ __forceinline__ FDiv fdiv_make(int d) { return {d, 1.0 / (double)d}; }
+__device__ __forceinline__ int fdiv(int x, const FDiv &f) { return (int)(((double)x + 0.5) * f.r); }
+__device__ __forceinline__ int64_t fdiv64(int64_t x, const FDiv &f) { return (int64_t)(((double)x + 0.5) * f.r); }
+
 // chirp c_n = exp(-pi i (n^2 mod 2N) / N), exact integer reduction
 __device__ __forceinline__ void chirp(int64_t n, int64_t N, double &c, double &s)
 {
@@ -319,6 +330,17 @@ template <typename T>
 struct Dft<T, 7> : DftOdd<T, 7> {};
 
 // four-step twiddle W_L^{n2 k1} (L = L1 L2) from two double tables, applied in double
+template <typename T>
+__device__ __forceinline__ cx<T> tw4mul(cx<T> x, int n2, int k1, const FDiv &L2d, const double *hi,
+                                        const double *lo)
+{
+    const int64_t q = (int64_t)n2 * k1;
+    const int qa = (int)fdiv64(q, L2d);
+    const int qb = (int)(q - (int64_t)qa * L2d.d);
+    const double ax = hi[2 * qa], ay = hi[2 * qa + 1], bx = lo[2 * qb], by = lo[2 * qb + 1];
+    return cmul_d(x, ax * bx - ay * by, ax * by + ay * bx);
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> tw4mul(cx<T> x, int n2, int k1, int L2, const double *hi, const double *lo)
 {

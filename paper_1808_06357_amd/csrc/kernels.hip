@@ -40,24 +40,27 @@ namespace lt {
 // positions (t - t mod Ns) R + (t mod Ns) + r Ns (autosorting Stockham; the
 // result after the last stage is in natural order).  All reads of a stage
 // finish before any write (one barrier between), so the stage is in place.
+// Kept out of line: each radix's butterflies then get registers of their own
+// instead of one allocation covering every radix of the dispatch below.
 template <typename T, int R, int EPT>
-__device__ __forceinline__ void stage(cx<T> *s, int L, int nseq, int es, int ss, bool seqfast,
+__device__ __attribute__((noinline)) void stage(cx<T> *s, int L, int nseq, int es, int ss, bool seqfast,
                                       int Ns, const Tw<T> *__restrict__ tw)
 {
     constexpr int J = (EPT + R - 1) / R;
     const int bps = L / R;
     const int nb = nseq * bps;
     const int twstep = L / (Ns * R);
+    const FDiv dq = fdiv_make(seqfast ? nseq : bps), dns = fdiv_make(Ns);
     cx<T> v[J][R];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int b = threadIdx.x + j * kThreads;
         if (b < nb) {
             int q, t;
-            if (seqfast) { q = b % nseq; t = b / nseq; }
-            else { t = b % bps; q = b / bps; }
+            if (seqfast) { t = fdiv(b, dq); q = b - t * nseq; }
+            else { q = fdiv(b, dq); t = b - q * bps; }
             const cx<T> *base = s + q * ss;
-            const int jj = t % Ns;
+            const int jj = t - fdiv(t, dns) * Ns;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[j][r] = base[(t + r * bps) * es];
             if (Ns > 1) {
@@ -73,10 +76,10 @@ __device__ __forceinline__ void stage(cx<T> *s, int L, int nseq, int es, int ss,
         const int b = threadIdx.x + j * kThreads;
         if (b < nb) {
             int q, t;
-            if (seqfast) { q = b % nseq; t = b / nseq; }
-            else { t = b % bps; q = b / bps; }
+            if (seqfast) { t = fdiv(b, dq); q = b - t * nseq; }
+            else { q = fdiv(b, dq); t = b - q * bps; }
             cx<T> *base = s + q * ss;
-            const int jj = t % Ns;
+            const int jj = t - fdiv(t, dns) * Ns;
             const int ob = (t - jj) * R + jj;
 #pragma unroll
             for (int r = 0; r < R; ++r) base[(ob + r * Ns) * es] = v[j][r];
@@ -102,7 +105,9 @@ __device__ void fft_lds(cx<T> *s, const Radices &rd, int nseq, int es, int ss, b
         case 5: stage<T, 5, EPT>(s, L, nseq, es, ss, seqfast, Ns, tw); break;
         case 7: stage<T, 7, EPT>(s, L, nseq, es, ss, seqfast, Ns, tw); break;
         case 8: stage<T, 8, EPT>(s, L, nseq, es, ss, seqfast, Ns, tw); break;
-        case 16: stage<T, 16, EPT>(s, L, nseq, es, ss, seqfast, Ns, tw); break;
+        case 16:  // float only: the double schedules stop at radix 8
+            if constexpr (sizeof(T) == 4) stage<T, 16, EPT>(s, L, nseq, es, ss, seqfast, Ns, tw);
+            break;
         default: break;
         }
         Ns *= R;
@@ -128,14 +133,15 @@ __device__ void col_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
     const int c0 = tile * C;
     const int cw = min(C, L2 - c0);           // valid columns in this tile
     const int tot = L1 * Cq;
+    const FDiv dCq = fdiv_make(Cq), dC = fdiv_make(C), dL2 = fdiv_make(L2);
     cx<T> *buf0 = (cx<T> *)a.buf + b * a.buf_bs;
     cx<T> *buf1 = a.adjoint ? (cx<T> *)a.buf2 + b * a.buf2_bs : nullptr;
     const Tw<T> *twa = (const Tw<T> *)a.twa;
 
     // ---- load
     for (int e = threadIdx.x; e < tot; e += kThreads) {
-        const int q = e % Cq, n1 = e / Cq;
-        const int vec = q / C, qc = q - vec * C;
+        const int n1 = fdiv(e, dCq), q = e - n1 * Cq;
+        const int vec = q >= C, qc = q - vec * C;
         cx<T> x = {0, 0};
         if (qc < cw) {
             const int n2 = c0 + qc;
@@ -143,7 +149,7 @@ __device__ void col_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
             if (a.pre_inv) {
                 x = vec ? buf1[gi] : buf0[gi];
                 x = conjg(x);
-                if (a.twiddle) x = tw4mul(x, n2, n1, L2, a.tw4hi, a.tw4lo);
+                if (a.twiddle) x = tw4mul(x, n2, n1, dL2, a.tw4hi, a.tw4lo);
             } else {
                 const void *src = vec ? a.in2 : a.in;
                 const int64_t bs = vec ? a.in2_bs : a.in_bs;
@@ -159,7 +165,7 @@ __device__ void col_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
     // ---- point-domain work (natural index n)
     const double *vb = a.v ? a.v + b * a.v_bs : nullptr;
     for (int e = threadIdx.x; e < L1 * C; e += kThreads) {
-        const int qc = e % C, n1 = e / C;
+        const int n1 = fdiv(e, dC), qc = e - n1 * C;
         if (qc >= cw) continue;
         const int64_t n = (int64_t)n1 * L2 + c0 + qc;
         const int e0 = n1 * Cq + qc;
@@ -226,13 +232,13 @@ __device__ void col_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
 
     // ---- store
     for (int e = threadIdx.x; e < tot; e += kThreads) {
-        const int q = e % Cq, k1 = e / Cq;
-        const int vec = q / C, qc = q - vec * C;
+        const int k1 = fdiv(e, dCq), q = e - k1 * Cq;
+        const int vec = q >= C, qc = q - vec * C;
         if (qc >= cw) continue;
         const int n2 = c0 + qc;
         const int64_t gi = (int64_t)k1 * L2 + n2;
         cx<T> x = s[e];
-        if (a.twiddle) x = tw4mul(x, n2, k1, L2, a.tw4hi, a.tw4lo);
+        if (a.twiddle) x = tw4mul(x, n2, k1, dL2, a.tw4hi, a.tw4lo);
         if (vec) buf1[gi] = x;
         else buf0[gi] = x;
     }
@@ -257,8 +263,9 @@ __device__ void row_body(const RowArgs &a, int blk, int64_t b, cx<T> *s)
     cx<T> *buf = (cx<T> *)a.buf + b * a.buf_bs + (int64_t)r0 * L2;
     const Tw<T> *twb = (const Tw<T> *)a.twb;
     const int tot = a.rows * L2;
+    const int valid = rw * L2;
     for (int e = threadIdx.x; e < tot; e += kThreads)
-        s[e] = (e / L2) < rw ? buf[e] : cx<T>{0, 0};
+        s[e] = e < valid ? buf[e] : cx<T>{0, 0};
     __syncthreads();
     fft_lds<T, EPT>(s, a.rad, a.rows, 1, L2, false, twb);
     if (a.fft_only) {
@@ -515,6 +522,26 @@ __global__ void k_ktab_multi(const KtabDesc *d)
     }
 }
 
+// per-point multiplier exp(-i phase v[n]) as a Tw<T> entry (complex double, or
+// hi/lo complex floats), angle formed and reduced in FP64
+template <typename T>
+__global__ void k_phase_table(Tw<T> *dst, const double *v, int64_t v_bs, int nv, int64_t N, double phase)
+{
+    const int b = blockIdx.y;
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+        double c, s;
+        expm_i(phase * v[b * v_bs + n], c, s);
+        Tw<T> t;
+        if constexpr (sizeof(T) == 8) {
+            t.w = {c, s};
+        } else {
+            t.hi = {(float)c, (float)s};
+            t.lo = {(float)(c - (double)t.hi.x), (float)(s - (double)t.hi.y)};
+        }
+        dst[b * N + n] = t;
+    }
+}
+
 __global__ void k_reduce_batch(double *dst, const double *src, int64_t N, int batch)
 {
     for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N;
@@ -554,17 +581,19 @@ int kernels_init()
     if (done) return 0;
     done = 1;
     const int lim = 160 * 1024;
-    hipFuncSetAttribute((const void *)k_col<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_col<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_col<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void *)k_row<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_col<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_col<double, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_row<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_row<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void *)k_resident<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_resident<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_resident<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void *)k_col_multi<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_col_multi<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_col_multi<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void *)k_row_multi<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_row_multi<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_row_multi<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipFuncSetAttribute((const void *)k_resident_multi<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_resident_multi<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_resident_multi<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipGetLastError();
     return 0;
@@ -579,9 +608,14 @@ int launch_col(int prec, const Sched &s, const ColArgs &a, int batch, void *stre
     const int nvec = a.adjoint ? 2 : 1;
     const size_t lds = (size_t)a.L1 * a.C * nvec * esize(prec);
     dim3 grid(a.ntiles, batch);
+    if (a.adjoint && (int64_t)a.L1 * a.C * 2 > kTileElems) {  // state and cotangent: up to 2 x 4096 elements
+        if (prec == LT_C128)
+            return timed_launch(LT_KIND_COLUMN, k_col<double, 32>, grid, dim3(kThreads), lds, stream, a);
+        return timed_launch(LT_KIND_COLUMN, k_col<float, 32>, grid, dim3(kThreads), lds, stream, a);
+    }
     if (prec == LT_C128)
         return timed_launch(LT_KIND_COLUMN, k_col<double, 16>, grid, dim3(kThreads), lds, stream, a);
-    return timed_launch(LT_KIND_COLUMN, k_col<float, 32>, grid, dim3(kThreads), lds, stream, a);
+    return timed_launch(LT_KIND_COLUMN, k_col<float, 16>, grid, dim3(kThreads), lds, stream, a);
 }
 
 int launch_row(int prec, const Sched &s, const RowArgs &a, int batch, void *stream)
@@ -594,7 +628,7 @@ int launch_row(int prec, const Sched &s, const RowArgs &a, int batch, void *stre
     dim3 grid(a.nblk, batch);
     if (prec == LT_C128)
         return timed_launch(LT_KIND_ROW, k_row<double, 16>, grid, dim3(kThreads), lds, stream, a);
-    return timed_launch(LT_KIND_ROW, k_row<float, 32>, grid, dim3(kThreads), lds, stream, a);
+    return timed_launch(LT_KIND_ROW, k_row<float, 16>, grid, dim3(kThreads), lds, stream, a);
 }
 
 int launch_resident(int prec, const Sched &s, const ResArgs &a, int batch, void *stream)
@@ -603,7 +637,7 @@ int launch_resident(int prec, const Sched &s, const ResArgs &a, int batch, void 
     (void)s;
     if (prec == LT_C128)
         return timed_launch(LT_KIND_RESIDENT, k_resident<double, 16>, dim3(batch), dim3(kThreads), lds, stream, a);
-    return timed_launch(LT_KIND_RESIDENT, k_resident<float, 32>, dim3(batch), dim3(kThreads), lds, stream, a);
+    return timed_launch(LT_KIND_RESIDENT, k_resident<float, 16>, dim3(batch), dim3(kThreads), lds, stream, a);
 }
 
 int launch_col_multi(int prec, const BatchDesc *d, const int *start, int ninst, int nblocks, int64_t g,
@@ -612,7 +646,7 @@ int launch_col_multi(int prec, const BatchDesc *d, const int *start, int ninst, 
     if (prec == LT_C128)
         return timed_launch(LT_KIND_COLUMN, k_col_multi<double, 16>, dim3(nblocks), dim3(kThreads), lds, stream,
                             d, start, ninst, g);
-    return timed_launch(LT_KIND_COLUMN, k_col_multi<float, 32>, dim3(nblocks), dim3(kThreads), lds, stream, d,
+    return timed_launch(LT_KIND_COLUMN, k_col_multi<float, 16>, dim3(nblocks), dim3(kThreads), lds, stream, d,
                         start, ninst, g);
 }
 
@@ -622,7 +656,7 @@ int launch_row_multi(int prec, const BatchDesc *d, const int *start, int ninst, 
     if (prec == LT_C128)
         return timed_launch(LT_KIND_ROW, k_row_multi<double, 16>, dim3(nblocks), dim3(kThreads), lds, stream,
                             d, start, ninst, g);
-    return timed_launch(LT_KIND_ROW, k_row_multi<float, 32>, dim3(nblocks), dim3(kThreads), lds, stream, d,
+    return timed_launch(LT_KIND_ROW, k_row_multi<float, 16>, dim3(nblocks), dim3(kThreads), lds, stream, d,
                         start, ninst, g);
 }
 
@@ -640,7 +674,7 @@ int launch_resident_multi(int prec, const ResArgs *d, int ninst, size_t lds, voi
     if (prec == LT_C128)
         return timed_launch(LT_KIND_RESIDENT, k_resident_multi<double, 16>, dim3(ninst), dim3(kThreads), lds,
                             stream, d);
-    return timed_launch(LT_KIND_RESIDENT, k_resident_multi<float, 32>, dim3(ninst), dim3(kThreads), lds, stream,
+    return timed_launch(LT_KIND_RESIDENT, k_resident_multi<float, 16>, dim3(ninst), dim3(kThreads), lds, stream,
                         d);
 }
 
@@ -677,6 +711,19 @@ int launch_ktab(double *dst, int64_t count, double kin, double scale, void *stre
 {
     hipLaunchKernelGGL(k_ktab, dim3(grid1d(count)), dim3(256), 0, (hipStream_t)stream, dst, count, kin,
                        scale);
+    return (int)hipGetLastError();
+}
+
+int launch_phase_table(int prec, void *dst, const double *v, int64_t v_bs, int nv, int64_t N, double phase,
+                       void *stream)
+{
+    dim3 grid(grid1d(N) > 2048 ? 2048 : grid1d(N), nv);
+    if (prec == LT_C128)
+        hipLaunchKernelGGL(k_phase_table<double>, grid, dim3(256), 0, (hipStream_t)stream, (Tw<double> *)dst, v,
+                           v_bs, nv, N, phase);
+    else
+        hipLaunchKernelGGL(k_phase_table<float>, grid, dim3(256), 0, (hipStream_t)stream, (Tw<float> *)dst, v,
+                           v_bs, nv, N, phase);
     return (int)hipGetLastError();
 }
 

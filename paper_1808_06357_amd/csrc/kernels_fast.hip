@@ -155,7 +155,9 @@ __device__ __forceinline__ void tw4_series(double (&wr)[R], double (&wi)[R], int
 }
 
 // Steady-state column pass: [inverse column DFT -> point-domain multiplier
-// (and chirp-z mask) -> forward column DFT], in place.
+// (and chirp-z mask) -> forward column DFT], in place.  MID 0: the merged
+// potential step from the per-point table; MID 1: the chirp-z kinetic step
+// from the table indexed by the squared norm.
 template <typename T, int R, int NS, int E, int NT, int MINW, int MID>
 __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
 {
@@ -186,39 +188,78 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
         }
     }
     F::run(v, s, B, false);
-    // point-domain multiplier: the inputs of all of this thread's elements are
-    // loaded in one batch (one exposed latency), then applied element by
-    // element.  The scheduling barriers keep the batch after the DFT and the
-    // FP64 temporaries of different elements apart (register pressure).
+    // point-domain multiplier: the table entries of all of this thread's
+    // elements are loaded in one batch (one exposed latency), then applied
     __builtin_amdgcn_sched_barrier(0);
-    double pin[J][R];
+    if constexpr (MID == 0 && sizeof(T) == 4) {
+        // complex64: the merged potential step from the per-point hi/lo table,
+        // every entry of the thread in flight at once
+        const Tw<T> *pt = (const Tw<T> *)a.ptab + b * a.ptab_bs;
+        Tw<T> pin[J][R];
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int bf = threadIdx.x + j * NT;
-        const int q = F::q_of(bf), t = F::t_of(bf);
+        for (int j = 0; j < J; ++j) {
+            const int bf = threadIdx.x + j * NT;
+            const int q = F::q_of(bf), t = F::t_of(bf);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t n = (int64_t)(t + r * BPS) * L2 + c0 + q;
-            const bool ok = n < a.Nvalid;
-            if constexpr (MID == 0) pin[j][r] = ok ? a.v[b * a.v_bs + n] : 0.0;
-            else pin[j][r] = ok ? (double)a.s[n] : -1.0;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            cx<T> x = conjg(v[j][r]);
-            if constexpr (MID == 0) {
-                const int bf = threadIdx.x + j * NT;
-                const int64_t n = (int64_t)(F::t_of(bf) + r * BPS) * L2 + c0 + F::q_of(bf);
-                x = n < a.Nvalid ? mul_expm_i(x, a.phase * pin[j][r]) : cx<T>{0, 0};
-            } else {
-                const int m = (int)pin[j][r];
-                x = m >= 0 ? cmul_d(x, a.ktab[2 * m], a.ktab[2 * m + 1]) : cx<T>{0, 0};
+            for (int r = 0; r < R; ++r) {
+                const int64_t n = (int64_t)(t + r * BPS) * L2 + c0 + q;
+                pin[j][r] = pt[n < a.Nvalid ? n : 0];
             }
-            v[j][r] = x;
-            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int bf = threadIdx.x + j * NT;
+            const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t n = (int64_t)(t + r * BPS) * L2 + c0 + q;
+                v[j][r] = n < a.Nvalid ? twmul(conjg(v[j][r]), pin[j][r]) : cx<T>{0, 0};
+            }
+        }
+    } else if constexpr (MID == 0) {
+        // complex128: exp(-i phase v) in FP64 on the fly (the table would cost
+        // as many bytes as v and more registers than the kernel has)
+        double pin[J][R];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int bf = threadIdx.x + j * NT;
+            const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t n = (int64_t)(t + r * BPS) * L2 + c0 + q;
+                pin[j][r] = n < a.Nvalid ? a.v[b * a.v_bs + n] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int bf = threadIdx.x + j * NT;
+            const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t n = (int64_t)(t + r * BPS) * L2 + c0 + q;
+                v[j][r] = n < a.Nvalid ? mul_expm_i(conjg(v[j][r]), a.phase * pin[j][r]) : cx<T>{0, 0};
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    } else {
+        int pin[J][R];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int bf = threadIdx.x + j * NT;
+            const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t n = (int64_t)(t + r * BPS) * L2 + c0 + q;
+                pin[j][r] = n < a.Nvalid ? a.s[n] : -1;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int m = pin[j][r];
+                v[j][r] = m >= 0 ? cmul_d(conjg(v[j][r]), a.ktab[2 * m], a.ktab[2 * m + 1]) : cx<T>{0, 0};
+            }
         }
     }
     F::run(v, s, B, true);
@@ -237,6 +278,7 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
         for (int r = 0; r < R; ++r) buf[(int64_t)(t + r * BPS) * L2 + n2] = v[j][r];
     }
     (void)L1;
+    (void)TILE;
 }
 
 // Row pass: [DFT -> spectral multiplier -> inverse DFT], in place; the
@@ -351,7 +393,7 @@ template <typename T, int V, int R, int NS>
 int col_go(const ColArgs &a, int batch, void *stream)
 {
     constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW;
-    // MID 0: potential phase exp(-i phase v) (FP64 sincos); MID 1: kinetic table
+    // MID 0: merged potential step from the per-point table; MID 1: kinetic table
     auto k = a.v ? k_colf<T, R, NS, E, NT, MINW, 0> : k_colf<T, R, NS, E, NT, MINW, 1>;
     static bool attr = false;
     if (!attr) {
@@ -437,7 +479,8 @@ int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *st
     // steady-state passes only: the first / last / checkpoint passes of a run
     // and the adjoint passes take the general kernel
     const bool steady = a.pre_inv && a.post_fwd && !a.in && !a.out && !a.ck && !a.chirp &&
-                        a.scale == 1.0 && !a.adjoint && ((a.v != nullptr) != (a.ktab != nullptr));
+                        a.scale == 1.0 && !a.adjoint && ((a.v != nullptr) != (a.ktab != nullptr)) &&
+                        (prec == LT_C128 || !a.v || a.ptab);
     if (!steady || !fast_col_fits(prec, variant, a.L1, a.L2, a.C)) return -1;
     if (prec == LT_C128)
         return variant == 1 ? go<double, 1, true>(a.L1, a, batch, stream) : go<double, 2, true>(a.L1, a, batch, stream);

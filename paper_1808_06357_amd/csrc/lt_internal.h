@@ -70,6 +70,8 @@ struct ColArgs {
     int64_t Nchirp;
     double scale;
     const double *tw4hi, *tw4lo;      // four-step twiddle tables (complex double)
+    const void *ptab; int64_t ptab_bs;// merged potential step exp(-i phase v[n]) per point, Tw<T>
+                                      // (fast passes; the general kernel uses v and phase)
     const void *twa;                  // Tw<T> table of W_{L1}
     Radices rad;
     void *ck; int64_t ck_bs;          // optional checkpoint store of the point value
@@ -153,6 +155,8 @@ int launch_unpermute_c128(void *dst_nat, const void *src, int64_t L, int L1, int
 int launch_chirp_filter(void *dst_c128, int64_t N, int64_t L, void *stream);
 int launch_reduce_batch(double *dst, const double *src, int64_t N, int batch, void *stream);
 int launch_ktab(double *dst, int64_t count, double kin, double scale, void *stream);
+int launch_phase_table(int prec, void *dst, const double *v, int64_t v_bs, int nv, int64_t N, double phase,
+                       void *stream);
 // fast register-staged variants (kernels_fast.hip); return -1 when the variant does not fit
 int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *stream);
 int launch_row_fast(int prec, int variant, const RowArgs &a, int batch, void *stream);
@@ -193,6 +197,6 @@ lt_status fail(lt_status st, const std::string &msg);
 Sched make_schedule(const lt_plan &p, int prec, bool force_two_pass);
 lt_status plan_index_set(lt_plan &p);
 lt_status ensure_device_tables(lt_plan &p, int which, int prec, void *stream);
-bool factor_radices(int64_t L, Radices &out);
+bool factor_radices(int64_t L, Radices &out, int max_log2 = 4);
 int64_t smooth7_at_least(int64_t x);
 }  // namespace lt

@@ -199,10 +199,11 @@ lt_status plan_index_set(lt_plan &p)
 }
 
 // ---------------------------------------------------------------- schedules
-bool factor_radices(int64_t L, Radices &out)
+bool factor_radices(int64_t L, Radices &out, int max_log2)
 {
-    // Power-of-two part in as few stages as possible (radix <= 16), spread
-    // evenly (512 = 8*8*8 rather than 16*16*2); then the odd radices 7, 5, 3.
+    // Power-of-two part in as few stages as possible (radix <= 2^max_log2),
+    // spread evenly (512 = 8*8*8 rather than 16*16*2); then the odd radices
+    // 7, 5, 3.
     out.L = (int)L;
     out.n = 0;
     if (L < 1) return false;
@@ -211,7 +212,7 @@ bool factor_radices(int64_t L, Radices &out)
     while (m % 2 == 0) { m /= 2; ++e; }
     std::vector<int> st;
     if (e > 0) {
-        int k = (e + 3) / 4;
+        int k = (e + max_log2 - 1) / max_log2;
         for (int i = 0; i < k; ++i) st.push_back(1 << (e / k + (i < e % k ? 1 : 0)));
     }
     for (int f : {7, 5, 3})
@@ -269,7 +270,8 @@ Sched make_schedule(const lt_plan &p, int prec, bool force_two_pass)
     Sched s;
     const int64_t tile = kTileElems;  // complex elements per workgroup tile
     s.ept = (int)(tile / kThreads);
-    (void)prec;
+    // general kernels: radix 16 butterflies in double need too many registers
+    const int mr = prec == LT_C128 ? 3 : 4;
     if (p.r > 2) return s;
     if (p.r == 2) {
         if (!is_smooth7(p.n[0]) || !is_smooth7(p.n[1])) return s;
@@ -278,7 +280,7 @@ Sched make_schedule(const lt_plan &p, int prec, bool force_two_pass)
         s.L1 = (int)p.n[0];
         s.L2 = (int)p.n[1];
         if (p.n[0] > tile || p.n[1] > tile) return s;
-        if (!factor_radices(p.n[0], s.ra) || !factor_radices(p.n[1], s.rb)) return s;
+        if (!factor_radices(p.n[0], s.ra, mr) || !factor_radices(p.n[1], s.rb, mr)) return s;
         if (p.N <= tile && !force_two_pass) {
             s.passes = 1;
         } else {
@@ -299,13 +301,13 @@ Sched make_schedule(const lt_plan &p, int prec, bool force_two_pass)
         s.passes = 1;
         s.L1 = (int)s.L;
         s.L2 = 1;
-        if (!factor_radices(s.L, s.ra)) return s;
+        if (!factor_radices(s.L, s.ra, mr)) return s;
         s.rb = s.ra;
         s.ok = true;
         return s;
     }
     if (!split_two_pass(s.L, tile, s.L1, s.L2)) return s;
-    if (!factor_radices(s.L1, s.ra) || !factor_radices(s.L2, s.rb)) return s;
+    if (!factor_radices(s.L1, s.ra, mr) || !factor_radices(s.L2, s.rb, mr)) return s;
     s.passes = 2;
     s.cols = (int)std::max<int64_t>(1, std::min<int64_t>(tile / s.L1, s.L2));
     s.rows = (int)std::max<int64_t>(1, std::min<int64_t>(tile / s.L2, s.L1));

@@ -1,6 +1,8 @@
 """GPU adjoint (strang_adjoint, reverse-time recomputation with checkpoint
 resets) against the oracle's recompute-forward VJP, plus the autograd
 Function and a dot-product test."""
+import os
+
 import numpy as np
 import pytest
 
@@ -93,3 +95,83 @@ def test_dot_product_identity(lt):
     lhs = np.vdot(y, u.cpu().numpy())
     rhs = np.vdot(g0.cpu().numpy(), x)
     assert abs(lhs - rhs) < 1e-11 * np.linalg.norm(x) * np.linalg.norm(y)
+
+
+# ---------------------------------------------------------------- full-size differentiation workload
+GOLD4 = os.path.join(os.path.dirname(__file__), "golden", "config4_oracle_grad.npz")
+
+
+@pytest.fixture(scope="module")
+def case4(lt):
+    import torch
+    gold = np.load(GOLD4)
+    c = W.config4()
+    plan = lt.lattice_plan(c.Z, c.n, c.I)
+    basis = torch.tensor(c.meta["series"].basis(c.meta["num"], c.N), dtype=torch.float64, device="cuda")
+    S = torch.tensor(gold["S"], device="cuda")
+    assert np.array_equal(gold["S"], W.config4_loss_points(c.N))
+    return c, plan, basis, S, gold
+
+
+def loss_and_grads(lt, c, plan, v, S, target, dtype, grads=True):
+    """J = sum_b (1/N) sum_{k in S} |u_b(T)_k - target_b,k|^2 and, through
+    strang_adjoint, (dJ/dv, dJ/du0)."""
+    import torch
+    N, m, every = c.N, c.steps, c.meta["ckpt_every"]
+    u = torch.tensor(c.u0, dtype=dtype, device="cuda")
+    B = u.shape[0]
+    ck = torch.empty(lt.num_checkpoints(m, every) * B * N, dtype=dtype, device="cuda") if grads else None
+    lt.strang_run(plan, v, u, c.gamma, c.dt, m, ckpt=ck, ckpt_every=every if grads else 0)
+    diff = u[:, S].to(torch.complex128) - target
+    J = float(torch.sum(torch.abs(diff) ** 2).item()) / N
+    if not grads:
+        return J, u
+    gT = torch.zeros_like(u)
+    gT[:, S] = ((2.0 / N) * diff).to(dtype)
+    g0, gv = lt.strang_adjoint(plan, v, u, gT, c.gamma, c.dt, m, ck, every)
+    return J, u, g0, gv
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 1e-4)])
+def test_config4_gradients_against_oracle(lt, case4, prec, tol):
+    """d = 4, N = 65521, 32 states, 500 steps, checkpoints every 50: the loss,
+    u(T), dJ/da (64 coefficients), dJ/dv and dJ/du0 against the FP64 oracle's
+    adjoint (stored samples)."""
+    import torch
+    c, plan, basis, S, gold = case4
+    dtype = torch.complex128 if prec == "c128" else torch.complex64
+    v = torch.tensor(c.v, dtype=torch.float64, device="cuda")
+    target = torch.tensor(gold["target_S"], device="cuda")
+    J, u, g0, gv = loss_and_grads(lt, c, plan, v, S, target, dtype)
+    dJda = (basis @ gv).cpu().numpy()
+    iu, iv = gold["idx_u"], gold["idx_v"]
+    errs = {"J": abs(J - float(gold["J"])) / abs(float(gold["J"])),
+            "uT": rel(u.cpu().numpy()[:, iu], gold["uT"]),
+            "dJ/da": rel(dJda, gold["dJ_da"]),
+            "dJ/dv": rel(gv.cpu().numpy()[iv], gold["dJ_dv"]),
+            "dJ/du0": rel(g0.cpu().numpy()[:, iu], gold["dJ_du0"])}
+    print(f"config4 {prec}: " + ", ".join(f"{k} {e:.2e}" for k, e in errs.items()), flush=True)
+    for k, e in errs.items():
+        assert e < tol, (k, e)
+
+
+def test_config4_central_differences_c128(lt, case4):
+    """dJ/da from the adjoint against central differences, h = 1e-6, every one
+    of the 64 coefficients, on the complex128 path."""
+    import torch
+    c, plan, basis, S, gold = case4
+    a = torch.tensor(c.meta["series"].a, dtype=torch.float64, device="cuda")
+    target = torch.tensor(gold["target_S"], device="cuda")
+    _, _, _, gv = loss_and_grads(lt, c, plan, (a @ basis).contiguous(), S, target, torch.complex128)
+    adj = (basis @ gv).cpu().numpy()
+    h = 1e-6
+    fd = np.empty(a.numel())
+    for t in range(a.numel()):
+        e = torch.zeros_like(a)
+        e[t] = h
+        jp, _ = loss_and_grads(lt, c, plan, ((a + e) @ basis).contiguous(), S, target, torch.complex128, False)
+        jm, _ = loss_and_grads(lt, c, plan, ((a - e) @ basis).contiguous(), S, target, torch.complex128, False)
+        fd[t] = (jp - jm) / (2 * h)
+    e = rel(fd, adj)
+    print(f"config4 central differences vs adjoint: rel {e:.2e} (|dJ/da| = {np.linalg.norm(adj):.3e})", flush=True)
+    assert e < 1e-6

@@ -61,3 +61,48 @@ def test_config1_reversible_c128(lt, case):
     lt.strang_run(plan, v, u, inst.gamma, inst.dt, 1000)
     lt.strang_run(plan, v, u, inst.gamma, -inst.dt, 1000)
     assert rel(u.cpu().numpy(), inst.u0) < 1e-11
+
+
+GOLD3 = os.path.join(os.path.dirname(__file__), "golden", "config3_oracle_samples.npz")
+
+
+@pytest.fixture(scope="module")
+def case3(lt):
+    import torch
+    gold = np.load(GOLD3)
+    inst = W.config3()
+    assert np.array_equal(inst.Z, gold["Z"]), "seeded rank-2 CBC search changed"
+    plan = lt.lattice_plan(inst.Z, inst.n, inst.I)
+    v = torch.tensor(inst.v, dtype=torch.float64, device="cuda")
+    return inst, plan, v, gold
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-11), ("c64", 1e-4)])
+def test_config3_rank2_against_oracle_samples(lt, case3, prec, tol):
+    """Rank-2 lattice n = (4096, 256), d = 10, 500 steps, autotuned kernels."""
+    import torch
+    inst, plan, v, gold = case3
+    dtype = torch.complex128 if prec == "c128" else torch.complex64
+    p = lt.LT_C128 if prec == "c128" else lt.LT_C64
+    lt.lattice_plan_autotune(plan, p, reps=3)
+    u = torch.tensor(inst.u0, dtype=dtype, device="cuda")
+    idx = gold["idx"]
+    lt.strang_run(plan, v, u, inst.gamma, inst.dt, 100)
+    u100 = u.cpu().numpy().astype(np.complex128)
+    lt.strang_run(plan, v, u, inst.gamma, inst.dt, 400)
+    u500 = u.cpu().numpy().astype(np.complex128)
+    e100, e500 = rel(u100[idx], gold["u100"]), rel(u500[idx], gold["u500"])
+    n500 = np.mean(np.abs(u500) ** 2)
+    print(f"rank-2 {prec}: sampled rel L2 step 100 {e100:.2e}, step 500 {e500:.2e}, norm^2 {n500:.15f}",
+          flush=True)
+    assert e100 < tol and e500 < tol
+    assert abs(n500 - float(gold["norm2_500"])) < 2.0 * tol
+
+
+def test_config3_reversible_c128(lt, case3):
+    import torch
+    inst, plan, v, _ = case3
+    u = torch.tensor(inst.u0, dtype=torch.complex128, device="cuda")
+    lt.strang_run(plan, v, u, inst.gamma, inst.dt, 500)
+    lt.strang_run(plan, v, u, inst.gamma, -inst.dt, 500)
+    assert rel(u.cpu().numpy(), inst.u0) < 1e-11

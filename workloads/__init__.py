@@ -421,6 +421,13 @@ def config3(steps: int = 500) -> Instance:
     return Instance(10, Z, n, H, 0.05, 2e-3, steps, v, u0, {"name": "config3", "R": 1})
 
 
+def config4_loss_points(N: int, count: int = 2048) -> np.ndarray:
+    """Seeded sorted point indices on which the differentiation workload's
+    misfit is measured (the loss restricted to a sample keeps its stored
+    target small)."""
+    return np.sort(rng(4, "shapes").choice(N, size=count, replace=False))
+
+
 def config4(batch: int = 32, steps: int = 500):
     """d = 4, N = 65521 (prime), Korobov z, minimal-l2 full set, batch of
     seeded packets sharing a 64-term cosine potential; a hidden 64-term
