@@ -112,12 +112,12 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            try:
+        try:
+            if h is not None and h.value:
                 lib.lattice_plan_destroy(h)
-            except Exception:  # interpreter shutdown: ctypes may already be torn down
-                pass
-            self._h = _P(0)
+                self._h = _P(0)
+        except Exception:  # interpreter shutdown: module globals may already be torn down
+            pass
 
 
 def lattice_plan(Z, n, H=None) -> Plan:

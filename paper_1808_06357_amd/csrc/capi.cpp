@@ -188,7 +188,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // runs in u itself), and for two-pass runs the merged potential multiplier
 // exp(-i dt v / gamma) per point (one table per distinct potential)
 struct RunWork {
-    size_t ktab = 0, w = 0, ptab = 0, total = 0;
+    size_t ktab = 0, w = 0, ptab = 0, conv = 0, conv_tmp = 0, total = 0;
 };
 
 RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool shared_v = true,
@@ -202,6 +202,14 @@ RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool s
     w.ptab = off;
     if (s.passes == 2 && phase_table && prec == LT_C64)
         off = align_up(off + (size_t)(shared_v ? 1 : batch) * p.N * 16);
+    if (s.bluestein && s.passes == 2 && phase_table) {
+        // kernel spectrum of the step's cyclic convolution (complex double, L)
+        // and a complex-double scratch vector of N
+        w.conv = off;
+        off = align_up(off + (size_t)s.L * 16);
+        w.conv_tmp = off;
+        off = align_up(off + (size_t)p.N * 16);
+    }
     w.total = off;
     return w;
 }
@@ -335,11 +343,67 @@ Roles two_pass_roles(const Sched &s, const DevTables &D, int64_t N, const double
     return R;
 }
 
-// forward run of a state batch through the two-pass sequence
+// Chirp-z lattices: the kinetic part F^-1 K F of a step is the cyclic
+// convolution of length N with kernel k = conj(F conj(K)) / sqrt(N), i.e.
+// k_j = (1/N) sum_xi K_xi exp(2 pi i xi j / N).  Embedded with zero padding in
+// the length L >= 2N-1 of the chirp-z schedule (g_j = k_j, g_{L-j} = k_{N-j}),
+// it becomes one length-L FFT pair, so a step needs two passes instead of the
+// four of a chirp-z DFT and its inverse.  This builds the spectrum
+// G = FFT_L(g) / L in complex double, in the row pass layout: k from one
+// chirp-z DFT of conj(K), then the embedding and one forward FFT.
+lt_status conv_spectrum(lt_plan &p, const double *ktab, void *G, void *tmp, hipStream_t st)
+{
+    const Sched &s = p.sched[0][LT_C128];
+    const DevTables &D = p.dev[0][LT_C128];
+    const int64_t N = p.N;
+    HIP_TRY(launch_conv_input(tmp, D.s_key, ktab, N, st), "convolution kernel");
+    ColArgs a = col_base(s, D, N);
+    a.buf = G;
+    a.buf_bs = s.L;
+    a.in = tmp;
+    a.in_bs = N;
+    a.post_fwd = 1;
+    a.chirp = 1;
+    HIP_TRY(launch_col(LT_C128, s, a, 1, st), "convolution kernel");
+    RowArgs r = row_base(s, D);
+    r.buf = G;
+    r.buf_bs = s.L;
+    r.bhat = D.bhat;
+    HIP_TRY(launch_row(LT_C128, s, r, 1, st), "convolution kernel");
+    ColArgs c = col_base(s, D, N);
+    c.buf = G;
+    c.buf_bs = s.L;
+    c.pre_inv = 1;
+    c.out = tmp;
+    c.out_bs = N;
+    c.chirp = 1;
+    HIP_TRY(launch_col(LT_C128, s, c, 1, st), "convolution kernel");  // tmp = F conj(K)
+    HIP_TRY(launch_conv_embed(G, tmp, N, s.L, 1.0 / ((double)s.L * std::sqrt((double)N)), st),
+            "convolution kernel");
+    ColArgs f = col_base(s, D, s.L);
+    f.buf = G;
+    f.buf_bs = s.L;
+    f.post_fwd = 1;
+    HIP_TRY(launch_col(LT_C128, s, f, 1, st), "convolution kernel");
+    RowArgs rf = row_base(s, D);
+    rf.buf = G;
+    rf.buf_bs = s.L;
+    rf.fft_only = 1;
+    HIP_TRY(launch_row(LT_C128, s, rf, 1, st), "convolution kernel");
+    return LT_OK;
+}
+
+// runs at least this long use the convolution form on chirp-z lattices (its
+// spectrum costs about five passes once)
+constexpr int64_t kConvMinSteps = 4;
+
+// forward run of a state batch through the two-pass sequence; `conv` (chirp-z
+// lattices) is the spectrum from conv_spectrum, or null for the chirp-z DFT
+// pair per step
 lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int prec, int batch,
                            const double *v, int64_t v_stride, void *u, double gamma, double dt,
                            int64_t steps, void *ckpt, int64_t ck_every, const double *ktab, void *W,
-                           void *ptab, hipStream_t st)
+                           void *ptab, const void *conv, hipStream_t st)
 {
     const int64_t N = p.N;
     const size_t S = esz(prec);
@@ -348,11 +412,17 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
         HIP_TRY(launch_phase_table(prec, ptab, v, v_stride, v_stride ? batch : 1, N, 2.0 * half, st),
                 "potential table");
     Roles R = two_pass_roles(s, D, N, v, v_stride, u, W, half, ktab, ptab);
+    const bool chirpz = s.bluestein && !conv;
+    if (conv) {
+        R.first.chirp = 0;
+        R.last.chirp = 0;
+        R.row.bhat = (const double *)conv;
+    }
     HIP_TRY(launch_col(prec, s, R.first, batch, st), "column pass");
     for (int64_t t = 0; t < steps; ++t) {
         R.row.conj_tab = 0;
         HIP_TRY(launch_row(prec, s, R.row, batch, st), "row pass");
-        if (s.bluestein) {
+        if (chirpz) {
             HIP_TRY(launch_col(prec, s, R.kin, batch, st), "column pass (kinetic)");
             R.row.conj_tab = 1;
             HIP_TRY(launch_row(prec, s, R.row, batch, st), "row pass");
@@ -365,7 +435,7 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
             m.ck_bs = N;
             m.ck_v = v;
             m.ck_phase = half;
-            m.ck_chirp = s.bluestein ? 1 : 0;
+            m.ck_chirp = chirpz ? 1 : 0;
         }
         HIP_TRY(launch_col(prec, s, m, batch, st), "column pass (potential)");
     }
@@ -679,8 +749,16 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
     if (ckpt)
         HIP_TRY(hipMemcpyAsync(ckpt, u, (size_t)batch * p.N * esz(prec), hipMemcpyDeviceToDevice, hs),
                 "checkpoint 0");
+    void *conv = nullptr;
+    const Sched &s128 = p.sched[0][LT_C128];
+    if (s.bluestein && steps >= kConvMinSteps && s128.ok && s128.passes == 2 && s128.L == s.L &&
+        s128.L1 == s.L1 && s128.L2 == s.L2) {
+        if ((st = ensure_device_tables(p, 0, LT_C128, stream))) return st;
+        conv = at(sc.ptr, L.conv);
+        if ((st = conv_spectrum(p, ktab, conv, at(sc.ptr, L.conv_tmp), hs))) return st;
+    }
     return two_pass_forward(p, s, D, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every,
-                            ktab, at(sc.ptr, L.w), prec == LT_C64 ? at(sc.ptr, L.ptab) : nullptr, hs);
+                            ktab, at(sc.ptr, L.w), prec == LT_C64 ? at(sc.ptr, L.ptab) : nullptr, conv, hs);
 }
 
 lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, int64_t v_stride,

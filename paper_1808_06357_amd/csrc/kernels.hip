@@ -522,6 +522,30 @@ __global__ void k_ktab_multi(const KtabDesc *d)
     }
 }
 
+// conj(K_xi) = conj(ktab[s[xi]]) for every key xi < N, complex double
+__global__ void k_conv_input(cx<double> *dst, const int32_t *s, const double *ktab, int64_t N)
+{
+    for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+        const int m = s[n];
+        dst[n] = {ktab[2 * m], -ktab[2 * m + 1]};
+    }
+}
+
+// zero-padded embedding of a length-N cyclic kernel into length L >= 2N-1:
+// g_j = conj(src_j) scale for j < N, g_{L-j} = conj(src_{N-j}) scale for
+// 0 < j < N, zero elsewhere
+__global__ void k_conv_embed(cx<double> *g, const cx<double> *src, int64_t N, int64_t L, double scale)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < L; j += (int64_t)gridDim.x * blockDim.x) {
+        int64_t m = -1;
+        if (j < N) m = j;
+        else if (j > L - N) m = N - (L - j);
+        cx<double> z = {0.0, 0.0};
+        if (m >= 0) z = {src[m].x * scale, -src[m].y * scale};
+        g[j] = z;
+    }
+}
+
 // per-point multiplier exp(-i phase v[n]) as a Tw<T> entry (complex double, or
 // hi/lo complex floats), angle formed and reduced in FP64
 template <typename T>
@@ -711,6 +735,20 @@ int launch_ktab(double *dst, int64_t count, double kin, double scale, void *stre
 {
     hipLaunchKernelGGL(k_ktab, dim3(grid1d(count)), dim3(256), 0, (hipStream_t)stream, dst, count, kin,
                        scale);
+    return (int)hipGetLastError();
+}
+
+int launch_conv_input(void *dst, const int32_t *s, const double *ktab, int64_t N, void *stream)
+{
+    hipLaunchKernelGGL(k_conv_input, dim3(grid1d(N)), dim3(256), 0, (hipStream_t)stream, (cx<double> *)dst, s,
+                       ktab, N);
+    return (int)hipGetLastError();
+}
+
+int launch_conv_embed(void *g, const void *src, int64_t N, int64_t L, double scale, void *stream)
+{
+    hipLaunchKernelGGL(k_conv_embed, dim3(grid1d(L)), dim3(256), 0, (hipStream_t)stream, (cx<double> *)g,
+                       (const cx<double> *)src, N, L, scale);
     return (int)hipGetLastError();
 }
 

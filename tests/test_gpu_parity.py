@@ -171,3 +171,12 @@ def test_every_kernel_variant(lt, N, d):
     for prec in (lt.LT_C64, lt.LT_C128):
         chosen = lt.lattice_plan_autotune(plan, prec, reps=3)
         assert all(x in (0, 1, 2) for x in chosen)
+
+
+@pytest.mark.parametrize("N,d", [(65521, 4), (8191, 3), (262139, 3)])
+def test_chirpz_step_forms(lt, N, d):
+    """Prime N: runs of fewer than 4 steps apply the chirp-z DFT pair in every
+    step; longer runs apply F^-1 K F as one zero-padded cyclic convolution.
+    Both against the oracle, including a run of exactly 4 steps."""
+    for steps in (3, 4, 9):
+        check_case(lt, *korobov_case(N, d, 30 + steps, steps))
