@@ -192,7 +192,7 @@ struct RunWork {
 };
 
 RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool shared_v = true,
-                   bool phase_table = true)
+                   bool phase_table = true, bool conv_space = true)
 {
     RunWork w;
     w.ktab = 0;
@@ -202,7 +202,7 @@ RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool s
     w.ptab = off;
     if (s.passes == 2 && phase_table && prec == LT_C64)
         off = align_up(off + (size_t)(shared_v ? 1 : batch) * p.N * 16);
-    if (s.bluestein && s.passes == 2 && phase_table) {
+    if (s.bluestein && s.passes == 2 && conv_space) {
         // kernel spectrum of the step's cyclic convolution (complex double, L)
         // and a complex-double scratch vector of N
         w.conv = off;
@@ -215,7 +215,7 @@ RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool s
 }
 
 struct AdjWork {
-    size_t ktab = 0, w = 0, gacc = 0, total = 0;
+    size_t ktab = 0, w = 0, gacc = 0, conv = 0, conv_tmp = 0, total = 0;
 };
 
 AdjWork adj_layout(const lt_plan &p, const Sched &s, int prec, int batch)
@@ -226,6 +226,12 @@ AdjWork adj_layout(const lt_plan &p, const Sched &s, int prec, int batch)
     off = align_up(off + (size_t)2 * batch * s.L * esz(prec));   // state and cotangent
     w.gacc = off;
     off = align_up(off + (size_t)batch * p.N * sizeof(double));
+    if (s.bluestein) {  // the convolution form's spectrum and scratch
+        w.conv = off;
+        off = align_up(off + (size_t)s.L * 16);
+        w.conv_tmp = off;
+        off = align_up(off + (size_t)p.N * 16);
+    }
     w.total = off;
     return w;
 }
@@ -351,10 +357,10 @@ Roles two_pass_roles(const Sched &s, const DevTables &D, int64_t N, const double
 // four of a chirp-z DFT and its inverse.  This builds the spectrum
 // G = FFT_L(g) / L in complex double, in the row pass layout: k from one
 // chirp-z DFT of conj(K), then the embedding and one forward FFT.
-lt_status conv_spectrum(lt_plan &p, const double *ktab, void *G, void *tmp, hipStream_t st)
+lt_status conv_spectrum(lt_plan &p, int which, const double *ktab, void *G, void *tmp, hipStream_t st)
 {
-    const Sched &s = p.sched[0][LT_C128];
-    const DevTables &D = p.dev[0][LT_C128];
+    const Sched &s = p.sched[which][LT_C128];
+    const DevTables &D = p.dev[which][LT_C128];
     const int64_t N = p.N;
     HIP_TRY(launch_conv_input(tmp, D.s_key, ktab, N, st), "convolution kernel");
     ColArgs a = col_base(s, D, N);
@@ -396,6 +402,14 @@ lt_status conv_spectrum(lt_plan &p, const double *ktab, void *G, void *tmp, hipS
 // runs at least this long use the convolution form on chirp-z lattices (its
 // spectrum costs about five passes once)
 constexpr int64_t kConvMinSteps = 4;
+
+// the convolution form needs the complex128 schedule of the same slot with the
+// same transform layout (its spectrum is built in double precision)
+bool conv_available(const lt_plan &p, int which, const Sched &s)
+{
+    const Sched &d = p.sched[which][LT_C128];
+    return s.bluestein && s.passes == 2 && d.ok && d.passes == 2 && d.L == s.L && d.L1 == s.L1 && d.L2 == s.L2;
+}
 
 // forward run of a state batch through the two-pass sequence; `conv` (chirp-z
 // lattices) is the spectrum from conv_spectrum, or null for the chirp-z DFT
@@ -458,7 +472,7 @@ BatchLayout batch_layout(int32_t B, const lt_plan *const *plans, int prec)
     b.off.resize(B);
     for (int i = 0; i < B; ++i) {
         b.off[i] = off;
-        off += run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1, true, false).total;
+        off += run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1, true, false, true).total;
     }
     b.desc = off;
     size_t d = 0;
@@ -750,12 +764,10 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
         HIP_TRY(hipMemcpyAsync(ckpt, u, (size_t)batch * p.N * esz(prec), hipMemcpyDeviceToDevice, hs),
                 "checkpoint 0");
     void *conv = nullptr;
-    const Sched &s128 = p.sched[0][LT_C128];
-    if (s.bluestein && steps >= kConvMinSteps && s128.ok && s128.passes == 2 && s128.L == s.L &&
-        s128.L1 == s.L1 && s128.L2 == s.L2) {
+    if (steps >= kConvMinSteps && conv_available(p, 0, s)) {
         if ((st = ensure_device_tables(p, 0, LT_C128, stream))) return st;
         conv = at(sc.ptr, L.conv);
-        if ((st = conv_spectrum(p, ktab, conv, at(sc.ptr, L.conv_tmp), hs))) return st;
+        if ((st = conv_spectrum(p, 0, ktab, conv, at(sc.ptr, L.conv_tmp), hs))) return st;
     }
     return two_pass_forward(p, s, D, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every,
                             ktab, at(sc.ptr, L.w), prec == LT_C64 ? at(sc.ptr, L.ptab) : nullptr, conv, hs);
@@ -794,6 +806,14 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
     const double dtb = -dt;  // the backward sweep runs the scheme with -dt
     const double halfb = dtb / (2.0 * gamma);
     if ((st = make_ktab(p, s, ktab, gamma, dtb, hs))) return st;
+    // the backward sweep's kinetic part F^-1 conj(K) F as one cyclic convolution
+    const void *conv = nullptr;
+    if (steps >= kConvMinSteps && conv_available(p, 1, s)) {
+        if ((st = ensure_device_tables(p, 1, LT_C128, stream))) return st;
+        if ((st = conv_spectrum(p, 1, ktab, at(sc.ptr, L.conv), at(sc.ptr, L.conv_tmp), hs))) return st;
+        conv = at(sc.ptr, L.conv);
+    }
+    const bool chirpz = s.bluestein && !conv;
     HIP_TRY(hipMemsetAsync(gacc, 0, (size_t)batch * N * sizeof(double), hs), "memset");
     const double c = dt / (2.0 * gamma);
     void *Wg = at(W, (size_t)batch * s.L * S);
@@ -807,7 +827,7 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
     base.buf2_bs = s.L;
     base.v = v;
     base.v_bs = v_stride;
-    base.chirp = s.bluestein ? 1 : 0;
+    base.chirp = chirpz ? 1 : 0;
     base.gacc = gacc;
     base.gacc_bs = N;
     base.reset_phase = c;
@@ -827,7 +847,9 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
     RowArgs r = row_base(s, D);
     r.buf = W;
     r.buf_bs = s.L;
-    if (s.bluestein) {
+    if (conv) {
+        r.bhat = (const double *)conv;
+    } else if (s.bluestein) {
         r.bhat = D.bhat;
     } else {
         r.s = D.s_row;
@@ -843,7 +865,7 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
     for (int64_t j = steps; j >= 1; --j) {
         r.conj_tab = 0;
         HIP_TRY(launch_row(prec, s, r, 2 * batch, hs), "adjoint row pass");
-        if (s.bluestein) {
+        if (chirpz) {
             HIP_TRY(launch_col(prec, s, kinp, 2 * batch, hs), "adjoint column pass (kinetic)");
             r.conj_tab = 1;
             HIP_TRY(launch_row(prec, s, r, 2 * batch, hs), "adjoint row pass");
@@ -905,6 +927,12 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
     std::vector<KtabDesc> kd;
     std::vector<ResArgs> res;
     std::vector<BatchDesc> two;
+    struct ConvJob {
+        lt_plan *p;
+        const double *ktab;
+        void *G, *tmp;
+    };
+    std::vector<ConvJob> conv_jobs;
     size_t lds_res = 0, lds_col = 0, lds_row = 0;
     int64_t max_ktab = 0;
     for (int i = 0; i < B; ++i) {
@@ -913,7 +941,7 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
         if ((st = ensure_device_tables(p, 0, prec, stream))) return st;
         const Sched &s = p.sched[0][prec];
         const DevTables &D = p.dev[0][prec];
-        const RunWork L = run_layout(p, s, prec, 1, true, false);
+        const RunWork L = run_layout(p, s, prec, 1, true, false, true);
         char *w = at(sc.ptr, BL.off[i]);
         double *ktab = (double *)(w + L.ktab);
         kd.push_back({ktab, p.max_s + 1, kinetic_angle(gamma[i], dt[i]), s.bluestein ? 1.0 : 1.0 / (double)s.L});
@@ -945,7 +973,17 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
             lds_res = std::max(lds_res, (size_t)s.L * S);
             continue;
         }
-        const Roles R = two_pass_roles(s, D, p.N, v[i], 0, u[i], w + L.w, half, ktab);
+        Roles R = two_pass_roles(s, D, p.N, v[i], 0, u[i], w + L.w, half, ktab);
+        // chirp-z problems of 4 steps or more: the convolution form (spectrum
+        // built below, once the kinetic tables exist)
+        const bool conv = steps[i] >= kConvMinSteps && conv_available(p, 0, s);
+        if (conv) {
+            if ((st = ensure_device_tables(p, 0, LT_C128, stream))) return st;
+            conv_jobs.push_back({&p, ktab, w + L.conv, w + L.conv_tmp});
+            R.first.chirp = 0;
+            R.last.chirp = 0;
+            R.row.bhat = (const double *)(w + L.conv);
+        }
         BatchDesc b;
         std::memset(&b, 0, sizeof(b));
         b.col[0] = R.first;
@@ -955,8 +993,8 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
         b.row[0] = R.row;
         b.row[1] = R.row;
         b.row[1].conj_tab = 1;
-        b.bluestein = s.bluestein ? 1 : 0;
-        b.npass = (s.bluestein ? 4 : 2) * steps[i] + 1;
+        b.bluestein = (s.bluestein && !conv) ? 1 : 0;
+        b.npass = (b.bluestein ? 4 : 2) * steps[i] + 1;
         two.push_back(b);
         lds_col = std::max(lds_col, (size_t)R.first.L1 * R.first.C * S);
         lds_row = std::max(lds_row, (size_t)R.row.rows * R.row.L2 * S);
@@ -981,6 +1019,8 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
     if ((st = upload_async(dd, blob.data(), blob.size(), hs))) return st;
     HIP_TRY(launch_ktab_multi((const KtabDesc *)(dd + BL.d_ktab), (int)kd.size(), max_ktab, hs),
             "kinetic tables");
+    for (const ConvJob &j : conv_jobs)
+        if ((st = conv_spectrum(*j.p, 0, j.ktab, j.G, j.tmp, hs))) return st;
     // problems that fit one workgroup: their whole step loop in one launch,
     // overlapped with the pass-by-pass launches of the others
     hipStream_t rs = hs;
