@@ -107,6 +107,32 @@ __device__ __forceinline__ void expm_i(double a, double &c, double &s)
     s = -sn;
 }
 
+// table entry as a double-precision complex (hi + lo for the float tables)
+__device__ __forceinline__ cx<double> tw_d(const Tw<double> &t) { return t.w; }
+__device__ __forceinline__ cx<double> tw_d(const Tw<float> &t)
+{
+    return {(double)t.hi.x + (double)t.lo.x, (double)t.hi.y + (double)t.lo.y};
+}
+
+// w^r for r = 0..R-1 in double by a balanced product tree
+// (w^r = w^(r/2) w^(r - r/2)): at most log2(R) rounding steps deep
+template <int R>
+__device__ __forceinline__ void powers(double wr, double wi, double (&pr)[R], double (&pi)[R])
+{
+    pr[0] = 1.0;
+    pi[0] = 0.0;
+    if constexpr (R > 1) {
+        pr[1] = wr;
+        pi[1] = wi;
+    }
+#pragma unroll
+    for (int r = 2; r < R; ++r) {
+        const int a = r / 2, b = r - r / 2;
+        pr[r] = pr[a] * pr[b] - pi[a] * pi[b];
+        pi[r] = pr[a] * pi[b] + pi[a] * pr[b];
+    }
+}
+
 // floor(x / d) by a double reciprocal, for 0 <= x < 2^50 and d >= 1: the
 // quotient (x + 1/2) / d lies at least 1/(2d) from an integer, far beyond the
 // relative error 2^-52 of the two roundings

@@ -44,28 +44,36 @@ namespace lt {
 // instead of one allocation covering every radix of the dispatch below.
 template <typename T, int R, int EPT>
 __device__ __attribute__((noinline)) void stage(cx<T> *s, int L, int nseq, int es, int ss, bool seqfast,
-                                      int Ns, const Tw<T> *__restrict__ tw)
+                                                int Ns, const Tw<T> *__restrict__ tw)
 {
     constexpr int J = (EPT + R - 1) / R;
     const int bps = L / R;
     const int nb = nseq * bps;
     const int twstep = L / (Ns * R);
+    const int in_stride = bps * es, out_stride = Ns * es;
     const FDiv dq = fdiv_make(seqfast ? nseq : bps), dns = fdiv_make(Ns);
     cx<T> v[J][R];
+    int obase[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int b = threadIdx.x + j * kThreads;
+        obase[j] = -1;
         if (b < nb) {
             int q, t;
             if (seqfast) { t = fdiv(b, dq); q = b - t * nseq; }
             else { q = fdiv(b, dq); t = b - q * bps; }
-            const cx<T> *base = s + q * ss;
             const int jj = t - fdiv(t, dns) * Ns;
+            const int ib = q * ss + t * es;
+            obase[j] = q * ss + ((t - jj) * R + jj) * es;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[j][r] = base[(t + r * bps) * es];
+            for (int r = 0; r < R; ++r) v[j][r] = s[ib + r * in_stride];
             if (Ns > 1) {
+                // W_{Ns R}^{jj r}: one table entry per butterfly, its powers in double
+                const cx<double> w = tw_d(tw[jj * twstep]);
+                double pr[R], pi[R];
+                powers<R>(w.x, w.y, pr, pi);
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[j][r] = twmul(v[j][r], tw[jj * r * twstep]);
+                for (int r = 1; r < R; ++r) v[j][r] = cmul_d(v[j][r], pr[r], pi[r]);
             }
             Dft<T, R>::run(v[j]);
         }
@@ -73,16 +81,9 @@ __device__ __attribute__((noinline)) void stage(cx<T> *s, int L, int nseq, int e
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        const int b = threadIdx.x + j * kThreads;
-        if (b < nb) {
-            int q, t;
-            if (seqfast) { t = fdiv(b, dq); q = b - t * nseq; }
-            else { q = fdiv(b, dq); t = b - q * bps; }
-            cx<T> *base = s + q * ss;
-            const int jj = t - fdiv(t, dns) * Ns;
-            const int ob = (t - jj) * R + jj;
+        if (obase[j] >= 0) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) base[(ob + r * Ns) * es] = v[j][r];
+            for (int r = 0; r < R; ++r) s[obase[j] + r * out_stride] = v[j][r];
         }
     }
     __syncthreads();
