@@ -37,17 +37,19 @@ def log(msg):
 
 def pass_bytes(plan_info, N, m, S):
     """Algorithmic HBM bytes of every column-pass and row-pass launch of one
-    run (two-pass chirp-z schedule of length L): each pass reads and writes
-    the state once and reads the tables its step needs -- v (FP64, 8 B per
-    point) for potential steps, the key-norm index (int32, 4 B per key) for
-    the kinetic step, the kernel spectrum (complex double, 16 B per bin) in
-    the row pass."""
+    run of the benchmark workload (prime N, so the kinetic part of each step
+    is one zero-padded cyclic convolution of length L): each pass reads and
+    writes the state once and reads the tables its step needs -- v (FP64,
+    8 B per point) in the first and last passes, the merged potential step
+    exp(-i dt v / gamma) per point in the middle ones (complex64: a hi/lo pair
+    of complex floats, 16 B; complex128: v again, 8 B), and the convolution
+    spectrum (complex double, 16 B per bin) in the row pass."""
     L = plan_info["fft_len"]
+    pot = 16 * N if S == 8 else 8 * N
     col = [N * S + 8 * N + L * S]                 # first: u, v in; transform out
-    col += [2 * L * S + 4 * N] * m                # kinetic steps
-    col += [2 * L * S + 8 * N] * (m - 1)          # merged potential steps P^2
+    col += [2 * L * S + pot] * (m - 1)            # merged potential steps P^2
     col += [L * S + 8 * N + N * S]                # last: transform in, v in, u out
-    row = [2 * L * S + 16 * L] * (2 * m)          # state in/out + kernel spectrum
+    row = [2 * L * S + 16 * L] * m                # state in/out + convolution spectrum
     return col, row
 
 
