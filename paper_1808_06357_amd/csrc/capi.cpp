@@ -156,13 +156,15 @@ RowArgs row_base(const Sched &s, const DevTables &D)
 }
 
 // kernel spectrum of the chirp-z convolution, natural order, complex double
-lt_status bhat_natural(lt_plan &p, void *nat, void *tmp, hipStream_t st)
+lt_status bhat_natural(lt_plan &p, int which, void *nat, void *tmp, hipStream_t st)
 {
-    const Sched &s = p.sched[0][LT_C128];
+    // built with the double-precision schedule of the same slot (same length
+    // and layout as the run precision's)
+    const Sched &s = p.sched[which][LT_C128];
     if (!s.ok) return fail(LT_E_UNSUPPORTED, "no double-precision schedule for the chirp-z kernel");
-    lt_status r = build_twiddles(p, 0, LT_C128);
+    lt_status r = build_twiddles(p, which, LT_C128);
     if (r) return r;
-    const DevTables &D = p.dev[0][LT_C128];
+    const DevTables &D = p.dev[which][LT_C128];
     HIP_TRY(launch_chirp_filter(tmp, p.N, s.L, st), "chirp filter");
     if (s.passes == 1) {
         HIP_TRY(launch_fft_single(s.ra, D.twa, tmp, s.L, st), "kernel spectrum");
@@ -554,7 +556,7 @@ lt_status ensure_device_tables(lt_plan &p, int which, int prec, void *stream)
         HIP_TRY(hipMalloc(&nat, (size_t)s.L * 16), "chirp-z tables");
         HIP_TRY(hipMalloc(&tmp, (size_t)s.L * 16), "chirp-z tables");
         HIP_TRY(hipMalloc((void **)&D.bhat, (size_t)s.L * 16), "chirp-z tables");
-        r = bhat_natural(p, nat, tmp, st);
+        r = bhat_natural(p, which, nat, tmp, st);
         if (!r) {
             const double scale = 1.0 / ((double)s.L * std::sqrt((double)p.N));
             hipError_t e = (hipError_t)launch_permute_c128(D.bhat, nat, s.L, s.L1, s.L2,

@@ -1,9 +1,9 @@
-// Register-staged column / row passes for the lengths the benchmark and the
-// large lattices use (R^NS with R in {8, 16}: 64, 256, 512, 4096).
+// Register-staged column / row passes for the power-of-two lengths 64..4096
+// (mixed radices 2..16 with equal first and last radix).
 //
 // Compared with the general kernels:
-//  * each thread owns E = 16 elements; every stage is one or two radix-R
-//    butterflies per thread, fully unrolled at compile time;
+//  * each thread owns E elements; every stage is E / R radix-R butterflies
+//    per thread, fully unrolled at compile time;
 //  * the first stage reads global memory straight into registers and the last
 //    stage's outputs stay in registers: the column pass goes
 //    [global -> inverse DFT -> point-domain phase -> forward DFT -> global] and
@@ -26,80 +26,120 @@ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 
-// Stockham DFT over a tile of NT*E elements = SEQ sequences of length L = R^NS.
-// COLS: element e of sequence q at e*SEQ + q (interleaved columns);
-// otherwise at q*L + e (contiguous rows).  Butterfly bf = tid + j*NT handles
-// sequence q, index t; v[j][r] holds element t + r*L/R on entry (stage-1
-// inputs) and on exit (last-stage outputs).  The stage twiddles
-// W_{Ns R}^{(t mod Ns) r} are powers of one base per stage and butterfly; the
-// bases are loaded once (load_bases) and the powers formed in double.
-template <typename T, int R, int NS, int E, int NT, bool COLS>
+// Stockham DFT over a tile of NT*E elements = SEQ sequences of length
+// L = R_0 R_1 ... R_{NS-1} (radices Rs, first and last equal).  COLS: element
+// e of sequence q at e*SEQ + q (interleaved columns); otherwise at q*L + e
+// (contiguous rows).  In stage s butterfly bf = tid + j*NT handles sequence q,
+// index t < L/R_s and the elements t + r L/R_s; the thread's E elements sit in
+// x[j R_s + r].  On entry x holds the first stage's inputs, on exit the last
+// stage's outputs (the same positions, since the two radices agree).  The
+// stage twiddles W_{Ns R_s}^{(t mod Ns) r} are powers of one base per stage
+// and butterfly; the bases are loaded once (load_bases) and the powers formed
+// in double.
+template <int... Rs>
+struct Radix {
+    static constexpr int n = sizeof...(Rs);
+    static constexpr int v[n] = {Rs...};
+    static constexpr int prod = (1 * ... * Rs);
+    static constexpr int min()
+    {
+        int m = v[0];
+        for (int i = 1; i < n; ++i) m = v[i] < m ? v[i] : m;
+        return m;
+    }
+    static constexpr int before(int st)
+    {
+        int p = 1;
+        for (int i = 0; i < st; ++i) p *= v[i];
+        return p;
+    }
+};
+
+template <typename T, int E, int NT, bool COLS, int... Rs>
 struct Fft {
-    static constexpr int L = ipow(R, NS);
+    using RL = Radix<Rs...>;
+    static constexpr int NS = RL::n;
+    static constexpr int L = RL::prod;
+    static constexpr int R = RL::v[0];
     static constexpr int TILE = NT * E;
     static constexpr int SEQ = TILE / L;
     static constexpr int J = E / R;
     static constexpr int BPS = L / R;
     static constexpr int NB = NS > 1 ? NS - 1 : 1;
-    static_assert(E % R == 0 && TILE % L == 0, "tile must hold whole sequences");
+    static constexpr int MAXJ = E / RL::min();
+    static_assert(RL::v[0] == RL::v[NS - 1], "first and last radix must agree");
+    static_assert(((E % Rs == 0) && ...) && TILE % L == 0, "tile must hold whole sequences");
 
     struct Bases {
-        double r[NB][J], i[NB][J];
+        double r[NB][MAXJ], i[NB][MAXJ];
     };
 
-    static __device__ __forceinline__ int q_of(int bf) { return COLS ? bf % SEQ : bf / BPS; }
-    static __device__ __forceinline__ int t_of(int bf) { return COLS ? bf / SEQ : bf % BPS; }
+    static __device__ __forceinline__ int qs(int bf, int bps) { return COLS ? bf % SEQ : bf / bps; }
+    static __device__ __forceinline__ int ts(int bf, int bps) { return COLS ? bf / SEQ : bf % bps; }
+    static __device__ __forceinline__ int q_of(int bf) { return qs(bf, BPS); }
+    static __device__ __forceinline__ int t_of(int bf) { return ts(bf, BPS); }
     static __device__ __forceinline__ int addr(int q, int e) { return pidx(COLS ? e * SEQ + q : q * L + e); }
 
-    static __device__ __forceinline__ void load_bases(Bases &B, const Tw<T> *__restrict__ tw)
+    template <int ST>
+    static __device__ __forceinline__ void bases_from(Bases &B, const Tw<T> *__restrict__ tw)
     {
-        int Ns = 1;
+        if constexpr (ST < NS) {
+            constexpr int Rc = RL::v[ST], Jc = E / Rc, BPSc = L / Rc, Ns = RL::before(ST);
+            constexpr int twstep = L / (Ns * Rc);
 #pragma unroll
-        for (int st = 1; st < NS; ++st) {
-            Ns *= R;
-            const int twstep = L / (Ns * R);
-#pragma unroll
-            for (int j = 0; j < J; ++j) {
-                const int t = t_of(threadIdx.x + j * NT);
+            for (int j = 0; j < Jc; ++j) {
+                const int t = ts(threadIdx.x + j * NT, BPSc);
                 const cx<double> w = tw_d(tw[(t % Ns) * twstep]);
-                B.r[st - 1][j] = w.x;
-                B.i[st - 1][j] = w.y;
+                B.r[ST - 1][j] = w.x;
+                B.i[ST - 1][j] = w.y;
             }
+            bases_from<ST + 1>(B, tw);
         }
     }
 
-    static __device__ __forceinline__ void run(cx<T> (&v)[J][R], cx<T> *s, const Bases &B, bool sync_first)
+    static __device__ __forceinline__ void load_bases(Bases &B, const Tw<T> *__restrict__ tw)
     {
+        bases_from<1>(B, tw);
+    }
+
+    template <int ST>
+    static __device__ __forceinline__ void stages_from(cx<T> (&x)[E], cx<T> *s, const Bases &B, bool sync_first)
+    {
+        if constexpr (ST < NS) {
+            constexpr int Rp = RL::v[ST - 1], Jp = E / Rp, BPSp = L / Rp, Nsp = RL::before(ST - 1);
+            constexpr int Rc = RL::v[ST], Jc = E / Rc, BPSc = L / Rc;
+            if (ST > 1 || sync_first) __syncthreads();
 #pragma unroll
-        for (int j = 0; j < J; ++j) Dft<T, R>::run(v[j]);
-        int Ns = 1;
-#pragma unroll
-        for (int st = 1; st < NS; ++st) {
-            if (st > 1 || sync_first) __syncthreads();
-#pragma unroll
-            for (int j = 0; j < J; ++j) {
+            for (int j = 0; j < Jp; ++j) {
                 const int bf = threadIdx.x + j * NT;
-                const int q = q_of(bf), t = t_of(bf);
-                const int jj = t % Ns;
-                const int ob = (t - jj) * R + jj;
+                const int q = qs(bf, BPSp), t = ts(bf, BPSp);
+                const int jj = t % Nsp;
+                const int ob = (t - jj) * Rp + jj;
 #pragma unroll
-                for (int r = 0; r < R; ++r) s[addr(q, ob + r * Ns)] = v[j][r];
+                for (int r = 0; r < Rp; ++r) s[addr(q, ob + r * Nsp)] = x[j * Rp + r];
             }
             __syncthreads();
-            Ns *= R;
 #pragma unroll
-            for (int j = 0; j < J; ++j) {
+            for (int j = 0; j < Jc; ++j) {
                 const int bf = threadIdx.x + j * NT;
-                const int q = q_of(bf), t = t_of(bf);
+                const int q = qs(bf, BPSc), t = ts(bf, BPSc);
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[j][r] = s[addr(q, t + r * BPS)];
-                double pr[R], pi[R];
-                powers<R>(B.r[st - 1][j], B.i[st - 1][j], pr, pi);
+                for (int r = 0; r < Rc; ++r) x[j * Rc + r] = s[addr(q, t + r * BPSc)];
+                double pr[Rc], pi[Rc];
+                powers<Rc>(B.r[ST - 1][j], B.i[ST - 1][j], pr, pi);
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[j][r] = cmul_d(v[j][r], pr[r], pi[r]);
-                Dft<T, R>::run(v[j]);
+                for (int r = 1; r < Rc; ++r) x[j * Rc + r] = cmul_d(x[j * Rc + r], pr[r], pi[r]);
+                Dft<T, Rc>::run(&x[j * Rc]);
             }
+            stages_from<ST + 1>(x, s, B, sync_first);
         }
+    }
+
+    static __device__ __forceinline__ void run(cx<T> (&x)[E], cx<T> *s, const Bases &B, bool sync_first)
+    {
+#pragma unroll
+        for (int j = 0; j < J; ++j) Dft<T, R>::run(&x[j * R]);
+        stages_from<1>(x, s, B, sync_first);
     }
 };
 
@@ -132,11 +172,11 @@ __device__ __forceinline__ void tw4_series(double (&wr)[R], double (&wi)[R], int
 // (and chirp-z mask) -> forward column DFT], in place.  MID 0: the merged
 // potential step from the per-point table; MID 1: the chirp-z kinetic step
 // from the table indexed by the squared norm.
-template <typename T, int R, int NS, int E, int NT, int MINW, int MID>
+template <typename T, int E, int NT, int MINW, int MID, int... Rs>
 __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
 {
-    using F = Fft<T, R, NS, E, NT, true>;
-    constexpr int C = F::SEQ, J = F::J, BPS = F::BPS, L1 = F::L, TILE = F::TILE;
+    using F = Fft<T, E, NT, true, Rs...>;
+    constexpr int C = F::SEQ, J = F::J, R = F::R, BPS = F::BPS, L1 = F::L, TILE = F::TILE;
     extern __shared__ char smem_raw[];
     cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
     const int L2 = a.L2;
@@ -146,19 +186,19 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
     cx<T> *buf = (cx<T> *)a.buf + b * a.buf_bs;
     typename F::Bases B;
     F::load_bases(B, (const Tw<T> *)a.twa);
-    cx<T> v[J][R];
+    cx<T> v[E];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int bf = threadIdx.x + j * NT;
         const int q = F::q_of(bf), t = F::t_of(bf);
         const int n2 = c0 + q;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[j][r] = conjg(buf[(int64_t)(t + r * BPS) * L2 + n2]);
+        for (int r = 0; r < R; ++r) v[j * R + r] = conjg(buf[(int64_t)(t + r * BPS) * L2 + n2]);
         if (a.twiddle) {
             double wr[R], wi[R];
             tw4_series<R>(wr, wi, n2, t, BPS, L2, a.tw4hi, a.tw4lo);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[j][r] = cmul_d(v[j][r], wr[r], wi[r]);
+            for (int r = 0; r < R; ++r) v[j * R + r] = cmul_d(v[j * R + r], wr[r], wi[r]);
         }
     }
     F::run(v, s, B, false);
@@ -187,7 +227,7 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t n = (int64_t)(t + r * BPS) * L2 + c0 + q;
-                v[j][r] = n < a.Nvalid ? twmul(conjg(v[j][r]), pin[j][r]) : cx<T>{0, 0};
+                v[j * R + r] = n < a.Nvalid ? twmul(conjg(v[j * R + r]), pin[j][r]) : cx<T>{0, 0};
             }
         }
     } else if constexpr (MID == 0) {
@@ -211,7 +251,7 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t n = (int64_t)(t + r * BPS) * L2 + c0 + q;
-                v[j][r] = n < a.Nvalid ? mul_expm_i(conjg(v[j][r]), a.phase * pin[j][r]) : cx<T>{0, 0};
+                v[j * R + r] = n < a.Nvalid ? mul_expm_i(conjg(v[j * R + r]), a.phase * pin[j][r]) : cx<T>{0, 0};
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -232,7 +272,7 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int m = pin[j][r];
-                v[j][r] = m >= 0 ? cmul_d(conjg(v[j][r]), a.ktab[2 * m], a.ktab[2 * m + 1]) : cx<T>{0, 0};
+                v[j * R + r] = m >= 0 ? cmul_d(conjg(v[j * R + r]), a.ktab[2 * m], a.ktab[2 * m + 1]) : cx<T>{0, 0};
             }
         }
     }
@@ -246,10 +286,10 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
             double wr[R], wi[R];
             tw4_series<R>(wr, wi, n2, t, BPS, L2, a.tw4hi, a.tw4lo);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[j][r] = cmul_d(v[j][r], wr[r], wi[r]);
+            for (int r = 0; r < R; ++r) v[j * R + r] = cmul_d(v[j * R + r], wr[r], wi[r]);
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) buf[(int64_t)(t + r * BPS) * L2 + n2] = v[j][r];
+        for (int r = 0; r < R; ++r) buf[(int64_t)(t + r * BPS) * L2 + n2] = v[j * R + r];
     }
     (void)L1;
     (void)TILE;
@@ -257,11 +297,11 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
 
 // Row pass: [DFT -> spectral multiplier -> inverse DFT], in place; the
 // multiplier (chirp-z kernel spectrum or kinetic table) is applied in registers.
-template <typename T, int R, int NS, int E, int NT, int MINW, int MID>
+template <typename T, int E, int NT, int MINW, int MID, int... Rs>
 __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
 {
-    using F = Fft<T, R, NS, E, NT, false>;
-    constexpr int L2 = F::L, RW = F::SEQ, J = F::J, BPS = F::BPS, TILE = F::TILE;
+    using F = Fft<T, E, NT, false, Rs...>;
+    constexpr int L2 = F::L, RW = F::SEQ, J = F::J, R = F::R, BPS = F::BPS, TILE = F::TILE;
     extern __shared__ char smem_raw[];
     cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
     const int r0 = blockIdx.x * RW;
@@ -270,13 +310,13 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
     typename F::Bases B;
     F::load_bases(B, (const Tw<T> *)a.twb);
     const int64_t p0 = (int64_t)r0 * L2;
-    cx<T> v[J][R];
+    cx<T> v[E];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int bf = threadIdx.x + j * NT;
         const int q = F::q_of(bf), t = F::t_of(bf);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[j][r] = buf[q * L2 + t + r * BPS];
+        for (int r = 0; r < R; ++r) v[j * R + r] = buf[q * L2 + t + r * BPS];
     }
     F::run(v, s, B, false);
     if constexpr (MID == 0) {
@@ -289,7 +329,7 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
             for (int r = 0; r < R; ++r) {
                 const int64_t pos = p0 + q * L2 + t + r * BPS;
                 const double br = a.bhat[2 * pos], bi = a.bhat[2 * pos + 1];
-                v[j][r] = conjg(cmul_d(v[j][r], br, a.conj_tab ? -bi : bi));
+                v[j * R + r] = conjg(cmul_d(v[j * R + r], br, a.conj_tab ? -bi : bi));
             }
         }
     } else {
@@ -300,7 +340,7 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
             const int bf = threadIdx.x + j * NT;
             const int q = F::q_of(bf), t = F::t_of(bf);
 #pragma unroll
-            for (int r = 0; r < R; ++r) s[F::addr(q, t + r * BPS)] = v[j][r];
+            for (int r = 0; r < R; ++r) s[F::addr(q, t + r * BPS)] = v[j * R + r];
         }
         __syncthreads();
 #pragma unroll 1
@@ -314,7 +354,7 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
             const int bf = threadIdx.x + j * NT;
             const int q = F::q_of(bf), t = F::t_of(bf);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[j][r] = s[F::addr(q, t + r * BPS)];
+            for (int r = 0; r < R; ++r) v[j * R + r] = s[F::addr(q, t + r * BPS)];
         }
     }
     F::run(v, s, B, true);
@@ -323,7 +363,7 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
         const int bf = threadIdx.x + j * NT;
         const int q = F::q_of(bf), t = F::t_of(bf);
 #pragma unroll
-        for (int r = 0; r < R; ++r) buf[q * L2 + t + r * BPS] = conjg(v[j][r]);
+        for (int r = 0; r < R; ++r) buf[q * L2 + t + r * BPS] = conjg(v[j * R + r]);
     }
 }
 
@@ -363,76 +403,83 @@ size_t lds_bytes()
     return (size_t)(tile + tile / 16) * sizeof(cx<T>);
 }
 
-template <typename T, int V, int R, int NS>
+template <typename T, int V, int... Rs>
 int col_go(const ColArgs &a, int batch, void *stream)
 {
     constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW;
     // MID 0: merged potential step from the per-point table; MID 1: kinetic table
-    auto k = a.v ? k_colf<T, R, NS, E, NT, MINW, 0> : k_colf<T, R, NS, E, NT, MINW, 1>;
+    auto k = a.v ? k_colf<T, E, NT, MINW, 0, Rs...> : k_colf<T, E, NT, MINW, 1, Rs...>;
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void *)k_colf<T, R, NS, E, NT, MINW, 0>,
+        hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 0, Rs...>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        hipFuncSetAttribute((const void *)k_colf<T, R, NS, E, NT, MINW, 1>,
+        hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 1, Rs...>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    constexpr int C = NT * E / ipow(R, NS);
+    constexpr int C = NT * E / Radix<Rs...>::prod;
     dim3 grid(a.L2 / C, batch);
     const size_t lds = lds_bytes<T, V>();
     return timed(LT_KIND_COLUMN, k, grid, dim3(NT), lds, stream, a);
 }
 
-template <typename T, int V, int R, int NS>
+template <typename T, int V, int... Rs>
 int row_go(const RowArgs &a, int batch, void *stream)
 {
     constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW;
-    auto k = a.bhat ? k_rowf<T, R, NS, E, NT, MINW, 0> : k_rowf<T, R, NS, E, NT, MINW, 1>;
+    auto k = a.bhat ? k_rowf<T, E, NT, MINW, 0, Rs...> : k_rowf<T, E, NT, MINW, 1, Rs...>;
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void *)k_rowf<T, R, NS, E, NT, MINW, 0>,
+        hipFuncSetAttribute((const void *)k_rowf<T, E, NT, MINW, 0, Rs...>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        hipFuncSetAttribute((const void *)k_rowf<T, R, NS, E, NT, MINW, 1>,
+        hipFuncSetAttribute((const void *)k_rowf<T, E, NT, MINW, 1, Rs...>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    constexpr int RW = NT * E / ipow(R, NS);
+    constexpr int RW = NT * E / Radix<Rs...>::prod;
     dim3 grid(a.L1 / RW, batch);
     const size_t lds = lds_bytes<T, V>();
     return timed(LT_KIND_ROW, k, grid, dim3(NT), lds, stream, a);
 }
 
-template <typename T, int V, int R, int NS, bool COL, class A>
+template <typename T, int V, bool COL, int... Rs, class A>
 int go1(const A &a, int batch, void *stream)
 {
-    if constexpr (COL) return col_go<T, V, R, NS>(a, batch, stream);
-    else return row_go<T, V, R, NS>(a, batch, stream);
+    if constexpr (COL) return col_go<T, V, Rs...>(a, batch, stream);
+    else return row_go<T, V, Rs...>(a, batch, stream);
 }
 
-// (radix, stages) of each supported length per variant
+// radix sequence of each supported length per variant (first radix = last;
+// every radix divides the elements per thread)
 template <typename T, int V, bool COL, class A>
 int go(int L, const A &a, int batch, void *stream)
 {
-    if constexpr (V == 1) {
+    if constexpr (V == 1) {  // 16 elements per thread
         switch (L) {
-        case 64: return go1<T, V, 8, 2, COL>(a, batch, stream);
-        case 256: return go1<T, V, 16, 2, COL>(a, batch, stream);
-        case 512: return go1<T, V, 8, 3, COL>(a, batch, stream);
-        case 4096: return go1<T, V, 16, 3, COL>(a, batch, stream);
+        case 64: return go1<T, V, COL, 8, 8>(a, batch, stream);
+        case 128: return go1<T, V, COL, 8, 2, 8>(a, batch, stream);
+        case 256: return go1<T, V, COL, 16, 16>(a, batch, stream);
+        case 512: return go1<T, V, COL, 8, 8, 8>(a, batch, stream);
+        case 1024: return go1<T, V, COL, 16, 4, 16>(a, batch, stream);
+        case 2048: return go1<T, V, COL, 16, 8, 16>(a, batch, stream);
+        case 4096: return go1<T, V, COL, 16, 16, 16>(a, batch, stream);
         default: return -1;
         }
-    } else {
+    } else {  // 8 elements per thread
         switch (L) {
-        case 64: return go1<T, V, 8, 2, COL>(a, batch, stream);
-        case 256: return go1<T, V, 4, 4, COL>(a, batch, stream);
-        case 512: return go1<T, V, 8, 3, COL>(a, batch, stream);
-        case 4096: return go1<T, V, 8, 4, COL>(a, batch, stream);
+        case 64: return go1<T, V, COL, 8, 8>(a, batch, stream);
+        case 128: return go1<T, V, COL, 8, 2, 8>(a, batch, stream);
+        case 256: return go1<T, V, COL, 4, 4, 4, 4>(a, batch, stream);
+        case 512: return go1<T, V, COL, 8, 8, 8>(a, batch, stream);
+        case 1024: return go1<T, V, COL, 8, 4, 4, 8>(a, batch, stream);
+        case 2048: return go1<T, V, COL, 8, 4, 8, 8>(a, batch, stream);
+        case 4096: return go1<T, V, COL, 8, 8, 8, 8>(a, batch, stream);
         default: return -1;
         }
     }
 }
 
-bool fast_len(int L) { return L == 64 || L == 256 || L == 512 || L == 4096; }
+bool fast_len(int L) { return L >= 64 && L <= 4096 && (L & (L - 1)) == 0; }
 constexpr int kTile = 4096;
 }  // namespace
 

@@ -294,8 +294,17 @@ Sched make_schedule(const lt_plan &p, int prec, bool force_two_pass)
     if (is_smooth7(p.N)) {
         s.L = p.N;
     } else {
+        // chirp-z length: any L >= 2N - 1 works.  One workgroup's tile: the
+        // smallest 7-smooth length; two passes: a power of two, whose factors
+        // the register-staged passes cover (up to 2x the 7-smooth length, at
+        // a fraction of the cost per element of the general passes)
         s.bluestein = true;
         s.L = smooth7_at_least(2 * p.N - 1);
+        if (s.L > tile || force_two_pass) {
+            int64_t q = 1;
+            while (q < 2 * p.N - 1) q <<= 1;
+            if (q <= tile * tile) s.L = q;
+        }
     }
     if (s.L <= tile && !force_two_pass) {
         s.passes = 1;

@@ -152,7 +152,8 @@ def test_checkpoints_match_shorter_runs(lt):
             assert rel(ck[c], ref) < 1e-11, (N, c)
 
 
-@pytest.mark.parametrize("N,d", [(65521, 4), (1 << 16, 3), (4096 * 64, 3)])
+@pytest.mark.parametrize("N,d", [(65521, 4), (1 << 16, 3), (4096 * 64, 3), (8209, 3), (1 << 13, 3),
+                                 (1 << 19, 3), (262147, 3)])
 def test_every_kernel_variant(lt, N, d):
     """All column/row kernel variants give the oracle's result (the autotuner
     may pick any of them)."""
