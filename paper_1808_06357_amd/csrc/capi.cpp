@@ -464,7 +464,21 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
 // block (kinetic-table, resident and two-pass descriptors, block prefix sums)
 struct BatchLayout {
     std::vector<size_t> off;
-    size_t desc = 0, d_ktab = 0, d_res = 0, d_two = 0, d_scol = 0, d_srow = 0, desc_bytes = 0, total = 0;
+    size_t desc = 0, d_ktab = 0, d_res = 0, d_two = 0, d_lists = 0, desc_bytes = 0, total = 0;
+};
+
+// kernel classes of a batch's pass launches: members listed by index into the
+// descriptor array (longest schedules first, so the members still running at
+// pass g are a prefix), with prefix sums of their blocks
+constexpr int kMaxBatchLists = 32;  // general + register-staged classes, columns and rows
+
+struct MemberList {
+    int key = 0;                 // fast length (columns: L1; rows: 2 L2 + multiplier kind), -1 general
+    std::vector<int> mem;        // member indices into the descriptor array
+    std::vector<int> start;      // block prefix sums, size mem + 1
+    std::vector<int64_t> npass;  // per member
+    size_t idx_off = 0, start_off = 0;  // int offsets in the list area
+    int act = 0;                 // members still running at the current pass
 };
 
 BatchLayout batch_layout(int32_t B, const lt_plan *const *plans, int prec)
@@ -484,10 +498,8 @@ BatchLayout batch_layout(int32_t B, const lt_plan *const *plans, int prec)
     d = align_up(d + (size_t)B * sizeof(ResArgs));
     b.d_two = d;
     d = align_up(d + (size_t)B * sizeof(BatchDesc));
-    b.d_scol = d;
-    d = align_up(d + (size_t)(B + 1) * sizeof(int));
-    b.d_srow = d;
-    d = align_up(d + (size_t)(B + 1) * sizeof(int));
+    b.d_lists = d;  // each member once in a column list and once in a row list
+    d = align_up(d + (size_t)(4 * B + 2 * kMaxBatchLists) * sizeof(int));
     b.desc_bytes = d;
     b.total = off + d;
     return b;
@@ -1006,17 +1018,50 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
     std::stable_sort(two.begin(), two.end(),
                      [](const BatchDesc &a, const BatchDesc &b) { return a.npass > b.npass; });
     const int n2 = (int)two.size();
-    std::vector<int> scol(n2 + 1, 0), srow(n2 + 1, 0);
+    // column and row kernel classes: register-staged passes where the length
+    // has one (two passes per step only), the general kernel otherwise
+    std::vector<MemberList> cols(1), rows(1);
+    cols[0].key = rows[0].key = -1;
+    auto list_for = [](std::vector<MemberList> &ls, int key) -> MemberList & {
+        for (auto &l : ls)
+            if (l.key == key) return l;
+        ls.emplace_back();
+        ls.back().key = key;
+        return ls.back();
+    };
     for (int i = 0; i < n2; ++i) {
-        scol[i + 1] = scol[i] + two[i].col[0].ntiles;
-        srow[i + 1] = srow[i] + two[i].row[0].nblk;
+        const BatchDesc &b = two[i];
+        const ColArgs &pc = b.col[1];
+        const RowArgs &pr = b.row[0];
+        const bool fc = !b.bluestein && pc.v && fast_col_fits(prec, 1, pc.L1, pc.L2, pc.C);
+        const bool fr = !b.bluestein && fast_row_fits(prec, 1, pr.L1, pr.L2, pr.rows);
+        MemberList &lc = fc ? list_for(cols, pc.L1) : cols[0];
+        MemberList &lr = fr ? list_for(rows, 2 * pr.L2 + (pr.bhat ? 0 : 1)) : rows[0];
+        lc.mem.push_back(i);
+        lc.npass.push_back(b.npass);
+        lr.mem.push_back(i);
+        lr.npass.push_back(b.npass);
+    }
+    if ((int)(cols.size() + rows.size()) > kMaxBatchLists) return fail(LT_E_UNSUPPORTED, "too many kernel classes");
+    std::vector<int> lists;
+    for (auto *ls : {&cols, &rows}) {
+        const bool is_col = ls == &cols;
+        for (auto &l : *ls) {
+            l.start.assign(1, 0);
+            for (int i : l.mem)
+                l.start.push_back(l.start.back() + (is_col ? two[i].col[0].ntiles : two[i].row[0].nblk));
+            l.idx_off = lists.size();
+            lists.insert(lists.end(), l.mem.begin(), l.mem.end());
+            l.start_off = lists.size();
+            lists.insert(lists.end(), l.start.begin(), l.start.end());
+            l.act = (int)l.mem.size();
+        }
     }
     std::vector<char> blob(BL.desc_bytes, 0);
     std::memcpy(blob.data() + BL.d_ktab, kd.data(), kd.size() * sizeof(KtabDesc));
     if (!res.empty()) std::memcpy(blob.data() + BL.d_res, res.data(), res.size() * sizeof(ResArgs));
     if (n2) std::memcpy(blob.data() + BL.d_two, two.data(), two.size() * sizeof(BatchDesc));
-    std::memcpy(blob.data() + BL.d_scol, scol.data(), scol.size() * sizeof(int));
-    std::memcpy(blob.data() + BL.d_srow, srow.data(), srow.size() * sizeof(int));
+    std::memcpy(blob.data() + BL.d_lists, lists.data(), lists.size() * sizeof(int));
     char *dd = at(sc.ptr, BL.desc);
     if ((st = upload_async(dd, blob.data(), blob.size(), hs))) return st;
     HIP_TRY(launch_ktab_multi((const KtabDesc *)(dd + BL.d_ktab), (int)kd.size(), max_ktab, hs),
@@ -1038,14 +1083,34 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
         HIP_TRY(launch_resident_multi(prec, (const ResArgs *)(dd + BL.d_res), (int)res.size(), lds_res, rs),
                 "resident batch");
     const BatchDesc *dtwo = (const BatchDesc *)(dd + BL.d_two);
-    const int *dscol = (const int *)(dd + BL.d_scol), *dsrow = (const int *)(dd + BL.d_srow);
-    int act = n2;
+    const int *dl = (const int *)(dd + BL.d_lists);
     const int64_t gmax = n2 ? two[0].npass : 0;
     int herr = 0;
     for (int64_t g = 0; g < gmax && !herr; ++g) {
-        while (act > 0 && two[act - 1].npass <= g) --act;
-        if (g & 1) herr = launch_row_multi(prec, dtwo, dsrow, act, srow[act], g, lds_row, hs);
-        else herr = launch_col_multi(prec, dtwo, dscol, act, scol[act], g, lds_col, hs);
+        const bool col = !(g & 1);
+        for (auto &l : col ? cols : rows) {
+            while (l.act > 0 && l.npass[l.act - 1] <= g) --l.act;
+            if (herr || l.act == 0) continue;
+            const int *idx = dl + l.idx_off, *start = dl + l.start_off;
+            if (!col) {
+                herr = l.key < 0 ? launch_row_multi(prec, dtwo, idx, start, l.act, l.start[l.act], 0, g, lds_row, hs)
+                                 : launch_row_fast_multi(prec, l.key / 2, l.key % 2, dtwo, idx, start, l.act,
+                                                         l.start[l.act], 0, g, hs);
+                continue;
+            }
+            if (l.key < 0 || g == 0) {  // general kernel: every role (the first pass of every member)
+                herr = launch_col_multi(prec, dtwo, idx, start, l.act, l.start[l.act], 0, g, lds_col, hs);
+                continue;
+            }
+            // register-staged interior passes, then the general kernel for the
+            // members whose last pass this is (a contiguous range [a, act))
+            herr = launch_col_fast_multi(prec, l.key, dtwo, idx, start, l.act, l.start[l.act], 0, g, hs);
+            int a = l.act;
+            while (a > 0 && l.npass[a - 1] == g + 1) --a;
+            if (!herr && a < l.act)
+                herr = launch_col_multi(prec, dtwo, idx, start, l.act, l.start[l.act] - l.start[a], l.start[a], g,
+                                        lds_col, hs);
+        }
     }
     if (ev_fork) {  // join even after a failed launch: the workspace must outlive the side stream's work
         if (!herr) herr = (int)hipEventRecord(ev_join, rs);

@@ -133,6 +133,18 @@ __device__ __forceinline__ void powers(double wr, double wi, double (&pr)[R], do
     }
 }
 
+// member k of a batch list with start[k] <= bid < start[k+1] (binary search)
+__device__ __forceinline__ int find_member(const int *start, int n, int bid)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (start[mid] <= bid) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // floor(x / d) by a double reciprocal, for 0 <= x < 2^50 and d >= 1: the
 // quotient (x + 1/2) / d lies at least 1/(2d) from an integer, far beyond the
 // relative error 2^-52 of the two roundings

@@ -391,47 +391,41 @@ __global__ void __launch_bounds__(kThreads) k_resident(ResArgs a)
 }
 
 // ---------------------------------------------------------------- batches of unrelated problems
-// One launch advances pass g of every two-pass problem of a batch.  Problem i
-// owns global blocks [start[i], start[i+1]) of the launch (column tiles or
-// row blocks); its role at pass g follows its schedule:
-//   smooth N:  g = 0 first, odd g row, other g potential P^2, last g last;
-//   chirp-z:   g = 0 first, g = 1, 3 mod 4 row (spectrum, conjugate spectrum),
-//              g = 2 mod 4 kinetic, g = 0 mod 4 potential, last g last.
-__device__ __forceinline__ int find_problem(const int *start, int ninst, int bid)
-{
-    int lo = 0, hi = ninst;  // start[lo] <= bid < start[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) / 2;
-        if (start[mid] <= bid) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
+// One launch runs pass g of the batch members listed in idx; member k owns
+// the blocks [start[k], start[k+1]) of the launch's block range, which begins
+// at block `off` (column tiles or row blocks).  A member's role at pass g
+// follows its schedule:
+//   two passes per step:  g = 0 first, odd g row, other g potential P^2, last g last;
+//   chirp-z DFT pairs:    g = 0 first, g = 1, 3 mod 4 row (spectrum, conjugate
+//                         spectrum), g = 2 mod 4 kinetic, g = 0 mod 4 potential, last g last.
 template <typename T, int EPT>
-__global__ void __launch_bounds__(kThreads) k_col_multi(const BatchDesc *d, const int *start, int ninst, int64_t g)
+__global__ void __launch_bounds__(kThreads) k_col_multi(const BatchDesc *d, const int *idx, const int *start,
+                                                        int nmem, int off, int64_t g)
 {
     extern __shared__ char smem_raw[];
-    const int i = find_problem(start, ninst, blockIdx.x);
-    const BatchDesc &p = d[i];
+    const int bid = blockIdx.x + off;
+    const int k = find_member(start, nmem, bid);
+    const BatchDesc &p = d[idx[k]];
     if (g >= p.npass || (g & 1)) return;
     int role;
     if (g == 0) role = 0;
     else if (g == p.npass - 1) role = 3;
     else if (p.bluestein && (g % 4) == 2) role = 2;
     else role = 1;
-    col_body<T, EPT>(p.col[role], blockIdx.x - start[i], 0, reinterpret_cast<cx<T> *>(smem_raw));
+    col_body<T, EPT>(p.col[role], bid - start[k], 0, reinterpret_cast<cx<T> *>(smem_raw));
 }
 
 template <typename T, int EPT>
-__global__ void __launch_bounds__(kThreads) k_row_multi(const BatchDesc *d, const int *start, int ninst, int64_t g)
+__global__ void __launch_bounds__(kThreads) k_row_multi(const BatchDesc *d, const int *idx, const int *start,
+                                                        int nmem, int off, int64_t g)
 {
     extern __shared__ char smem_raw[];
-    const int i = find_problem(start, ninst, blockIdx.x);
-    const BatchDesc &p = d[i];
+    const int bid = blockIdx.x + off;
+    const int k = find_member(start, nmem, bid);
+    const BatchDesc &p = d[idx[k]];
     if (g >= p.npass || !(g & 1)) return;
     const int role = (p.bluestein && (g % 4) == 3) ? 1 : 0;
-    row_body<T, EPT>(p.row[role], blockIdx.x - start[i], 0, reinterpret_cast<cx<T> *>(smem_raw));
+    row_body<T, EPT>(p.row[role], bid - start[k], 0, reinterpret_cast<cx<T> *>(smem_raw));
 }
 
 template <typename T, int EPT>
@@ -665,24 +659,24 @@ int launch_resident(int prec, const Sched &s, const ResArgs &a, int batch, void 
     return timed_launch(LT_KIND_RESIDENT, k_resident<float, 16>, dim3(batch), dim3(kThreads), lds, stream, a);
 }
 
-int launch_col_multi(int prec, const BatchDesc *d, const int *start, int ninst, int nblocks, int64_t g,
-                     size_t lds, void *stream)
+int launch_col_multi(int prec, const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks,
+                     int off, int64_t g, size_t lds, void *stream)
 {
     if (prec == LT_C128)
         return timed_launch(LT_KIND_COLUMN, k_col_multi<double, 16>, dim3(nblocks), dim3(kThreads), lds, stream,
-                            d, start, ninst, g);
+                            d, idx, start, nmem, off, g);
     return timed_launch(LT_KIND_COLUMN, k_col_multi<float, 16>, dim3(nblocks), dim3(kThreads), lds, stream, d,
-                        start, ninst, g);
+                        idx, start, nmem, off, g);
 }
 
-int launch_row_multi(int prec, const BatchDesc *d, const int *start, int ninst, int nblocks, int64_t g,
-                     size_t lds, void *stream)
+int launch_row_multi(int prec, const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks,
+                     int off, int64_t g, size_t lds, void *stream)
 {
     if (prec == LT_C128)
         return timed_launch(LT_KIND_ROW, k_row_multi<double, 16>, dim3(nblocks), dim3(kThreads), lds, stream,
-                            d, start, ninst, g);
-    return timed_launch(LT_KIND_ROW, k_row_multi<float, 16>, dim3(nblocks), dim3(kThreads), lds, stream, d,
-                        start, ninst, g);
+                            d, idx, start, nmem, off, g);
+    return timed_launch(LT_KIND_ROW, k_row_multi<float, 16>, dim3(nblocks), dim3(kThreads), lds, stream, d, idx,
+                        start, nmem, off, g);
 }
 
 int launch_ktab_multi(const KtabDesc *d, int count, int64_t max_len, void *stream)

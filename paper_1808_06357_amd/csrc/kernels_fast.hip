@@ -169,19 +169,17 @@ __device__ __forceinline__ void tw4_series(double (&wr)[R], double (&wi)[R], int
 }
 
 // Steady-state column pass: [inverse column DFT -> point-domain multiplier
-// (and chirp-z mask) -> forward column DFT], in place.  MID 0: the merged
-// potential step from the per-point table; MID 1: the chirp-z kinetic step
-// from the table indexed by the squared norm.
-template <typename T, int E, int NT, int MINW, int MID, int... Rs>
-__global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
+// (and chirp-z mask) -> forward column DFT], in place, on column tile `tile`
+// of batch item b.  MID 0: the merged potential step (complex64: from the
+// per-point table; complex128: FP64 phase of v); MID 1: the chirp-z kinetic
+// step from the table indexed by the squared norm; MID 2: the merged
+// potential step from v in FP64 (both precisions; batches carry no table).
+template <typename T, int E, int NT, int MID, int... Rs>
+__device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
 {
     using F = Fft<T, E, NT, true, Rs...>;
     constexpr int C = F::SEQ, J = F::J, R = F::R, BPS = F::BPS, L1 = F::L, TILE = F::TILE;
-    extern __shared__ char smem_raw[];
-    cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
     const int L2 = a.L2;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t b = blockIdx.y;
     const int c0 = tile * C;
     cx<T> *buf = (cx<T> *)a.buf + b * a.buf_bs;
     typename F::Bases B;
@@ -230,8 +228,8 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
                 v[j * R + r] = n < a.Nvalid ? twmul(conjg(v[j * R + r]), pin[j][r]) : cx<T>{0, 0};
             }
         }
-    } else if constexpr (MID == 0) {
-        // complex128: exp(-i phase v) in FP64 on the fly (the table would cost
+    } else if constexpr (MID == 0 || MID == 2) {
+        // complex128 (and batches): exp(-i phase v) in FP64 on the fly (the table would cost
         // as many bytes as v and more registers than the kernel has)
         double pin[J][R];
 #pragma unroll
@@ -295,17 +293,38 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
     (void)TILE;
 }
 
+template <typename T, int E, int NT, int MINW, int MID, int... Rs>
+__global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
+{
+    extern __shared__ char smem_raw[];
+    colf_body<T, E, NT, MID, Rs...>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.y,
+                                    reinterpret_cast<cx<T> *>(smem_raw));
+}
+
+// Pass g of the batch members listed in idx (prefix sums of their column
+// tiles in start, block offset off): the merged potential step of each
+// member whose schedule is at an interior column pass; first and last
+// column passes take the general kernel.
+template <typename T, int E, int NT, int MINW, int... Rs>
+__global__ void __launch_bounds__(NT, MINW) k_colf_multi(const BatchDesc *d, const int *idx, const int *start,
+                                                          int nmem, int off, int64_t g)
+{
+    extern __shared__ char smem_raw[];
+    const int bid = blockIdx.x + off;
+    const int k = find_member(start, nmem, bid);
+    const BatchDesc &p = d[idx[k]];
+    if (g == 0 || (g & 1) || g >= p.npass - 1) return;
+    colf_body<T, E, NT, 2, Rs...>(p.col[1], bid - start[k], 0, reinterpret_cast<cx<T> *>(smem_raw));
+}
+
 // Row pass: [DFT -> spectral multiplier -> inverse DFT], in place; the
 // multiplier (chirp-z kernel spectrum or kinetic table) is applied in registers.
-template <typename T, int E, int NT, int MINW, int MID, int... Rs>
-__global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
+template <typename T, int E, int NT, int MID, int... Rs>
+__device__ __forceinline__ void rowf_body(const RowArgs &a, int blk, int64_t b, cx<T> *s)
 {
     using F = Fft<T, E, NT, false, Rs...>;
     constexpr int L2 = F::L, RW = F::SEQ, J = F::J, R = F::R, BPS = F::BPS, TILE = F::TILE;
-    extern __shared__ char smem_raw[];
-    cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
-    const int r0 = blockIdx.x * RW;
-    const int64_t b = blockIdx.y;
+    const int r0 = blk * RW;
     cx<T> *buf = (cx<T> *)a.buf + b * a.buf_bs + (int64_t)r0 * L2;
     typename F::Bases B;
     F::load_bases(B, (const Tw<T> *)a.twb);
@@ -367,6 +386,28 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
     }
 }
 
+template <typename T, int E, int NT, int MINW, int MID, int... Rs>
+__global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
+{
+    extern __shared__ char smem_raw[];
+    rowf_body<T, E, NT, MID, Rs...>(a, blockIdx.x, blockIdx.y, reinterpret_cast<cx<T> *>(smem_raw));
+}
+
+// Row pass g of the batch members listed in idx (prefix sums of their row
+// blocks in start, block offset off); MID 0: spectrum table, MID 1: kinetic
+// table, as in k_rowf.
+template <typename T, int E, int NT, int MINW, int MID, int... Rs>
+__global__ void __launch_bounds__(NT, MINW) k_rowf_multi(const BatchDesc *d, const int *idx, const int *start,
+                                                          int nmem, int off, int64_t g)
+{
+    extern __shared__ char smem_raw[];
+    const int bid = blockIdx.x + off;
+    const int k = find_member(start, nmem, bid);
+    const BatchDesc &p = d[idx[k]];
+    if (!(g & 1) || g >= p.npass) return;
+    rowf_body<T, E, NT, MID, Rs...>(p.row[0], bid - start[k], 0, reinterpret_cast<cx<T> *>(smem_raw));
+}
+
 // ---------------------------------------------------------------- dispatch
 // Variant 1: 256 threads x 16 elements (radix 16 / 8); variant 2: 512 threads
 // x 8 elements (radix 8 / 4, twice the waves per CU).  Both hold a
@@ -393,6 +434,19 @@ int timed(int kind, K kernel, dim3 grid, dim3 block, size_t lds, void *stream, c
                               args);
     else
         hipLaunchKernelGGL(kernel, grid, block, lds, (hipStream_t)stream, args);
+    return (int)hipGetLastError();
+}
+
+template <typename K, typename... A>
+int timed_multi(int kind, K kernel, dim3 grid, dim3 block, size_t lds, void *stream, A... args)
+{
+    void *e0 = nullptr, *e1 = nullptr;
+    timing_events(kind, &e0, &e1);
+    if (e0)
+        hipExtLaunchKernelGGL(kernel, grid, block, lds, (hipStream_t)stream, (hipEvent_t)e0, (hipEvent_t)e1, 0,
+                              args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, (hipStream_t)stream, args...);
     return (int)hipGetLastError();
 }
 
@@ -480,6 +534,57 @@ int go(int L, const A &a, int batch, void *stream)
 }
 
 bool fast_len(int L) { return L >= 64 && L <= 4096 && (L & (L - 1)) == 0; }
+
+template <typename T, int... Rs>
+int col_multi_go(const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks, int off, int64_t g,
+                 void *stream)
+{
+    constexpr int NT = Geo<1>::NT, E = Geo<1>::E, MINW = Geo<1>::MINW;
+    auto k = k_colf_multi<T, E, NT, MINW, Rs...>;
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    return timed_multi(LT_KIND_COLUMN, k, dim3(nblocks), dim3(NT), lds_bytes<T, 1>(), stream, d, idx, start, nmem,
+                       off, g);
+}
+
+template <typename T, int MID, int... Rs>
+int row_multi_go(const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks, int off, int64_t g,
+                 void *stream)
+{
+    constexpr int NT = Geo<1>::NT, E = Geo<1>::E, MINW = Geo<1>::MINW;
+    auto k = k_rowf_multi<T, E, NT, MINW, MID, Rs...>;
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    return timed_multi(LT_KIND_ROW, k, dim3(nblocks), dim3(NT), lds_bytes<T, 1>(), stream, d, idx, start, nmem,
+                       off, g);
+}
+
+// radix sequences of the 16-elements-per-thread geometry (as in go<T, 1, ...>)
+template <typename T, bool COL, int MID>
+int multi_go(int L, const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks, int off,
+             int64_t g, void *stream)
+{
+#define LT_MULTI(...)                                                                              \
+    (COL ? col_multi_go<T, __VA_ARGS__>(d, idx, start, nmem, nblocks, off, g, stream)              \
+         : row_multi_go<T, MID, __VA_ARGS__>(d, idx, start, nmem, nblocks, off, g, stream))
+    switch (L) {
+    case 64: return LT_MULTI(8, 8);
+    case 128: return LT_MULTI(8, 2, 8);
+    case 256: return LT_MULTI(16, 16);
+    case 512: return LT_MULTI(8, 8, 8);
+    case 1024: return LT_MULTI(16, 4, 16);
+    case 2048: return LT_MULTI(16, 8, 16);
+    case 4096: return LT_MULTI(16, 16, 16);
+    default: return -1;
+    }
+#undef LT_MULTI
+}
 constexpr int kTile = 4096;
 }  // namespace
 
@@ -514,6 +619,23 @@ int launch_row_fast(int prec, int variant, const RowArgs &a, int batch, void *st
     if (prec == LT_C128)
         return variant == 1 ? go<double, 1, false>(a.L2, a, batch, stream) : go<double, 2, false>(a.L2, a, batch, stream);
     return variant == 1 ? go<float, 1, false>(a.L2, a, batch, stream) : go<float, 2, false>(a.L2, a, batch, stream);
+}
+
+int launch_col_fast_multi(int prec, int L1, const BatchDesc *d, const int *idx, const int *start, int nmem,
+                          int nblocks, int off, int64_t g, void *stream)
+{
+    if (prec == LT_C128) return multi_go<double, true, 0>(L1, d, idx, start, nmem, nblocks, off, g, stream);
+    return multi_go<float, true, 0>(L1, d, idx, start, nmem, nblocks, off, g, stream);
+}
+
+int launch_row_fast_multi(int prec, int L2, int mid, const BatchDesc *d, const int *idx, const int *start,
+                          int nmem, int nblocks, int off, int64_t g, void *stream)
+{
+    if (prec == LT_C128)
+        return mid ? multi_go<double, false, 1>(L2, d, idx, start, nmem, nblocks, off, g, stream)
+                   : multi_go<double, false, 0>(L2, d, idx, start, nmem, nblocks, off, g, stream);
+    return mid ? multi_go<float, false, 1>(L2, d, idx, start, nmem, nblocks, off, g, stream)
+               : multi_go<float, false, 0>(L2, d, idx, start, nmem, nblocks, off, g, stream);
 }
 
 }  // namespace lt

@@ -142,10 +142,16 @@ int launch_col(int prec, const Sched &s, const ColArgs &a, int batch, void *stre
 int launch_row(int prec, const Sched &s, const RowArgs &a, int batch, void *stream);
 int launch_resident(int prec, const Sched &s, const ResArgs &a, int batch, void *stream);
 int launch_fft_single(const Radices &ra, const void *twa_c128, void *buf, int64_t L, void *stream);
-int launch_col_multi(int prec, const BatchDesc *d, const int *start, int ninst, int nblocks, int64_t g,
-                     size_t lds, void *stream);
-int launch_row_multi(int prec, const BatchDesc *d, const int *start, int ninst, int nblocks, int64_t g,
-                     size_t lds, void *stream);
+int launch_col_multi(int prec, const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks,
+                     int off, int64_t g, size_t lds, void *stream);
+int launch_row_multi(int prec, const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks,
+                     int off, int64_t g, size_t lds, void *stream);
+// register-staged multi-member passes (kernels_fast.hip); -1 when the length
+// has no such pass
+int launch_col_fast_multi(int prec, int L1, const BatchDesc *d, const int *idx, const int *start, int nmem,
+                          int nblocks, int off, int64_t g, void *stream);
+int launch_row_fast_multi(int prec, int L2, int mid, const BatchDesc *d, const int *idx, const int *start,
+                          int nmem, int nblocks, int off, int64_t g, void *stream);
 int launch_resident_multi(int prec, const ResArgs *d, int ninst, size_t lds, void *stream);
 int launch_ktab_multi(const KtabDesc *d, int count, int64_t max_len, void *stream);
 int launch_permute_c128(void *dst, const void *src_nat, int64_t L, int L1, int L2, int transposed,

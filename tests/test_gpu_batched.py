@@ -94,12 +94,13 @@ def test_mixed_batch_against_oracle(lt, mixed, prec):
 
 def test_batch_equals_single_runs(lt, mixed):
     """Each problem of the batch gives what strang_run gives on its own with the
-    same (general) kernels."""
+    same kernels (register-staged passes of the 256-thread geometry where the
+    length has one, the general passes otherwise)."""
     import torch
     probs, plans, _ = mixed
     got = run_batched(lt, plans, probs, "c128")
     for i, (pl, p) in enumerate(zip(plans, probs)):
-        lt.lattice_plan_set_kernels(pl, lt.LT_C128, 0, 0)
+        lt.lattice_plan_set_kernels(pl, lt.LT_C128, 1, 1)
         u = torch.tensor(p["u0"], dtype=torch.complex128, device="cuda")
         v = torch.tensor(p["v"], dtype=torch.float64, device="cuda")
         lt.strang_run(pl, v, u, p["gamma"], p["dt"], p["steps"])
