@@ -620,8 +620,9 @@ int kernels_init()
 
 int launch_col(int prec, const Sched &s, const ColArgs &a, int batch, void *stream)
 {
-    if (s.col_var > 0 && !a.adjoint) {
-        const int r = launch_col_fast(prec, s.col_var, a, batch, stream);
+    if (s.col_var > 0) {
+        const int r = a.adjoint ? launch_col_fast_adjoint(prec, s.col_var, a, batch, stream)
+                                : launch_col_fast(prec, s.col_var, a, batch, stream);
         if (r >= 0) return r;
     }
     const int nvec = a.adjoint ? 2 : 1;

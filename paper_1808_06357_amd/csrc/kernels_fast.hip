@@ -301,6 +301,100 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
                                     reinterpret_cast<cx<T> *>(smem_raw));
 }
 
+// Interior merge pass of the adjoint sweep (no checkpoint reset, no chirp):
+// the tile holds C/2 state columns (sequences q < C/2, buffer buf) and the
+// same C/2 cotangent columns (sequences q >= C/2, buffer buf2).  After the
+// inverse column DFTs the two values of each point meet through LDS:
+// a = state, mu = cotangent; dJ/dv[n] += gcoef Im(conj(mu) a); both are
+// multiplied by exp(-i phase v[n]); then the forward column DFTs.
+template <typename T, int E, int NT, int MINW, int... Rs>
+__global__ void __launch_bounds__(NT, MINW) k_colf_adj(ColArgs a)
+{
+    using F = Fft<T, E, NT, true, Rs...>;
+    constexpr int C = F::SEQ, H = C / 2, J = F::J, R = F::R, BPS = F::BPS, L1 = F::L;
+    static_assert(C % 2 == 0, "state and cotangent columns pair up");
+    extern __shared__ char smem_raw[];
+    cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
+    const int L2 = a.L2;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t b = blockIdx.y;
+    const int c0 = tile * H;
+    cx<T> *buf0 = (cx<T> *)a.buf + b * a.buf_bs;
+    cx<T> *buf1 = (cx<T> *)a.buf2 + b * a.buf2_bs;
+    typename F::Bases B;
+    F::load_bases(B, (const Tw<T> *)a.twa);
+    cx<T> v[E];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int bf = threadIdx.x + j * NT;
+        const int q = F::q_of(bf), t = F::t_of(bf);
+        const int n2 = c0 + (q < H ? q : q - H);
+        cx<T> *bq = q < H ? buf0 : buf1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[j * R + r] = conjg(bq[(int64_t)(t + r * BPS) * L2 + n2]);
+        if (a.twiddle) {
+            double wr[R], wi[R];
+            tw4_series<R>(wr, wi, n2, t, BPS, L2, a.tw4hi, a.tw4lo);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[j * R + r] = cmul_d(v[j * R + r], wr[r], wi[r]);
+        }
+    }
+    F::run(v, s, B, false);
+    // pair the two vectors of each point through LDS
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int bf = threadIdx.x + j * NT;
+        const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[F::addr(q, t + r * BPS)] = conjg(v[j * R + r]);
+    }
+    __syncthreads();
+    const double *vb = a.v + b * a.v_bs;
+    double *gb = a.gacc + b * a.gacc_bs;
+    for (int i = threadIdx.x; i < H * L1; i += NT) {
+        const int k1 = i / H, q = i - k1 * H;
+        const int64_t n = (int64_t)k1 * L2 + c0 + q;
+        const int ax = F::addr(q, k1), ay = F::addr(q + H, k1);
+        if (n >= a.Nvalid) {
+            s[ax] = {0, 0};
+            s[ay] = {0, 0};
+            continue;
+        }
+        const cx<T> x = s[ax], y = s[ay];
+        const double im = (double)y.x * (double)x.y - (double)y.y * (double)x.x;
+        gb[n] += a.gcoef * im;
+        double c, sn;
+        expm_i(a.phase * vb[n], c, sn);
+        s[ax] = cmul_d(x, c, sn);
+        s[ay] = cmul_d(y, c, sn);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int bf = threadIdx.x + j * NT;
+        const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[j * R + r] = s[F::addr(q, t + r * BPS)];
+    }
+    F::run(v, s, B, true);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int bf = threadIdx.x + j * NT;
+        const int q = F::q_of(bf), t = F::t_of(bf);
+        const int n2 = c0 + (q < H ? q : q - H);
+        cx<T> *bq = q < H ? buf0 : buf1;
+        if (a.twiddle) {
+            double wr[R], wi[R];
+            tw4_series<R>(wr, wi, n2, t, BPS, L2, a.tw4hi, a.tw4lo);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[j * R + r] = cmul_d(v[j * R + r], wr[r], wi[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) bq[(int64_t)(t + r * BPS) * L2 + n2] = v[j * R + r];
+    }
+}
+
 // Pass g of the batch members listed in idx (prefix sums of their column
 // tiles in start, block offset off): the merged potential step of each
 // member whose schedule is at an interior column pass; first and last
@@ -619,6 +713,43 @@ int launch_row_fast(int prec, int variant, const RowArgs &a, int batch, void *st
     if (prec == LT_C128)
         return variant == 1 ? go<double, 1, false>(a.L2, a, batch, stream) : go<double, 2, false>(a.L2, a, batch, stream);
     return variant == 1 ? go<float, 1, false>(a.L2, a, batch, stream) : go<float, 2, false>(a.L2, a, batch, stream);
+}
+
+template <typename T, int... Rs>
+int adj_go(const ColArgs &a, int batch, void *stream)
+{
+    constexpr int NT = Geo<1>::NT, E = Geo<1>::E, MINW = Geo<1>::MINW;
+    auto k = k_colf_adj<T, E, NT, MINW, Rs...>;
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    constexpr int H = NT * E / Radix<Rs...>::prod / 2;
+    return timed_multi(LT_KIND_COLUMN, k, dim3(a.L2 / H, batch), dim3(NT), lds_bytes<T, 1>(), stream, a);
+}
+
+template <typename T>
+int adj_dispatch(const ColArgs &a, int batch, void *stream)
+{
+    switch (a.L1) {  // 4096-point columns leave one column per tile: no pairing
+    case 64: return adj_go<T, 8, 8>(a, batch, stream);
+    case 128: return adj_go<T, 8, 2, 8>(a, batch, stream);
+    case 256: return adj_go<T, 16, 16>(a, batch, stream);
+    case 512: return adj_go<T, 8, 8, 8>(a, batch, stream);
+    case 1024: return adj_go<T, 16, 4, 16>(a, batch, stream);
+    case 2048: return adj_go<T, 16, 8, 16>(a, batch, stream);
+    default: return -1;
+    }
+}
+
+int launch_col_fast_adjoint(int prec, int variant, const ColArgs &a, int batch, void *stream)
+{
+    if (variant < 1 || a.adjoint != 2 || a.reset || a.chirp || !a.pre_inv || !a.post_fwd || a.in || a.out ||
+        !fast_len(a.L1) || a.L1 > 2048 || a.C != kTile / a.L1 / 2 || a.L2 % a.C)
+        return -1;
+    if (prec == LT_C128) return adj_dispatch<double>(a, batch, stream);
+    return adj_dispatch<float>(a, batch, stream);
 }
 
 int launch_col_fast_multi(int prec, int L1, const BatchDesc *d, const int *idx, const int *start, int nmem,

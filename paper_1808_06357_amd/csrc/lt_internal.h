@@ -146,6 +146,8 @@ int launch_col_multi(int prec, const BatchDesc *d, const int *idx, const int *st
                      int off, int64_t g, size_t lds, void *stream);
 int launch_row_multi(int prec, const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks,
                      int off, int64_t g, size_t lds, void *stream);
+// register-staged interior merge pass of the adjoint sweep; -1 when it does not apply
+int launch_col_fast_adjoint(int prec, int variant, const ColArgs &a, int batch, void *stream);
 // register-staged multi-member passes (kernels_fast.hip); -1 when the length
 // has no such pass
 int launch_col_fast_multi(int prec, int L1, const BatchDesc *d, const int *idx, const int *start, int nmem,
