@@ -197,6 +197,29 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
                              size_t work_bytes, void *stream);
 
 /*
+ * lattice_diagnostics -- the conserved quantities of Sec. 3.3 for `batch`
+ * states of lattice values u: the L2 norm^2 and the energy <H u, u> with
+ * H = -(gamma/2) lap + v/gamma, on the lattice
+ *   norm^2 = (1/N) sum_k |u_k|^2,
+ *   E      = (1/N) [ sum_xi 2 pi^2 gamma ||h_xi||^2 |U_xi|^2 + (1/gamma) sum_k v_k |u_k|^2 ],
+ * U = F u the unitary lattice DFT (eq. (Fn) / (Fnx)), so that uhat = U / sqrt(N)
+ * are the coefficients on the anti-aliasing set (Parseval).  The transform runs in
+ * the precision of u; every sum accumulates in double.
+ *   v      device, N doubles per state (v_stride as in strang_run).
+ *   u      device, batch x N complex of `prec` (not modified).
+ *   out    device, batch x 2 doubles: (norm^2, E) per state.
+ *   work   device workspace of at least lattice_diagnostics_workspace_size
+ *          bytes, or NULL.
+ * With strang_run's checkpoints as u this gives the norm and energy history
+ * of a run (every ckpt_every steps).
+ */
+lt_status lattice_diagnostics_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch,
+                                             size_t *bytes);
+lt_status lattice_diagnostics(const lt_plan *p, lt_prec prec, int32_t batch, const double *v,
+                              int64_t v_stride, const void *u, double gamma, double *out,
+                              void *work, size_t work_bytes, void *stream);
+
+/*
  * Kernel selection for two-pass schedules.  Each column / row pass can run
  * on one of several kernels with identical results (within rounding):
  *   0 = general LDS Stockham kernel (any 7-smooth length),

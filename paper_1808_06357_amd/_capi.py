@@ -67,6 +67,8 @@ _SIGS = {
     "strang_adjoint": [_P, _i32, _i32, _P, _i64, _P, _P, _f64, _f64, _i64, _P, _i64, _P, _P, _P, _sz, _P],
     "strang_batched_workspace_size": [_i32, _P, _i32, ctypes.POINTER(_sz)],
     "strang_run_batched": [_i32, _P, _i32, _P, _P, _P, _P, _P, _P, _sz, _P],
+    "lattice_diagnostics_workspace_size": [_P, _i32, _i32, ctypes.POINTER(_sz)],
+    "lattice_diagnostics": [_P, _i32, _i32, _P, _i64, _P, _f64, _P, _P, _sz, _P],
     "lattice_plan_autotune": [_P, _i32, _i32, _P],
     "lattice_plan_set_kernels": [_P, _i32, _i32, _i32],
     "lattice_plan_get_kernels": [_P, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
@@ -293,6 +295,37 @@ def strang_run_batched(plans: Sequence[Plan], vs, us, gammas, dts, steps, work=N
     _check(lib.strang_run_batched(B, parr, prec, varr, uarr, _np_ptr(g), _np_ptr(dtt), _np_ptr(st),
                                   _dev_ptr(work), wb, _stream(stream)), "strang_run_batched")
     return us
+
+
+def lattice_diagnostics_workspace_size(plan: Plan, prec: int, batch: int) -> int:
+    n = _sz()
+    _check(lib.lattice_diagnostics_workspace_size(plan.handle, prec, batch, ctypes.byref(n)),
+           "lattice_diagnostics_workspace_size")
+    return n.value
+
+
+def lattice_diagnostics(plan: Plan, v, u, gamma: float, out=None, work=None, stream=None):
+    """(norm^2, energy) of each state of u (device, (N,) or (batch, N)) under v
+    (device float64, (N,) shared or (batch, N)): a (batch, 2) float64 tensor."""
+    import torch
+    N = plan.N
+    prec = _prec_of(u)
+    batch = u.numel() // N
+    _check_dev(u, "u", numel=batch * N)
+    _check_dev(v, "v", torch.float64)
+    if v.numel() not in (N, batch * N):
+        raise ValueError("v must hold N or batch*N values")
+    if out is None:
+        out = torch.empty((batch, 2), dtype=torch.float64, device=u.device)
+    _check_dev(out, "out", torch.float64, 2 * batch)
+    wb = 0
+    if work is not None:
+        _check_dev(work, "work")
+        wb = work.numel() * work.element_size()
+    _check(lib.lattice_diagnostics(plan.handle, prec, batch, _dev_ptr(v), 0 if v.numel() == N else N, _dev_ptr(u),
+                                   float(gamma), _dev_ptr(out), _dev_ptr(work), wb, _stream(stream)),
+           "lattice_diagnostics")
+    return out
 
 
 LT_KIND_COLUMN, LT_KIND_ROW, LT_KIND_RESIDENT = 0, 1, 2

@@ -1123,6 +1123,97 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
     return LT_OK;
 }
 
+// ---------------------------------------------------------------- diagnostics
+// workspace: the transform buffer (batch x L), the chirp-z spectrum in natural
+// order (batch x N), point and spectral partial sums
+struct DiagWork {
+    size_t w = 0, nat = 0, pp = 0, ps = 0, total = 0;
+};
+
+DiagWork diag_layout(const lt_plan &p, const Sched &s, int prec, int batch)
+{
+    DiagWork d;
+    size_t off = 0;
+    d.w = off;
+    off = align_up(off + (size_t)batch * s.L * esz(prec));
+    d.nat = off;
+    if (s.bluestein) off = align_up(off + (size_t)batch * p.N * esz(prec));
+    d.pp = off;
+    off = align_up(off + (size_t)batch * diag_partials() * 2 * sizeof(double));
+    d.ps = off;
+    off = align_up(off + (size_t)batch * diag_partials() * 2 * sizeof(double));
+    d.total = off;
+    return d;
+}
+
+lt_status lattice_diagnostics_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, size_t *bytes)
+{
+    if (!p || !bytes) return fail(LT_E_ARG, "NULL argument");
+    if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
+    if (batch < 0) return fail(LT_E_ARG, "batch must be >= 0");
+    *bytes = diag_layout(*p, p->sched[1][prec], prec, batch).total;
+    return LT_OK;
+}
+
+lt_status lattice_diagnostics(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, int64_t v_stride,
+                              const void *u, double gamma, double *out, void *work, size_t work_bytes,
+                              void *stream)
+{
+    lt_status st = check_common(cp, prec, batch, gamma, 0.0, 0);
+    if (st) return st;
+    lt_plan &p = *const_cast<lt_plan *>(cp);
+    if (batch == 0) return LT_OK;
+    if (!v || !u || !out) return fail(LT_E_ARG, "v, u and out must not be NULL");
+    if (v_stride != 0 && v_stride < p.N) return fail(LT_E_ARG, "v_stride must be 0 or >= N");
+    // the two-pass schedule of the adjoint slot exists for every plan
+    if ((st = ensure_device_tables(p, 1, prec, stream))) return st;
+    const Sched &s = p.sched[1][prec];
+    const DevTables &D = p.dev[1][prec];
+    hipStream_t hs = (hipStream_t)stream;
+    const int64_t N = p.N;
+    const DiagWork L = diag_layout(p, s, prec, batch);
+    Scratch sc;
+    if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
+    void *W = at(sc.ptr, L.w);
+    double *pp = (double *)at(sc.ptr, L.pp), *ps = (double *)at(sc.ptr, L.ps);
+    HIP_TRY(launch_sums(prec, u, N, N, batch, nullptr, v, v_stride, pp, hs), "point sums");
+    // U = F u: first column pass (with the chirp for chirp-z), then the rows
+    ColArgs c = col_base(s, D, N);
+    c.buf = W;
+    c.buf_bs = s.L;
+    c.in = u;
+    c.in_bs = N;
+    c.post_fwd = 1;
+    c.chirp = s.bluestein ? 1 : 0;
+    HIP_TRY(launch_col(prec, s, c, batch, hs), "diagnostics transform");
+    RowArgs r = row_base(s, D);
+    r.buf = W;
+    r.buf_bs = s.L;
+    double kscale;
+    if (s.bluestein) {
+        r.bhat = D.bhat;
+        HIP_TRY(launch_row(prec, s, r, batch, hs), "diagnostics transform");
+        void *nat = at(sc.ptr, L.nat);
+        ColArgs e = col_base(s, D, N);
+        e.buf = W;
+        e.buf_bs = s.L;
+        e.pre_inv = 1;
+        e.out = nat;
+        e.out_bs = N;
+        e.chirp = 1;
+        HIP_TRY(launch_col(prec, s, e, batch, hs), "diagnostics transform");  // unitary F u, key order
+        HIP_TRY(launch_sums(prec, nat, N, N, batch, D.s_key, nullptr, 0, ps, hs), "spectral sums");
+        kscale = 1.0;
+    } else {
+        r.fft_only = 1;  // unnormalised F u at the row-pass positions
+        HIP_TRY(launch_row(prec, s, r, batch, hs), "diagnostics transform");
+        HIP_TRY(launch_sums(prec, W, s.L, s.L, batch, D.s_row, nullptr, 0, ps, hs), "spectral sums");
+        kscale = 1.0 / (double)N;
+    }
+    HIP_TRY(launch_diag_finish(pp, ps, batch, N, gamma, kscale, out, hs), "diagnostics");
+    return LT_OK;
+}
+
 lt_status lattice_plan_set_kernels(lt_plan *p, lt_prec prec, int32_t col_variant, int32_t row_variant)
 {
     if (!p) return fail(LT_E_ARG, "plan is NULL");

@@ -561,6 +561,60 @@ __global__ void k_phase_table(Tw<T> *dst, const double *v, int64_t v_bs, int nv,
     }
 }
 
+// per-block partial sums of one state (blockIdx.y), fixed order:
+//   p[0] = sum |x_i|^2 * (w ? w[i] : 1),  p[1] = sum |x_i|^2 * vw[i] (vw optional)
+constexpr int kSumBlocks = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sums(const cx<T> *x, int64_t x_bs, int64_t count, const int32_t *w,
+                                              const double *vw, int64_t vw_bs, double *partial)
+{
+    __shared__ double red[2][256];
+    const int64_t b = blockIdx.y;
+    const cx<T> *xb = x + b * x_bs;
+    const double *vb = vw ? vw + b * vw_bs : nullptr;
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        const cx<T> z = xb[i];
+        const double a2 = (double)z.x * (double)z.x + (double)z.y * (double)z.y;
+        s0 += w ? a2 * (double)w[i] : a2;
+        if (vb) s1 += a2 * vb[i];
+    }
+    red[0][threadIdx.x] = s0;
+    red[1][threadIdx.x] = s1;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double *pb = partial + (b * gridDim.x + blockIdx.x) * 2;
+        pb[0] = red[0][0];
+        pb[1] = red[1][0];
+    }
+}
+
+// (norm^2, energy) per state from the point sums (|u|^2, v|u|^2) and the
+// spectral sum (s |U|^2, scaled by kscale)
+__global__ void k_diag_finish(const double *pp, const double *ps, int nblk, int batch, int64_t N, double gamma,
+                              double kscale, double *out)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    double n2 = 0.0, pe = 0.0, ke = 0.0;
+    for (int i = 0; i < nblk; ++i) {
+        n2 += pp[(b * nblk + i) * 2];
+        pe += pp[(b * nblk + i) * 2 + 1];
+        ke += ps[(b * nblk + i) * 2];
+    }
+    const double pi = 3.14159265358979323846;
+    out[2 * b] = n2 / (double)N;
+    out[2 * b + 1] = (2.0 * pi * pi * gamma * ke * kscale + pe / gamma) / (double)N;
+}
+
 __global__ void k_reduce_batch(double *dst, const double *src, int64_t N, int batch)
 {
     for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N;
@@ -758,6 +812,29 @@ int launch_phase_table(int prec, void *dst, const double *v, int64_t v_bs, int n
     else
         hipLaunchKernelGGL(k_phase_table<float>, grid, dim3(256), 0, (hipStream_t)stream, (Tw<float> *)dst, v,
                            v_bs, nv, N, phase);
+    return (int)hipGetLastError();
+}
+
+int diag_partials() { return kSumBlocks; }
+
+int launch_sums(int prec, const void *x, int64_t x_bs, int64_t count, int batch, const int32_t *w,
+                const double *vw, int64_t vw_bs, double *partial, void *stream)
+{
+    dim3 grid(kSumBlocks, batch);
+    if (prec == LT_C128)
+        hipLaunchKernelGGL(k_sums<double>, grid, dim3(256), 0, (hipStream_t)stream, (const cx<double> *)x, x_bs,
+                           count, w, vw, vw_bs, partial);
+    else
+        hipLaunchKernelGGL(k_sums<float>, grid, dim3(256), 0, (hipStream_t)stream, (const cx<float> *)x, x_bs,
+                           count, w, vw, vw_bs, partial);
+    return (int)hipGetLastError();
+}
+
+int launch_diag_finish(const double *pp, const double *ps, int batch, int64_t N, double gamma, double kscale,
+                       double *out, void *stream)
+{
+    hipLaunchKernelGGL(k_diag_finish, dim3((batch + 127) / 128), dim3(128), 0, (hipStream_t)stream, pp, ps,
+                       kSumBlocks, batch, N, gamma, kscale, out);
     return (int)hipGetLastError();
 }
 

@@ -163,6 +163,11 @@ int launch_unpermute_c128(void *dst_nat, const void *src, int64_t L, int L1, int
 int launch_chirp_filter(void *dst_c128, int64_t N, int64_t L, void *stream);
 int launch_reduce_batch(double *dst, const double *src, int64_t N, int batch, void *stream);
 int launch_ktab(double *dst, int64_t count, double kin, double scale, void *stream);
+int diag_partials();  // blocks per state of launch_sums
+int launch_sums(int prec, const void *x, int64_t x_bs, int64_t count, int batch, const int32_t *w,
+                const double *vw, int64_t vw_bs, double *partial, void *stream);
+int launch_diag_finish(const double *pp, const double *ps, int batch, int64_t N, double gamma, double kscale,
+                       double *out, void *stream);
 int launch_conv_input(void *dst, const int32_t *s, const double *ktab, int64_t N, void *stream);
 int launch_conv_embed(void *g, const void *src, int64_t N, int64_t L, double scale, void *stream);
 int launch_phase_table(int prec, void *dst, const double *v, int64_t v_bs, int nv, int64_t N, double phase,

@@ -160,3 +160,13 @@ def test_config2_lattices_bitexact_on_golden_instances():
     insts = W.config2(shapes=shapes[: max(sel) + 1])
     for i in sel:
         _planner_matches_oracle(insts[i].Z, insts[i].n)
+
+
+def test_diagnostics_argument_errors_on_host():
+    p = C.lattice_plan(np.array([[1, 34]]), np.array([55]))
+    h = p.handle
+    assert C.lib.lattice_diagnostics(h, 1, 1, None, 0, None, 0.1, None, None, 0, None) == 1   # NULL buffers
+    assert C.lib.lattice_diagnostics(h, 1, 1, None, 0, None, -0.1, None, None, 0, None) == 1  # gamma <= 0
+    assert C.lib.lattice_diagnostics(h, 3, 1, None, 0, None, 0.1, None, None, 0, None) == 1   # precision
+    assert C.lib.lattice_diagnostics(h, 2, 0, None, 0, None, 0.1, None, None, 0, None) == 0   # empty batch
+    assert C.lattice_diagnostics_workspace_size(p, C.LT_C128, 4) > C.lattice_diagnostics_workspace_size(p, C.LT_C128, 1)
