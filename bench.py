@@ -14,7 +14,9 @@ throughput, the FP64 oracle timed on the host, accuracy indicators, and three
 companion workloads: 256 unrelated problems advanced by strang_run_batched in
 complex64 against the same problems run one by one in complex128; the d = 10
 rank-2 lattice 4096 x 256; and a forward run with checkpoints plus its adjoint
-(d = 4, N = 65521, 32 states).
+(d = 4, N = 65521, 32 states); and the norm / energy conservation setting of
+Sec. 3.3 on a 2^20-point lattice; and the time-step convergence protocol of
+Sec. 3.2 on a lattice of the paper's Table 1 (d = 3, n = 2^22).
 """
 from __future__ import annotations
 
@@ -250,6 +252,85 @@ def bench_adjoint(lt, torch, K, W):
     return out
 
 
+def bench_conservation(lt, torch, K, W):
+    """The conservation setting of Sec. 3.3 (gamma = 0.5, d = 5, g1, harmonic
+    v2) on a 2^20-point lattice: 1000 steps with checkpoints every 10, norm and
+    energy of every checkpoint by lattice_diagnostics, delta = (max-min)/mean."""
+    import numpy as np
+
+    import workloads as W_
+    N, d, gamma, dt, steps, every = 1 << 20, 5, 0.5, 1e-3, 1000, 10
+    z = W_.korobov_good(N, d, np.random.default_rng(33))
+    Z, n = z.reshape(1, -1), np.array([N])
+    num = W_.point_numerators(Z, n)
+    plan = lt.lattice_plan(Z, n)
+    dev = torch.device("cuda:0")
+    v = torch.tensor(W_.v_harmonic_paper(num, N), device=dev)
+    u0 = W_.paper_g1(num, N, gamma)
+    out = {"workload": f"Sec. 3.3 setting: rank-1 d={d} N=2^20 (best-of-8 Korobov), gamma={gamma}, g1, "
+                       f"harmonic v2, dt={dt}, {steps} steps, norm and energy every {every} steps"}
+    nck = lt.num_checkpoints(steps, every)
+    for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
+        u = torch.tensor(u0, dtype=dtype, device=dev)
+        ck = torch.empty(nck * N, dtype=dtype, device=dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lt.strang_run(plan, v, u, gamma, dt, steps, ckpt=ck, ckpt_every=every)
+        diag = lt.lattice_diagnostics(plan, v, ck.view(nck, N), gamma)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t
+        h = diag.cpu().numpy()
+        out[name] = {"norm_delta": float((h[:, 0].max() - h[:, 0].min()) / h[:, 0].mean()),
+                     "energy_delta": float((h[:, 1].max() - h[:, 1].min()) / h[:, 1].mean()),
+                     "energy_0": float(h[0, 1]), "ms_run_plus_diagnostics": t * 1e3}
+        log(f"conservation {name}: norm delta {out[name]['norm_delta']:.2e}, "
+            f"energy delta {out[name]['energy_delta']:.2e}, {t * 1e3:.1f} ms")
+        del u, ck
+    return out
+
+
+def bench_convergence(lt, torch, K, W):
+    """Time-step convergence on a lattice of the paper's Table 1 (d = 3,
+    n = 2^22, z = (1, 1737355, 261247)) with g1, gamma = 0.5, T = 1, for the
+    smooth v1 and the harmonic v2: reference dt = 1/10000, errors for dt = 1/m
+    (complex128)."""
+    import numpy as np
+
+    import workloads as W_
+    Z, n = W_.paper_lattice(3, 1 << 22)
+    N = int(n[0])
+    num = W_.point_numerators(Z, n)
+    gamma = 0.5
+    plan = lt.lattice_plan(Z, n)
+    dev = torch.device("cuda:0")
+    u0 = torch.tensor(W_.paper_g1(num, N, gamma), dtype=torch.complex128, device=dev)
+    out = {"workload": "paper Table 1 lattice d=3 n=2^22 z=(1,1737355,261247), minimal-l2 index set, g1, "
+                       "gamma=0.5, T=1, reference dt=1e-4, complex128"}
+    for name, vfun in (("v1", W_.v_smooth_paper), ("v2", W_.v_harmonic_paper)):
+        v = torch.tensor(vfun(num, N), device=dev)
+
+        def solve(m):
+            u = u0.clone()
+            lt.strang_run(plan, v, u, gamma, 1.0 / m, m)
+            return u
+
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ref = solve(10000)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t
+        ms = [10, 20, 40, 80, 160, 320, 640]
+        errs = [float(torch.sqrt(torch.mean(torch.abs(solve(m) - ref) ** 2)).item()) for m in ms]
+        orders = [float(np.log2(errs[i] / errs[i + 1])) for i in range(len(ms) - 1)]
+        fit = float(np.polyfit(np.log(1.0 / np.asarray(ms, dtype=float)), np.log(errs), 1)[0])
+        log(f"convergence {name}: errors {['%.2e' % e for e in errs]}, orders {['%.2f' % o for o in orders]}, "
+            f"fitted {fit:.2f}")
+        out[name] = {"m": ms, "l2_error": errs, "observed_order": orders, "fitted_order": fit,
+                     "reference_run": {"value": N * 10000 / t, "unit": "lattice-point-steps/s", "seconds": t}}
+        del ref
+    return out
+
+
 def cpu_baseline(inst, seconds):
     import numpy as np
 
@@ -281,7 +362,7 @@ def main():
     ap.add_argument("--no-c128", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched, rank-2 and adjoint workloads")
-    ap.add_argument("--only", choices=["batched", "rank2", "adjoint"],
+    ap.add_argument("--only", choices=["batched", "rank2", "adjoint", "conservation", "convergence"],
                     help="run one companion workload alone (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device (counter calibration for the traffic figure)")
@@ -307,7 +388,8 @@ def main():
     import paper_1808_06357_amd as lt
     import workloads as W
 
-    extras = {"batched": bench_batched, "rank2": bench_rank2, "adjoint": bench_adjoint}
+    extras = {"batched": bench_batched, "rank2": bench_rank2, "adjoint": bench_adjoint,
+              "conservation": bench_conservation, "convergence": bench_convergence}
     if args.only:
         print(json.dumps({args.only: extras[args.only](lt, torch, args.steps, args.warmup)}), flush=True)
         return

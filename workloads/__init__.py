@@ -421,6 +421,22 @@ def config3(steps: int = 500) -> Instance:
     return Instance(10, Z, n, H, 0.05, 2e-3, steps, v, u0, {"name": "config3", "R": 1})
 
 
+# Generating vectors the paper prints for its experiments (Sec. 3.1, Table 1):
+# (d, n) -> z.  For d >= 4 the paper takes the first d components of the
+# 12-component vector at n = 2^25.
+_TABLE1_Z12 = (1, 12386359, 15699201, 6807287, 13966305, 6107923, 4432603, 2304135, 7323801, 5705679,
+               5643703, 3867405)
+PAPER_TABLE1 = {(2, 1 << 18): (1, 100135), (2, 1 << 20): (1, 443165), (3, 1 << 22): (1, 1737355, 261247),
+                (3, 1 << 25): (1, 12386359, 15699201)}
+PAPER_TABLE1.update({(d, 1 << 25): _TABLE1_Z12[:d] for d in range(4, 13)})
+
+
+def paper_lattice(d: int, n: int):
+    """(Z, n) of a Table 1 lattice as rank-1 arrays."""
+    z = np.asarray(PAPER_TABLE1[(d, n)], dtype=np.int64)
+    return z.reshape(1, -1), np.array([n], dtype=np.int64)
+
+
 def config4_loss_points(N: int, count: int = 2048) -> np.ndarray:
     """Seeded sorted point indices on which the differentiation workload's
     misfit is measured (the loss restricted to a sample keeps its stored
