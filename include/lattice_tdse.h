@@ -197,6 +197,25 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
                              size_t work_bytes, void *stream);
 
 /*
+ * splitting_run -- m steps of a symmetric composition of the Strang step of
+ * eq. (StrangTDSE): order 2 is the Strang step itself (as strang_run, in the
+ * two-pass layout); order 4 is the triple jump S(w1 dt) S(w0 dt) S(w1 dt) with
+ * w1 = 1 / (2 - 2^(1/3)), w0 = 1 - 2 w1 (Yoshida's composition; global error
+ * O(dt^4)), the higher-order splitting the paper names as a continuation
+ * (Sec. 5).  Consecutive half potential steps are merged.  Arguments as in
+ * strang_run (no checkpoints); work: at least splitting_workspace_size bytes,
+ * or NULL.  Errors: LT_E_ARG for an order other than 2 or 4 (and as
+ * strang_run); LT_E_UNSUPPORTED for a chirp-z lattice whose complex128
+ * schedule differs from the run's (the convolution spectra are built in
+ * double).  Every substep of a chirp-z lattice runs in the convolution form.
+ */
+lt_status splitting_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, int32_t shared_v,
+                                   int32_t order, size_t *bytes);
+lt_status splitting_run(const lt_plan *p, lt_prec prec, int32_t batch, const double *v,
+                        int64_t v_stride, void *u, double gamma, double dt, int64_t steps,
+                        int32_t order, void *work, size_t work_bytes, void *stream);
+
+/*
  * lattice_diagnostics -- the conserved quantities of Sec. 3.3 for `batch`
  * states of lattice values u: the L2 norm^2 and the energy <H u, u> with
  * H = -(gamma/2) lap + v/gamma, on the lattice

@@ -67,6 +67,8 @@ _SIGS = {
     "strang_adjoint": [_P, _i32, _i32, _P, _i64, _P, _P, _f64, _f64, _i64, _P, _i64, _P, _P, _P, _sz, _P],
     "strang_batched_workspace_size": [_i32, _P, _i32, ctypes.POINTER(_sz)],
     "strang_run_batched": [_i32, _P, _i32, _P, _P, _P, _P, _P, _P, _sz, _P],
+    "splitting_workspace_size": [_P, _i32, _i32, _i32, _i32, ctypes.POINTER(_sz)],
+    "splitting_run": [_P, _i32, _i32, _P, _i64, _P, _f64, _f64, _i64, _i32, _P, _sz, _P],
     "lattice_diagnostics_workspace_size": [_P, _i32, _i32, ctypes.POINTER(_sz)],
     "lattice_diagnostics": [_P, _i32, _i32, _P, _i64, _P, _f64, _P, _P, _sz, _P],
     "lattice_plan_autotune": [_P, _i32, _i32, _P],
@@ -295,6 +297,33 @@ def strang_run_batched(plans: Sequence[Plan], vs, us, gammas, dts, steps, work=N
     _check(lib.strang_run_batched(B, parr, prec, varr, uarr, _np_ptr(g), _np_ptr(dtt), _np_ptr(st),
                                   _dev_ptr(work), wb, _stream(stream)), "strang_run_batched")
     return us
+
+
+def splitting_workspace_size(plan: Plan, prec: int, batch: int, shared_v: bool, order: int) -> int:
+    n = _sz()
+    _check(lib.splitting_workspace_size(plan.handle, prec, batch, int(bool(shared_v)), order, ctypes.byref(n)),
+           "splitting_workspace_size")
+    return n.value
+
+
+def splitting_run(plan: Plan, v, u, gamma: float, dt: float, steps: int, order: int = 4, work=None, stream=None):
+    """In-place run of a symmetric composition of Strang steps (order 2 or 4)."""
+    import torch
+    N = plan.N
+    prec = _prec_of(u)
+    batch = u.numel() // N
+    _check_dev(u, "u", numel=batch * N)
+    _check_dev(v, "v", torch.float64)
+    if v.numel() not in (N, batch * N):
+        raise ValueError("v must hold N or batch*N values")
+    wb = 0
+    if work is not None:
+        _check_dev(work, "work")
+        wb = work.numel() * work.element_size()
+    _check(lib.splitting_run(plan.handle, prec, batch, _dev_ptr(v), 0 if v.numel() == N else N, _dev_ptr(u),
+                             float(gamma), float(dt), int(steps), int(order), _dev_ptr(work), wb,
+                             _stream(stream)), "splitting_run")
+    return u
 
 
 def lattice_diagnostics_workspace_size(plan: Plan, prec: int, batch: int) -> int:

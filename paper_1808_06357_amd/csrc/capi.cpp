@@ -1123,6 +1123,54 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
     return LT_OK;
 }
 
+// ---------------------------------------------------------------- compositions
+// One step of a symmetric composition: Strang steps of dt * w[i], i < P.
+// Workspace of a composed run (two-pass slot): per distinct substep a
+// kinetic table and (chirp-z) a convolution spectrum, per boundary a merged
+// potential table (complex64), the transform buffer (chirp-z) and scratch.
+struct ComposedWork {
+    size_t ktab[3] = {}, conv[3] = {}, ptab[3] = {}, w = 0, tmp = 0, total = 0;
+};
+
+ComposedWork composed_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool shared_v, int P)
+{
+    ComposedWork c;
+    size_t off = 0;
+    for (int i = 0; i < P; ++i) {
+        c.ktab[i] = off;
+        off = align_up(off + (size_t)(p.max_s + 1) * 16);
+        if (s.bluestein) {
+            c.conv[i] = off;
+            off = align_up(off + (size_t)s.L * 16);
+        }
+        if (prec == LT_C64) {
+            c.ptab[i] = off;
+            off = align_up(off + (size_t)(shared_v ? 1 : batch) * p.N * 16);
+        }
+    }
+    c.w = off;
+    if (s.bluestein) off = align_up(off + (size_t)batch * s.L * esz(prec));
+    c.tmp = off;
+    if (s.bluestein) off = align_up(off + (size_t)p.N * 16);
+    c.total = off;
+    return c;
+}
+
+// fourth order: the triple jump w1, w0, w1 with w1 = 1 / (2 - 2^(1/3)),
+// w0 = 1 - 2 w1 (Yoshida's symmetric composition of a second-order
+// symmetric step; local error O(dt^5))
+int composition_weights(int order, double *w)
+{
+    if (order == 2) {
+        w[0] = 1.0;
+        return 1;
+    }
+    const double c = std::cbrt(2.0);
+    w[0] = w[2] = 1.0 / (2.0 - c);
+    w[1] = 1.0 - 2.0 * w[0];
+    return 3;
+}
+
 // ---------------------------------------------------------------- diagnostics
 // workspace: the transform buffer (batch x L), the chirp-z spectrum in natural
 // order (batch x N), point and spectral partial sums
@@ -1211,6 +1259,75 @@ lt_status lattice_diagnostics(const lt_plan *cp, lt_prec prec, int32_t batch, co
         kscale = 1.0 / (double)N;
     }
     HIP_TRY(launch_diag_finish(pp, ps, batch, N, gamma, kscale, out, hs), "diagnostics");
+    return LT_OK;
+}
+
+lt_status splitting_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, int32_t shared_v,
+                                   int32_t order, size_t *bytes)
+{
+    if (!p || !bytes) return fail(LT_E_ARG, "NULL argument");
+    if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
+    if (batch < 0) return fail(LT_E_ARG, "batch must be >= 0");
+    if (order != 2 && order != 4) return fail(LT_E_ARG, "order must be 2 or 4");
+    double w[3];
+    *bytes = composed_layout(*p, p->sched[1][prec], prec, batch, shared_v != 0, composition_weights(order, w)).total;
+    return LT_OK;
+}
+
+lt_status splitting_run(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, int64_t v_stride,
+                        void *u, double gamma, double dt, int64_t steps, int32_t order, void *work,
+                        size_t work_bytes, void *stream)
+{
+    lt_status st = check_common(cp, prec, batch, gamma, dt, steps);
+    if (st) return st;
+    if (order != 2 && order != 4) return fail(LT_E_ARG, "order must be 2 or 4");
+    lt_plan &p = *const_cast<lt_plan *>(cp);
+    if (batch == 0 || steps == 0) return LT_OK;
+    if (!v || !u) return fail(LT_E_ARG, "v and u must not be NULL");
+    if (v_stride != 0 && v_stride < p.N) return fail(LT_E_ARG, "v_stride must be 0 or >= N");
+    // the two-pass slot exists for every plan; chirp-z lattices use the
+    // convolution form for every substep
+    const Sched &s = p.sched[1][prec];
+    if (s.bluestein && !conv_available(p, 1, s))
+        return fail(LT_E_UNSUPPORTED, "no double-precision schedule for the convolution spectra");
+    if ((st = ensure_device_tables(p, 1, prec, stream))) return st;
+    if (s.bluestein && (st = ensure_device_tables(p, 1, LT_C128, stream))) return st;
+    const DevTables &D = p.dev[1][prec];
+    hipStream_t hs = (hipStream_t)stream;
+    double w[3];
+    const int P = composition_weights(order, w);
+    const ComposedWork L = composed_layout(p, s, prec, batch, v_stride == 0, P);
+    Scratch sc;
+    if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
+    const int64_t N = p.N;
+    void *W = s.bluestein ? at(sc.ptr, L.w) : nullptr;
+    Roles R[3];
+    for (int i = 0; i < P; ++i) {
+        const double dti = w[i] * dt;
+        double *ktab = (double *)at(sc.ptr, L.ktab[i]);
+        if ((st = make_ktab(p, s, ktab, gamma, dti, hs))) return st;
+        void *conv = s.bluestein ? at(sc.ptr, L.conv[i]) : nullptr;
+        if (conv && (st = conv_spectrum(p, 1, ktab, conv, at(sc.ptr, L.tmp), hs))) return st;
+        // merged potential step after substep i: half phases of substeps i and i+1
+        const double merged = (dti + w[(i + 1) % P] * dt) / (2.0 * gamma);
+        void *ptab = prec == LT_C64 ? at(sc.ptr, L.ptab[i]) : nullptr;
+        if (ptab) HIP_TRY(launch_phase_table(prec, ptab, v, v_stride, v_stride ? batch : 1, N, merged, hs),
+                          "potential table");
+        R[i] = two_pass_roles(s, D, N, v, v_stride, u, W, dti / (2.0 * gamma), ktab, ptab);
+        R[i].pot.phase = merged;
+        R[i].first.chirp = 0;
+        R[i].last.chirp = 0;
+        if (conv) R[i].row.bhat = (const double *)conv;
+    }
+    HIP_TRY(launch_col(prec, s, R[0].first, batch, hs), "column pass");
+    const int64_t total = steps * P;
+    for (int64_t k = 0; k < total; ++k) {
+        const Roles &r = R[k % P];
+        HIP_TRY(launch_row(prec, s, r.row, batch, hs), "row pass");
+        if (k == total - 1) break;
+        HIP_TRY(launch_col(prec, s, r.pot, batch, hs), "column pass (potential)");
+    }
+    HIP_TRY(launch_col(prec, s, R[(total - 1) % P].last, batch, hs), "column pass (last)");
     return LT_OK;
 }
 

@@ -287,6 +287,29 @@ def test_second_order_against_exact_propagator():
     assert np.all((orders > 1.9) & (orders < 2.1)), orders
 
 
+def test_fourth_order_composition_against_exact_propagator():
+    """The triple jump of Strang steps (weights summing to 1, w1^3 + w0^3 + w1^3
+    = 0) converges at fourth order against the exact propagator of the
+    lattice Hamiltonian: the error falls by ~16 per halving of dt."""
+    Z, n = np.array([[1, 34]]), np.array([55])
+    h, s, _ = O.index_set(Z, n)
+    num = W.point_numerators(Z, n)
+    v = W.v_sum_one_minus_cos(num, 55)
+    x = O.points(Z, n)
+    u0 = np.exp(-np.sum((x - 0.5) ** 2, axis=1) / 0.05).astype(complex)
+    gamma, T = 0.3, 0.4
+    _, (F, Fi, Wn, Dn) = _dense_coefficient_strang(Z, n, s, v, u0, gamma, 0.1, 0)
+    exact = Fi @ (scipy.linalg.expm(-1j * (Wn / gamma + gamma * Dn / 2) * T) @ (F @ u0))
+    w = O.composition_weights(4)
+    assert abs(sum(w) - 1.0) < 1e-15 and abs(sum(x ** 3 for x in w)) < 1e-14
+    errs = [np.linalg.norm(O.composed_run(n, s, v, u0, gamma, T / m, m) - exact) for m in (16, 32, 64, 128)]
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all((orders > 3.85) & (orders < 4.15)), orders
+    # order 2 is the plain Strang run
+    assert np.allclose(O.composed_run(n, s, v, u0, gamma, 0.05, 3, order=2),
+                       O.strang_run(n, s, v, u0, gamma, 0.05, 3), rtol=0, atol=1e-13)
+
+
 def test_config0_second_order_paper_protocol():
     """Sec. 3.2 protocol: reference at dt = 1e-4, errors at larger dt, T fixed,
     observed order 2 (here T = 0.2 so the reference stays cheap)."""

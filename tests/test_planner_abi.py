@@ -170,3 +170,21 @@ def test_diagnostics_argument_errors_on_host():
     assert C.lib.lattice_diagnostics(h, 3, 1, None, 0, None, 0.1, None, None, 0, None) == 1   # precision
     assert C.lib.lattice_diagnostics(h, 2, 0, None, 0, None, 0.1, None, None, 0, None) == 0   # empty batch
     assert C.lattice_diagnostics_workspace_size(p, C.LT_C128, 4) > C.lattice_diagnostics_workspace_size(p, C.LT_C128, 1)
+
+
+def test_splitting_argument_errors_on_host():
+    p = C.lattice_plan(np.array([[1, 34]]), np.array([55]))
+    h = p.handle
+    args = (None, 0, None, 0.1, 0.01, 5)
+    assert C.lib.splitting_run(h, 2, 1, *args, 3, None, 0, None) == 1           # order
+    assert b"order" in C.lib.lt_last_error()
+    assert C.lib.splitting_run(h, 2, 1, *args, 4, None, 0, None) == 1           # NULL v, u
+    assert C.lib.splitting_run(h, 3, 1, *args, 4, None, 0, None) == 1           # precision
+    assert C.lib.splitting_run(h, 2, 1, None, 0, None, 0.1, 0.01, -1, 4, None, 0, None) == 1  # steps
+    assert C.lib.splitting_run(h, 2, 0, *args, 4, None, 0, None) == 0           # empty batch
+    assert C.lib.splitting_run(h, 2, 1, None, 0, None, 0.1, 0.01, 0, 4, None, 0, None) == 0  # no steps
+    with pytest.raises(C.LatticeError):
+        C.splitting_workspace_size(p, C.LT_C128, 1, True, 6)
+    s2 = C.splitting_workspace_size(p, C.LT_C64, 1, True, 2)
+    s4 = C.splitting_workspace_size(p, C.LT_C64, 1, True, 4)
+    assert s4 > s2 > 0
