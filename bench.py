@@ -15,8 +15,10 @@ companion workloads: 256 unrelated problems advanced by strang_run_batched in
 complex64 against the same problems run one by one in complex128; the d = 10
 rank-2 lattice 4096 x 256; and a forward run with checkpoints plus its adjoint
 (d = 4, N = 65521, 32 states); and the norm / energy conservation setting of
-Sec. 3.3 on a 2^20-point lattice; and the time-step convergence protocol of
-Sec. 3.2 on a lattice of the paper's Table 1 (d = 3, n = 2^22).
+Sec. 3.3 on a 2^20-point lattice; the time-step convergence protocol of
+Sec. 3.2 on a lattice of the paper's Table 1 (d = 3, n = 2^22); and the
+fourth-order composition and a time-dependent potential (Sec. 5) on the
+benchmark lattice.
 """
 from __future__ import annotations
 
@@ -331,6 +333,59 @@ def bench_convergence(lt, torch, K, W):
     return out
 
 
+def bench_splitting(lt, torch, K, W):
+    """Higher-order splitting and time-dependent potentials (the two method
+    variants of Sec. 5) on the benchmark lattice (d = 6, N = 1048573):
+    splitting_run with the fourth-order triple jump, 300 composed steps of
+    dt = 1e-3 (900 Strang substeps), with v fixed and with the amplitude-
+    modulated v(x, t) = (1 + 0.5 sin(20 t)) v(x); and the accuracy of order 2
+    against order 4 at equal cost (900 substeps over T = 0.9) against an
+    order-4 reference with dt / 10 (complex128)."""
+    import numpy as np
+
+    import workloads as W_
+    inst = W_.config1(steps=1)
+    plan = lt.lattice_plan(inst.Z, inst.n, inst.I)
+    dev = torch.device("cuda:0")
+    N, m, dt = inst.N, 300, 1e-3
+    v = torch.tensor(inst.v, dtype=torch.float64, device=dev)
+    out = {"workload": f"benchmark lattice d=6 N={N}, gamma={inst.gamma}, order 4 (triple jump), {m} steps "
+                       f"of dt={dt} (3 substeps each); time-dependent: v(x,t) = (1 + 0.5 sin 20t) v(x)",
+           "unit": "lattice-point-steps/s (composed fourth-order steps)"}
+    f = lambda t: 0.5 * np.sin(20.0 * np.asarray(t))  # noqa: E731
+    for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
+        prec = lt.LT_C64 if name == "c64" else lt.LT_C128
+        lt.lattice_plan_autotune(plan, prec, reps=10)
+        u = torch.tensor(inst.u0, dtype=dtype, device=dev)
+        work = torch.empty(lt.splitting_workspace_size(plan, prec, 1, True, 4), dtype=torch.uint8, device=dev)
+        fk = f(lt.splitting_times(4, m, 0.0, dt))
+        fixed = lambda: lt.splitting_run(plan, v, u, inst.gamma, dt, m, order=4, work=work)  # noqa: E731
+        tdv = lambda: lt.splitting_run(plan, v, u, inst.gamma, dt, m, order=4, v1=v, f=fk,  # noqa: E731
+                                       work=work)
+        tf, tt = wall(fixed, K, W), wall(tdv, K, W)
+        out[name] = {"value": N * m / tf, "ms_per_run": tf * 1e3,
+                     "time_dependent": {"value": N * m / tt, "ms_per_run": tt * 1e3},
+                     "kernels": kernel_summary(lt, fixed, 1),
+                     "time_dependent_kernels": kernel_summary(lt, tdv, 1)}
+        log(f"splitting {name}: order 4 {N * m / tf:.3e} pt-steps/s ({tf * 1e3:.1f} ms), "
+            f"time-dependent {N * m / tt:.3e} ({tt * 1e3:.1f} ms)")
+        del u, work
+    # accuracy at equal cost: 900 substeps over T = 0.9 as order 2 (900 steps) or
+    # order 4 (300 steps); reference: order 4 with 3000 steps
+    u0 = torch.tensor(inst.u0, dtype=torch.complex128, device=dev)
+
+    def solve(order, steps):
+        u = u0.clone()
+        lt.splitting_run(plan, v, u, inst.gamma, 0.9 / steps, steps, order=order)
+        return u
+    ref = solve(4, 3000)
+    e2 = float(torch.linalg.vector_norm(solve(2, 900) - ref) / torch.linalg.vector_norm(ref))
+    e4 = float(torch.linalg.vector_norm(solve(4, 300) - ref) / torch.linalg.vector_norm(ref))
+    out["equal_cost_accuracy"] = {"substeps": 900, "T": 0.9, "order2_rel_l2": e2, "order4_rel_l2": e4}
+    log(f"splitting equal cost (900 substeps, T=0.9): order 2 rel err {e2:.2e}, order 4 {e4:.2e}")
+    return out
+
+
 def cpu_baseline(inst, seconds):
     import numpy as np
 
@@ -361,8 +416,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c128", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the batched, rank-2 and adjoint workloads")
-    ap.add_argument("--only", choices=["batched", "rank2", "adjoint", "conservation", "convergence"],
+                    help="skip the companion workloads")
+    ap.add_argument("--only", choices=["batched", "rank2", "adjoint", "conservation", "convergence", "splitting"],
                     help="run one companion workload alone (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device (counter calibration for the traffic figure)")
@@ -389,7 +444,8 @@ def main():
     import workloads as W
 
     extras = {"batched": bench_batched, "rank2": bench_rank2, "adjoint": bench_adjoint,
-              "conservation": bench_conservation, "convergence": bench_convergence}
+              "conservation": bench_conservation, "convergence": bench_convergence,
+              "splitting": bench_splitting}
     if args.only:
         print(json.dumps({args.only: extras[args.only](lt, torch, args.steps, args.warmup)}), flush=True)
         return

@@ -202,18 +202,42 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
  * two-pass layout); order 4 is the triple jump S(w1 dt) S(w0 dt) S(w1 dt) with
  * w1 = 1 / (2 - 2^(1/3)), w0 = 1 - 2 w1 (Yoshida's composition; global error
  * O(dt^4)), the higher-order splitting the paper names as a continuation
- * (Sec. 5).  Consecutive half potential steps are merged.  Arguments as in
- * strang_run (no checkpoints); work: at least splitting_workspace_size bytes,
- * or NULL.  Errors: LT_E_ARG for an order other than 2 or 4 (and as
- * strang_run); LT_E_UNSUPPORTED for a chirp-z lattice whose complex128
- * schedule differs from the run's (the convolution spectra are built in
- * double).  Every substep of a chirp-z lattice runs in the convolution form.
+ * (Sec. 5).  Consecutive half potential steps are merged.
+ *
+ * Time-dependent potentials (the other continuation named in Sec. 5):
+ * v(x, tau) = v(x) + f(tau) v1(x).  Time advances with the kinetic flow, so
+ * a substep of length h from tau applies the potential half steps at tau
+ * and at tau + h: exp(-i h v(., tau) / (2 gamma)), F^-1 K(h) F,
+ * exp(-i h v(., tau + h) / (2 gamma)).  This is the Strang step of the
+ * autonomous system extended by the clock; it keeps order 2, and the triple
+ * jump keeps order 4, for smooth f.
+ *   v1     device, N doubles per state (strided as v), or NULL for a
+ *          time-independent potential.
+ *   f      host, m * P + 1 doubles (P = 1 for order 2, 3 for order 4):
+ *          f at the substep boundaries tau_j that splitting_times returns,
+ *          read during the call; ignored when v1 is NULL.
+ * Other arguments as in strang_run (no checkpoints); work: at least
+ * splitting_workspace_size bytes, or NULL.  Errors: LT_E_ARG for an order
+ * other than 2 or 4, for v1 without f, or non-finite f (and as strang_run);
+ * LT_E_UNSUPPORTED for a chirp-z lattice whose complex128 schedule differs
+ * from the run's (the convolution spectra are built in double).  Every
+ * substep of a chirp-z lattice runs in the convolution form.
  */
 lt_status splitting_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, int32_t shared_v,
                                    int32_t order, size_t *bytes);
 lt_status splitting_run(const lt_plan *p, lt_prec prec, int32_t batch, const double *v,
-                        int64_t v_stride, void *u, double gamma, double dt, int64_t steps,
-                        int32_t order, void *work, size_t work_bytes, void *stream);
+                        const double *v1, int64_t v_stride, const double *f, void *u, double gamma,
+                        double dt, int64_t steps, int32_t order, void *work, size_t work_bytes,
+                        void *stream);
+
+/*
+ * splitting_times -- the substep boundaries of an m-step run of
+ * splitting_run started at t0: tau[k P + i] = t0 + (k + c_i) dt for
+ * k < m, i < P, with c_0 = 0 and c_{i+1} = c_i + w_i, and tau[m P] = t0 + m dt
+ * (for order 4 the middle boundaries step backwards, w0 < 0).
+ * tau: host, m * P + 1 doubles (caller-owned).  Errors: LT_E_ARG.
+ */
+lt_status splitting_times(int32_t order, int64_t steps, double t0, double dt, double *tau);
 
 /*
  * lattice_diagnostics -- the conserved quantities of Sec. 3.3 for `batch`

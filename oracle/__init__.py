@@ -12,8 +12,9 @@ Paper references (arXiv:1808.06357):
   * Strang step: Sec. 2.4, eq. (StrangTDSE); Algorithm 1;
   * rank-r orderings: Sec. 2.5;
   * norm / energy: Sec. 3.3;
-  * fourth-order composition of Strang steps: Sec. 5 (higher-order splitting,
-    taken as Yoshida's symmetric triple jump).
+  * fourth-order composition of Strang steps and time-dependent potentials:
+    the two continuations named in Sec. 5 (the composition taken as Yoshida's
+    symmetric triple jump, time advanced with the kinetic flow).
 
 Every function here is pinned by ``tests/test_oracle.py`` against values the
 paper and the mathematics fix (closed forms, brute force, library routines).
@@ -227,13 +228,33 @@ def composition_weights(order):
     return (w1, 1.0 - 2.0 * w1, w1)
 
 
-def composed_run(n, s_of_key, v, u0, gamma, dt, steps, order=4, method="auto"):
+def composed_run(n, s_of_key, v, u0, gamma, dt, steps, order=4, v1=None, f=None, t0=0.0, method="auto"):
     """`steps` steps of the composition: each step runs one Strang step of
-    length w dt per weight w, in order (no merging of the potential halves)."""
+    length w dt per weight w, in order (no merging of the potential halves).
+
+    Time-dependent potential v(x, t) = v(x) + f(t) v1(x) (v1 shaped as v, f a
+    function of t): time advances with the kinetic part, so a substep of
+    length h starting at tau applies exp(-i h v(., tau) / (2 gamma)), the
+    kinetic flow of length h (a Strang step with zero potential), then
+    exp(-i h v(., tau + h) / (2 gamma)); tau runs through t0 + (k + partial
+    sums of the weights) dt."""
     u = np.array(u0, dtype=np.complex128, copy=True)
-    for _ in range(steps):
+    if v1 is None:
+        for _ in range(steps):
+            for w in composition_weights(order):
+                u = strang_run(n, s_of_key, v, u, gamma, w * dt, 1, method=method)
+        return u
+    v = np.asarray(v, dtype=np.float64)
+    v1 = np.asarray(v1, dtype=np.float64)
+    zero = np.zeros(v.shape[-1])
+    for k in range(steps):
+        tau = t0 + k * dt
         for w in composition_weights(order):
-            u = strang_run(n, s_of_key, v, u, gamma, w * dt, 1, method=method)
+            h = w * dt
+            u = np.exp(-1j * h * (v + f(tau) * v1) / (2.0 * gamma)) * u
+            u = strang_run(n, s_of_key, zero, u, gamma, h, 1, method=method)
+            tau += h
+            u = np.exp(-1j * h * (v + f(tau) * v1) / (2.0 * gamma)) * u
     return u
 
 

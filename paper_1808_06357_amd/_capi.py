@@ -68,7 +68,8 @@ _SIGS = {
     "strang_batched_workspace_size": [_i32, _P, _i32, ctypes.POINTER(_sz)],
     "strang_run_batched": [_i32, _P, _i32, _P, _P, _P, _P, _P, _P, _sz, _P],
     "splitting_workspace_size": [_P, _i32, _i32, _i32, _i32, ctypes.POINTER(_sz)],
-    "splitting_run": [_P, _i32, _i32, _P, _i64, _P, _f64, _f64, _i64, _i32, _P, _sz, _P],
+    "splitting_run": [_P, _i32, _i32, _P, _P, _i64, _P, _P, _f64, _f64, _i64, _i32, _P, _sz, _P],
+    "splitting_times": [_i32, _i64, _f64, _f64, _P],
     "lattice_diagnostics_workspace_size": [_P, _i32, _i32, ctypes.POINTER(_sz)],
     "lattice_diagnostics": [_P, _i32, _i32, _P, _i64, _P, _f64, _P, _P, _sz, _P],
     "lattice_plan_autotune": [_P, _i32, _i32, _P],
@@ -306,8 +307,23 @@ def splitting_workspace_size(plan: Plan, prec: int, batch: int, shared_v: bool, 
     return n.value
 
 
-def splitting_run(plan: Plan, v, u, gamma: float, dt: float, steps: int, order: int = 4, work=None, stream=None):
-    """In-place run of a symmetric composition of Strang steps (order 2 or 4)."""
+def splitting_times(order: int, steps: int, t0: float, dt: float):
+    """Substep boundaries tau (numpy, steps * P + 1) at which splitting_run
+    samples the coefficient f of a time-dependent field."""
+    import numpy as np
+    P = 3 if order == 4 else 1
+    tau = np.empty(max(0, steps) * P + 1)
+    _check(lib.splitting_times(int(order), int(steps), float(t0), float(dt),
+                               tau.ctypes.data_as(ctypes.c_void_p)), "splitting_times")
+    return tau
+
+
+def splitting_run(plan: Plan, v, u, gamma: float, dt: float, steps: int, order: int = 4, v1=None, f=None,
+                  work=None, stream=None):
+    """In-place run of a symmetric composition of Strang steps (order 2 or 4)
+    under v, or under v + f(tau) v1 when v1 (device float64, shaped as v) and
+    f (host values at splitting_times(order, steps, t0, dt)) are given."""
+    import numpy as np
     import torch
     N = plan.N
     prec = _prec_of(u)
@@ -316,11 +332,20 @@ def splitting_run(plan: Plan, v, u, gamma: float, dt: float, steps: int, order: 
     _check_dev(v, "v", torch.float64)
     if v.numel() not in (N, batch * N):
         raise ValueError("v must hold N or batch*N values")
+    fh = None
+    if v1 is not None:
+        _check_dev(v1, "v1", torch.float64, v.numel())
+        if f is None:
+            raise ValueError("a time-dependent field v1 needs its coefficients f")
+        fh = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        if fh.size != steps * (3 if order == 4 else 1) + 1:
+            raise ValueError("f must hold steps * P + 1 values (P = 3 for order 4, else 1)")
     wb = 0
     if work is not None:
         _check_dev(work, "work")
         wb = work.numel() * work.element_size()
-    _check(lib.splitting_run(plan.handle, prec, batch, _dev_ptr(v), 0 if v.numel() == N else N, _dev_ptr(u),
+    _check(lib.splitting_run(plan.handle, prec, batch, _dev_ptr(v), _dev_ptr(v1), 0 if v.numel() == N else N,
+                             None if fh is None else fh.ctypes.data_as(ctypes.c_void_p), _dev_ptr(u),
                              float(gamma), float(dt), int(steps), int(order), _dev_ptr(work), wb,
                              _stream(stream)), "splitting_run")
     return u

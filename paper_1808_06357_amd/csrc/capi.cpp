@@ -1274,9 +1274,23 @@ lt_status splitting_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch
     return LT_OK;
 }
 
-lt_status splitting_run(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, int64_t v_stride,
-                        void *u, double gamma, double dt, int64_t steps, int32_t order, void *work,
-                        size_t work_bytes, void *stream)
+lt_status splitting_times(int32_t order, int64_t steps, double t0, double dt, double *tau)
+{
+    if (order != 2 && order != 4) return fail(LT_E_ARG, "order must be 2 or 4");
+    if (steps < 0) return fail(LT_E_ARG, "steps must be >= 0");
+    if (!tau) return fail(LT_E_ARG, "tau is NULL");
+    double w[3], c[4] = {0.0, 0.0, 0.0, 0.0};
+    const int P = composition_weights(order, w);
+    for (int i = 0; i < P; ++i) c[i + 1] = c[i] + w[i];
+    for (int64_t k = 0; k < steps; ++k)
+        for (int i = 0; i < P; ++i) tau[k * P + i] = t0 + ((double)k + c[i]) * dt;
+    tau[steps * P] = t0 + (double)steps * dt;
+    return LT_OK;
+}
+
+lt_status splitting_run(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, const double *v1,
+                        int64_t v_stride, const double *f, void *u, double gamma, double dt, int64_t steps,
+                        int32_t order, void *work, size_t work_bytes, void *stream)
 {
     lt_status st = check_common(cp, prec, batch, gamma, dt, steps);
     if (st) return st;
@@ -1284,7 +1298,14 @@ lt_status splitting_run(const lt_plan *cp, lt_prec prec, int32_t batch, const do
     lt_plan &p = *const_cast<lt_plan *>(cp);
     if (batch == 0 || steps == 0) return LT_OK;
     if (!v || !u) return fail(LT_E_ARG, "v and u must not be NULL");
+    if (v1 && !f) return fail(LT_E_ARG, "a time-dependent field v1 needs its coefficients f");
     if (v_stride != 0 && v_stride < p.N) return fail(LT_E_ARG, "v_stride must be 0 or >= N");
+    double w[3];
+    const int P = composition_weights(order, w);
+    const int64_t total = steps * P;  // substeps; f holds total + 1 values
+    if (v1)
+        for (int64_t j = 0; j <= total; ++j)
+            if (!std::isfinite(f[j])) return fail(LT_E_ARG, "f must be finite");
     // the two-pass slot exists for every plan; chirp-z lattices use the
     // convolution form for every substep
     const Sched &s = p.sched[1][prec];
@@ -1294,8 +1315,6 @@ lt_status splitting_run(const lt_plan *cp, lt_prec prec, int32_t batch, const do
     if (s.bluestein && (st = ensure_device_tables(p, 1, LT_C128, stream))) return st;
     const DevTables &D = p.dev[1][prec];
     hipStream_t hs = (hipStream_t)stream;
-    double w[3];
-    const int P = composition_weights(order, w);
     const ComposedWork L = composed_layout(p, s, prec, batch, v_stride == 0, P);
     Scratch sc;
     if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
@@ -1310,7 +1329,8 @@ lt_status splitting_run(const lt_plan *cp, lt_prec prec, int32_t batch, const do
         if (conv && (st = conv_spectrum(p, 1, ktab, conv, at(sc.ptr, L.tmp), hs))) return st;
         // merged potential step after substep i: half phases of substeps i and i+1
         const double merged = (dti + w[(i + 1) % P] * dt) / (2.0 * gamma);
-        void *ptab = prec == LT_C64 ? at(sc.ptr, L.ptab[i]) : nullptr;
+        // complex64, time-independent v: the merged phases as per-point tables
+        void *ptab = prec == LT_C64 && !v1 ? at(sc.ptr, L.ptab[i]) : nullptr;
         if (ptab) HIP_TRY(launch_phase_table(prec, ptab, v, v_stride, v_stride ? batch : 1, N, merged, hs),
                           "potential table");
         R[i] = two_pass_roles(s, D, N, v, v_stride, u, W, dti / (2.0 * gamma), ktab, ptab);
@@ -1318,16 +1338,23 @@ lt_status splitting_run(const lt_plan *cp, lt_prec prec, int32_t batch, const do
         R[i].first.chirp = 0;
         R[i].last.chirp = 0;
         if (conv) R[i].row.bhat = (const double *)conv;
+        if (v1) R[i].first.v2 = R[i].pot.v2 = R[i].last.v2 = v1;
     }
-    HIP_TRY(launch_col(prec, s, R[0].first, batch, hs), "column pass");
-    const int64_t total = steps * P;
+    // time-dependent field: the angle at substep boundary j carries f[j] v1
+    ColArgs first = R[0].first;
+    if (v1) first.phase2 = first.phase * f[0];
+    HIP_TRY(launch_col(prec, s, first, batch, hs), "column pass");
     for (int64_t k = 0; k < total; ++k) {
         const Roles &r = R[k % P];
         HIP_TRY(launch_row(prec, s, r.row, batch, hs), "row pass");
         if (k == total - 1) break;
-        HIP_TRY(launch_col(prec, s, r.pot, batch, hs), "column pass (potential)");
+        ColArgs pot = r.pot;
+        if (v1) pot.phase2 = pot.phase * f[k + 1];
+        HIP_TRY(launch_col(prec, s, pot, batch, hs), "column pass (potential)");
     }
-    HIP_TRY(launch_col(prec, s, R[(total - 1) % P].last, batch, hs), "column pass (last)");
+    ColArgs last = R[(total - 1) % P].last;
+    if (v1) last.phase2 = last.phase * f[total];
+    HIP_TRY(launch_col(prec, s, last, batch, hs), "column pass (last)");
     return LT_OK;
 }
 

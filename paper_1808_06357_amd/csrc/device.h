@@ -408,12 +408,13 @@ __device__ __forceinline__ cx<T> mul_expm_i(cx<T> x, double a)
 
 // point-domain multiplier of a column pass (see ColArgs)
 template <typename T>
-__device__ __forceinline__ cx<T> col_mid(cx<T> x, const ColArgs &a, const double *vb, int64_t n)
+__device__ __forceinline__ cx<T> col_mid(cx<T> x, const ColArgs &a, const double *vb, const double *vb2,
+                                         int64_t n)
 {
     const bool any = vb || a.ktab || a.chirp || a.scale != 1.0;
     if (!any) return x;
     double c = 1.0, s = 0.0;
-    if (vb) expm_i(a.phase * vb[n], c, s);
+    if (vb) expm_i(vb2 ? a.phase * vb[n] + a.phase2 * vb2[n] : a.phase * vb[n], c, s);
     if (a.ktab) {
         const int m = a.s[n];
         const double kr = a.ktab[2 * m], ki = a.ktab[2 * m + 1];

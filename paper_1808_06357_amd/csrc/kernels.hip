@@ -165,6 +165,7 @@ __device__ void col_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
 
     // ---- point-domain work (natural index n)
     const double *vb = a.v ? a.v + b * a.v_bs : nullptr;
+    const double *vb2 = a.v && a.v2 ? a.v2 + b * a.v_bs : nullptr;
     for (int e = threadIdx.x; e < L1 * C; e += kThreads) {
         const int n1 = fdiv(e, dC), qc = e - n1 * C;
         if (qc >= cw) continue;
@@ -179,7 +180,7 @@ __device__ void col_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
         }
         if (!a.adjoint) {
             if (a.ck) col_checkpoint(x, a, b, n);
-            x = col_mid(x, a, vb, n);
+            x = col_mid(x, a, vb, vb2, n);
             if (a.out) ((cx<T> *)a.out)[b * a.out_bs + n] = x;
             else s[e0] = x;
         } else {

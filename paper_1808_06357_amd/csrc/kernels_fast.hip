@@ -228,9 +228,10 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
                 v[j * R + r] = n < a.Nvalid ? twmul(conjg(v[j * R + r]), pin[j][r]) : cx<T>{0, 0};
             }
         }
-    } else if constexpr (MID == 0 || MID == 2) {
+    } else if constexpr (MID == 0 || MID == 2 || MID == 3) {
         // complex128 (and batches): exp(-i phase v) in FP64 on the fly (the table would cost
-        // as many bytes as v and more registers than the kernel has)
+        // as many bytes as v and more registers than the kernel has).  MID 3: the angle
+        // phase v[n] + phase2 v2[n] of a time-dependent potential, both fields in FP64
         double pin[J][R];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -242,6 +243,18 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
                 pin[j][r] = n < a.Nvalid ? a.v[b * a.v_bs + n] : 0.0;
             }
         }
+        if constexpr (MID == 3) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int bf = threadIdx.x + j * NT;
+                const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t n = (int64_t)(t + r * BPS) * L2 + c0 + q;
+                    pin[j][r] = a.phase * pin[j][r] + (n < a.Nvalid ? a.phase2 * a.v2[b * a.v_bs + n] : 0.0);
+                }
+            }
+        }
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             const int bf = threadIdx.x + j * NT;
@@ -249,7 +262,8 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t n = (int64_t)(t + r * BPS) * L2 + c0 + q;
-                v[j * R + r] = n < a.Nvalid ? mul_expm_i(conjg(v[j * R + r]), a.phase * pin[j][r]) : cx<T>{0, 0};
+                const double ang = MID == 3 ? pin[j][r] : a.phase * pin[j][r];
+                v[j * R + r] = n < a.Nvalid ? mul_expm_i(conjg(v[j * R + r]), ang) : cx<T>{0, 0};
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -555,13 +569,17 @@ template <typename T, int V, int... Rs>
 int col_go(const ColArgs &a, int batch, void *stream)
 {
     constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW;
-    // MID 0: merged potential step from the per-point table; MID 1: kinetic table
-    auto k = a.v ? k_colf<T, E, NT, MINW, 0, Rs...> : k_colf<T, E, NT, MINW, 1, Rs...>;
+    // MID 0: merged potential step from the per-point table; MID 1: kinetic table;
+    // MID 3: potential with a time-dependent second field
+    auto k = a.v ? (a.v2 ? k_colf<T, E, NT, MINW, 3, Rs...> : k_colf<T, E, NT, MINW, 0, Rs...>)
+                 : k_colf<T, E, NT, MINW, 1, Rs...>;
     static bool attr = false;
     if (!attr) {
         hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 0, Rs...>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 1, Rs...>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 3, Rs...>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
@@ -700,7 +718,7 @@ int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *st
     // and the adjoint passes take the general kernel
     const bool steady = a.pre_inv && a.post_fwd && !a.in && !a.out && !a.ck && !a.chirp &&
                         a.scale == 1.0 && !a.adjoint && ((a.v != nullptr) != (a.ktab != nullptr)) &&
-                        (prec == LT_C128 || !a.v || a.ptab);
+                        (prec == LT_C128 || !a.v || a.ptab || a.v2);
     if (!steady || !fast_col_fits(prec, variant, a.L1, a.L2, a.C)) return -1;
     if (prec == LT_C128)
         return variant == 1 ? go<double, 1, true>(a.L1, a, batch, stream) : go<double, 2, true>(a.L1, a, batch, stream);

@@ -65,6 +65,8 @@ struct ColArgs {
     int64_t Nvalid;
     int pre_inv, post_fwd, twiddle;
     const double *v; int64_t v_bs; double phase;
+    const double *v2; double phase2; // optional second field: angle phase v[n] + phase2 v2[n]
+                                      // (time-dependent potentials; v2 strided as v)
     const int32_t *s; const double *ktab;
     int chirp;                        // +1: times c_n, -1: times conj(c_n), 0: none
     int64_t Nchirp;

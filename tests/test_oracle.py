@@ -8,6 +8,7 @@ import itertools
 
 import numpy as np
 import pytest
+import scipy.integrate
 import scipy.linalg
 
 import oracle as O
@@ -308,6 +309,56 @@ def test_fourth_order_composition_against_exact_propagator():
     # order 2 is the plain Strang run
     assert np.allclose(O.composed_run(n, s, v, u0, gamma, 0.05, 3, order=2),
                        O.strang_run(n, s, v, u0, gamma, 0.05, 3), rtol=0, atol=1e-13)
+
+
+def _tdv_case():
+    Z, n = np.array([[1, 34]]), np.array([55])
+    h, s, _ = O.index_set(Z, n)
+    num = W.point_numerators(Z, n)
+    v = W.v_sum_one_minus_cos(num, 55)
+    v1 = W.v_product(num, 55, 0.7)
+    x = O.points(Z, n)
+    u0 = np.exp(-np.sum((x - 0.5) ** 2, axis=1) / 0.05).astype(complex)
+    return Z, n, s, v, v1, u0
+
+
+def test_time_dependent_special_cases():
+    """A constant coefficient f = c is the time-independent run under v + c v1;
+    a spatially constant v1 with f linear in t only adds the global phase
+    exp(-(i/gamma) int f dt) (the substep boundaries' trapezoid sums are exact
+    for linear f, also across the backward middle substep of order 4)."""
+    Z, n, s, v, v1, u0 = _tdv_case()
+    gamma, dt, m = 0.3, 0.05, 6
+    for order in (2, 4):
+        a = O.composed_run(n, s, v, u0, gamma, dt, m, order=order, v1=v1, f=lambda t: 0.8)
+        b = O.composed_run(n, s, v + 0.8 * v1, u0, gamma, dt, m, order=order)
+        assert np.allclose(a, b, rtol=0, atol=1e-13), order
+        t0, T = 0.2, m * dt
+        lin = lambda t: 1.5 - 2.0 * t
+        integral = 1.5 * T - (((t0 + T) ** 2) - t0 ** 2)
+        a = O.composed_run(n, s, v, u0, gamma, dt, m, order=order, v1=np.ones(55), f=lin, t0=t0)
+        b = O.composed_run(n, s, v, u0, gamma, dt, m, order=order) * np.exp(-1j * integral / gamma)
+        assert np.allclose(a, b, rtol=0, atol=1e-13), order
+
+
+def test_time_dependent_orders_against_ode_solution():
+    """v(x, t) = v(x) + f(t) v1(x) with f(t) = 1 + 2 sin 5t: against a DOP853
+    solution (rtol 1e-13) of the lattice ODE i gamma u' = (gamma^2/2)
+    F^-1 D_n F u + v(., t) u, the composition converges at order 2 (Strang)
+    and 4 (triple jump)."""
+    Z, n, s, v, v1, u0 = _tdv_case()
+    gamma, T = 0.3, 0.4
+    _, (F, Fi, Wn, Dn) = _dense_coefficient_strang(Z, n, s, v, u0, gamma, 0.1, 0)
+    Kpt = Fi @ (gamma * Dn / 2) @ F
+    f = lambda t: 1.0 + 2.0 * np.sin(5.0 * t)
+    sol = scipy.integrate.solve_ivp(lambda t, y: -1j * ((v + f(t) * v1) / gamma * y + Kpt @ y), (0, T), u0,
+                                    method="DOP853", rtol=1e-13, atol=1e-13)
+    ref = sol.y[:, -1]
+    for order, ms, lo, hi in ((2, (16, 32, 64), 1.95, 2.05), (4, (32, 64, 128), 3.85, 4.15)):
+        errs = [np.linalg.norm(O.composed_run(n, s, v, u0, gamma, T / m, m, order=order, v1=v1, f=f) - ref)
+                for m in ms]
+        orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+        assert np.all((orders > lo) & (orders < hi)), (order, orders)
 
 
 def test_config0_second_order_paper_protocol():

@@ -175,16 +175,34 @@ def test_diagnostics_argument_errors_on_host():
 def test_splitting_argument_errors_on_host():
     p = C.lattice_plan(np.array([[1, 34]]), np.array([55]))
     h = p.handle
-    args = (None, 0, None, 0.1, 0.01, 5)
-    assert C.lib.splitting_run(h, 2, 1, *args, 3, None, 0, None) == 1           # order
-    assert b"order" in C.lib.lt_last_error()
-    assert C.lib.splitting_run(h, 2, 1, *args, 4, None, 0, None) == 1           # NULL v, u
-    assert C.lib.splitting_run(h, 3, 1, *args, 4, None, 0, None) == 1           # precision
-    assert C.lib.splitting_run(h, 2, 1, None, 0, None, 0.1, 0.01, -1, 4, None, 0, None) == 1  # steps
-    assert C.lib.splitting_run(h, 2, 0, *args, 4, None, 0, None) == 0           # empty batch
-    assert C.lib.splitting_run(h, 2, 1, None, 0, None, 0.1, 0.01, 0, 4, None, 0, None) == 0  # no steps
+    r = C.lib.splitting_run
+
+    def call(prec=2, batch=1, v1=None, f=None, steps=5, order=4, gamma=0.1):
+        return r(h, prec, batch, None, v1, 0, f, None, gamma, 0.01, steps, order, None, 0, None)
+    assert call(order=3) == 1 and b"order" in C.lib.lt_last_error()
+    assert call() == 1                       # NULL v, u
+    assert call(prec=3) == 1                 # precision
+    assert call(steps=-1) == 1
+    assert call(gamma=0.0) == 1
+    assert call(batch=0) == 0                # empty batch
+    assert call(steps=0) == 0                # no steps
     with pytest.raises(C.LatticeError):
         C.splitting_workspace_size(p, C.LT_C128, 1, True, 6)
     s2 = C.splitting_workspace_size(p, C.LT_C64, 1, True, 2)
     s4 = C.splitting_workspace_size(p, C.LT_C64, 1, True, 4)
     assert s4 > s2 > 0
+
+
+def test_splitting_times():
+    """Substep boundaries: order 2 is the plain grid t0 + k dt; order 4 steps
+    through t0 + (k + c_i) dt with c = (0, w1, w1 + w0) and ends at t0 + m dt."""
+    assert np.array_equal(C.splitting_times(2, 4, 1.0, 0.25), 1.0 + 0.25 * np.arange(5))
+    w1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+    tau = C.splitting_times(4, 2, 0.5, 0.1)
+    c = np.array([0.0, w1, 1.0 - w1])
+    assert tau.shape == (7,)
+    assert np.allclose(tau[:6], 0.5 + 0.1 * (np.repeat([0.0, 1.0], 3) + np.tile(c, 2)), rtol=0, atol=1e-15)
+    assert abs(tau[6] - 0.7) < 1e-15
+    assert tau[2] < tau[1]                   # the middle substep runs backwards
+    with pytest.raises(C.LatticeError):
+        C.splitting_times(3, 2, 0.0, 0.1)
