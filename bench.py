@@ -18,7 +18,8 @@ rank-2 lattice 4096 x 256; and a forward run with checkpoints plus its adjoint
 Sec. 3.3 on a 2^20-point lattice; the time-step convergence protocol of
 Sec. 3.2 on a lattice of the paper's Table 1 (d = 3, n = 2^22); and the
 fourth-order composition and a time-dependent potential (Sec. 5) on the
-benchmark lattice.
+benchmark lattice; and the Table 1 lattice d = 6, n = 2^25, whose transform
+takes rows of 8192 points.
 """
 from __future__ import annotations
 
@@ -333,6 +334,39 @@ def bench_convergence(lt, torch, K, W):
     return out
 
 
+def bench_wide(lt, torch, K, W):
+    """The paper's Table 1 lattice d = 6, n = 2^25 (the transform split into
+    columns of 4096 and rows of 8192 points) with g1, the smooth v1,
+    gamma = 0.5, dt = 1e-3, 100 steps per run."""
+    import workloads as W_
+    Z, n = W_.paper_lattice(6, 1 << 25)
+    N, m, gamma, dt = int(n[0]), 100, 0.5, 1e-3
+    t = time.perf_counter()
+    plan = lt.lattice_plan(Z, n)
+    tplan = time.perf_counter() - t
+    info = plan.info
+    num = W_.point_numerators(Z, n)
+    dev = torch.device("cuda:0")
+    v = torch.tensor(W_.v_smooth_paper(num, N), device=dev)
+    u0 = W_.paper_g1(num, N, gamma)
+    out = {"workload": f"paper Table 1 lattice d=6 n=2^25 z={list(map(int, Z[0]))}, minimal-l2 index set, g1, v1, "
+                       f"gamma={gamma}, dt={dt}, {m} steps per run; transform {info['L1']} x {info['L2']}",
+           "unit": "lattice-point-steps/s", "plan_seconds": tplan}
+    for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
+        prec = lt.LT_C64 if name == "c64" else lt.LT_C128
+        kernels = lt.lattice_plan_autotune(plan, prec, reps=3)
+        u = torch.tensor(u0, dtype=dtype, device=dev)
+        work = torch.empty(lt.strang_workspace_size(plan, prec, 1, True), dtype=torch.uint8, device=dev)
+        run = lambda: lt.strang_run(plan, v, u, gamma, dt, m, work=work)  # noqa: E731
+        sec = wall(run, K, W)
+        out[name] = {"value": N * m / sec, "ms_per_run": sec * 1e3, "kernel_variants": list(kernels),
+                     "kernels": kernel_summary(lt, run, 1)}
+        log(f"wide {name}: {N * m / sec:.3e} pt-steps/s, {sec * 1e3:.1f} ms per {m}-step run")
+        del u, work
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_splitting(lt, torch, K, W):
     """Higher-order splitting and time-dependent potentials (the two method
     variants of Sec. 5) on the benchmark lattice (d = 6, N = 1048573):
@@ -417,7 +451,8 @@ def main():
     ap.add_argument("--no-c128", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the companion workloads")
-    ap.add_argument("--only", choices=["batched", "rank2", "adjoint", "conservation", "convergence", "splitting"],
+    ap.add_argument("--only", choices=["batched", "rank2", "adjoint", "conservation", "convergence", "splitting",
+                                       "wide"],
                     help="run one companion workload alone (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device (counter calibration for the traffic figure)")
@@ -445,7 +480,7 @@ def main():
 
     extras = {"batched": bench_batched, "rank2": bench_rank2, "adjoint": bench_adjoint,
               "conservation": bench_conservation, "convergence": bench_convergence,
-              "splitting": bench_splitting}
+              "splitting": bench_splitting, "wide": bench_wide}
     if args.only:
         print(json.dumps({args.only: extras[args.only](lt, torch, args.steps, args.warmup)}), flush=True)
         return

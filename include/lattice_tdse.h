@@ -76,7 +76,8 @@ typedef struct {
     int32_t bluestein;       /* 1: the length-N transform runs as a chirp-z convolution */
     int32_t passes;          /* 1: whole run in one workgroup; 2: column + row passes  */
     int64_t fft_len;         /* transform length L (N, or the convolution length)    */
-    int32_t L1, L2;          /* column / row lengths of the two-pass layout (L = L1*L2) */
+    int32_t L1, L2;          /* column / row lengths of the two-pass layout (L = L1*L2;
+                                up to 4096 x 4096, above that 4096 x 8192 at most) */
     int32_t cols;            /* columns per column-pass workgroup                     */
     int32_t rows;            /* rows per row-pass workgroup                           */
 } lt_plan_info;

@@ -987,6 +987,7 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
             lds_res = std::max(lds_res, (size_t)s.L * S);
             continue;
         }
+        if (s.L2 > kTileElems) return fail(LT_E_UNSUPPORTED, "batch members take rows of at most 4096 points");
         Roles R = two_pass_roles(s, D, p.N, v[i], 0, u[i], w + L.w, half, ktab);
         // chirp-z problems of 4 steps or more: the convolution form (spectrum
         // built below, once the kinetic tables exist)

@@ -661,6 +661,8 @@ int kernels_init()
     hipFuncSetAttribute((const void *)k_col<double, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_row<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_row<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_row<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipFuncSetAttribute((const void *)k_row<double, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_resident<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_resident<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_col_multi<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
@@ -701,6 +703,11 @@ int launch_row(int prec, const Sched &s, const RowArgs &a, int batch, void *stre
     }
     const size_t lds = (size_t)a.rows * a.L2 * esize(prec);
     dim3 grid(a.nblk, batch);
+    if ((int64_t)a.rows * a.L2 > kTileElems) {  // one row of up to kWideRow points
+        if (prec == LT_C128)
+            return timed_launch(LT_KIND_ROW, k_row<double, 32>, grid, dim3(kThreads), lds, stream, a);
+        return timed_launch(LT_KIND_ROW, k_row<float, 32>, grid, dim3(kThreads), lds, stream, a);
+    }
     if (prec == LT_C128)
         return timed_launch(LT_KIND_ROW, k_row<double, 16>, grid, dim3(kThreads), lds, stream, a);
     return timed_launch(LT_KIND_ROW, k_row<float, 16>, grid, dim3(kThreads), lds, stream, a);

@@ -552,7 +552,27 @@ __device__ __forceinline__ void rowf_body(const RowArgs &a, int blk, int64_t b, 
 #pragma unroll
         for (int r = 0; r < R; ++r) v[j * R + r] = bload<T>(rb, voff[j], r * rstep);
     }
+    // kinetic table: the squared-norm index of every element (4 bytes at the
+    // element's offset scaled by 4 / sizeof(cx<T>)); after the forward DFT
+    // each thread holds the spectrum at the same positions, so the
+    // multiplier is applied in registers.  The indices are loaded with the
+    // state, except in the complex128 8192-point rows, where holding them
+    // through the DFT would spill.
+    constexpr bool kPreS = MID == 1 && !(sizeof(T) == 8 && TILE > 4096);
+    int sk[MID == 1 ? E : 1];
+    auto load_sk = [&]() {
+        const rsrc_t rs = make_rsrc(a.s + p0, (int64_t)TILE * 4);
+        constexpr uint32_t ss = (uint32_t)sizeof(cx<T>) / 4;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                sk[j * R + r] = (int)__builtin_amdgcn_raw_buffer_load_b32(rs, voff[j] / ss, r * (rstep / ss), 0);
+        }
+    };
+    if constexpr (kPreS) load_sk();
     F::run(v, s, B, false);
+    if constexpr (MID == 1 && !kPreS) load_sk();
     if constexpr (MID == 0) {
         // chirp-z kernel spectrum: one complex-double load per element, at the
         // element's offset scaled by 16 / sizeof(cx<T>)
@@ -573,28 +593,19 @@ __device__ __forceinline__ void rowf_body(const RowArgs &a, int blk, int64_t b, 
             }
         }
     } else {
-        // kinetic table indexed by the squared norm: gather through LDS
-        __syncthreads();
+        // kinetic table indexed by the squared norm (a small table, cached):
+        // every entry of the thread in flight at once.  The indices come
+        // from the plan's squared-norm table and stay below the table's
+        // length, so the resource carries no tighter bound.
+        const rsrc_t rk = make_rsrc(a.ktab, (int64_t)1 << 30);
+        constexpr int KC = kPreS ? E : 8;  // entries in flight (fewer where registers are short)
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const int bf = threadIdx.x + j * NT;
-            const int q = F::q_of(bf), t = F::t_of(bf);
+        for (int e0 = 0; e0 < E; e0 += KC) {
+            cx<double> k[KC];
 #pragma unroll
-            for (int r = 0; r < R; ++r) s[F::addr(q, t + r * BPS)] = v[j * R + r];
-        }
-        __syncthreads();
-#pragma unroll 1
-        for (int i = threadIdx.x; i < TILE; i += NT) {
-            const int at = pidx(i);
-            s[at] = conjg(row_mid(s[at], a, p0 + i));
-        }
-        __syncthreads();
+            for (int e = 0; e < KC; ++e) k[e] = bload<double>(rk, (uint32_t)sk[e0 + e] * 16u, 0);
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const int bf = threadIdx.x + j * NT;
-            const int q = F::q_of(bf), t = F::t_of(bf);
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[j * R + r] = s[F::addr(q, t + r * BPS)];
+            for (int e = 0; e < KC; ++e) v[e0 + e] = conjg(cmul_d(v[e0 + e], k[e].x, k[e].y));
         }
     }
     F::run(v, s, B, true);
@@ -641,6 +652,10 @@ struct Geo<1> {
 template <>
 struct Geo<2> {
     static constexpr int NT = 512, E = 8, MINW = 4;
+};
+template <>
+struct Geo<3> {  // rows of kWideRow points: one row per workgroup
+    static constexpr int NT = 512, E = 16, MINW = 1;
 };
 
 template <typename K, typename A>
@@ -731,7 +746,10 @@ int go1(const A &a, int batch, void *stream)
 template <typename T, int V, bool COL, class A>
 int go(int L, const A &a, int batch, void *stream)
 {
-    if constexpr (V == 1) {  // 16 elements per thread
+    if constexpr (V == 3) {  // 16 elements per thread, 512 threads: rows of 8192
+        if (L == 8192 && !COL) return go1<T, V, COL, 16, 4, 8, 16>(a, batch, stream);
+        return -1;
+    } else if constexpr (V == 1) {  // 16 elements per thread
         switch (L) {
         case 64: return go1<T, V, COL, 8, 8>(a, batch, stream);
         case 128: return go1<T, V, COL, 8, 2, 8>(a, batch, stream);
@@ -838,7 +856,12 @@ int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *st
 
 int launch_row_fast(int prec, int variant, const RowArgs &a, int batch, void *stream)
 {
-    if (a.fft_only || !fast_row_fits(prec, variant, a.L1, a.L2, a.rows)) return -1;
+    if (a.fft_only) return -1;
+    if (a.L2 == kWideRow && a.rows == 1 && (variant == 1 || variant == 2)) {
+        if (prec == LT_C128) return go<double, 3, false>(a.L2, a, batch, stream);
+        return go<float, 3, false>(a.L2, a, batch, stream);
+    }
+    if (!fast_row_fits(prec, variant, a.L1, a.L2, a.rows)) return -1;
     if (prec == LT_C128)
         return variant == 1 ? go<double, 1, false>(a.L2, a, batch, stream) : go<double, 2, false>(a.L2, a, batch, stream);
     return variant == 1 ? go<float, 1, false>(a.L2, a, batch, stream) : go<float, 2, false>(a.L2, a, batch, stream);

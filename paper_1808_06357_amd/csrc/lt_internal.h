@@ -15,6 +15,7 @@ namespace lt {
 constexpr int kThreads = 256;           // workgroup size of every FFT kernel
 constexpr int kMaxStages = 24;
 constexpr int64_t kTileElems = 4096;     // complex elements per workgroup tile
+constexpr int64_t kWideRow = 8192;       // row length of the widest two-pass split (one row per workgroup)
 
 // Radix sequence of one sub-transform of length L (product of radices).
 struct Radices {

@@ -303,7 +303,7 @@ Sched make_schedule(const lt_plan &p, int prec, bool force_two_pass)
         if (s.L > tile || force_two_pass) {
             int64_t q = 1;
             while (q < 2 * p.N - 1) q <<= 1;
-            if (q <= tile * tile) s.L = q;
+            if (q <= tile * kWideRow) s.L = q;
         }
     }
     if (s.L <= tile && !force_two_pass) {
@@ -315,7 +315,13 @@ Sched make_schedule(const lt_plan &p, int prec, bool force_two_pass)
         s.ok = true;
         return s;
     }
-    if (!split_two_pass(s.L, tile, s.L1, s.L2)) return s;
+    if (!split_two_pass(s.L, tile, s.L1, s.L2)) {
+        // above tile^2 points: rows of kWideRow points, one per workgroup
+        // (columns of at most one tile)
+        if (s.L % kWideRow || s.L / kWideRow > tile || !is_smooth7(s.L / kWideRow)) return s;
+        s.L1 = (int)(s.L / kWideRow);
+        s.L2 = (int)kWideRow;
+    }
     if (!factor_radices(s.L1, s.ra, mr) || !factor_radices(s.L2, s.rb, mr)) return s;
     s.passes = 2;
     s.cols = (int)std::max<int64_t>(1, std::min<int64_t>(tile / s.L1, s.L2));

@@ -1,0 +1,107 @@
+"""Lattices above 4096^2 transform points, split into columns of 4096 and
+rows of 8192 points (one row per workgroup): the paper's Table 1 lattice
+d = 3, n = 2^25 (Sec. 3.2) and a prime N = 8388617 whose chirp-z length is
+2^25, against stored FP64 oracle samples after 4 steps
+(tests/golden/make_wide_golden.py), with both the general and the
+register-staged row kernels; and properties at full size: a sum of low
+modes under v = 0 evolves in closed form, and a run with -dt undoes a run
+with dt."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from test_gpu_parity import TOL, _dtype, rel
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "wide_oracle_samples.npz")
+GAMMA, DT, STEPS = 0.5, 1e-3, 4
+_plans = {}
+
+
+def _case(lt, name):
+    if name not in _plans:
+        if name == "table1_d3":
+            Z, n = W.paper_lattice(3, 1 << 25)
+            vfun = W.v_smooth_paper
+        else:
+            N = 8388617
+            z = W.korobov_good(N, 2, np.random.default_rng(3))
+            Z, n = z.reshape(1, -1), np.array([N])
+            vfun = W.v_harmonic_paper
+        print(f"planning {name}", flush=True)
+        plan = lt.lattice_plan(Z, n)
+        _plans[name] = (Z, n, vfun, plan)
+    return _plans[name]
+
+
+@pytest.mark.parametrize("name", ["table1_d3", "prime_d2"])
+def test_wide_rows_against_oracle_samples(lt, name):
+    import torch
+    gold = np.load(GOLD)
+    Z, n, vfun, plan = _case(lt, name)
+    assert np.array_equal(Z[0], gold[f"{name}_z"])
+    info = plan.info
+    assert (info["passes"], info["L1"], info["L2"], info["fft_len"]) == (2, 4096, 8192, 1 << 25)
+    N = int(n[0])
+    num = W.point_numerators(Z, n)
+    v = torch.tensor(vfun(num, N), device="cuda")
+    u0 = W.paper_g1(num, N, GAMMA)
+    idx = gold[f"{name}_idx"]
+    for variant in (0, 1):
+        for prec in ("c128", "c64"):
+            p = lt.LT_C128 if prec == "c128" else lt.LT_C64
+            lt.lattice_plan_set_kernels(plan, p, variant, variant)
+            u = torch.tensor(u0, dtype=_dtype(prec), device="cuda")
+            print(f"  {name} variant={variant} {prec}", flush=True)
+            lt.strang_run(plan, v, u, GAMMA, DT, STEPS)
+            torch.cuda.synchronize()
+            norm2 = float(torch.mean(torch.abs(u.to(torch.complex128)) ** 2))
+            got = u[torch.from_numpy(idx).to("cuda")].cpu().numpy().astype(np.complex128)
+            e = rel(got, gold[f"{name}_u"])
+            print(f"    rel_l2={e:.2e} norm2={norm2:.15f}", flush=True)
+            assert e < TOL[prec], (variant, prec, e)
+            assert abs(norm2 - float(gold[f"{name}_norm2"])) < 2.0 * TOL[prec]
+            del u
+
+
+def test_wide_free_modes_closed_form_and_reversibility(lt):
+    """v = 0: u0 = sum_k c_k exp(2 pi i h_k . x) for low modes h_k (each the
+    minimal representative of its key) evolves to sum_k c_k exp(-i 2 pi^2
+    gamma ||h_k||^2 m dt) exp(2 pi i h_k . x) exactly."""
+    import torch
+    Z, n, _, plan = _case(lt, "table1_d3")
+    N = int(n[0])
+    num = W.point_numerators(Z, n)
+    H = np.array([[0, 0, 0], [1, 0, 0], [0, -2, 1], [3, 1, -1], [-1, 2, 2]])
+    c = np.array([0.5, 1.0 - 0.5j, 0.25j, -0.7, 0.3 + 0.1j])
+    gamma, dt, m = 0.05, 2e-3, 6
+
+    def modes(t):
+        u = np.zeros(N, dtype=np.complex128)
+        for h, ck in zip(H, c):
+            ph = (num @ h) % N  # exact integer phase numerator of h . x
+            u += ck * np.exp(-2j * np.pi ** 2 * gamma * float(h @ h) * t) * np.exp(2j * np.pi * ph / N)
+        return u
+
+    u0, uT = modes(0.0), modes(m * dt)
+    zero = torch.zeros(N, dtype=torch.float64, device="cuda")
+    for prec in ("c128", "c64"):
+        p = lt.LT_C128 if prec == "c128" else lt.LT_C64
+        lt.lattice_plan_set_kernels(plan, p, 1, 1)
+        u = torch.tensor(u0, dtype=_dtype(prec), device="cuda")
+        lt.strang_run(plan, zero, u, gamma, dt, m)
+        e = rel(u.cpu().numpy().astype(np.complex128), uT)
+        print(f"  free modes {prec}: rel_l2={e:.2e}", flush=True)
+        assert e < TOL[prec], (prec, e)
+        del u
+    v = torch.tensor(W.v_smooth_paper(num, N), device="cuda")
+    u = torch.tensor(W.paper_g1(num, N, GAMMA), dtype=torch.complex128, device="cuda")
+    ref = u.clone()
+    lt.strang_run(plan, v, u, GAMMA, DT, 5)
+    lt.strang_run(plan, v, u, GAMMA, -DT, 5)
+    e = float(torch.linalg.vector_norm(u - ref) / torch.linalg.vector_norm(ref))
+    print(f"  reversibility c128: {e:.2e}", flush=True)
+    assert e < 1e-12
