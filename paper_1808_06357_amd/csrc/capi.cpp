@@ -202,7 +202,7 @@ RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool s
     w.w = off;
     if (s.bluestein && s.passes == 2) off = align_up(off + (size_t)batch * s.L * esz(prec));
     w.ptab = off;
-    if (s.passes == 2 && phase_table && prec == LT_C64)
+    if (s.passes == 2 && phase_table)
         off = align_up(off + (size_t)(shared_v ? 1 : batch) * p.N * 16);
     if (s.bluestein && s.passes == 2 && conv_space) {
         // kernel spectrum of the step's cyclic convolution (complex double, L)
@@ -784,7 +784,7 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
         if ((st = conv_spectrum(p, 0, ktab, conv, at(sc.ptr, L.conv_tmp), hs))) return st;
     }
     return two_pass_forward(p, s, D, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every,
-                            ktab, at(sc.ptr, L.w), prec == LT_C64 ? at(sc.ptr, L.ptab) : nullptr, conv, hs);
+                            ktab, at(sc.ptr, L.w), at(sc.ptr, L.ptab), conv, hs);
 }
 
 lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, int64_t v_stride,
@@ -1144,10 +1144,8 @@ ComposedWork composed_layout(const lt_plan &p, const Sched &s, int prec, int bat
             c.conv[i] = off;
             off = align_up(off + (size_t)s.L * 16);
         }
-        if (prec == LT_C64) {
-            c.ptab[i] = off;
-            off = align_up(off + (size_t)(shared_v ? 1 : batch) * p.N * 16);
-        }
+        c.ptab[i] = off;
+        off = align_up(off + (size_t)(shared_v ? 1 : batch) * p.N * 16);
     }
     c.w = off;
     if (s.bluestein) off = align_up(off + (size_t)batch * s.L * esz(prec));
@@ -1330,8 +1328,8 @@ lt_status splitting_run(const lt_plan *cp, lt_prec prec, int32_t batch, const do
         if (conv && (st = conv_spectrum(p, 1, ktab, conv, at(sc.ptr, L.tmp), hs))) return st;
         // merged potential step after substep i: half phases of substeps i and i+1
         const double merged = (dti + w[(i + 1) % P] * dt) / (2.0 * gamma);
-        // complex64, time-independent v: the merged phases as per-point tables
-        void *ptab = prec == LT_C64 && !v1 ? at(sc.ptr, L.ptab[i]) : nullptr;
+        // time-independent v: the merged phases as per-point tables
+        void *ptab = !v1 ? at(sc.ptr, L.ptab[i]) : nullptr;
         if (ptab) HIP_TRY(launch_phase_table(prec, ptab, v, v_stride, v_stride ? batch : 1, N, merged, hs),
                           "potential table");
         R[i] = two_pass_roles(s, D, N, v, v_stride, u, W, dti / (2.0 * gamma), ktab, ptab);

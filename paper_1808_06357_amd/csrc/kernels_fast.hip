@@ -257,10 +257,11 @@ __device__ __forceinline__ void tw4_base_step(cx<double> &b, cx<double> &st, int
 
 // Steady-state column pass: [inverse column DFT -> point-domain multiplier
 // (and chirp-z mask) -> forward column DFT], in place, on column tile `tile`
-// of batch item b.  MID 0: the merged potential step (complex64: from the
-// per-point table; complex128: FP64 phase of v); MID 1: the chirp-z kinetic
-// step from the table indexed by the squared norm; MID 2: the merged
-// potential step from v in FP64 (both precisions; batches carry no table).
+// of batch item b.  MID 0: the merged potential step from the per-point
+// table the run built; MID 1: the chirp-z
+// kinetic step from the table indexed by the squared norm; MID 2: the merged
+// potential step from v in FP64 (batches carry no table); MID 3: the angle of
+// a time-dependent potential from two fields.
 template <typename T, int E, int NT, int MID, int... Rs>
 __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
 {
@@ -310,20 +311,22 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
     // point-domain multiplier: the table entries of all of this thread's
     // elements are loaded in one batch (one exposed latency), then applied
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (MID == 0 && sizeof(T) == 4) {
-        // complex64: the merged potential step from the per-point hi/lo table
-        // (16 bytes per point, twice the state's 8), every entry of the thread
-        // in flight at once.  The whole byte offset sits in the per-lane
-        // register, so the buffer's range check reads the entries of the
-        // zero padding (n >= Nvalid) as 0, which zeroes those points.
+    if constexpr (MID == 0) {
+        // the merged potential step from the per-point table (16 bytes per
+        // point: a hi/lo pair of complex floats, or one complex double), every
+        // entry of the thread in flight at once.  The whole byte offset sits
+        // in the per-lane register, so the buffer's range check reads the
+        // entries of the zero padding (n >= Nvalid) as 0, which zeroes those
+        // points.
         const rsrc_t rp = make_rsrc((const Tw<T> *)a.ptab + b * a.ptab_bs, a.Nvalid * (int64_t)sizeof(Tw<T>));
+        constexpr uint32_t ps = (uint32_t)(sizeof(Tw<T>) / sizeof(cx<T>));
         Tw<T> pin[J][R];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 pin[j][r] = __builtin_bit_cast(
-                    Tw<T>, __builtin_amdgcn_raw_buffer_load_b128(rp, 2 * (voff[j] + r * rstep), 0, 0));
+                    Tw<T>, __builtin_amdgcn_raw_buffer_load_b128(rp, ps * (voff[j] + r * rstep), 0, 0));
         }
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -696,9 +699,15 @@ int col_go(const ColArgs &a, int batch, void *stream)
 {
     constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW;
     // MID 0: merged potential step from the per-point table; MID 1: kinetic table;
-    // MID 3: potential with a time-dependent second field
-    auto k = a.v ? (a.v2 ? k_colf<T, E, NT, MINW, 3, Rs...> : k_colf<T, E, NT, MINW, 0, Rs...>)
-                 : k_colf<T, E, NT, MINW, 1, Rs...>;
+    // MID 2 (complex128 runs without a table): FP64 phase of v; MID 3:
+    // potential with a time-dependent second field
+    auto k = k_colf<T, E, NT, MINW, 1, Rs...>;
+    if (a.v) {
+        if (a.v2) k = k_colf<T, E, NT, MINW, 3, Rs...>;
+        else if (a.ptab) k = k_colf<T, E, NT, MINW, 0, Rs...>;
+        else if constexpr (sizeof(T) == 8) k = k_colf<T, E, NT, MINW, 2, Rs...>;
+        else return -1;
+    }
     static bool attr = false;
     if (!attr) {
         hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 0, Rs...>,
@@ -707,6 +716,9 @@ int col_go(const ColArgs &a, int batch, void *stream)
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 3, Rs...>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if constexpr (sizeof(T) == 8)
+            hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 2, Rs...>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
     constexpr int C = NT * E / Radix<Rs...>::prod;
