@@ -18,8 +18,9 @@ rank-2 lattice 4096 x 256; and a forward run with checkpoints plus its adjoint
 Sec. 3.3 on a 2^20-point lattice; the time-step convergence protocol of
 Sec. 3.2 on a lattice of the paper's Table 1 (d = 3, n = 2^22); and the
 fourth-order composition and a time-dependent potential (Sec. 5) on the
-benchmark lattice; and the Table 1 lattice d = 6, n = 2^25, whose transform
-takes rows of 8192 points.
+benchmark lattice; the Table 1 lattice d = 6, n = 2^25, whose transform
+takes rows of 8192 points; and the benchmark lattice with 8 states, whose
+working set exceeds the 256 MB Infinity Cache.
 """
 from __future__ import annotations
 
@@ -58,15 +59,15 @@ def pass_bytes(plan_info, N, m, S):
     return col, row
 
 
-def pmc_traffic():
-    """Measured HBM bytes per steady-state column launch (complex64), from the
-    committed counter summary (FETCH_SIZE / WRITE_SIZE scaled by a plain
-    copy's readings); None when absent."""
+def pmc_traffic(kind="column"):
+    """Measured HBM bytes per steady-state launch of one pass kind (complex64),
+    from the committed counter summary (FETCH_SIZE / WRITE_SIZE scaled by a
+    plain copy's readings); None when absent."""
     path = os.path.join(ROOT, "profiles", "k_colf_k_rowf_c64_d6_N1048573_hbm_traffic.md")
     if not os.path.exists(path):
         return None
     for line in open(path):
-        if "column_c64_hbm_bytes_per_launch:" in line:
+        if f"{kind}_c64_hbm_bytes_per_launch:" in line:
             return float(line.split(":")[1])
     return None
 
@@ -367,6 +368,46 @@ def bench_wide(lt, torch, K, W):
     return out
 
 
+def bench_hbm(lt, torch, K, W):
+    """The benchmark lattice with a batch of 8 states (complex128: about 440 MB
+    of states, transform buffers and tables, beyond the 256 MB Infinity
+    Cache), 100 steps: the same steady-state passes as the headline run, with
+    a working set that has to stream from HBM."""
+    import numpy as np
+
+    import workloads as W_
+    inst = W_.config1(steps=1)
+    plan = lt.lattice_plan(inst.Z, inst.n, inst.I)
+    info = plan.info
+    dev = torch.device("cuda:0")
+    N, m, B = inst.N, 100, 8
+    v = torch.tensor(inst.v, dtype=torch.float64, device=dev)
+    out = {"workload": f"benchmark lattice d=6 N={N}, batch of {B} states sharing v, {m} steps per run",
+           "unit": "lattice-point-steps/s"}
+    for name, dtype, S in (("c64", torch.complex64, 8), ("c128", torch.complex128, 16)):
+        prec = lt.LT_C64 if name == "c64" else lt.LT_C128
+        lt.lattice_plan_autotune(plan, prec, reps=5)
+        u = torch.tensor(np.tile(inst.u0, (B, 1)), dtype=dtype, device=dev)
+        work = torch.empty(lt.strang_workspace_size(plan, prec, B, True), dtype=torch.uint8, device=dev)
+        run = lambda: lt.strang_run(plan, v, u, inst.gamma, inst.dt, m, work=work)  # noqa: E731
+        sec = wall(run, K, W)
+        ks = kernel_summary(lt, run, 1)
+        col_b, row_b = pass_bytes(info, N, m, S)
+        L = info["fft_len"]
+        col_steady = B * (2 * L * S) + 16 * N   # the shared table is read once per launch
+        row_steady = B * (2 * L * S) + 16 * L
+        resident = B * (N * S + L * S) + 16 * N + 16 * L
+        out[name] = {"value": B * N * m / sec, "ms_per_run": sec * 1e3, "working_set_MB": resident / 1e6,
+                     "column_us": ks["column"]["avg_us"], "row_us": ks["row"]["avg_us"],
+                     "column_GBs": col_steady / (ks["column"]["avg_us"] * 1e-6) / 1e9,
+                     "row_GBs": row_steady / (ks["row"]["avg_us"] * 1e-6) / 1e9}
+        log(f"hbm {name}: {B * N * m / sec:.3e} pt-steps/s, working set {resident / 1e6:.0f} MB, column "
+            f"{out[name]['column_GBs']:.0f} GB/s, row {out[name]['row_GBs']:.0f} GB/s")
+        del u, work
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_splitting(lt, torch, K, W):
     """Higher-order splitting and time-dependent potentials (the two method
     variants of Sec. 5) on the benchmark lattice (d = 6, N = 1048573):
@@ -452,7 +493,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the companion workloads")
     ap.add_argument("--only", choices=["batched", "rank2", "adjoint", "conservation", "convergence", "splitting",
-                                       "wide"],
+                                       "wide", "hbm"],
                     help="run one companion workload alone (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device (counter calibration for the traffic figure)")
@@ -480,7 +521,7 @@ def main():
 
     extras = {"batched": bench_batched, "rank2": bench_rank2, "adjoint": bench_adjoint,
               "conservation": bench_conservation, "convergence": bench_convergence,
-              "splitting": bench_splitting, "wide": bench_wide}
+              "splitting": bench_splitting, "wide": bench_wide, "hbm": bench_hbm}
     if args.only:
         print(json.dumps({args.only: extras[args.only](lt, torch, args.steps, args.warmup)}), flush=True)
         return
@@ -564,6 +605,16 @@ def main():
                      "avg_launch_us": dom["avg_us"],
                      "bytes_per_launch": dom["bytes_per_launch"],
                      "instrumented_ms_per_run": head["instrumented_ms_per_run"]},
+        "bytes_per_point_step": {
+            name_: {"algorithmic_floor": 4 * S_,
+                    "pass_model": (sum(pass_bytes(info, N, m, S_)[0]) + sum(pass_bytes(info, N, m, S_)[1])) / (N * m),
+                    "counter": (pmc_traffic("column") * (m + 1) + pmc_traffic("row") * m) / (N * m)
+                    if (name_ == "c64" and pmc_traffic("column") and pmc_traffic("row")) else None,
+                    "note": "floor: state read and written once plus the two diagonal tables at S bytes each; "
+                            "pass model: every launch of the two-pass convolution schedule; counter: the "
+                            "steady-state column and row passes' measured HBM bytes (rocprofv3 FETCH_SIZE / "
+                            "WRITE_SIZE, copy-calibrated), complex64"}
+            for name_, S_ in (("c64", 8), ("c128", 16)) if name_ in results},
         "kernels_c64": head["kinds"],
         "kernel_variants": {k: list(r_["kernels"]) for k, r_ in results.items()},
         "accuracy": acc,
