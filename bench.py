@@ -19,8 +19,9 @@ Sec. 3.3 on a 2^20-point lattice; the time-step convergence protocol of
 Sec. 3.2 on a lattice of the paper's Table 1 (d = 3, n = 2^22); and the
 fourth-order composition and a time-dependent potential (Sec. 5) on the
 benchmark lattice; the Table 1 lattice d = 6, n = 2^25, whose transform
-takes rows of 8192 points; and the benchmark lattice with 8 states, whose
-working set exceeds the 256 MB Infinity Cache.
+takes rows of 8192 points; the benchmark lattice with 8 states, whose
+working set exceeds the 256 MB Infinity Cache; and the initial discretization
+error of Sec. 3.4 on Table 1 lattices.
 """
 from __future__ import annotations
 
@@ -408,6 +409,41 @@ def bench_hbm(lt, torch, K, W):
     return out
 
 
+def bench_initial(lt, torch, K, W):
+    """The initial discretization error of Sec. 3.4 for the paper's g1 with
+    gamma = 1 on Table 1 lattices (d = 2, n = 2^18 and 2^20; d = 3, n = 2^22):
+    e_total^2 = ||g||^2 - sum_A |ghat|^2 + sum_A |ghat - ghat_a|^2, the key sums
+    from lattice_projection_error (complex128), the exact coefficients of g1
+    from 1-D Gauss-Legendre integrals."""
+    import numpy as np
+
+    import workloads as W_
+    gamma = 1.0
+    out = {"workload": "paper g1 with gamma = 1 on Table 1 lattices; complex128 lattice DFT and key sums",
+           "unit": "e_total (L2 error of the initial projection)"}
+    for d, n in ((2, 1 << 18), (2, 1 << 20), (3, 1 << 22)):
+        Z, nn = W_.paper_lattice(d, n)
+        plan = lt.lattice_plan(Z, nn)
+        _, _, h = lt.lattice_plan_keys(plan)
+        kmax = int(np.abs(h).max()) + 1
+        tables, norm2 = W_.paper_g1_coefficients(d, gamma, kmax, nodes=max(4096, 4 * kmax))
+        ghat = torch.tensor(W_.coefficients_at(h.astype(np.int64), tables), device="cuda:0")
+        num = W_.point_numerators(Z, nn)
+        u = torch.tensor(W_.paper_g1(num, n, gamma, normalize=False), device="cuda:0")
+        work = torch.empty(lt.lattice_projection_error_workspace_size(plan, lt.LT_C128, 1), dtype=torch.uint8,
+                           device="cuda:0")
+        call = lambda: lt.lattice_projection_error(plan, u, ghat, work=work)  # noqa: E731
+        sec = wall(call, K, W)
+        s0, s1 = call().cpu().numpy()[0]
+        e2 = norm2 - s0 + s1
+        out[f"d{d}_n{n}"] = {"e_total": float(np.sqrt(max(e2, 0.0))), "norm2": norm2, "outside_A": norm2 - s0,
+                             "aliasing_on_A": float(s1), "ms_per_call": sec * 1e3}
+        log(f"initial d={d} n=2^{n.bit_length() - 1}: e_total {np.sqrt(max(e2, 0.0)):.3e} "
+            f"(outside A {norm2 - s0:.2e}, on A {s1:.2e}), {sec * 1e3:.2f} ms per call")
+        del u, ghat, work
+    return out
+
+
 def bench_splitting(lt, torch, K, W):
     """Higher-order splitting and time-dependent potentials (the two method
     variants of Sec. 5) on the benchmark lattice (d = 6, N = 1048573):
@@ -493,7 +529,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the companion workloads")
     ap.add_argument("--only", choices=["batched", "rank2", "adjoint", "conservation", "convergence", "splitting",
-                                       "wide", "hbm"],
+                                       "wide", "hbm", "initial"],
                     help="run one companion workload alone (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device (counter calibration for the traffic figure)")
@@ -521,7 +557,8 @@ def main():
 
     extras = {"batched": bench_batched, "rank2": bench_rank2, "adjoint": bench_adjoint,
               "conservation": bench_conservation, "convergence": bench_convergence,
-              "splitting": bench_splitting, "wide": bench_wide, "hbm": bench_hbm}
+              "splitting": bench_splitting, "wide": bench_wide, "hbm": bench_hbm,
+              "initial": bench_initial}
     if args.only:
         print(json.dumps({args.only: extras[args.only](lt, torch, args.steps, args.warmup)}), flush=True)
         return

@@ -198,6 +198,28 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
                              size_t work_bytes, void *stream);
 
 /*
+ * lattice_projection_error -- the two key sums of the initial (spatial)
+ * discretization error of Sec. 3.4: for a function g with Fourier
+ * coefficients ghat(h) and its lattice approximation g_a (coefficients
+ * ghat_a(h_xi) = (1/N) sum_k g(p_k) exp(-2 pi i h_xi . p_k) on the index set
+ * A = {h_xi}: e_total^2 = ||g||^2 - sum_A |ghat|^2 + sum_A |ghat - ghat_a|^2
+ * (the first two terms are the coefficients outside A).  The library forms
+ * ghat_a by the lattice DFT of the point values and returns both sums.
+ *   u      device, batch x N complex of `prec`: g at the lattice points.
+ *   ghat   device, batch x N complex double (interleaved), key order: the
+ *          coefficient of g at the plan's representative h_xi of key xi
+ *          (lattice_plan_keys h_of_key).
+ *   out    device, batch x 2 doubles: (sum_A |ghat|^2, sum_A |ghat - ghat_a|^2).
+ *   work   at least lattice_projection_error_workspace_size bytes, or NULL.
+ * The transform runs in the precision of u; the sums accumulate in double.
+ * Errors: LT_E_ARG (NULL buffers, precision, batch < 0).
+ */
+lt_status lattice_projection_error_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, size_t *bytes);
+lt_status lattice_projection_error(const lt_plan *p, lt_prec prec, int32_t batch, const void *u,
+                                   const double *ghat, double *out, void *work, size_t work_bytes,
+                                   void *stream);
+
+/*
  * splitting_run -- m steps of a symmetric composition of the Strang step of
  * eq. (StrangTDSE): order 2 is the Strang step itself (as strang_run, in the
  * two-pass layout); order 4 is the triple jump S(w1 dt) S(w0 dt) S(w1 dt) with

@@ -12,6 +12,7 @@ Paper references (arXiv:1808.06357):
   * Strang step: Sec. 2.4, eq. (StrangTDSE); Algorithm 1;
   * rank-r orderings: Sec. 2.5;
   * norm / energy: Sec. 3.3;
+  * initial discretization error: Sec. 3.4;
   * fourth-order composition of Strang steps and time-dependent potentials:
     the two continuations named in Sec. 5 (the composition taken as Yoshida's
     symmetric triple jump, time advanced with the kinetic flow).
@@ -256,6 +257,23 @@ def composed_run(n, s_of_key, v, u0, gamma, dt, steps, order=4, v1=None, f=None,
             tau += h
             u = np.exp(-1j * h * (v + f(tau) * v1) / (2.0 * gamma)) * u
     return u
+
+
+def projection_error(n, u, ghat, method="auto"):
+    """The two key sums of the initial discretization error (Sec. 3.4):
+    (sum_A |ghat|^2, sum_A |ghat - ghat_a|^2) with ghat_a(h_xi) = (1/N) times
+    the lattice DFT of the point values u at key xi (eq. (Fn) / (Fnx) without
+    the 1/sqrt(N)), for u and ghat of shape (N,) or (batch, N) in key order.
+    e_total^2 = ||g||^2 - first + second."""
+    n = np.ascontiguousarray(np.atleast_1d(np.asarray(n, dtype=np.int64)))
+    N = int(np.prod(n))
+    u = np.asarray(u, dtype=np.complex128).reshape(-1, N)
+    g = np.asarray(ghat, dtype=np.complex128).reshape(-1, N)
+    out = np.empty((u.shape[0], 2))
+    for b in range(u.shape[0]):
+        ga = fftn(u[b], n, -1, method) / N
+        out[b] = (np.sum(np.abs(g[b]) ** 2), np.sum(np.abs(g[b] - ga) ** 2))
+    return out
 
 
 def diagnostics(n, s_of_key, v, u, gamma, method="auto"):

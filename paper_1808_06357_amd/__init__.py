@@ -2,11 +2,13 @@
 
 Python face of the HIP library (include/lattice_tdse.h): plans, runs,
 adjoints, batched runs, fourth-order compositions, time-dependent
-potentials and norm / energy diagnostics, plus a torch.autograd.Function.
+potentials, norm / energy diagnostics and the initial discretization
+error, plus a torch.autograd.Function.
 All arithmetic of a run happens in the library's HIP kernels.
 """
 from ._capi import (LT_C64, LT_C128, LT_KIND_COLUMN, LT_KIND_RESIDENT, LT_KIND_ROW, LatticeError,
                     Plan, lattice_diagnostics, lattice_diagnostics_workspace_size, lattice_plan,
+                    lattice_projection_error, lattice_projection_error_workspace_size,
                     lattice_plan_autotune, lattice_plan_get_kernels, lattice_plan_info,
                     lattice_plan_keys, lattice_plan_points, lattice_plan_set_kernels,
                     lt_timing_enable, lt_timing_summary, num_checkpoints, splitting_run,
@@ -22,4 +24,5 @@ __all__ = ["LT_C64", "LT_C128", "LatticeError", "Plan", "lattice_plan", "lattice
            "lattice_strang", "lt_timing_enable", "lt_timing_summary", "LT_KIND_COLUMN",
            "LT_KIND_ROW", "LT_KIND_RESIDENT", "lattice_plan_autotune", "lattice_plan_set_kernels",
            "lattice_plan_get_kernels", "lattice_diagnostics", "lattice_diagnostics_workspace_size",
-           "splitting_run", "splitting_workspace_size", "splitting_times"]
+           "splitting_run", "splitting_workspace_size", "splitting_times", "lattice_projection_error",
+           "lattice_projection_error_workspace_size"]

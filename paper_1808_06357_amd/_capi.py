@@ -67,6 +67,8 @@ _SIGS = {
     "strang_adjoint": [_P, _i32, _i32, _P, _i64, _P, _P, _f64, _f64, _i64, _P, _i64, _P, _P, _P, _sz, _P],
     "strang_batched_workspace_size": [_i32, _P, _i32, ctypes.POINTER(_sz)],
     "strang_run_batched": [_i32, _P, _i32, _P, _P, _P, _P, _P, _P, _sz, _P],
+    "lattice_projection_error_workspace_size": [_P, _i32, _i32, ctypes.POINTER(_sz)],
+    "lattice_projection_error": [_P, _i32, _i32, _P, _P, _P, _P, _sz, _P],
     "splitting_workspace_size": [_P, _i32, _i32, _i32, _i32, ctypes.POINTER(_sz)],
     "splitting_run": [_P, _i32, _i32, _P, _P, _i64, _P, _P, _f64, _f64, _i64, _i32, _P, _sz, _P],
     "splitting_times": [_i32, _i64, _f64, _f64, _P],
@@ -305,6 +307,35 @@ def splitting_workspace_size(plan: Plan, prec: int, batch: int, shared_v: bool, 
     _check(lib.splitting_workspace_size(plan.handle, prec, batch, int(bool(shared_v)), order, ctypes.byref(n)),
            "splitting_workspace_size")
     return n.value
+
+
+def lattice_projection_error_workspace_size(plan: Plan, prec: int, batch: int) -> int:
+    n = _sz()
+    _check(lib.lattice_projection_error_workspace_size(plan.handle, prec, batch, ctypes.byref(n)),
+           "lattice_projection_error_workspace_size")
+    return n.value
+
+
+def lattice_projection_error(plan: Plan, u, ghat, out=None, work=None, stream=None):
+    """(sum_A |ghat|^2, sum_A |ghat - ghat_a|^2) per state (device float64,
+    (batch, 2)) for point values u (device, (N,) or (batch, N)) and the exact
+    coefficients ghat (device complex128, same shape, key order)."""
+    import torch
+    N = plan.N
+    prec = _prec_of(u)
+    batch = u.numel() // N
+    _check_dev(u, "u", numel=batch * N)
+    _check_dev(ghat, "ghat", torch.complex128, batch * N)
+    if out is None:
+        out = torch.empty((batch, 2), dtype=torch.float64, device=u.device)
+    _check_dev(out, "out", torch.float64, 2 * batch)
+    wb = 0
+    if work is not None:
+        _check_dev(work, "work")
+        wb = work.numel() * work.element_size()
+    _check(lib.lattice_projection_error(plan.handle, prec, batch, _dev_ptr(u), _dev_ptr(ghat), _dev_ptr(out),
+                                        _dev_ptr(work), wb, _stream(stream)), "lattice_projection_error")
+    return out
 
 
 def splitting_times(order: int, steps: int, t0: float, dt: float):

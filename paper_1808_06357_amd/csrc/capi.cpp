@@ -1261,6 +1261,66 @@ lt_status lattice_diagnostics(const lt_plan *cp, lt_prec prec, int32_t batch, co
     return LT_OK;
 }
 
+// ---------------------------------------------------------------- projection error
+// workspace: the transform buffer, the chirp-z spectrum in key order, partials
+lt_status lattice_projection_error_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, size_t *bytes)
+{
+    return lattice_diagnostics_workspace_size(p, prec, batch, bytes);
+}
+
+lt_status lattice_projection_error(const lt_plan *cp, lt_prec prec, int32_t batch, const void *u,
+                                   const double *ghat, double *out, void *work, size_t work_bytes, void *stream)
+{
+    lt_status st = check_common(cp, prec, batch, 1.0, 0.0, 0);
+    if (st) return st;
+    lt_plan &p = *const_cast<lt_plan *>(cp);
+    if (batch == 0) return LT_OK;
+    if (!u || !ghat || !out) return fail(LT_E_ARG, "u, ghat and out must not be NULL");
+    if ((st = ensure_device_tables(p, 1, prec, stream))) return st;
+    const Sched &s = p.sched[1][prec];
+    const DevTables &D = p.dev[1][prec];
+    hipStream_t hs = (hipStream_t)stream;
+    const int64_t N = p.N;
+    const DiagWork L = diag_layout(p, s, prec, batch);
+    Scratch sc;
+    if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
+    void *W = at(sc.ptr, L.w);
+    double *pp = (double *)at(sc.ptr, L.pp);
+    // U = F u (the lattice DFT of the point values), as for the diagnostics
+    ColArgs c = col_base(s, D, N);
+    c.buf = W;
+    c.buf_bs = s.L;
+    c.in = u;
+    c.in_bs = N;
+    c.post_fwd = 1;
+    c.chirp = s.bluestein ? 1 : 0;
+    HIP_TRY(launch_col(prec, s, c, batch, hs), "projection transform");
+    RowArgs r = row_base(s, D);
+    r.buf = W;
+    r.buf_bs = s.L;
+    if (s.bluestein) {
+        r.bhat = D.bhat;
+        HIP_TRY(launch_row(prec, s, r, batch, hs), "projection transform");
+        void *nat = at(sc.ptr, L.nat);
+        ColArgs e = col_base(s, D, N);
+        e.buf = W;
+        e.buf_bs = s.L;
+        e.pre_inv = 1;
+        e.out = nat;
+        e.out_bs = N;
+        e.chirp = 1;
+        HIP_TRY(launch_col(prec, s, e, batch, hs), "projection transform");  // unitary F u, key order
+        HIP_TRY(launch_proj_sums(prec, nat, N, N, batch, 1.0 / std::sqrt((double)N), 0, s.L1, s.L2, ghat, N, pp,
+                                 out, hs), "projection sums");
+    } else {
+        r.fft_only = 1;  // unnormalised F u at the row-pass positions
+        HIP_TRY(launch_row(prec, s, r, batch, hs), "projection transform");
+        HIP_TRY(launch_proj_sums(prec, W, s.L, N, batch, 1.0 / (double)N, transposed_layout(s) ? 1 : 0, s.L1, s.L2,
+                                 ghat, N, pp, out, hs), "projection sums");
+    }
+    return LT_OK;
+}
+
 lt_status splitting_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, int32_t shared_v,
                                    int32_t order, size_t *bytes)
 {

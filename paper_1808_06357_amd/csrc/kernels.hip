@@ -616,6 +616,62 @@ __global__ void k_diag_finish(const double *pp, const double *ps, int nblk, int 
     out[2 * b + 1] = (2.0 * pi * pi * gamma * ke * kscale + pe / gamma) / (double)N;
 }
 
+// Projection sums of one batch item: sum over keys of |ghat|^2 and of
+// |ghat - scale x|^2, where x is the lattice DFT of the point values at
+// position pos and ghat the caller's coefficient of the key at pos (key =
+// pos, or k1 + L1 k2 for the transposed layout pos = k1 L2 + k2)
+template <typename T>
+__global__ void __launch_bounds__(256) k_proj_sums(const cx<T> *x, int64_t x_bs, int64_t count, double scale,
+                                                   int transposed, int L1, int L2, const double *ghat,
+                                                   int64_t g_bs, double *partial)
+{
+    __shared__ double red[2][256];
+    const int64_t b = blockIdx.y;
+    const cx<T> *xb = x + b * x_bs;
+    const double *gb = ghat + 2 * b * g_bs;
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t key = i;
+        if (transposed) {
+            const int64_t k1 = i / L2;
+            key = k1 + (int64_t)L1 * (i - k1 * L2);
+        }
+        const double gr = gb[2 * key], gi = gb[2 * key + 1];
+        const cx<T> z = xb[i];
+        const double dr = gr - scale * (double)z.x, di = gi - scale * (double)z.y;
+        s0 += gr * gr + gi * gi;
+        s1 += dr * dr + di * di;
+    }
+    red[0][threadIdx.x] = s0;
+    red[1][threadIdx.x] = s1;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double *pb = partial + (b * gridDim.x + blockIdx.x) * 2;
+        pb[0] = red[0][0];
+        pb[1] = red[1][0];
+    }
+}
+
+__global__ void k_proj_finish(const double *partial, int nblk, int batch, double *out)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = 0; i < nblk; ++i) {
+        s0 += partial[(b * nblk + i) * 2];
+        s1 += partial[(b * nblk + i) * 2 + 1];
+    }
+    out[2 * b] = s0;
+    out[2 * b + 1] = s1;
+}
+
 __global__ void k_reduce_batch(double *dst, const double *src, int64_t N, int batch)
 {
     for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N;
@@ -843,6 +899,23 @@ int launch_diag_finish(const double *pp, const double *ps, int batch, int64_t N,
 {
     hipLaunchKernelGGL(k_diag_finish, dim3((batch + 127) / 128), dim3(128), 0, (hipStream_t)stream, pp, ps,
                        kSumBlocks, batch, N, gamma, kscale, out);
+    return (int)hipGetLastError();
+}
+
+int launch_proj_sums(int prec, const void *x, int64_t x_bs, int64_t count, int batch, double scale, int transposed,
+                     int L1, int L2, const double *ghat, int64_t g_bs, double *partial, double *out, void *stream)
+{
+    dim3 grid(kSumBlocks, batch);
+    if (prec == LT_C128)
+        hipLaunchKernelGGL(k_proj_sums<double>, grid, dim3(256), 0, (hipStream_t)stream, (const cx<double> *)x,
+                           x_bs, count, scale, transposed, L1, L2, ghat, g_bs, partial);
+    else
+        hipLaunchKernelGGL(k_proj_sums<float>, grid, dim3(256), 0, (hipStream_t)stream, (const cx<float> *)x,
+                           x_bs, count, scale, transposed, L1, L2, ghat, g_bs, partial);
+    const int e = (int)hipGetLastError();
+    if (e) return e;
+    hipLaunchKernelGGL(k_proj_finish, dim3((batch + 127) / 128), dim3(128), 0, (hipStream_t)stream, partial,
+                       kSumBlocks, batch, out);
     return (int)hipGetLastError();
 }
 

@@ -169,6 +169,8 @@ int launch_ktab(double *dst, int64_t count, double kin, double scale, void *stre
 int diag_partials();  // blocks per state of launch_sums
 int launch_sums(int prec, const void *x, int64_t x_bs, int64_t count, int batch, const int32_t *w,
                 const double *vw, int64_t vw_bs, double *partial, void *stream);
+int launch_proj_sums(int prec, const void *x, int64_t x_bs, int64_t count, int batch, double scale, int transposed,
+                     int L1, int L2, const double *ghat, int64_t g_bs, double *partial, double *out, void *stream);
 int launch_diag_finish(const double *pp, const double *ps, int batch, int64_t N, double gamma, double kscale,
                        double *out, void *stream);
 int launch_conv_input(void *dst, const int32_t *s, const double *ktab, int64_t N, void *stream);

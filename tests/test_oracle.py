@@ -361,6 +361,64 @@ def test_time_dependent_orders_against_ode_solution():
         assert np.all((orders > lo) & (orders < hi)), (order, orders)
 
 
+def test_projection_error_trigonometric_polynomial_and_aliased_mode():
+    """Sec. 3.4: a trigonometric polynomial on the index set is reproduced
+    exactly (both error terms vanish); a single mode outside it aliases onto
+    its key, giving e_total^2 = 1 (its own coefficient) + 1 (the aliased one)."""
+    Z, n = np.array([[1, 34]]), np.array([55])
+    h, s, _ = O.index_set(Z, n)
+    num = W.point_numerators(Z, n)
+    keys = O.keys(Z, n, h)
+    g = np.random.default_rng(5)
+    pick = g.choice(55, 6, replace=False)
+    c = g.standard_normal(6) + 1j * g.standard_normal(6)
+    u = np.zeros(55, dtype=complex)
+    ghat = np.zeros(55, dtype=complex)
+    for i, ck in zip(pick, c):
+        u += ck * np.exp(2j * np.pi * ((num @ h[i]) % 55) / 55)
+        ghat[keys[i]] = ck
+    s0, s1 = O.projection_error(n, u, ghat)[0]
+    assert abs(s0 - np.sum(np.abs(c) ** 2)) < 1e-12 and s1 < 1e-24
+    e2 = np.sum(np.abs(c) ** 2) - s0 + s1
+    assert abs(e2) < 1e-12
+    # h_out = h + (55, 0) has the key of h but is not in the minimal set
+    h_in = h[pick[0]]
+    h_out = h_in + np.array([55, 0])
+    assert O.keys(Z, n, h_out[None])[0] == keys[pick[0]]
+    u = np.exp(2j * np.pi * (num @ h_out) / 55.0)
+    s0, s1 = O.projection_error(n, u, np.zeros(55))[0]
+    assert s0 == 0.0 and abs(s1 - 1.0) < 1e-13
+    assert abs((1.0 - s0 + s1) - 2.0) < 1e-13
+
+
+def test_projection_error_gaussian_against_direct_integral():
+    """e_total^2 of the paper's g1 on the Fig. 1 lattice, from the key sums,
+    against the definition int |g - g_a|^2 dx by a tensor Gauss-Legendre rule
+    (g_a the trigonometric polynomial on the index set with the lattice
+    coefficients)."""
+    Z, n = np.array([[1, 34]]), np.array([55])
+    h, s, _ = O.index_set(Z, n)
+    keys = O.keys(Z, n, h)
+    hk = np.empty_like(h)
+    hk[keys] = h
+    num = W.point_numerators(Z, n)
+    gamma = 1.0
+    tables, norm2 = W.paper_g1_coefficients(2, gamma, 64)
+    ghat = W.coefficients_at(hk, tables)
+    u = W.paper_g1(num, 55, gamma, normalize=False)
+    s0, s1 = O.projection_error(n, u, ghat)[0]
+    e2 = norm2 - s0 + s1
+    ga = O.fftn(u, n) / 55.0                    # lattice coefficients in key order
+    t, w = np.polynomial.legendre.leggauss(300)
+    x, w = 0.5 * (t + 1.0), 0.5 * w
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    gx = np.exp(-((2 * np.pi * X1 - 1.5 * np.pi) ** 2 + (2 * np.pi * X2 - np.pi) ** 2) / gamma)
+    gax = sum(ga[kk] * np.exp(2j * np.pi * (hk[kk, 0] * X1 + hk[kk, 1] * X2)) for kk in range(55))
+    direct = float(np.sum(np.outer(w, w) * np.abs(gx - gax) ** 2))
+    assert direct > 1e-6
+    assert abs(e2 - direct) < 1e-12 * max(1.0, norm2), (e2, direct)
+
+
 def test_config0_second_order_paper_protocol():
     """Sec. 3.2 protocol: reference at dt = 1e-4, errors at larger dt, T fixed,
     observed order 2 (here T = 0.2 so the reference stays cheap)."""

@@ -276,13 +276,46 @@ def seeded_packet(num: np.ndarray, N: int, g: np.random.Generator, sigma: float 
     return gaussian_packet(num, N, c, k0, sigma)
 
 
-def paper_g1(num: np.ndarray, N: int, gamma: float) -> np.ndarray:
-    """The paper's Gaussian initial condition g1 (Sec. 3.2), unit lattice-rule norm."""
+def paper_g1(num: np.ndarray, N: int, gamma: float, normalize: bool = True) -> np.ndarray:
+    """The paper's Gaussian initial condition g1 (Sec. 3.2) at the lattice
+    points, scaled to unit lattice-rule norm unless normalize is False."""
     x = num.astype(np.float64) / N
     e = (2 * np.pi * x[:, 0] - 1.5 * np.pi) ** 2 + np.sum((2 * np.pi * x[:, 1:] - np.pi) ** 2, axis=1)
     u = np.exp(-e / gamma).astype(np.complex128)
-    u /= np.sqrt(np.mean(np.abs(u) ** 2))
+    if normalize:
+        u /= np.sqrt(np.mean(np.abs(u) ** 2))
     return u
+
+
+def paper_g1_coefficients(d: int, gamma: float, kmax: int, nodes: int = 4096):
+    """Fourier coefficients of the (unscaled) g1 on [0,1)^d: g1 is a product of
+    1-D factors exp(-(2 pi x - c)^2 / gamma) (c = 3 pi / 2 in the first
+    coordinate, pi in the others), so ghat(h) = prod_j I_j(h_j) with
+    I_j(k) = int_0^1 exp(-(2 pi x - c_j)^2 / gamma) exp(-2 pi i k x) dx.
+    Returns (tables (d, 2 kmax + 1) complex, I_j(k) at column k + kmax; the
+    squared L2 norm of g1), both from a Gauss-Legendre rule with `nodes`
+    points on [0, 1] (exact to rounding for |k| well below nodes / 2)."""
+    t, w = np.polynomial.legendre.leggauss(nodes)
+    x, w = 0.5 * (t + 1.0), 0.5 * w
+    k = np.arange(-kmax, kmax + 1)
+    tables = np.empty((d, 2 * kmax + 1), dtype=np.complex128)
+    norm2 = 1.0
+    for j in range(d):
+        c = 1.5 * np.pi if j == 0 else np.pi
+        f = np.exp(-(2 * np.pi * x - c) ** 2 / gamma)
+        tables[j] = np.exp(-2j * np.pi * np.outer(k, x)) @ (w * f)
+        norm2 *= float(np.sum(w * f * f))
+    return tables, norm2
+
+
+def coefficients_at(h: np.ndarray, tables: np.ndarray) -> np.ndarray:
+    """prod_j tables[j, h_j + kmax] for integer vectors h (rows), the Fourier
+    coefficient of a product function at frequencies h."""
+    kmax = (tables.shape[1] - 1) // 2
+    out = np.ones(h.shape[0], dtype=np.complex128)
+    for j in range(h.shape[1]):
+        out *= tables[j, h[:, j] + kmax]
+    return out
 
 
 # ---------------------------------------------------------------- configurations
