@@ -152,6 +152,7 @@ RowArgs row_base(const Sched &s, const DevTables &D)
     a.nblk = (s.L1 + s.rows - 1) / s.rows;
     a.twb = D.twb;
     a.rad = s.rb;
+    a.ktab_n = D.ktab_n;
     return a;
 }
 
@@ -557,6 +558,7 @@ lt_status ensure_device_tables(lt_plan &p, int which, int prec, void *stream)
     std::lock_guard<std::mutex> lock(p.mu);
     DevTables &D = p.dev[which][prec];
     if (D.built) return LT_OK;
+    D.ktab_n = p.max_s + 1;
     const Sched &s = p.sched[which][prec];
     if (!s.ok) return fail(LT_E_UNSUPPORTED, "no GPU schedule for this lattice in this precision");
     lt_status r = bind_device(p);

@@ -597,10 +597,8 @@ __device__ __forceinline__ void rowf_body(const RowArgs &a, int blk, int64_t b, 
         }
     } else {
         // kinetic table indexed by the squared norm (a small table, cached):
-        // every entry of the thread in flight at once.  The indices come
-        // from the plan's squared-norm table and stay below the table's
-        // length, so the resource carries no tighter bound.
-        const rsrc_t rk = make_rsrc(a.ktab, (int64_t)1 << 30);
+        // every entry of the thread in flight at once
+        const rsrc_t rk = make_rsrc(a.ktab, a.ktab_n * 16);
         constexpr int KC = kPreS ? E : 8;  // entries in flight (fewer where registers are short)
 #pragma unroll
         for (int e0 = 0; e0 < E; e0 += KC) {

@@ -50,6 +50,7 @@ struct DevTables {
     int32_t *s_key = nullptr;// ||h_chi||^2 per key, natural order
     int32_t *s_row = nullptr;// ||h_chi||^2 at the row-pass positions (two-pass, no chirp-z)
     double *bhat = nullptr;  // chirp-z kernel spectrum / (L sqrt N), complex double, schedule layout
+    int64_t ktab_n = 0;      // entries of a run's kinetic table (max_s + 1)
 };
 
 // ---------------------------------------------------------------- kernel arguments
@@ -100,6 +101,7 @@ struct RowArgs {
     int L1, L2, rows, nblk;
     const double *bhat; int conj_tab;
     const int32_t *s; const double *ktab;
+    int64_t ktab_n;                   // entries of ktab (its squared-norm range)
     int fft_only;
     const void *twb;                  // Tw<T> table of W_{L2}
     Radices rad;
