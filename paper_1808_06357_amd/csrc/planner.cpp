@@ -291,7 +291,19 @@ Sched make_schedule(const lt_plan &p, int prec, bool force_two_pass)
         s.ok = true;
         return s;
     }
-    if (is_smooth7(p.N)) {
+    // Smooth N: the DFT of length N itself -- unless N is not a power of two
+    // and needs two passes: its factors 3, 5, 7 only fit the general passes
+    // (runtime radices), so it takes the chirp-z convolution of power-of-two
+    // length >= 2N - 1 like a prime, whose passes are register-staged (about
+    // 3x cheaper per element, and with more workgroups), while that length
+    // has a two-pass split.
+    bool direct = is_smooth7(p.N);
+    if (direct && (p.N & (p.N - 1)) != 0 && p.N > tile) {
+        int64_t q = 1;
+        while (q < 2 * p.N - 1) q <<= 1;
+        if (q <= tile * kWideRow) direct = false;
+    }
+    if (direct) {
         s.L = p.N;
     } else {
         // chirp-z length: any L >= 2N - 1 works.  One workgroup's tile: the
