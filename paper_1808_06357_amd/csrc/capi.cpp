@@ -1423,8 +1423,8 @@ lt_status lattice_plan_set_kernels(lt_plan *p, lt_prec prec, int32_t col_variant
 {
     if (!p) return fail(LT_E_ARG, "plan is NULL");
     if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
-    if (col_variant < 0 || col_variant > 2 || row_variant < 0 || row_variant > 2)
-        return fail(LT_E_ARG, "kernel variants are 0, 1 or 2");
+    if (col_variant < 0 || col_variant > 3 || row_variant < 0 || row_variant > 3)
+        return fail(LT_E_ARG, "kernel variants are 0, 1, 2 or 3");
     std::lock_guard<std::mutex> lock(p->mu);
     for (int w = 0; w < 2; ++w) {
         if (p->sched[w][prec].passes != 2) continue;
@@ -1495,7 +1495,7 @@ lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *st
     };
     int best_c = 0, best_r = 0;
     float tc = 1e30f, tr = 1e30f;
-    for (int var = 0; var <= 2 && !st; ++var) {
+    for (int var = 0; var <= 3 && !st; ++var) {
         float ms = 0.f;
         if (var == 0 || fast_col_fits(prec, var, s.L1, s.L2, s.cols)) {
             st = time_it(true, var, ms);

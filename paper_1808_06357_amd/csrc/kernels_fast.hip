@@ -658,6 +658,10 @@ template <>
 struct Geo<3> {  // rows of kWideRow points: one row per workgroup
     static constexpr int NT = 512, E = 16, MINW = 1;
 };
+template <>
+struct Geo<4> {  // small tiles (one wave, 1024 elements): more workgroups for small transforms
+    static constexpr int NT = 64, E = 16, MINW = 2;
+};
 
 template <typename K, typename A>
 int timed(int kind, K kernel, dim3 grid, dim3 block, size_t lds, void *stream, const A &args)
@@ -759,6 +763,15 @@ int go(int L, const A &a, int batch, void *stream)
     if constexpr (V == 3) {  // 16 elements per thread, 512 threads: rows of 8192
         if (L == 8192 && !COL) return go1<T, V, COL, 16, 4, 8, 16>(a, batch, stream);
         return -1;
+    } else if constexpr (V == 4) {  // 16 elements per thread, 64 threads: lengths up to 1024
+        switch (L) {
+        case 64: return go1<T, V, COL, 8, 8>(a, batch, stream);
+        case 128: return go1<T, V, COL, 8, 2, 8>(a, batch, stream);
+        case 256: return go1<T, V, COL, 16, 16>(a, batch, stream);
+        case 512: return go1<T, V, COL, 8, 8, 8>(a, batch, stream);
+        case 1024: return go1<T, V, COL, 16, 4, 16>(a, batch, stream);
+        default: return -1;
+        }
     } else if constexpr (V == 1) {  // 16 elements per thread
         switch (L) {
         case 64: return go1<T, V, COL, 8, 8>(a, batch, stream);
@@ -839,15 +852,21 @@ int multi_go(int L, const BatchDesc *d, const int *idx, const int *start, int nm
 constexpr int kTile = 4096;
 }  // namespace
 
+constexpr int kSmallTile = Geo<4>::NT * Geo<4>::E;
+
+// variants 1 and 2 take the plan's tile (C columns / rows of a 4096-element
+// tile); variant 3 uses its own 1024-element tiles
 bool fast_col_fits(int prec, int variant, int L1, int L2, int C)
 {
     (void)prec;
+    if (variant == 3) return fast_len(L1) && L1 <= kSmallTile && L2 % (kSmallTile / L1) == 0;
     return (variant == 1 || variant == 2) && fast_len(L1) && C == kTile / L1 && L2 % C == 0;
 }
 
 bool fast_row_fits(int prec, int variant, int L1, int L2, int rows)
 {
     (void)prec;
+    if (variant == 3) return fast_len(L2) && L2 <= kSmallTile && L1 % (kSmallTile / L2) == 0;
     return (variant == 1 || variant == 2) && fast_len(L2) && rows == kTile / L2 && L1 % rows == 0;
 }
 
@@ -860,8 +879,12 @@ int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *st
                         (prec == LT_C128 || !a.v || a.ptab || a.v2);
     if (!steady || !fast_col_fits(prec, variant, a.L1, a.L2, a.C)) return -1;
     if (prec == LT_C128)
-        return variant == 1 ? go<double, 1, true>(a.L1, a, batch, stream) : go<double, 2, true>(a.L1, a, batch, stream);
-    return variant == 1 ? go<float, 1, true>(a.L1, a, batch, stream) : go<float, 2, true>(a.L1, a, batch, stream);
+        return variant == 1   ? go<double, 1, true>(a.L1, a, batch, stream)
+               : variant == 2 ? go<double, 2, true>(a.L1, a, batch, stream)
+                              : go<double, 4, true>(a.L1, a, batch, stream);
+    return variant == 1   ? go<float, 1, true>(a.L1, a, batch, stream)
+           : variant == 2 ? go<float, 2, true>(a.L1, a, batch, stream)
+                          : go<float, 4, true>(a.L1, a, batch, stream);
 }
 
 int launch_row_fast(int prec, int variant, const RowArgs &a, int batch, void *stream)
@@ -873,8 +896,12 @@ int launch_row_fast(int prec, int variant, const RowArgs &a, int batch, void *st
     }
     if (!fast_row_fits(prec, variant, a.L1, a.L2, a.rows)) return -1;
     if (prec == LT_C128)
-        return variant == 1 ? go<double, 1, false>(a.L2, a, batch, stream) : go<double, 2, false>(a.L2, a, batch, stream);
-    return variant == 1 ? go<float, 1, false>(a.L2, a, batch, stream) : go<float, 2, false>(a.L2, a, batch, stream);
+        return variant == 1   ? go<double, 1, false>(a.L2, a, batch, stream)
+               : variant == 2 ? go<double, 2, false>(a.L2, a, batch, stream)
+                              : go<double, 4, false>(a.L2, a, batch, stream);
+    return variant == 1   ? go<float, 1, false>(a.L2, a, batch, stream)
+           : variant == 2 ? go<float, 2, false>(a.L2, a, batch, stream)
+                          : go<float, 4, false>(a.L2, a, batch, stream);
 }
 
 template <typename T, int... Rs>

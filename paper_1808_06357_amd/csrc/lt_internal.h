@@ -35,7 +35,8 @@ struct Sched {
     int cols = 1;            // columns per column-pass workgroup
     int rows = 1;            // rows per row-pass workgroup
     int ept = 16;            // max complex elements per thread (register budget)
-    int col_var = 1;         // column-pass kernel: 0 general, 1 fast 256x16, 2 fast 512x8
+    int col_var = 1;         // column-pass kernel: 0 general, 1 fast 256x16, 2 fast 512x8,
+                             // 3 fast 64x16 (1024-element tiles)
     int row_var = 1;         // row-pass kernel (same codes)
     Radices ra{}, rb{};      // radices of L1 (or L) and of L2
 };

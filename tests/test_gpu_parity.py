@@ -161,8 +161,8 @@ def test_every_kernel_variant(lt, N, d):
     plan = lt.lattice_plan(Z, n)
     _, s, _ = O.index_set(Z, n)
     ref = O.strang_run(n, s, v, u0, gamma, dt, steps)
-    for cv in (0, 1, 2):
-        for rv in (0, 1, 2):
+    for cv in (0, 1, 2, 3):
+        for rv in (0, 1, 2, 3):
             for prec in ("c128", "c64"):
                 p = lt.LT_C128 if prec == "c128" else lt.LT_C64
                 lt.lattice_plan_set_kernels(plan, p, cv, rv)
@@ -171,7 +171,7 @@ def test_every_kernel_variant(lt, N, d):
                 assert e < TOL[prec], (cv, rv, prec, e)
     for prec in (lt.LT_C64, lt.LT_C128):
         chosen = lt.lattice_plan_autotune(plan, prec, reps=3)
-        assert all(x in (0, 1, 2) for x in chosen)
+        assert all(x in (0, 1, 2, 3) for x in chosen)
 
 
 @pytest.mark.parametrize("N,d", [(65521, 4), (8191, 3), (262139, 3)])

@@ -119,7 +119,7 @@ def test_schedules():
     C.lattice_plan_set_kernels(c1, C.LT_C64, 2, 0)
     assert C.lattice_plan_get_kernels(c1, C.LT_C64) == (2, 0)
     with pytest.raises(C.LatticeError):
-        C.lattice_plan_set_kernels(c1, C.LT_C64, 3, 0)
+        C.lattice_plan_set_kernels(c1, C.LT_C64, 4, 0)
 
 
 def test_plan_poor_lattice_fails_within_budget():
