@@ -291,11 +291,14 @@ lt_status lattice_diagnostics(const lt_plan *p, lt_prec prec, int32_t batch, con
  *   0 = general LDS Stockham kernel (any 7-smooth length),
  *   1 = register-staged kernel, 256 threads x 16 elements (radix 16 / 8),
  *   2 = register-staged kernel, 512 threads x 8 elements (radix 8 / 4),
- *   3 = register-staged kernel, 64 threads x 16 elements: 1024-element
- *       tiles, four times the workgroups of 1 and 2 (small transforms).
+ *   3 = register-staged kernel with its own tiles: 64 threads x 16
+ *       elements (1024-element tiles, four times the workgroups of 1 and 2,
+ *       for small transforms), or, for 4096-point columns, 512 threads x 16
+ *       elements holding two columns per tile.
  * Variants 1 and 2 exist for the power-of-two lengths 64 ... 4096, variant
- * 3 for 64 ... 1024; elsewhere the general kernel runs whatever is
- * selected (rows of 8192 points always take their own 512-thread kernel).
+ * 3 for 64 ... 1024 and 4096-point columns; elsewhere the general kernel
+ * runs whatever is selected (rows of 8192 points always take their own
+ * 512-thread kernel).
  * The default is 1.
  * lattice_plan_autotune times every applicable variant of the plan's
  * steady-state column and row passes on `stream` (reps launches each, on a

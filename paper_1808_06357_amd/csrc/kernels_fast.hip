@@ -760,8 +760,9 @@ int go1(const A &a, int batch, void *stream)
 template <typename T, int V, bool COL, class A>
 int go(int L, const A &a, int batch, void *stream)
 {
-    if constexpr (V == 3) {  // 16 elements per thread, 512 threads: rows of 8192
+    if constexpr (V == 3) {  // 16 elements per thread, 512 threads: rows of 8192, pairs of 4096-point columns
         if (L == 8192 && !COL) return go1<T, V, COL, 16, 4, 8, 16>(a, batch, stream);
+        if (L == 4096 && COL) return go1<T, V, COL, 16, 16, 16>(a, batch, stream);
         return -1;
     } else if constexpr (V == 4) {  // 16 elements per thread, 64 threads: lengths up to 1024
         switch (L) {
@@ -855,11 +856,13 @@ constexpr int kTile = 4096;
 constexpr int kSmallTile = Geo<4>::NT * Geo<4>::E;
 
 // variants 1 and 2 take the plan's tile (C columns / rows of a 4096-element
-// tile); variant 3 uses its own 1024-element tiles
+// tile); variant 3 uses its own tiles: 1024 elements for lengths up to 1024,
+// and two 4096-point columns per 8192-element tile
 bool fast_col_fits(int prec, int variant, int L1, int L2, int C)
 {
     (void)prec;
-    if (variant == 3) return fast_len(L1) && L1 <= kSmallTile && L2 % (kSmallTile / L1) == 0;
+    if (variant == 3)
+        return (fast_len(L1) && L1 <= kSmallTile && L2 % (kSmallTile / L1) == 0) || (L1 == 4096 && L2 % 2 == 0);
     return (variant == 1 || variant == 2) && fast_len(L1) && C == kTile / L1 && L2 % C == 0;
 }
 
@@ -878,6 +881,8 @@ int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *st
                         a.scale == 1.0 && !a.adjoint && ((a.v != nullptr) != (a.ktab != nullptr)) &&
                         (prec == LT_C128 || !a.v || a.ptab || a.v2);
     if (!steady || !fast_col_fits(prec, variant, a.L1, a.L2, a.C)) return -1;
+    if (variant == 3 && a.L1 == 4096)
+        return prec == LT_C128 ? go<double, 3, true>(a.L1, a, batch, stream) : go<float, 3, true>(a.L1, a, batch, stream);
     if (prec == LT_C128)
         return variant == 1   ? go<double, 1, true>(a.L1, a, batch, stream)
                : variant == 2 ? go<double, 2, true>(a.L1, a, batch, stream)

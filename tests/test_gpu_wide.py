@@ -50,7 +50,7 @@ def test_wide_rows_against_oracle_samples(lt, name):
     v = torch.tensor(vfun(num, N), device="cuda")
     u0 = W.paper_g1(num, N, GAMMA)
     idx = gold[f"{name}_idx"]
-    for variant in (0, 1):
+    for variant in (0, 1, 3):
         for prec in ("c128", "c64"):
             p = lt.LT_C128 if prec == "c128" else lt.LT_C64
             lt.lattice_plan_set_kernels(plan, p, variant, variant)
