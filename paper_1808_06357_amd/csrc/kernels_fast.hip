@@ -285,6 +285,19 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
 #pragma unroll
         for (int r = 0; r < R; ++r) v[j * R + r] = bload<T>(rb, voff[j], r * rstep);
     }
+    // complex64 merged potential step: with two or more butterfly groups per
+    // thread, the table entries of the first group are loaded with the state
+    // (halving the burst of table loads after the inverse DFT), the rest
+    // after the inverse DFT
+    constexpr bool kPreP = MID == 0 && sizeof(T) == 4 && J > 1;
+    constexpr uint32_t ps = (uint32_t)(sizeof(Tw<T>) / sizeof(cx<T>));
+    Tw<T> pre[kPreP ? R : 1];
+    if constexpr (kPreP) {
+        const rsrc_t rp = make_rsrc((const Tw<T> *)a.ptab + b * a.ptab_bs, a.Nvalid * (int64_t)sizeof(Tw<T>));
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            pre[r] = __builtin_bit_cast(Tw<T>, __builtin_amdgcn_raw_buffer_load_b128(rp, ps * (voff[0] + r * rstep), 0, 0));
+    }
     // four-step twiddle base and step of each butterfly group: the forward
     // pass at the end multiplies by the same series, so they are kept
     const bool tw = a.twiddle != 0;
@@ -319,14 +332,18 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
         // entries of the zero padding (n >= Nvalid) as 0, which zeroes those
         // points.
         const rsrc_t rp = make_rsrc((const Tw<T> *)a.ptab + b * a.ptab_bs, a.Nvalid * (int64_t)sizeof(Tw<T>));
-        constexpr uint32_t ps = (uint32_t)(sizeof(Tw<T>) / sizeof(cx<T>));
+        constexpr int j0 = kPreP ? 1 : 0;
         Tw<T> pin[J][R];
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
+        for (int j = j0; j < J; ++j) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 pin[j][r] = __builtin_bit_cast(
                     Tw<T>, __builtin_amdgcn_raw_buffer_load_b128(rp, ps * (voff[j] + r * rstep), 0, 0));
+        }
+        if constexpr (kPreP) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) pin[0][r] = pre[r];
         }
 #pragma unroll
         for (int j = 0; j < J; ++j) {
