@@ -74,12 +74,15 @@ typedef struct {
     int64_t n_completed;     /* keys given minimal-l2 representatives (N - |I|)      */
     int64_t max_s;           /* max ||h_chi||^2 over all keys                        */
     int32_t bluestein;       /* 1: the length-N transform runs as a chirp-z convolution */
-    int32_t passes;          /* 1: whole run in one workgroup; 2: column + row passes  */
+    int32_t passes;          /* 1: whole run in one workgroup; 2: column + row passes;
+                                3: three levels (power-of-two L of 2^24 points or more) */
     int64_t fft_len;         /* transform length L (N, or the convolution length)    */
     int32_t L1, L2;          /* column / row lengths of the two-pass layout (L = L1*L2;
-                                up to 4096 x 4096, above that 4096 x 8192 at most) */
+                                up to 4096 x 4096, above that 4096 x 8192 at most);
+                                three levels: outer and inner column lengths      */
     int32_t cols;            /* columns per column-pass workgroup                     */
     int32_t rows;            /* rows per row-pass workgroup                           */
+    int32_t L3;              /* three levels: row length (L = L1*L2*L3); else 0       */
 } lt_plan_info;
 
 /*
@@ -303,8 +306,9 @@ lt_status lattice_diagnostics(const lt_plan *p, lt_prec prec, int32_t batch, con
  * lattice_plan_autotune times every applicable variant of the plan's
  * steady-state column and row passes on `stream` (reps launches each, on a
  * scratch buffer it allocates and frees) and keeps the fastest; it must not
- * run concurrently with runs of the same plan.  One-workgroup schedules have
- * nothing to tune.
+ * run concurrently with runs of the same plan.  One-workgroup and
+ * three-level schedules have nothing to tune (the latter run the default
+ * variant 1).
  */
 lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *stream);
 lt_status lattice_plan_set_kernels(lt_plan *p, lt_prec prec, int32_t col_variant, int32_t row_variant);

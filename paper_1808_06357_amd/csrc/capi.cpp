@@ -88,6 +88,9 @@ lt_status build_twiddles(lt_plan &p, int which, int prec)
     if (s.passes == 1) {
         La = s.rank2 ? s.L1 : s.L;
         Lb = s.rank2 ? s.L2 : 1;
+    } else if (s.passes == 3) {
+        La = s.L1;
+        Lb = s.L3;  // the row pass
     } else {
         La = s.L1;
         Lb = s.L2;
@@ -104,10 +107,21 @@ lt_status build_twiddles(lt_plan &p, int which, int prec)
         if ((st = upload((void **)&D.tw4hi, roots_d(s.L, s.L1, s.L2), "twiddles"))) return st;
         if ((st = upload((void **)&D.tw4lo, roots_d(s.L, s.L2, 1), "twiddles"))) return st;
     }
+    if (s.passes == 3) {
+        // outer four-step over L1 x M (M = L2 L3), inner four-step over L2 x L3
+        const int64_t M = (int64_t)s.L2 * s.L3;
+        if ((st = upload((void **)&D.tw4hi, roots_d(s.L, s.L1, M), "twiddles"))) return st;
+        if ((st = upload((void **)&D.tw4lo, roots_d(s.L, M, 1), "twiddles"))) return st;
+        if ((st = upload((void **)&D.tw4hi2, roots_d(M, s.L2, s.L3), "twiddles"))) return st;
+        if ((st = upload((void **)&D.tw4lo2, roots_d(M, s.L3, 1), "twiddles"))) return st;
+        if (prec == LT_C128) st = upload(&D.twc, roots_d(s.L2, s.L2, 1), "twiddles");
+        else st = upload(&D.twc, roots_f(s.L2, s.L2), "twiddles");
+        if (st) return st;
+    }
     std::vector<int32_t> sk((size_t)p.N);
     for (int64_t t = 0; t < p.N; ++t) sk[(size_t)t] = (int32_t)p.s_of_key[(size_t)t];
     if ((st = upload((void **)&D.s_key, sk, "key norms"))) return st;
-    if (s.passes == 2 && !s.bluestein) {
+    if (s.passes >= 2 && !s.bluestein) {
         // kinetic angles are read at the row-pass positions
         std::vector<int32_t> sr((size_t)p.N);
         for (int64_t pos = 0; pos < p.N; ++pos) {
@@ -115,6 +129,12 @@ lt_status build_twiddles(lt_plan &p, int which, int prec)
             if (transposed_layout(s)) {
                 const int64_t k1 = pos / s.L2, k2 = pos - k1 * s.L2;
                 chi = k1 + (int64_t)s.L1 * k2;
+            } else if (s.passes == 3) {
+                // pos = k1 M + k2 L3 + k3 holds xi = k1 + L1 (k2 + L2 k3)
+                const int64_t M = (int64_t)s.L2 * s.L3;
+                const int64_t k1 = pos / M, rem = pos - k1 * M;
+                const int64_t k2 = rem / s.L3, k3 = rem - k2 * s.L3;
+                chi = k1 + (int64_t)s.L1 * (k2 + (int64_t)s.L2 * k3);
             }
             sr[(size_t)pos] = sk[(size_t)chi];
         }
@@ -203,7 +223,7 @@ RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool s
     w.w = off;
     if (s.bluestein && s.passes == 2) off = align_up(off + (size_t)batch * s.L * esz(prec));
     w.ptab = off;
-    if (s.passes == 2 && phase_table)
+    if (s.passes >= 2 && phase_table)
         off = align_up(off + (size_t)(shared_v ? 1 : batch) * p.N * 16);
     if (s.bluestein && s.passes == 2 && conv_space) {
         // kernel spectrum of the step's cyclic convolution (complex double, L)
@@ -460,6 +480,108 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
     return LT_OK;
 }
 
+// Three-level run (power-of-two L of 2^24 points or more, L = L1 L2 L3, M =
+// L2 L3): each step is the inner forward column pass over L2 inside each of
+// the L1 blocks of M points, the row pass over L3 (kinetic step), the inner
+// inverse column pass, then the outer column pass over L1 (row length M)
+// with the merged potential step.  Spectrum index xi = k1 + L1 (k2 + L2 k3)
+// sits at k1 M + k2 L3 + k3; the plan's row-order norms follow it.
+lt_status three_level_forward(lt_plan &p, const Sched &s, const DevTables &D, int prec, int batch,
+                              const double *v, int64_t v_stride, void *u, double gamma, double dt,
+                              int64_t steps, void *ckpt, int64_t ck_every, const double *ktab, void *ptab,
+                              hipStream_t st)
+{
+    const int64_t N = p.N, M = (int64_t)s.L2 * s.L3;
+    const size_t S = esz(prec);
+    const double half = dt / (2.0 * gamma);
+    if (ptab && steps > 1)
+        HIP_TRY(launch_phase_table(prec, ptab, v, v_stride, v_stride ? batch : 1, N, 2.0 * half, st),
+                "potential table");
+    ColArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.L1 = s.L1;
+    a.L2 = (int)M;
+    a.C = s.cols;
+    a.ntiles = (int)(M / s.cols);
+    a.Nvalid = N;
+    a.twiddle = 1;
+    a.tw4hi = D.tw4hi;
+    a.tw4lo = D.tw4lo;
+    a.twa = D.twa;
+    a.rad = s.ra;
+    a.scale = 1.0;
+    a.buf = u;
+    a.buf_bs = N;
+    a.v = v;
+    a.v_bs = v_stride;
+    ColArgs first = a, pot = a, last = a;
+    first.in = u;
+    first.in_bs = N;
+    first.post_fwd = 1;
+    first.phase = half;
+    pot.pre_inv = 1;
+    pot.post_fwd = 1;
+    pot.phase = 2.0 * half;
+    pot.ptab = ptab;
+    pot.ptab_bs = v_stride ? N : 0;
+    last.pre_inv = 1;
+    last.out = u;
+    last.out_bs = N;
+    last.phase = half;
+    // the inner level: columns of L2 points, stride L3, in each block of M
+    ColArgs in;
+    std::memset(&in, 0, sizeof(in));
+    in.L1 = s.L2;
+    in.L2 = s.L3;
+    in.C = s.cols2;
+    in.ntiles = s.L3 / s.cols2;
+    in.Nvalid = M;
+    in.twiddle = 1;
+    in.tw4hi = D.tw4hi2;
+    in.tw4lo = D.tw4lo2;
+    in.twa = D.twc;
+    in.rad = s.rc;
+    in.scale = 1.0;
+    in.buf = u;
+    in.buf_bs = M;
+    ColArgs fwd = in, inv = in;
+    fwd.post_fwd = 1;
+    inv.pre_inv = 1;
+    const int blocks = batch * s.L1;
+    // rows of L3 points, L1 L2 of them per state
+    RowArgs r;
+    std::memset(&r, 0, sizeof(r));
+    r.buf = u;
+    r.buf_bs = N;
+    r.L1 = s.L1 * s.L2;
+    r.L2 = s.L3;
+    r.rows = s.rows;
+    r.nblk = r.L1 / r.rows;
+    r.s = D.s_row;
+    r.ktab = ktab;
+    r.ktab_n = D.ktab_n;
+    r.twb = D.twb;
+    r.rad = s.rb;
+    HIP_TRY(launch_col(prec, s, first, batch, st), "column pass");
+    for (int64_t t = 0; t < steps; ++t) {
+        HIP_TRY(launch_col_inner(prec, fwd, blocks, st), "inner column pass");
+        HIP_TRY(launch_row(prec, s, r, batch, st), "row pass");
+        HIP_TRY(launch_col_inner(prec, inv, blocks, st), "inner column pass");
+        if (t == steps - 1) break;
+        ColArgs m = pot;
+        const int64_t k = t + 1;
+        if (ckpt && k % ck_every == 0) {
+            m.ck = at(ckpt, (size_t)(k / ck_every) * batch * N * S);
+            m.ck_bs = N;
+            m.ck_v = v;
+            m.ck_phase = half;
+        }
+        HIP_TRY(launch_col(prec, s, m, batch, st), "column pass (potential)");
+    }
+    HIP_TRY(launch_col(prec, s, last, batch, st), "column pass (last)");
+    return LT_OK;
+}
+
 // ---------------------------------------------------------------- batches
 // workspace of a batch: per problem its run workspace, then the descriptor
 // block (kinetic-table, resident and two-pass descriptors, block prefix sums)
@@ -656,6 +778,7 @@ lt_status lattice_plan_info(const lt_plan *p, lt_plan_info *info)
     info->L2 = s.L2;
     info->cols = s.cols;
     info->rows = s.rows;
+    info->L3 = s.L3;
     return LT_OK;
 }
 
@@ -702,6 +825,9 @@ void lattice_plan_destroy(lt_plan *p)
             hipFree(D.s_key);
             hipFree(D.s_row);
             hipFree(D.bhat);
+            hipFree(D.twc);
+            hipFree(D.tw4hi2);
+            hipFree(D.tw4lo2);
         }
     delete p;
 }
@@ -779,6 +905,9 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
     if (ckpt)
         HIP_TRY(hipMemcpyAsync(ckpt, u, (size_t)batch * p.N * esz(prec), hipMemcpyDeviceToDevice, hs),
                 "checkpoint 0");
+    if (s.passes == 3)
+        return three_level_forward(p, s, D, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every,
+                                   ktab, at(sc.ptr, L.ptab), hs);
     void *conv = nullptr;
     if (steps >= kConvMinSteps && conv_available(p, 0, s)) {
         if ((st = ensure_device_tables(p, 0, LT_C128, stream))) return st;
@@ -989,7 +1118,8 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
             lds_res = std::max(lds_res, (size_t)s.L * S);
             continue;
         }
-        if (s.L2 > kTileElems) return fail(LT_E_UNSUPPORTED, "batch members take rows of at most 4096 points");
+        if (s.L2 > kTileElems || s.passes == 3)
+            return fail(LT_E_UNSUPPORTED, "batch members take transforms of at most 4096 x 4096 points");
         Roles R = two_pass_roles(s, D, p.N, v[i], 0, u[i], w + L.w, half, ktab);
         // chirp-z problems of 4 steps or more: the convolution form (spectrum
         // built below, once the kinetic tables exist)
@@ -1427,7 +1557,7 @@ lt_status lattice_plan_set_kernels(lt_plan *p, lt_prec prec, int32_t col_variant
         return fail(LT_E_ARG, "kernel variants are 0, 1, 2 or 3");
     std::lock_guard<std::mutex> lock(p->mu);
     for (int w = 0; w < 2; ++w) {
-        if (p->sched[w][prec].passes != 2) continue;
+        if (p->sched[w][prec].passes < 2) continue;
         p->sched[w][prec].col_var = col_variant;
         p->sched[w][prec].row_var = row_variant;
     }

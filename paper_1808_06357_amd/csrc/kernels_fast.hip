@@ -314,17 +314,28 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
             tw4_base_step(tb[j], ts[j], c0 + F::q_of(bf), F::t_of(bf), BPS, L2, a.tw4hi, a.tw4lo);
         }
     }
+    // MID 5: forward DFT only (then the four-step twiddle); MID 6: inverse
+    // DFT only (the conjugated twiddle first) -- the inner passes of a
+    // three-level transform
+    constexpr bool kInv = MID != 5, kFwd = MID != 6;
+    if constexpr (kInv) {
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
+        for (int j = 0; j < J; ++j) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[j * R + r] = conjg(v[j * R + r]);
-        if (tw) apply_series<T, R>(&v[j * R], tb[j], ts[j]);
+            for (int r = 0; r < R; ++r) v[j * R + r] = conjg(v[j * R + r]);
+            if (tw) apply_series<T, R>(&v[j * R], tb[j], ts[j]);
+        }
+        F::run(v, s, B, false);
     }
-    F::run(v, s, B, false);
     // point-domain multiplier: the table entries of all of this thread's
     // elements are loaded in one batch (one exposed latency), then applied
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (MID == 0) {
+    if constexpr (MID == 5) {
+        // nothing between the transforms
+    } else if constexpr (MID == 6) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = conjg(v[e]);
+    } else if constexpr (MID == 0) {
         // the merged potential step from the per-point table (16 bytes per
         // point: a hi/lo pair of complex floats, or one complex double), every
         // entry of the thread in flight at once.  The whole byte offset sits
@@ -410,10 +421,10 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
             }
         }
     }
-    F::run(v, s, B, true);
+    if constexpr (kFwd) F::run(v, s, B, kInv);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        if (tw) apply_series<T, R>(&v[j * R], tb[j], ts[j]);
+        if (kFwd && tw) apply_series<T, R>(&v[j * R], tb[j], ts[j]);
 #pragma unroll
         for (int r = 0; r < R; ++r) bstore(v[j * R + r], rb, voff[j], r * rstep);
     }
@@ -721,6 +732,21 @@ int col_go(const ColArgs &a, int batch, void *stream)
     // MID 2 (complex128 runs without a table): FP64 phase of v; MID 3:
     // potential with a time-dependent second field
     auto k = k_colf<T, E, NT, MINW, 1, Rs...>;
+    if constexpr (V == 1) {
+        if (a.pre_inv != a.post_fwd) {
+            k = a.post_fwd ? k_colf<T, E, NT, MINW, 5, Rs...> : k_colf<T, E, NT, MINW, 6, Rs...>;
+            static bool attr_io = false;
+            if (!attr_io) {
+                hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 5, Rs...>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 6, Rs...>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                attr_io = true;
+            }
+            constexpr int C = NT * E / Radix<Rs...>::prod;
+            return timed(LT_KIND_COLUMN, k, dim3(a.L2 / C, batch), dim3(NT), lds_bytes<T, V>(), stream, a);
+        }
+    }
     if (a.v) {
         if (a.v2) k = k_colf<T, E, NT, MINW, 3, Rs...>;
         else if (a.ptab) k = k_colf<T, E, NT, MINW, 0, Rs...>;
@@ -907,6 +933,16 @@ int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *st
     return variant == 1   ? go<float, 1, true>(a.L1, a, batch, stream)
            : variant == 2 ? go<float, 2, true>(a.L1, a, batch, stream)
                           : go<float, 4, true>(a.L1, a, batch, stream);
+}
+
+int launch_col_inner(int prec, const ColArgs &a, int batch, void *stream)
+{
+    // a forward-only (post_fwd) or inverse-only (pre_inv) column pass in place,
+    // the inner level of a three-level transform: register-staged kernel only
+    const bool io = (a.pre_inv != a.post_fwd) && !a.in && !a.out && !a.v && !a.ktab && !a.ck && !a.chirp &&
+                    a.scale == 1.0 && !a.adjoint;
+    if (!io || !fast_col_fits(prec, 1, a.L1, a.L2, a.C)) return -1;
+    return prec == LT_C128 ? go<double, 1, true>(a.L1, a, batch, stream) : go<float, 1, true>(a.L1, a, batch, stream);
 }
 
 int launch_row_fast(int prec, int variant, const RowArgs &a, int batch, void *stream)

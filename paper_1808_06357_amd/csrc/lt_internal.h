@@ -39,6 +39,13 @@ struct Sched {
                              // 3 fast 64x16 (1024-element tiles)
     int row_var = 1;         // row-pass kernel (same codes)
     Radices ra{}, rb{};      // radices of L1 (or L) and of L2
+    // three-level layout (passes == 3, power-of-two L of at least 2^24 points):
+    // L = L1 * L2 * L3; the column pass over L1 takes L2 := L2 * L3 as its row
+    // length, the inner column pass runs over L2 (radices rc) inside each of
+    // the L1 blocks of L2 * L3 points, and the row pass over L3 (radices rb)
+    int L3 = 0;
+    int cols2 = 1;           // inner columns per workgroup
+    Radices rc{};
 };
 
 // Device tables of a plan for one precision (built lazily, then immutable).
@@ -52,6 +59,10 @@ struct DevTables {
     int32_t *s_row = nullptr;// ||h_chi||^2 at the row-pass positions (two-pass, no chirp-z)
     double *bhat = nullptr;  // chirp-z kernel spectrum / (L sqrt N), complex double, schedule layout
     int64_t ktab_n = 0;      // entries of a run's kinetic table (max_s + 1)
+    // three-level layout: W_{L2} stage table and the inner four-step twiddles
+    // W_M^{q}, M = L2 L3 (hi: qa < L2 in steps of L3, lo: qb < L3)
+    void *twc = nullptr;
+    double *tw4hi2 = nullptr, *tw4lo2 = nullptr;
 };
 
 // ---------------------------------------------------------------- kernel arguments
@@ -172,6 +183,7 @@ int launch_ktab(double *dst, int64_t count, double kin, double scale, void *stre
 int diag_partials();  // blocks per state of launch_sums
 int launch_sums(int prec, const void *x, int64_t x_bs, int64_t count, int batch, const int32_t *w,
                 const double *vw, int64_t vw_bs, double *partial, void *stream);
+int launch_col_inner(int prec, const ColArgs &a, int batch, void *stream);
 int launch_proj_sums(int prec, const void *x, int64_t x_bs, int64_t count, int batch, double scale, int transposed,
                      int L1, int L2, const double *ghat, int64_t g_bs, double *partial, double *out, void *stream);
 int launch_diag_finish(const double *pp, const double *ps, int batch, int64_t N, double gamma, double kscale,

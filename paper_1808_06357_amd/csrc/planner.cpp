@@ -318,6 +318,24 @@ Sched make_schedule(const lt_plan &p, int prec, bool force_two_pass)
             if (q <= tile * kWideRow) s.L = q;
         }
     }
+    // power-of-two transforms of 2^24 points or more: three levels, so that
+    // no pass holds a 4096-point column (one column per tile, one cache line
+    // per element); L1 = 512 columns (8 per tile), an inner level of 64, rows
+    // of L / 32768 (512 or 1024 points)
+    if (!s.bluestein && !force_two_pass && (s.L & (s.L - 1)) == 0 && s.L >= ((int64_t)1 << 24) &&
+        s.L <= ((int64_t)1 << 25)) {
+        s.L1 = 512;
+        s.L2 = 64;
+        s.L3 = (int)(s.L / (512 * 64));
+        if (!factor_radices(s.L1, s.ra, mr) || !factor_radices(s.L2, s.rc, mr) || !factor_radices(s.L3, s.rb, mr))
+            return s;
+        s.passes = 3;
+        s.cols = (int)(tile / s.L1);
+        s.cols2 = (int)(tile / s.L2);
+        s.rows = (int)(tile / s.L3);
+        s.ok = true;
+        return s;
+    }
     if (s.L <= tile && !force_two_pass) {
         s.passes = 1;
         s.L1 = (int)s.L;

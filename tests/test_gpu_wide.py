@@ -1,7 +1,7 @@
-"""Lattices above 4096^2 transform points, split into columns of 4096 and
-rows of 8192 points (one row per workgroup): the paper's Table 1 lattice
-d = 3, n = 2^25 (Sec. 3.2) and a prime N = 8388617 whose chirp-z length is
-2^25, against stored FP64 oracle samples after 4 steps
+"""Lattices of 2^25 transform points: the paper's Table 1 lattice d = 3,
+n = 2^25 (Sec. 3.2; three levels 512 x 64 x 1024) and a prime N = 8388617
+whose chirp-z length is 2^25 (columns of 4096 and rows of 8192 points, one
+row per workgroup), against stored FP64 oracle samples after 4 steps
 (tests/golden/make_wide_golden.py), with both the general and the
 register-staged row kernels; and properties at full size: a sum of low
 modes under v = 0 evolves in closed form, and a run with -dt undoes a run
@@ -44,7 +44,10 @@ def test_wide_rows_against_oracle_samples(lt, name):
     Z, n, vfun, plan = _case(lt, name)
     assert np.array_equal(Z[0], gold[f"{name}_z"])
     info = plan.info
-    assert (info["passes"], info["L1"], info["L2"], info["fft_len"]) == (2, 4096, 8192, 1 << 25)
+    layout = (info["passes"], info["L1"], info["L2"], info["L3"], info["fft_len"])
+    # the power-of-two lattice runs three levels (512 x 64 x 1024); the chirp-z
+    # convolution of the prime keeps two passes of 4096 x 8192
+    assert layout == ((3, 512, 64, 1024, 1 << 25) if name == "table1_d3" else (2, 4096, 8192, 0, 1 << 25))
     N = int(n[0])
     num = W.point_numerators(Z, n)
     v = torch.tensor(vfun(num, N), device="cuda")
