@@ -108,3 +108,28 @@ def test_wide_free_modes_closed_form_and_reversibility(lt):
     e = float(torch.linalg.vector_norm(u - ref) / torch.linalg.vector_norm(ref))
     print(f"  reversibility c128: {e:.2e}", flush=True)
     assert e < 1e-12
+
+
+def test_three_level_checkpoints_match_shorter_runs(lt):
+    """The three-level run's checkpoints (stored by its outer column pass)
+    equal the states of shorter runs."""
+    import torch
+    Z, n, vfun, plan = _case(lt, "table1_d3")
+    assert plan.info["passes"] == 3
+    N = int(n[0])
+    num = W.point_numerators(Z, n)
+    v = torch.tensor(vfun(num, N), device="cuda")
+    u0 = torch.tensor(W.paper_g1(num, N, GAMMA), dtype=torch.complex128, device="cuda")
+    steps, every = 5, 2
+    lt.lattice_plan_set_kernels(plan, lt.LT_C128, 1, 1)
+    ck = torch.empty(lt.num_checkpoints(steps, every) * N, dtype=torch.complex128, device="cuda")
+    u = u0.clone()
+    lt.strang_run(plan, v, u, GAMMA, DT, steps, ckpt=ck, ckpt_every=every)
+    ck = ck.view(-1, N)
+    for c in range(ck.shape[0]):
+        w = u0.clone()
+        if c * every:
+            lt.strang_run(plan, v, w, GAMMA, DT, c * every)
+        e = float(torch.linalg.vector_norm(ck[c] - w) / torch.linalg.vector_norm(w))
+        print(f"  checkpoint {c}: rel_l2={e:.2e}", flush=True)
+        assert e < 1e-13, (c, e)
