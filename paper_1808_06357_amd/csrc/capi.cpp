@@ -238,10 +238,10 @@ RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool s
 }
 
 struct AdjWork {
-    size_t ktab = 0, w = 0, gacc = 0, conv = 0, conv_tmp = 0, total = 0;
+    size_t ktab = 0, w = 0, gacc = 0, ptab = 0, conv = 0, conv_tmp = 0, total = 0;
 };
 
-AdjWork adj_layout(const lt_plan &p, const Sched &s, int prec, int batch)
+AdjWork adj_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool shared_v)
 {
     AdjWork w;
     size_t off = align_up((size_t)(p.max_s + 1) * 16);
@@ -249,6 +249,8 @@ AdjWork adj_layout(const lt_plan &p, const Sched &s, int prec, int batch)
     off = align_up(off + (size_t)2 * batch * s.L * esz(prec));   // state and cotangent
     w.gacc = off;
     off = align_up(off + (size_t)batch * p.N * sizeof(double));
+    w.ptab = off;  // the interior merge passes' potential phase per point
+    off = align_up(off + (size_t)(shared_v ? 1 : batch) * p.N * 16);
     if (s.bluestein) {  // the convolution form's spectrum and scratch
         w.conv = off;
         off = align_up(off + (size_t)s.L * 16);
@@ -848,8 +850,7 @@ lt_status strang_adjoint_workspace_size(const lt_plan *p, lt_prec prec, int32_t 
     if (!p || !bytes) return fail(LT_E_ARG, "NULL argument");
     if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
     if (batch < 0) return fail(LT_E_ARG, "batch must be >= 0");
-    (void)shared_v;
-    *bytes = adj_layout(*p, p->sched[1][prec], prec, batch).total;
+    *bytes = adj_layout(*p, p->sched[1][prec], prec, batch, shared_v != 0).total;
     return LT_OK;
 }
 
@@ -942,7 +943,7 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
     if ((st = ensure_device_tables(p, 1, prec, stream))) return st;
     const Sched &s = p.sched[1][prec];
     const DevTables &D = p.dev[1][prec];
-    const AdjWork L = adj_layout(p, s, prec, batch);
+    const AdjWork L = adj_layout(p, s, prec, batch, shared);
     Scratch sc;
     if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
     void *W = at(sc.ptr, L.w);
@@ -961,6 +962,12 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
     const bool chirpz = s.bluestein && !conv;
     HIP_TRY(hipMemsetAsync(gacc, 0, (size_t)batch * N * sizeof(double), hs), "memset");
     const double c = dt / (2.0 * gamma);
+    // the backward merged potential step exp(-i 2 halfb v) of the interior
+    // merge passes, as a per-point table
+    void *ptab = at(sc.ptr, L.ptab);
+    if (steps > 1)
+        HIP_TRY(launch_phase_table(prec, ptab, v, v_stride, shared ? 1 : batch, N, 2.0 * halfb, hs),
+                "potential table");
     void *Wg = at(W, (size_t)batch * s.L * S);
 
     ColArgs base = col_base(s, D, N);
@@ -1024,6 +1031,10 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
             m.phase = 2.0 * halfb;
             m.post_fwd = 1;
             m.gcoef = 2.0 * c;
+            if (!m.reset) {
+                m.ptab = ptab;
+                m.ptab_bs = shared ? 0 : N;
+            }
         } else {
             m.adjoint = 3;
             m.phase = halfb;

@@ -518,7 +518,13 @@ __global__ void __launch_bounds__(NT, MINW) k_colf_adj(ColArgs a)
         const double im = (double)y.x * (double)x.y - (double)y.y * (double)x.x;
         gb[n] += a.gcoef * im;
         double c, sn;
-        expm_i(a.phase * vb[n], c, sn);
+        if (a.ptab) {  // the sweep's table of exp(-i phase v[n])
+            const cx<double> w = tw_d(((const Tw<T> *)a.ptab)[b * a.ptab_bs + n]);
+            c = w.x;
+            sn = w.y;
+        } else {
+            expm_i(a.phase * vb[n], c, sn);
+        }
         s[ax] = cmul_d(x, c, sn);
         s[ay] = cmul_d(y, c, sn);
     }
