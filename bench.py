@@ -251,6 +251,8 @@ def bench_adjoint(lt, torch, K, W):
         tf = wall(fwd, K, W)
         ta = wall(adj, K, W)
         out[name] = {"value": B * N * m / (tf + ta), "forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3,
+                     "variants": {"one_state": lt.lattice_plan_get_kernels_batch(plan, prec, 1),
+                                  f"{B}_states": lt.lattice_plan_get_kernels_batch(plan, prec, B)},
                      "adjoint_kernels": kernel_summary(lt, adj, 1)}
         log(f"adjoint {name}: fwd {tf * 1e3:.1f} ms, adj {ta * 1e3:.1f} ms, "
             f"{B * N * m / (tf + ta):.3e} pt-steps/s")

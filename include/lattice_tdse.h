@@ -303,17 +303,30 @@ lt_status lattice_diagnostics(const lt_plan *p, lt_prec prec, int32_t batch, con
  * runs whatever is selected (rows of 8192 points always take their own
  * 512-thread kernel).
  * The default is 1.
+ * A plan keeps two choices per pass: one for launches of a single state (or
+ * of few points) and one for launches of many states, batch >= 2 with
+ * batch * L >= 2^20 points (L = the schedule's transform length).  A
+ * single state's grid fits the chip in one residency wave whose load,
+ * compute and store phases run in lockstep; many states give several waves
+ * that overlap, and the fastest variant differs between the two.
  * lattice_plan_autotune times every applicable variant of the plan's
- * steady-state column and row passes on `stream` (reps launches each, on a
- * scratch buffer it allocates and frees) and keeps the fastest; it must not
- * run concurrently with runs of the same plan.  One-workgroup and
- * three-level schedules have nothing to tune (the latter run the default
- * variant 1).
+ * steady-state column and row passes on `stream`, once on one state and
+ * once on max(2, ceil(2^22 / L)) states sharing v (reps launches each, on a
+ * scratch buffer it allocates and frees), and keeps the fastest of each
+ * class; it must not run concurrently with runs of the same plan.
+ * One-workgroup and three-level schedules have nothing to tune (the latter
+ * run the default variant 1).
+ * lattice_plan_set_kernels sets both classes to the given variants;
+ * lattice_plan_get_kernels reports the single-state choice and
+ * lattice_plan_get_kernels_batch the choice a launch of `batch` states
+ * (batch >= 1) takes.
  */
 lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *stream);
 lt_status lattice_plan_set_kernels(lt_plan *p, lt_prec prec, int32_t col_variant, int32_t row_variant);
 lt_status lattice_plan_get_kernels(const lt_plan *p, lt_prec prec, int32_t *col_variant,
                                    int32_t *row_variant);
+lt_status lattice_plan_get_kernels_batch(const lt_plan *p, lt_prec prec, int32_t batch,
+                                         int32_t *col_variant, int32_t *row_variant);
 
 /*
  * Diagnostics: HIP-event timing of the library's own launches.  While

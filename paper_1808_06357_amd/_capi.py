@@ -77,6 +77,7 @@ _SIGS = {
     "lattice_plan_autotune": [_P, _i32, _i32, _P],
     "lattice_plan_set_kernels": [_P, _i32, _i32, _i32],
     "lattice_plan_get_kernels": [_P, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+    "lattice_plan_get_kernels_batch": [_P, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
     "lt_timing_enable": [_i32],
     "lt_timing_summary": [_i32, ctypes.POINTER(_i64), ctypes.POINTER(_f64)],
     "lt_last_error": [],
@@ -428,8 +429,9 @@ def lt_timing_summary(kind: int):
 
 
 def lattice_plan_autotune(plan: Plan, prec: int, reps: int = 10, stream=None):
-    """Time the kernel variants of the plan's passes and keep the fastest;
-    returns the chosen (column, row) variants."""
+    """Time the kernel variants of the plan's passes on one state and on many
+    states and keep the fastest of each; returns the single-state (column,
+    row) choice (lattice_plan_get_kernels_batch reports the other)."""
     _check(lib.lattice_plan_autotune(plan.handle, prec, reps, _stream(stream)), "lattice_plan_autotune")
     return lattice_plan_get_kernels(plan, prec)
 
@@ -443,4 +445,12 @@ def lattice_plan_get_kernels(plan: Plan, prec: int):
     cv, rv = _i32(), _i32()
     _check(lib.lattice_plan_get_kernels(plan.handle, prec, ctypes.byref(cv), ctypes.byref(rv)),
            "lattice_plan_get_kernels")
+    return cv.value, rv.value
+
+
+def lattice_plan_get_kernels_batch(plan: Plan, prec: int, batch: int):
+    """(column, row) variants a launch of `batch` states takes."""
+    cv, rv = _i32(), _i32()
+    _check(lib.lattice_plan_get_kernels_batch(plan.handle, prec, batch, ctypes.byref(cv), ctypes.byref(rv)),
+           "lattice_plan_get_kernels_batch")
     return cv.value, rv.value

@@ -1568,10 +1568,22 @@ lt_status lattice_plan_set_kernels(lt_plan *p, lt_prec prec, int32_t col_variant
         return fail(LT_E_ARG, "kernel variants are 0, 1, 2 or 3");
     std::lock_guard<std::mutex> lock(p->mu);
     for (int w = 0; w < 2; ++w) {
-        if (p->sched[w][prec].passes < 2) continue;
-        p->sched[w][prec].col_var = col_variant;
-        p->sched[w][prec].row_var = row_variant;
+        Sched &s = p->sched[w][prec];
+        if (s.passes < 2) continue;
+        s.col_var = s.col_var_m = col_variant;
+        s.row_var = s.row_var_m = row_variant;
     }
+    return LT_OK;
+}
+
+lt_status lattice_plan_get_kernels_batch(const lt_plan *p, lt_prec prec, int32_t batch, int32_t *col_variant,
+                                         int32_t *row_variant)
+{
+    if (!p || !col_variant || !row_variant) return fail(LT_E_ARG, "NULL argument");
+    if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
+    if (batch < 1) return fail(LT_E_ARG, "batch must be >= 1");
+    *col_variant = col_variant_of(p->sched[0][prec], batch);
+    *row_variant = row_variant_of(p->sched[0][prec], batch);
     return LT_OK;
 }
 
@@ -1593,16 +1605,19 @@ lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *st
     if (p->sched[0][prec].passes != 2) return LT_OK;
     lt_status st = ensure_device_tables(*p, 0, prec, stream);
     if (st) return st;
-    Sched &s = p->sched[0][prec];
+    const Sched &s = p->sched[0][prec];
     const DevTables &D = p->dev[0][prec];
     hipStream_t hs = (hipStream_t)stream;
+    // the many-state class is timed on about 2^22 points of states sharing v
+    const int many = (int)std::max<int64_t>(2, ((int64_t(1) << 22) + s.L - 1) / s.L);
     void *buf = nullptr, *v = nullptr, *kt = nullptr, *pt = nullptr;
     const size_t ktn = (size_t)(p->max_s + 1);
-    HIP_TRY(hipMalloc(&buf, (size_t)s.L * esz(prec)), "autotune buffer");
+    const size_t bytes = (size_t)many * s.L * esz(prec);
+    HIP_TRY(hipMalloc(&buf, bytes), "autotune buffer");
     HIP_TRY(hipMalloc(&v, (size_t)p->N * sizeof(double)), "autotune buffer");
     HIP_TRY(hipMalloc(&kt, ktn * 16), "autotune buffer");
     HIP_TRY(hipMalloc(&pt, (size_t)p->N * 16), "autotune buffer");
-    HIP_TRY(hipMemsetAsync(buf, 0, (size_t)s.L * esz(prec), hs), "memset");
+    HIP_TRY(hipMemsetAsync(buf, 0, bytes, hs), "memset");
     HIP_TRY(hipMemsetAsync(v, 0, (size_t)p->N * sizeof(double), hs), "memset");
     HIP_TRY(launch_ktab((double *)kt, (int64_t)ktn, 0.0, 1.0, hs), "kinetic table");
     HIP_TRY(launch_phase_table(prec, pt, (const double *)v, 0, 1, p->N, 1e-3, hs), "potential table");
@@ -1617,34 +1632,39 @@ lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *st
     c.v = (const double *)v;
     c.phase = 1e-3;
     c.ptab = pt;
+    c.ptab_bs = 0;
     RowArgs r = row_base(s, D);
     r.buf = buf;
     r.buf_bs = s.L;
     if (s.bluestein) r.bhat = D.bhat;
     else { r.s = D.s_row; r.ktab = (const double *)kt; }
-    auto time_it = [&](bool col, int var, float &ms) -> lt_status {
+    auto time_it = [&](bool col, int var, int batch, float &ms) -> lt_status {
         Sched t = s;
-        if (col) t.col_var = var; else t.row_var = var;
+        t.col_var = t.col_var_m = t.row_var = t.row_var_m = var;
         for (int i = 0; i < reps + 2; ++i) {
             if (i == 2) HIP_TRY(hipEventRecord(e0, hs), "event");
-            HIP_TRY(col ? launch_col(prec, t, c, 1, hs) : launch_row(prec, t, r, 1, hs), "autotune launch");
+            HIP_TRY(col ? launch_col(prec, t, c, batch, hs) : launch_row(prec, t, r, batch, hs),
+                    "autotune launch");
         }
         HIP_TRY(hipEventRecord(e1, hs), "event");
         HIP_TRY(hipEventSynchronize(e1), "event");
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "event");
         return LT_OK;
     };
-    int best_c = 0, best_r = 0;
-    float tc = 1e30f, tr = 1e30f;
-    for (int var = 0; var <= 3 && !st; ++var) {
-        float ms = 0.f;
-        if (var == 0 || fast_col_fits(prec, var, s.L1, s.L2, s.cols)) {
-            st = time_it(true, var, ms);
-            if (!st && ms < tc) { tc = ms; best_c = var; }
-        }
-        if (!st && (var == 0 || fast_row_fits(prec, var, s.L1, s.L2, s.rows))) {
-            st = time_it(false, var, ms);
-            if (!st && ms < tr) { tr = ms; best_r = var; }
+    int best_c[2] = {0, 0}, best_r[2] = {0, 0};
+    for (int cls = 0; cls < 2 && !st; ++cls) {
+        const int batch = cls ? many : 1;
+        float tc = 1e30f, tr = 1e30f;
+        for (int var = 0; var <= 3 && !st; ++var) {
+            float ms = 0.f;
+            if (var == 0 || fast_col_fits(prec, var, s.L1, s.L2, s.cols)) {
+                st = time_it(true, var, batch, ms);
+                if (!st && ms < tc) { tc = ms; best_c[cls] = var; }
+            }
+            if (!st && (var == 0 || fast_row_fits(prec, var, s.L1, s.L2, s.rows))) {
+                st = time_it(false, var, batch, ms);
+                if (!st && ms < tr) { tr = ms; best_r[cls] = var; }
+            }
         }
     }
     hipEventDestroy(e0);
@@ -1654,7 +1674,16 @@ lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *st
     hipFree(kt);
     hipFree(pt);
     if (st) return st;
-    return lattice_plan_set_kernels(p, prec, best_c, best_r);
+    std::lock_guard<std::mutex> lock(p->mu);
+    for (int w = 0; w < 2; ++w) {
+        Sched &t = p->sched[w][prec];
+        if (t.passes < 2) continue;
+        t.col_var = best_c[0];
+        t.row_var = best_r[0];
+        t.col_var_m = best_c[1];
+        t.row_var_m = best_r[1];
+    }
+    return LT_OK;
 }
 
 }  // extern "C"

@@ -733,9 +733,10 @@ int kernels_init()
 
 int launch_col(int prec, const Sched &s, const ColArgs &a, int batch, void *stream)
 {
-    if (s.col_var > 0) {
-        const int r = a.adjoint ? launch_col_fast_adjoint(prec, s.col_var, a, batch, stream)
-                                : launch_col_fast(prec, s.col_var, a, batch, stream);
+    const int var = col_variant_of(s, batch);
+    if (var > 0) {
+        const int r = a.adjoint ? launch_col_fast_adjoint(prec, var, a, batch, stream)
+                                : launch_col_fast(prec, var, a, batch, stream);
         if (r >= 0) return r;
     }
     const int nvec = a.adjoint ? 2 : 1;
@@ -753,8 +754,9 @@ int launch_col(int prec, const Sched &s, const ColArgs &a, int batch, void *stre
 
 int launch_row(int prec, const Sched &s, const RowArgs &a, int batch, void *stream)
 {
-    if (s.row_var > 0 && !a.fft_only) {
-        const int r = launch_row_fast(prec, s.row_var, a, batch, stream);
+    const int var = row_variant_of(s, batch);
+    if (var > 0 && !a.fft_only) {
+        const int r = launch_row_fast(prec, var, a, batch, stream);
         if (r >= 0) return r;
     }
     const size_t lds = (size_t)a.rows * a.L2 * esize(prec);

@@ -38,6 +38,8 @@ struct Sched {
     int col_var = 1;         // column-pass kernel: 0 general, 1 fast 256x16, 2 fast 512x8,
                              // 3 fast 64x16 (1024-element tiles)
     int row_var = 1;         // row-pass kernel (same codes)
+    int col_var_m = 1;       // the same choices for launches of many states
+    int row_var_m = 1;       // (see many_states)
     Radices ra{}, rb{};      // radices of L1 (or L) and of L2
     // three-level layout (passes == 3, power-of-two L of at least 2^24 points):
     // L = L1 * L2 * L3; the column pass over L1 takes L2 := L2 * L3 as its row
@@ -47,6 +49,15 @@ struct Sched {
     int cols2 = 1;           // inner columns per workgroup
     Radices rc{};
 };
+
+// A launch over many states fills the chip with several residency waves of
+// workgroups, whose load, compute and store phases overlap; a single state's
+// grid runs them in lockstep.  The fastest kernel variant differs between the
+// two regimes, so a plan keeps one choice for each.
+constexpr int64_t kManyPoints = int64_t(1) << 20;
+inline bool many_states(const Sched &s, int batch) { return batch > 1 && batch * s.L >= kManyPoints; }
+inline int col_variant_of(const Sched &s, int batch) { return many_states(s, batch) ? s.col_var_m : s.col_var; }
+inline int row_variant_of(const Sched &s, int batch) { return many_states(s, batch) ? s.row_var_m : s.row_var; }
 
 // Device tables of a plan for one precision (built lazily, then immutable).
 struct DevTables {

@@ -172,6 +172,19 @@ def test_every_kernel_variant(lt, N, d):
     for prec in (lt.LT_C64, lt.LT_C128):
         chosen = lt.lattice_plan_autotune(plan, prec, reps=3)
         assert all(x in (0, 1, 2, 3) for x in chosen)
+        assert lt.lattice_plan_get_kernels_batch(plan, prec, 1) == tuple(chosen)
+        assert all(x in (0, 1, 2, 3) for x in lt.lattice_plan_get_kernels_batch(plan, prec, 64))
+    # a batch large enough for the many-state choice the autotuner made
+    L = plan.info["fft_len"]
+    batch = max(2, -(-(1 << 20) // L))
+    Z, n, v, u0, gamma, dt, steps = korobov_case(N, d, 22, 5, batch=batch)
+    ref = O.strang_run(n, s, v, u0, gamma, dt, steps)
+    for prec in ("c128", "c64"):
+        p = lt.LT_C128 if prec == "c128" else lt.LT_C64
+        e = rel(gpu_run(lt, plan, v, u0, gamma, dt, steps, prec), ref)
+        print(f"  N={N} batch={batch} variants={lt.lattice_plan_get_kernels_batch(plan, p, batch)} "
+              f"{prec} rel_l2={e:.2e}", flush=True)
+        assert e < TOL[prec], (batch, prec, e)
 
 
 @pytest.mark.parametrize("N,d", [(65521, 4), (8191, 3), (262139, 3)])

@@ -116,10 +116,17 @@ def test_schedules():
     c1 = C.lattice_plan(np.array([[1, 253]]), np.array([65521]))
     assert C.strang_workspace_size(c1, C.LT_C64, 3, True) >= 3 * c1.info["fft_len"] * 8
     # kernel selection is host state: set / get without a GPU
+    assert C.lattice_plan_get_kernels_batch(c1, C.LT_C64, 64) == (1, 1)
     C.lattice_plan_set_kernels(c1, C.LT_C64, 2, 0)
     assert C.lattice_plan_get_kernels(c1, C.LT_C64) == (2, 0)
+    # a forced choice holds for single-state and many-state launches alike
+    for batch in (1, 2, 8, 64, 4096):
+        assert C.lattice_plan_get_kernels_batch(c1, C.LT_C64, batch) == (2, 0)
+    assert C.lattice_plan_get_kernels_batch(c1, C.LT_C128, 64) == (1, 1)
     with pytest.raises(C.LatticeError):
         C.lattice_plan_set_kernels(c1, C.LT_C64, 4, 0)
+    with pytest.raises(C.LatticeError):
+        C.lattice_plan_get_kernels_batch(c1, C.LT_C64, 0)
 
 
 def test_plan_poor_lattice_fails_within_budget():
