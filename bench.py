@@ -372,10 +372,11 @@ def bench_wide(lt, torch, K, W):
 
 
 def bench_hbm(lt, torch, K, W):
-    """The benchmark lattice with a batch of 8 states (complex128: about 440 MB
-    of states, transform buffers and tables, beyond the 256 MB Infinity
-    Cache), 100 steps: the same steady-state passes as the headline run, with
-    a working set that has to stream from HBM."""
+    """The benchmark lattice with a batch of states sharing v (16 in complex64,
+    8 in complex128: about 500 and 450 MB of states, transform buffers and
+    tables, beyond the 256 MB Infinity Cache), 100 steps: the same
+    steady-state passes as the headline run, with a working set that has to
+    stream from HBM."""
     import numpy as np
 
     import workloads as W_
@@ -383,11 +384,12 @@ def bench_hbm(lt, torch, K, W):
     plan = lt.lattice_plan(inst.Z, inst.n, inst.I)
     info = plan.info
     dev = torch.device("cuda:0")
-    N, m, B = inst.N, 100, 8
+    N, m = inst.N, 100
     v = torch.tensor(inst.v, dtype=torch.float64, device=dev)
-    out = {"workload": f"benchmark lattice d=6 N={N}, batch of {B} states sharing v, {m} steps per run",
+    out = {"workload": f"benchmark lattice d=6 N={N}, batches of 16 (complex64) and 8 (complex128) states "
+                       f"sharing v, {m} steps per run",
            "unit": "lattice-point-steps/s"}
-    for name, dtype, S in (("c64", torch.complex64, 8), ("c128", torch.complex128, 16)):
+    for name, dtype, S, B in (("c64", torch.complex64, 8, 16), ("c128", torch.complex128, 16, 8)):
         prec = lt.LT_C64 if name == "c64" else lt.LT_C128
         lt.lattice_plan_autotune(plan, prec, reps=5)
         u = torch.tensor(np.tile(inst.u0, (B, 1)), dtype=dtype, device=dev)
@@ -400,7 +402,8 @@ def bench_hbm(lt, torch, K, W):
         col_steady = B * (2 * L * S) + 16 * N   # the shared table is read once per launch
         row_steady = B * (2 * L * S) + 16 * L
         resident = B * (N * S + L * S) + 16 * N + 16 * L
-        out[name] = {"value": B * N * m / sec, "ms_per_run": sec * 1e3, "working_set_MB": resident / 1e6,
+        out[name] = {"value": B * N * m / sec, "states": B, "ms_per_run": sec * 1e3,
+                     "working_set_MB": resident / 1e6,
                      "column_us": ks["column"]["avg_us"], "row_us": ks["row"]["avg_us"],
                      "column_GBs": col_steady / (ks["column"]["avg_us"] * 1e-6) / 1e9,
                      "row_GBs": row_steady / (ks["row"]["avg_us"] * 1e-6) / 1e9}

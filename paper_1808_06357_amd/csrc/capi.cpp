@@ -613,7 +613,7 @@ BatchLayout batch_layout(int32_t B, const lt_plan *const *plans, int prec)
     b.off.resize(B);
     for (int i = 0; i < B; ++i) {
         b.off[i] = off;
-        off += run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1, true, false, true).total;
+        off += run_layout(*plans[i], plans[i]->sched[0][prec], prec, 1, true, true, true).total;
     }
     b.desc = off;
     size_t d = 0;
@@ -1097,7 +1097,7 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
         if ((st = ensure_device_tables(p, 0, prec, stream))) return st;
         const Sched &s = p.sched[0][prec];
         const DevTables &D = p.dev[0][prec];
-        const RunWork L = run_layout(p, s, prec, 1, true, false, true);
+        const RunWork L = run_layout(p, s, prec, 1, true, true, true);
         char *w = at(sc.ptr, BL.off[i]);
         double *ktab = (double *)(w + L.ktab);
         kd.push_back({ktab, p.max_s + 1, kinetic_angle(gamma[i], dt[i]), s.bluestein ? 1.0 : 1.0 / (double)s.L});
@@ -1131,7 +1131,12 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
         }
         if (s.L2 > kTileElems || s.passes == 3)
             return fail(LT_E_UNSUPPORTED, "batch members take transforms of at most 4096 x 4096 points");
-        Roles R = two_pass_roles(s, D, p.N, v[i], 0, u[i], w + L.w, half, ktab);
+        // the merged potential step exp(-i dt v / gamma) of the interior column
+        // passes, as a per-point table
+        void *ptab = steps[i] > 1 ? (void *)(w + L.ptab) : nullptr;
+        if (ptab)
+            HIP_TRY(launch_phase_table(prec, ptab, v[i], 0, 1, p.N, 2.0 * half, hs), "potential table");
+        Roles R = two_pass_roles(s, D, p.N, v[i], 0, u[i], w + L.w, half, ktab, ptab);
         // chirp-z problems of 4 steps or more: the convolution form (spectrum
         // built below, once the kinetic tables exist)
         const bool conv = steps[i] >= kConvMinSteps && conv_available(p, 0, s);

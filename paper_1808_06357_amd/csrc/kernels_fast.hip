@@ -260,7 +260,7 @@ __device__ __forceinline__ void tw4_base_step(cx<double> &b, cx<double> &st, int
 // of batch item b.  MID 0: the merged potential step from the per-point
 // table the run built; MID 1: the chirp-z
 // kinetic step from the table indexed by the squared norm; MID 2: the merged
-// potential step from v in FP64 (batches carry no table); MID 3: the angle of
+// potential step from v in FP64 (runs without a table); MID 3: the angle of
 // a time-dependent potential from two fields.
 template <typename T, int E, int NT, int MID, int... Rs>
 __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
@@ -362,8 +362,7 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
             for (int r = 0; r < R; ++r) v[j * R + r] = twmul(conjg(v[j * R + r]), pin[j][r]);
         }
     } else if constexpr (MID == 0 || MID == 2 || MID == 3) {
-        // complex128 (and batches): exp(-i phase v) in FP64 on the fly (the table would cost
-        // as many bytes as v and more registers than the kernel has).  MID 3: the angle
+        // passes without a table: exp(-i phase v) in FP64 on the fly.  MID 3: the angle
         // phase v[n] + phase2 v2[n] of a time-dependent potential, both fields in FP64
         double pin[J][R];
 #pragma unroll
@@ -562,7 +561,8 @@ __global__ void __launch_bounds__(NT, MINW) k_colf_multi(const BatchDesc *d, con
     const int k = find_member(start, nmem, bid);
     const BatchDesc &p = d[idx[k]];
     if (g == 0 || (g & 1) || g >= p.npass - 1) return;
-    colf_body<T, E, NT, 2, Rs...>(p.col[1], bid - start[k], 0, reinterpret_cast<cx<T> *>(smem_raw));
+    // members with interior passes carry the per-point table of the merged potential step
+    colf_body<T, E, NT, 0, Rs...>(p.col[1], bid - start[k], 0, reinterpret_cast<cx<T> *>(smem_raw));
 }
 
 // Row pass: [DFT -> spectral multiplier -> inverse DFT], in place; the
