@@ -152,6 +152,11 @@ lt_status strang_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, i
  *          (then the call allocates and frees it stream-ordered).
  * Successive half potential steps are merged into one full step, which
  * equals the literal scheme within rounding.
+ * With `work` given, and once an earlier call on the plan and precision has
+ * built the plan's device tables, the call enqueues kernel launches (and,
+ * with checkpoints, one device-to-device copy) on `stream` and nothing else:
+ * no allocation, memset or synchronisation, so a caller can capture it into
+ * a HIP graph and replay it.
  */
 lt_status strang_run(const lt_plan *p, lt_prec prec, int32_t batch, const double *v,
                      int64_t v_stride, void *u, double gamma, double dt, int64_t steps,
