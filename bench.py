@@ -611,6 +611,16 @@ def main():
         log(f"{name}: {results[name]['value']:.3e} pt-steps/s, {results[name]['ms_per_step']:.2f} ms/run; "
             + ", ".join(f"{k}: {v_['avg_us']:.1f} us/launch {v_['achieved_GBs'] or 0:.0f} GB/s"
                         for k, v_ in per_kind.items()))
+        if name == "c64":
+            # the same run captured once into a HIP graph and replayed
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                lt.strang_run(plan, v, u, inst.gamma, inst.dt, m, work=work)
+            g_sec = wall(g.replay, args.steps, args.warmup)
+            results[name]["graph"] = {"eager_ms_per_run": elapsed / args.steps * 1e3, "graph_ms_per_run": g_sec * 1e3,
+                                      "passes_per_run": 2 * m + 1}
+            log(f"{name}: graph replay {g_sec * 1e3:.2f} ms/run against eager {elapsed / args.steps * 1e3:.2f}")
+            del g
         del work, u
         torch.cuda.empty_cache()
 
@@ -662,6 +672,7 @@ def main():
             for name_, S_ in (("c64", 8), ("c128", 16)) if name_ in results},
         "kernels_c64": head["kinds"],
         "kernel_variants": {k: list(r_["kernels"]) for k, r_ in results.items()},
+        "graph_c64": head.get("graph"),
         "accuracy": acc,
     }
     if "c128" in results:
