@@ -107,6 +107,12 @@ def case4(lt):
     gold = np.load(GOLD4)
     c = W.config4()
     plan = lt.lattice_plan(c.Z, c.n, c.I)
+    # the kernels the benchmark times: autotuned (the 32-state runs take the
+    # many-state choice)
+    for p in (lt.LT_C64, lt.LT_C128):
+        lt.lattice_plan_autotune(plan, p, reps=3)
+        print(f"config4 kernels {p}: one state {lt.lattice_plan_get_kernels_batch(plan, p, 1)}, "
+              f"32 states {lt.lattice_plan_get_kernels_batch(plan, p, 32)}", flush=True)
     basis = torch.tensor(c.meta["series"].basis(c.meta["num"], c.N), dtype=torch.float64, device="cuda")
     S = torch.tensor(gold["S"], device="cuda")
     assert np.array_equal(gold["S"], W.config4_loss_points(c.N))
