@@ -83,6 +83,11 @@ typedef struct {
     int32_t cols;            /* columns per column-pass workgroup                     */
     int32_t rows;            /* rows per row-pass workgroup                           */
     int32_t L3;              /* three levels: row length (L = L1*L2*L3); else 0       */
+    int32_t swapped;         /* 1: a rank-2 tensor n1 x n2 whose n1-point columns are
+                                long (n1 >= 2048, n2 <= n1/4): strang_run calls without
+                                checkpoints transpose the state and v into the
+                                workspace and run on n2-point columns and n1-point
+                                rows (L1, L2 above describe the untransposed layout) */
 } lt_plan_info;
 
 /*

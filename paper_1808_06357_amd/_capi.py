@@ -51,7 +51,8 @@ class PlanInfo(ctypes.Structure):
                 ("N", ctypes.c_int64), ("n_index", ctypes.c_int64), ("n_completed", ctypes.c_int64),
                 ("max_s", ctypes.c_int64), ("bluestein", ctypes.c_int32), ("passes", ctypes.c_int32),
                 ("fft_len", ctypes.c_int64), ("L1", ctypes.c_int32), ("L2", ctypes.c_int32),
-                ("cols", ctypes.c_int32), ("rows", ctypes.c_int32), ("L3", ctypes.c_int32)]
+                ("cols", ctypes.c_int32), ("rows", ctypes.c_int32), ("L3", ctypes.c_int32),
+                ("swapped", ctypes.c_int32)]
 
 
 _P, _i32, _i64, _f64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t

@@ -79,6 +79,26 @@ lt_status bind_device(lt_plan &p)
 
 bool transposed_layout(const Sched &s) { return s.passes == 2 && !s.rank2; }
 
+// A two-pass rank-2 tensor n1 x n2 (row-major, n2 contiguous) whose columns
+// of n1 points fill a tile with one or two columns, so that every element of a
+// column pass sits on its own cache line: the same transform held transposed
+// (n2 x n1) reads n2-point columns many to a tile and n1-point rows.  Not ok
+// (unused) for other schedules.
+Sched swapped_schedule(const Sched &s0)
+{
+    Sched s;
+    if (!s0.ok || !s0.rank2 || s0.passes != 2 || s0.L1 < 2048 || (int64_t)s0.L2 * 4 > s0.L1) return s;
+    s = s0;
+    s.swapped = true;
+    s.L1 = s0.L2;
+    s.L2 = s0.L1;
+    s.ra = s0.rb;
+    s.rb = s0.ra;
+    s.cols = (int)std::max<int64_t>(1, std::min<int64_t>(kTileElems / s.L1, s.L2));
+    s.rows = (int)std::max<int64_t>(1, std::min<int64_t>(kTileElems / s.L2, s.L1));
+    return s;
+}
+
 lt_status build_twiddles(lt_plan &p, int which, int prec)
 {
     DevTables &D = p.dev[which][prec];
@@ -126,7 +146,10 @@ lt_status build_twiddles(lt_plan &p, int which, int prec)
         std::vector<int32_t> sr((size_t)p.N);
         for (int64_t pos = 0; pos < p.N; ++pos) {
             int64_t chi = pos;
-            if (transposed_layout(s)) {
+            if (transposed_layout(s) || s.swapped) {
+                // rank-1 four-step: pos = k1 L2 + k2 holds xi = k1 + L1 k2; a
+                // swapped rank-2 tensor: pos = k2 n1 + k1 holds (k1, k2), key
+                // k1 n2 + k2 -- the same map with L1 = n2, L2 = n1
                 const int64_t k1 = pos / s.L2, k2 = pos - k1 * s.L2;
                 chi = k1 + (int64_t)s.L1 * k2;
             } else if (s.passes == 3) {
@@ -710,6 +733,56 @@ lt_status ensure_device_tables(lt_plan &p, int which, int prec, void *stream)
     D.built = true;
     return LT_OK;
 }
+
+// Workspace of a run on the swapped rank-2 schedule: the run's own layout,
+// then the transposed state (batch x N) and potential (1 or batch x N).
+struct SwapWork {
+    RunWork run;
+    size_t u = 0, v = 0, total = 0;
+};
+
+SwapWork swap_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool shared_v)
+{
+    SwapWork w;
+    w.run = run_layout(p, s, prec, batch, shared_v);
+    size_t off = w.run.total;
+    w.u = off;
+    off = align_up(off + (size_t)batch * p.N * esz(prec));
+    w.v = off;
+    off = align_up(off + (size_t)(shared_v ? 1 : batch) * p.N * sizeof(double));
+    w.total = off;
+    return w;
+}
+
+// A run without checkpoints of a rank-2 tensor on its swapped schedule: the
+// state and the potential are transposed into the workspace (n2 x n1), the
+// steps run there, and the state is transposed back.
+lt_status swapped_forward(lt_plan &p, int prec, int batch, const double *v, int64_t v_stride, void *u,
+                          double gamma, double dt, int64_t steps, void *work, size_t work_bytes, void *stream)
+{
+    hipStream_t hs = (hipStream_t)stream;
+    lt_status st;
+    if ((st = ensure_device_tables(p, 2, prec, stream))) return st;
+    const Sched &s = p.sched[2][prec];
+    const DevTables &D = p.dev[2][prec];
+    const bool shared = v_stride == 0;
+    const SwapWork L = swap_layout(p, s, prec, batch, shared);
+    Scratch sc;
+    if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
+    double *ktab = (double *)at(sc.ptr, L.run.ktab);
+    if ((st = make_ktab(p, s, ktab, gamma, dt, hs))) return st;
+    const int n1 = s.L2, n2 = s.L1;
+    void *U = at(sc.ptr, L.u);
+    double *V = (double *)at(sc.ptr, L.v);
+    HIP_TRY(launch_transpose((int)esz(prec), U, u, batch, n1, n2, p.N, p.N, hs), "state transpose");
+    HIP_TRY(launch_transpose(8, V, v, shared ? 1 : batch, n1, n2, p.N, shared ? p.N : v_stride, hs),
+            "potential transpose");
+    if ((st = two_pass_forward(p, s, D, prec, batch, V, shared ? 0 : p.N, U, gamma, dt, steps, nullptr, 0, ktab,
+                               at(sc.ptr, L.run.w), at(sc.ptr, L.run.ptab), nullptr, hs)))
+        return st;
+    HIP_TRY(launch_transpose((int)esz(prec), u, U, batch, n2, n1, p.N, p.N, hs), "state transpose");
+    return LT_OK;
+}
 }  // namespace lt
 
 // ---------------------------------------------------------------- C-ABI
@@ -752,6 +825,7 @@ lt_status lattice_plan(int32_t d, int32_t r, const int64_t *Z, const int64_t *n,
             p->sched[0][prec] = make_schedule(*p, prec, false);
             p->sched[1][prec] = p->sched[0][prec].passes == 2 ? p->sched[0][prec]
                                                               : make_schedule(*p, prec, true);
+            p->sched[2][prec] = swapped_schedule(p->sched[0][prec]);
         }
     } catch (const std::bad_alloc &) {
         delete p;
@@ -781,6 +855,7 @@ lt_status lattice_plan_info(const lt_plan *p, lt_plan_info *info)
     info->cols = s.cols;
     info->rows = s.rows;
     info->L3 = s.L3;
+    info->swapped = (p->sched[0][LT_C64].ok ? p->sched[2][LT_C64] : p->sched[2][LT_C128]).ok ? 1 : 0;
     return LT_OK;
 }
 
@@ -841,6 +916,8 @@ lt_status strang_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, i
     if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
     if (batch < 0) return fail(LT_E_ARG, "batch must be >= 0");
     *bytes = run_layout(*p, p->sched[0][prec], prec, batch, shared_v != 0).total;
+    if (p->sched[2][prec].ok)
+        *bytes = std::max(*bytes, swap_layout(*p, p->sched[2][prec], prec, batch, shared_v != 0).total);
     return LT_OK;
 }
 
@@ -865,6 +942,8 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
     if (!v || !u) return fail(LT_E_ARG, "v and u must not be NULL");
     if (v_stride != 0 && v_stride < p.N) return fail(LT_E_ARG, "v_stride must be 0 or >= N");
     if (ckpt && ckpt_every < 1) return fail(LT_E_ARG, "ckpt_every must be >= 1 with a checkpoint buffer");
+    if (!ckpt && p.sched[2][prec].ok)
+        return swapped_forward(p, prec, batch, v, v_stride, u, gamma, dt, steps, work, work_bytes, stream);
     hipStream_t hs = (hipStream_t)stream;
     if ((st = ensure_device_tables(p, 0, prec, stream))) return st;
     const Sched &s = p.sched[0][prec];
@@ -1572,7 +1651,7 @@ lt_status lattice_plan_set_kernels(lt_plan *p, lt_prec prec, int32_t col_variant
     if (col_variant < 0 || col_variant > 3 || row_variant < 0 || row_variant > 3)
         return fail(LT_E_ARG, "kernel variants are 0, 1, 2 or 3");
     std::lock_guard<std::mutex> lock(p->mu);
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < 3; ++w) {
         Sched &s = p->sched[w][prec];
         if (s.passes < 2) continue;
         s.col_var = s.col_var_m = col_variant;
@@ -1587,8 +1666,9 @@ lt_status lattice_plan_get_kernels_batch(const lt_plan *p, lt_prec prec, int32_t
     if (!p || !col_variant || !row_variant) return fail(LT_E_ARG, "NULL argument");
     if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
     if (batch < 1) return fail(LT_E_ARG, "batch must be >= 1");
-    *col_variant = col_variant_of(p->sched[0][prec], batch);
-    *row_variant = row_variant_of(p->sched[0][prec], batch);
+    const Sched &s = p->sched[2][prec].ok ? p->sched[2][prec] : p->sched[0][prec];
+    *col_variant = col_variant_of(s, batch);
+    *row_variant = row_variant_of(s, batch);
     return LT_OK;
 }
 
@@ -1596,22 +1676,21 @@ lt_status lattice_plan_get_kernels(const lt_plan *p, lt_prec prec, int32_t *col_
 {
     if (!p || !col_variant || !row_variant) return fail(LT_E_ARG, "NULL argument");
     if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
-    *col_variant = p->sched[0][prec].col_var;
-    *row_variant = p->sched[0][prec].row_var;
+    const Sched &s = p->sched[2][prec].ok ? p->sched[2][prec] : p->sched[0][prec];
+    *col_variant = s.col_var;
+    *row_variant = s.row_var;
     return LT_OK;
 }
 
-lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *stream)
+// Times the kernel variants of slot w's steady column and row passes on one
+// state and on many; best_c / best_r receive the single-state [0] and
+// many-state [1] choices.
+static lt_status tune_slot(lt_plan *p, int w, lt_prec prec, int32_t reps, void *stream, int best_c[2], int best_r[2])
 {
-    if (!p) return fail(LT_E_ARG, "plan is NULL");
-    if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
-    if (reps < 1) return fail(LT_E_ARG, "reps must be >= 1");
-    if (!p->sched[0][prec].ok) return fail(LT_E_UNSUPPORTED, "no GPU schedule for this precision");
-    if (p->sched[0][prec].passes != 2) return LT_OK;
-    lt_status st = ensure_device_tables(*p, 0, prec, stream);
+    lt_status st = ensure_device_tables(*p, w, prec, stream);
     if (st) return st;
-    const Sched &s = p->sched[0][prec];
-    const DevTables &D = p->dev[0][prec];
+    const Sched &s = p->sched[w][prec];
+    const DevTables &D = p->dev[w][prec];
     hipStream_t hs = (hipStream_t)stream;
     // the many-state class is timed on about 2^22 points of states sharing v
     const int many = (int)std::max<int64_t>(2, ((int64_t(1) << 22) + s.L - 1) / s.L);
@@ -1656,7 +1735,7 @@ lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *st
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "event");
         return LT_OK;
     };
-    int best_c[2] = {0, 0}, best_r[2] = {0, 0};
+    best_c[0] = best_c[1] = best_r[0] = best_r[1] = 0;
     for (int cls = 0; cls < 2 && !st; ++cls) {
         const int batch = cls ? many : 1;
         float tc = 1e30f, tr = 1e30f;
@@ -1679,14 +1758,32 @@ lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *st
     hipFree(kt);
     hipFree(pt);
     if (st) return st;
-    std::lock_guard<std::mutex> lock(p->mu);
-    for (int w = 0; w < 2; ++w) {
-        Sched &t = p->sched[w][prec];
-        if (t.passes < 2) continue;
-        t.col_var = best_c[0];
-        t.row_var = best_r[0];
-        t.col_var_m = best_c[1];
-        t.row_var_m = best_r[1];
+    return LT_OK;
+}
+
+lt_status lattice_plan_autotune(lt_plan *p, lt_prec prec, int32_t reps, void *stream)
+{
+    if (!p) return fail(LT_E_ARG, "plan is NULL");
+    if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
+    if (reps < 1) return fail(LT_E_ARG, "reps must be >= 1");
+    if (!p->sched[0][prec].ok) return fail(LT_E_UNSUPPORTED, "no GPU schedule for this precision");
+    if (p->sched[0][prec].passes != 2) return LT_OK;
+    // slot 0 (and the adjoint's slot 1, the same schedule); slot 2 when the
+    // plan has a swapped rank-2 schedule
+    for (int w : {0, 2}) {
+        if (w == 2 && !p->sched[2][prec].ok) continue;
+        int bc[2], br[2];
+        lt_status st = tune_slot(p, w, prec, reps, stream, bc, br);
+        if (st) return st;
+        std::lock_guard<std::mutex> lock(p->mu);
+        for (int t = w; t <= (w == 0 ? 1 : 2); ++t) {
+            Sched &x = p->sched[t][prec];
+            if (x.passes < 2) continue;
+            x.col_var = bc[0];
+            x.row_var = br[0];
+            x.col_var_m = bc[1];
+            x.row_var_m = br[1];
+        }
     }
     return LT_OK;
 }

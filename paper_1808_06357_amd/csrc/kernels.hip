@@ -921,6 +921,46 @@ int launch_proj_sums(int prec, const void *x, int64_t x_bs, int64_t count, int b
     return (int)hipGetLastError();
 }
 
+// dst[b][c][r] = src[b][r][c] for a batch of rows x cols matrices, through
+// 32 x 32 tiles in LDS (rows of the tile read and written contiguously)
+struct alignas(16) B16 {
+    double x, y;
+};
+template <typename E>
+__global__ void __launch_bounds__(256) k_transpose(E *dst, const E *src, int rows, int cols, int64_t dst_bs,
+                                                   int64_t src_bs)
+{
+    __shared__ E t[32][33];
+    const E *sb = src + (int64_t)blockIdx.z * src_bs;
+    E *db = dst + (int64_t)blockIdx.z * dst_bs;
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int i = ty; i < 32; i += 8) {
+        const int r = r0 + i, c = c0 + tx;
+        if (r < rows && c < cols) t[i][tx] = sb[(int64_t)r * cols + c];
+    }
+    __syncthreads();
+    for (int i = ty; i < 32; i += 8) {
+        const int c = c0 + i, r = r0 + tx;
+        if (r < rows && c < cols) db[(int64_t)c * rows + r] = t[tx][i];
+    }
+}
+
+int launch_transpose(int esize, void *dst, const void *src, int batch, int rows, int cols, int64_t dst_bs,
+                     int64_t src_bs, void *stream)
+{
+    if (batch < 1 || batch > 65535 || rows < 1 || cols < 1 || (esize != 8 && esize != 16))
+        return (int)hipErrorInvalidValue;
+    const dim3 grid((cols + 31) / 32, (rows + 31) / 32, batch);
+    if (esize == 16)
+        hipLaunchKernelGGL(k_transpose<B16>, grid, dim3(256), 0, (hipStream_t)stream, (B16 *)dst,
+                           (const B16 *)src, rows, cols, dst_bs, src_bs);
+    else
+        hipLaunchKernelGGL(k_transpose<uint64_t>, grid, dim3(256), 0, (hipStream_t)stream, (uint64_t *)dst,
+                           (const uint64_t *)src, rows, cols, dst_bs, src_bs);
+    return (int)hipGetLastError();
+}
+
 int launch_reduce_batch(double *dst, const double *src, int64_t N, int batch, void *stream)
 {
     hipLaunchKernelGGL(k_reduce_batch, dim3(grid1d(N)), dim3(256), 0, (hipStream_t)stream, dst, src,

@@ -48,6 +48,10 @@ struct Sched {
     int L3 = 0;
     int cols2 = 1;           // inner columns per workgroup
     Radices rc{};
+    // rank-2 tensor held transposed (n2 x n1): the column pass runs over n2,
+    // the row pass over the contiguous n1 (a run's first and last steps
+    // transpose the state and the potential)
+    bool swapped = false;
 };
 
 // A launch over many states fills the chip with several residency waves of
@@ -190,6 +194,9 @@ int launch_unpermute_c128(void *dst_nat, const void *src, int64_t L, int L1, int
                           void *stream);
 int launch_chirp_filter(void *dst_c128, int64_t N, int64_t L, void *stream);
 int launch_reduce_batch(double *dst, const double *src, int64_t N, int batch, void *stream);
+// dst[b][c][r] = src[b][r][c]: batch rows x cols matrices of 8- or 16-byte elements
+int launch_transpose(int esize, void *dst, const void *src, int batch, int rows, int cols, int64_t dst_bs,
+                     int64_t src_bs, void *stream);
 int launch_ktab(double *dst, int64_t count, double kin, double scale, void *stream);
 int diag_partials();  // blocks per state of launch_sums
 int launch_sums(int prec, const void *x, int64_t x_bs, int64_t count, int batch, const int32_t *w,
@@ -230,10 +237,12 @@ struct lt_plan {
     std::vector<int32_t> h_of_key; // N x d
     int64_t n_index = 0, n_completed = 0, max_s = 0;
     // [0]: the run schedule; [1]: a two-pass schedule (used by the adjoint,
-    // identical to [0] when [0] is already two-pass); inner index lt_prec
-    lt::Sched sched[2][3];
+    // identical to [0] when [0] is already two-pass); [2]: the transposed
+    // schedule of a rank-2 tensor whose columns are long (ok only then; runs
+    // without checkpoints take it); inner index lt_prec
+    lt::Sched sched[3][3];
     std::mutex mu;
-    lt::DevTables dev[2][3];
+    lt::DevTables dev[3][3];
     int device = -1;
 };
 

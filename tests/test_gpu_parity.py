@@ -105,6 +105,57 @@ def test_rank2_resident_and_two_pass(lt):
         assert plan.info["passes"] == (1 if N <= 4096 else 2)
 
 
+@pytest.mark.parametrize("n1,n2,d", [(4096, 256, 6), (2048, 64, 5)])
+def test_rank2_swapped_layout(lt, n1, n2, d):
+    """Rank-2 tensors with long columns (n1 >= 2048, n2 <= n1 / 4) run
+    transposed when no checkpoints are asked for: every kernel variant, shared
+    and per-state potentials, then the untransposed run with checkpoints and an
+    autotuned run, against the oracle."""
+    torch = _torch()
+    H = W.hyperbolic_cross(d, 1)
+    Z = W.cbc_rank2(H, n1, n2, np.random.default_rng(n1 + n2))
+    n = np.array([n1, n2])
+    num = W.point_numerators(Z, n)
+    N = n1 * n2
+    g = np.random.default_rng(17)
+    vs = np.stack([W.cosine_series(d, 8, g).at(num, N) for _ in range(2)])
+    u0 = np.stack([W.seeded_packet(num, N, g) for _ in range(2)])
+    gamma, dt, steps = 0.05, 2e-3, 6
+    plan = lt.lattice_plan(Z, n, H)
+    assert plan.info["swapped"] == 1
+    _, s, _ = O.index_set(Z, n, H)
+    refs = {"shared": O.strang_run(n, s, vs[0], u0, gamma, dt, steps),
+            "per-state": O.strang_run(n, s, vs, u0, gamma, dt, steps)}
+    for cv in (0, 1, 2, 3):
+        for rv in (0, 1, 3):
+            for prec in ("c128", "c64"):
+                p = lt.LT_C128 if prec == "c128" else lt.LT_C64
+                lt.lattice_plan_set_kernels(plan, p, cv, rv)
+                for kind, v in (("shared", vs[0]), ("per-state", vs)):
+                    e = rel(gpu_run(lt, plan, v, u0, gamma, dt, steps, prec), refs[kind])
+                    print(f"  rank-2 {n1}x{n2} col={cv} row={rv} {prec} {kind} rel_l2={e:.2e}", flush=True)
+                    assert e < TOL[prec], (cv, rv, prec, kind, e)
+    # checkpoints: the untransposed schedule, same result
+    every = 4
+    for prec in ("c128", "c64"):
+        dtype = _dtype(prec)
+        u = torch.tensor(u0, dtype=dtype, device="cuda")
+        ck = torch.empty(lt.num_checkpoints(steps, every) * 2 * N, dtype=dtype, device="cuda")
+        lt.strang_run(plan, torch.tensor(vs, device="cuda"), u, gamma, dt, steps, ckpt=ck, ckpt_every=every)
+        torch.cuda.synchronize()
+        e = rel(u.cpu().numpy().astype(np.complex128), refs["per-state"])
+        print(f"  rank-2 {n1}x{n2} with checkpoints {prec} rel_l2={e:.2e}", flush=True)
+        assert e < TOL[prec], (prec, e)
+        ck1 = ck.view(-1, 2, N)[1].cpu().numpy().astype(np.complex128)
+        assert rel(ck1, O.strang_run(n, s, vs, u0, gamma, dt, every)) < TOL[prec]
+    for prec, p in (("c64", lt.LT_C64), ("c128", lt.LT_C128)):
+        lt.lattice_plan_autotune(plan, p, reps=3)
+        e = rel(gpu_run(lt, plan, vs[0], u0, gamma, dt, steps, prec), refs["shared"])
+        print(f"  rank-2 {n1}x{n2} autotuned {lt.lattice_plan_get_kernels_batch(plan, p, 2)} {prec} "
+              f"rel_l2={e:.2e}", flush=True)
+        assert e < TOL[prec], (prec, e)
+
+
 def test_batch_shared_and_per_state_potential(lt):
     check_case(lt, *korobov_case(4096 * 3, 3, 8, 12, batch=3, shared=True))
     check_case(lt, *korobov_case(65521, 3, 9, 6, batch=2, shared=False))

@@ -129,6 +129,22 @@ def test_schedules():
         C.lattice_plan_get_kernels_batch(c1, C.LT_C64, 0)
 
 
+def test_swapped_rank2_schedule():
+    """Rank-2 tensors whose n1-point columns are long run transposed: the
+    plan says so, and a run's workspace holds the transposed state and v."""
+    for n1, n2, swapped in [(2048, 64, 1), (4096, 256, 1), (1024, 64, 0), (2048, 1024, 0), (64, 16, 0)]:
+        H = W.hyperbolic_cross(4, 1)
+        Z = W.cbc_rank2(H, n1, n2, np.random.default_rng(n1 + n2))
+        p = C.lattice_plan(Z, np.array([n1, n2]), H)
+        assert p.info["swapped"] == swapped, (n1, n2)
+        if swapped:
+            N = n1 * n2
+            assert C.strang_workspace_size(p, C.LT_C64, 1, True) >= N * 8 + N * 8
+            assert C.strang_workspace_size(p, C.LT_C128, 3, False) >= 3 * N * 16 + 3 * N * 8
+    p = C.lattice_plan(np.array([[1, 253]]), np.array([1 << 16]))
+    assert p.info["swapped"] == 0
+
+
 def test_plan_poor_lattice_fails_within_budget():
     """z = (1, ..., 1): keys are coordinate sums, so minimal-l2 representatives
     of far keys lie far out; the planner stops at its enumeration budget with
