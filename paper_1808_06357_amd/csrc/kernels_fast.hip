@@ -918,6 +918,8 @@ bool fast_col_fits(int prec, int variant, int L1, int L2, int C)
 bool fast_row_fits(int prec, int variant, int L1, int L2, int rows)
 {
     (void)prec;
+    // rows of kWideRow points: one per workgroup, the 512-thread kernel (variants 1 and 2)
+    if (L2 == kWideRow) return rows == 1 && (variant == 1 || variant == 2);
     if (variant == 3) return fast_len(L2) && L2 <= kSmallTile && L1 % (kSmallTile / L2) == 0;
     return (variant == 1 || variant == 2) && fast_len(L2) && rows == kTile / L2 && L1 % rows == 0;
 }
