@@ -949,16 +949,23 @@ __global__ void __launch_bounds__(256) k_transpose(E *dst, const E *src, int row
 int launch_transpose(int esize, void *dst, const void *src, int batch, int rows, int cols, int64_t dst_bs,
                      int64_t src_bs, void *stream)
 {
-    if (batch < 1 || batch > 65535 || rows < 1 || cols < 1 || (esize != 8 && esize != 16))
-        return (int)hipErrorInvalidValue;
-    const dim3 grid((cols + 31) / 32, (rows + 31) / 32, batch);
-    if (esize == 16)
-        hipLaunchKernelGGL(k_transpose<B16>, grid, dim3(256), 0, (hipStream_t)stream, (B16 *)dst,
-                           (const B16 *)src, rows, cols, dst_bs, src_bs);
-    else
-        hipLaunchKernelGGL(k_transpose<uint64_t>, grid, dim3(256), 0, (hipStream_t)stream, (uint64_t *)dst,
-                           (const uint64_t *)src, rows, cols, dst_bs, src_bs);
-    return (int)hipGetLastError();
+    if (batch < 1 || rows < 1 || cols < 1 || (esize != 8 && esize != 16)) return (int)hipErrorInvalidValue;
+    // the batch runs along the grid's z, in chunks of at most 65535
+    for (int b0 = 0; b0 < batch; b0 += 65535) {
+        const dim3 grid((cols + 31) / 32, (rows + 31) / 32, std::min(65535, batch - b0));
+        const size_t d0 = (size_t)b0 * dst_bs * esize, s0 = (size_t)b0 * src_bs * esize;
+        if (esize == 16)
+            hipLaunchKernelGGL(k_transpose<B16>, grid, dim3(256), 0, (hipStream_t)stream,
+                               (B16 *)((char *)dst + d0), (const B16 *)((const char *)src + s0), rows, cols,
+                               dst_bs, src_bs);
+        else
+            hipLaunchKernelGGL(k_transpose<uint64_t>, grid, dim3(256), 0, (hipStream_t)stream,
+                               (uint64_t *)((char *)dst + d0), (const uint64_t *)((const char *)src + s0), rows,
+                               cols, dst_bs, src_bs);
+        const int e = (int)hipGetLastError();
+        if (e) return e;
+    }
+    return 0;
 }
 
 int launch_reduce_batch(double *dst, const double *src, int64_t N, int batch, void *stream)
