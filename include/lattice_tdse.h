@@ -157,6 +157,11 @@ lt_status strang_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, i
  *          (then the call allocates and frees it stream-ordered).
  * Successive half potential steps are merged into one full step, which
  * equals the literal scheme within rounding.
+ * A rank-2 plan with lattice_plan_info.swapped = 1 runs a call without
+ * checkpoints on the transposed tensor: u and v are transposed into the
+ * workspace, stepped there and u is transposed back (the caller's buffers
+ * stay in kappa order; the result equals the untransposed run within
+ * rounding).
  * With `work` given, and once an earlier call on the plan and precision has
  * built the plan's device tables, the call enqueues kernel launches (and,
  * with checkpoints, one device-to-device copy) on `stream` and nothing else:
