@@ -138,7 +138,7 @@ def bench_batched(lt, torch, K, W):
 
     import workloads as W_
     t = time.perf_counter()
-    insts = W_.config2()
+    insts = W_.mixed_batch()
     plans = [lt.lattice_plan(c.Z, c.n, c.I) for c in insts]
     log(f"batched: inputs and {len(plans)} plans in {time.perf_counter() - t:.1f}s")
     dev = torch.device("cuda:0")
@@ -170,7 +170,7 @@ def bench_batched(lt, torch, K, W):
     res["single_c128"] = {"value": pt_steps / sec, "ms_per_call": sec * 1e3}
     log(f"single-state c128: {pt_steps / sec:.3e} pt-steps/s, {sec * 1e3:.1f} ms")
     # accuracy of the batched complex64 result against stored FP64 oracle samples
-    gold_path = os.path.join(ROOT, "tests", "golden", "config2_oracle_samples.npz")
+    gold_path = os.path.join(ROOT, "tests", "golden", "mixed_batch_oracle_samples.npz")
     acc = None
     if os.path.exists(gold_path):
         gold = np.load(gold_path)
@@ -198,7 +198,7 @@ def bench_batched(lt, torch, K, W):
 def bench_rank2(lt, torch, K, W):
     """d = 10 rank-2 lattice n = (4096, 256), 500 steps."""
     import workloads as W_
-    c = W_.config3()
+    c = W_.rank2_d10_n4096x256()
     plan = lt.lattice_plan(c.Z, c.n, c.I)
     dev = torch.device("cuda:0")
     v = torch.tensor(c.v, dtype=torch.float64, device=dev)
@@ -222,7 +222,7 @@ def bench_adjoint(lt, torch, K, W):
     """Forward run with checkpoints every 50 steps plus strang_adjoint: d = 4,
     N = 65521, 32 states sharing v, 500 steps."""
     import workloads as W_
-    c = W_.config4()
+    c = W_.adjoint_d4_n65521()
     plan = lt.lattice_plan(c.Z, c.n, c.I)
     dev = torch.device("cuda:0")
     v = torch.tensor(c.v, dtype=torch.float64, device=dev)
@@ -383,7 +383,7 @@ def bench_hbm(lt, torch, K, W):
     import numpy as np
 
     import workloads as W_
-    inst = W_.config1(steps=1)
+    inst = W_.cross_d6_n1048573(steps=1)
     plan = lt.lattice_plan(inst.Z, inst.n, inst.I)
     info = plan.info
     dev = torch.device("cuda:0")
@@ -463,7 +463,7 @@ def bench_splitting(lt, torch, K, W):
     import numpy as np
 
     import workloads as W_
-    inst = W_.config1(steps=1)
+    inst = W_.cross_d6_n1048573(steps=1)
     plan = lt.lattice_plan(inst.Z, inst.n, inst.I)
     dev = torch.device("cuda:0")
     N, m, dt = inst.N, 300, 1e-3
@@ -554,7 +554,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(a single lattice state does not shard; see DESIGN.md)", file=sys.stderr)
+              "(a single lattice state does not shard)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -572,7 +572,7 @@ def main():
         return
 
     t = time.perf_counter()
-    inst = W.config1(steps=args.time_steps)
+    inst = W.cross_d6_n1048573(steps=args.time_steps)
     log(f"inputs {time.perf_counter() - t:.1f}s")
     t = time.perf_counter()
     plan = lt.lattice_plan(inst.Z, inst.n, inst.I)

@@ -1,9 +1,9 @@
-"""Write tests/golden/config4_oracle_grad.npz: the FP64 oracle's gradients for
+"""Write tests/golden/adjoint_d4_n65521_oracle_grad.npz: the FP64 oracle's gradients for
 the differentiation workload (d = 4, N = 65521, 32 states sharing a 64-term
 cosine potential v, gamma = 0.05, dt = 2e-3, 500 steps).  The target of state
 b is the oracle's run of u0_b under a hidden 64-term potential; the loss is
 J = sum_b (1/N) sum_{k in S} |u_b(T)_k - target_b,k|^2 over a seeded sample S
-of 2048 points (workloads.config4_loss_points).  Stored: S, the targets on S,
+of 2048 points (workloads.adjoint_d4_n65521_loss_points).  Stored: S, the targets on S,
 J, dJ/da for the 64 coefficients of v (a_t multiplies cos(2 pi h_t . x)),
 dJ/dv at 1024 seeded points, dJ/du0 and u(T) at 128 seeded points per state.
 Calls only oracle/ and workloads/.  Runtime: about 15 minutes on 8 cores."""
@@ -23,9 +23,9 @@ _C = {}
 
 
 def setup():
-    c = W.config4()
+    c = W.adjoint_d4_n65521()
     _, s, _ = O.index_set(c.Z, c.n, c.I)
-    _C.update(c=c, s=s, S=W.config4_loss_points(c.N))
+    _C.update(c=c, s=s, S=W.adjoint_d4_n65521_loss_points(c.N))
 
 
 def state(b):
@@ -55,7 +55,7 @@ def main():
     gv = np.sum([r[5] for r in res], axis=0)
     basis = c.meta["series"].basis(c.meta["num"], N)
     np.savez_compressed(
-        os.path.join(os.path.dirname(os.path.abspath(__file__)), "config4_oracle_grad.npz"),
+        os.path.join(os.path.dirname(os.path.abspath(__file__)), "adjoint_d4_n65521_oracle_grad.npz"),
         S=_C["S"], target_S=np.stack([r[1] for r in res]), J=sum(r[3] for r in res),
         dJ_da=basis @ gv, idx_v=idx_v, dJ_dv=gv[idx_v], idx_u=idx_u,
         dJ_du0=np.stack([r[4][idx_u] for r in res]), uT=np.stack([r[2][idx_u] for r in res]))

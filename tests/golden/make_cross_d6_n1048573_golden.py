@@ -1,4 +1,4 @@
-"""Write tests/golden/config1_oracle_samples.npz: the FP64 oracle's state for
+"""Write tests/golden/cross_d6_n1048573_oracle_samples.npz: the FP64 oracle's state for
 the benchmark workload (d = 6, N = 1048573, hyperbolic cross R = 10 completed
 with minimal-l2 representatives, gamma = 0.05, dt = 1e-3) after 100 and 1000
 Strang steps, at 8192 seeded sample points plus the first 64 points, with
@@ -17,7 +17,7 @@ import workloads as W  # noqa: E402
 
 
 def main():
-    c = W.config1(steps=1000)
+    c = W.cross_d6_n1048573(steps=1000)
     _, s, _ = O.index_set(c.Z, c.n, c.I)
     g = np.random.default_rng(20181808)
     idx = np.unique(np.concatenate([np.arange(64), g.choice(c.N, 8192, replace=False)]))
@@ -36,7 +36,7 @@ def main():
     nn0, E0 = O.diagnostics(c.n, s, c.v, c.u0, c.gamma)
     out["norm2_0"], out["energy_0"] = nn0, E0
     np.savez_compressed(os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                     "config1_oracle_samples.npz"), **out)
+                                     "cross_d6_n1048573_oracle_samples.npz"), **out)
 
 
 if __name__ == "__main__":

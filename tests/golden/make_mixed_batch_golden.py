@@ -1,4 +1,4 @@
-"""Write tests/golden/config2_oracle_samples.npz: the FP64 oracle's state
+"""Write tests/golden/mixed_batch_oracle_samples.npz: the FP64 oracle's state
 after 200 Strang steps for six instances of the batched workload (256
 problems, d in 2..10, N between 2^12 and 2^18, best-of-8 Korobov lattices
 with minimal-l2 full index sets, 16-term cosine potentials, gamma in
@@ -33,8 +33,8 @@ def pick(shapes):
 
 
 def run(i):
-    shapes = W.config2_shapes()
-    insts = W.config2(shapes=shapes[: i + 1])  # the generators draw in order: build the prefix
+    shapes = W.mixed_batch_shapes()
+    insts = W.mixed_batch(shapes=shapes[: i + 1])  # the generators draw in order: build the prefix
     c = insts[i]
     t = time.time()
     _, s, _ = O.index_set(c.Z, c.n, c.I)
@@ -47,7 +47,7 @@ def run(i):
 
 
 def main():
-    sel = pick(W.config2_shapes())
+    sel = pick(W.mixed_batch_shapes())
     with Pool(len(sel)) as pool:
         res = pool.map(run, sel)
     out = {"instances": np.array(sel), "steps": STEPS}
@@ -56,7 +56,7 @@ def main():
         out[f"u_{i}"] = ui
         out[f"norm2_{i}"] = nn
     np.savez_compressed(os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                     "config2_oracle_samples.npz"), **out)
+                                     "mixed_batch_oracle_samples.npz"), **out)
 
 
 if __name__ == "__main__":

@@ -1,4 +1,4 @@
-"""Write tests/golden/config3_oracle_samples.npz: the FP64 oracle's state for
+"""Write tests/golden/rank2_d10_n4096x256_oracle_samples.npz: the FP64 oracle's state for
 the rank-2 workload (d = 10, n = (4096, 256), cross {-1,0,1}^10 completed with
 minimal-l2 representatives, gamma = 0.05, 32-term cosine potential,
 dt = 2e-3) after 100 and 500 Strang steps, at 4096 seeded sample points plus
@@ -17,7 +17,7 @@ import workloads as W  # noqa: E402
 
 
 def main():
-    c = W.config3()
+    c = W.rank2_d10_n4096x256()
     t = time.time()
     _, s, _ = O.index_set(c.Z, c.n, c.I)
     print(f"index set {time.time() - t:.0f}s", flush=True)
@@ -34,7 +34,7 @@ def main():
         out[f"norm2_{mark}"] = float(np.mean(np.abs(u) ** 2))
         print(f"step {mark}: {time.time() - t:.0f}s norm2={out[f'norm2_{mark}']:.15f}", flush=True)
     np.savez_compressed(os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                     "config3_oracle_samples.npz"), **out)
+                                     "rank2_d10_n4096x256_oracle_samples.npz"), **out)
 
 
 if __name__ == "__main__":

@@ -98,24 +98,24 @@ def test_dot_product_identity(lt):
 
 
 # ---------------------------------------------------------------- full-size differentiation workload
-GOLD4 = os.path.join(os.path.dirname(__file__), "golden", "config4_oracle_grad.npz")
+GOLD4 = os.path.join(os.path.dirname(__file__), "golden", "adjoint_d4_n65521_oracle_grad.npz")
 
 
 @pytest.fixture(scope="module")
 def case4(lt):
     import torch
     gold = np.load(GOLD4)
-    c = W.config4()
+    c = W.adjoint_d4_n65521()
     plan = lt.lattice_plan(c.Z, c.n, c.I)
     # the kernels the benchmark times: autotuned (the 32-state runs take the
     # many-state choice)
     for p in (lt.LT_C64, lt.LT_C128):
         lt.lattice_plan_autotune(plan, p, reps=3)
-        print(f"config4 kernels {p}: one state {lt.lattice_plan_get_kernels_batch(plan, p, 1)}, "
+        print(f"adjoint_d4_n65521 kernels {p}: one state {lt.lattice_plan_get_kernels_batch(plan, p, 1)}, "
               f"32 states {lt.lattice_plan_get_kernels_batch(plan, p, 32)}", flush=True)
     basis = torch.tensor(c.meta["series"].basis(c.meta["num"], c.N), dtype=torch.float64, device="cuda")
     S = torch.tensor(gold["S"], device="cuda")
-    assert np.array_equal(gold["S"], W.config4_loss_points(c.N))
+    assert np.array_equal(gold["S"], W.adjoint_d4_n65521_loss_points(c.N))
     return c, plan, basis, S, gold
 
 
@@ -139,7 +139,7 @@ def loss_and_grads(lt, c, plan, v, S, target, dtype, grads=True):
 
 
 @pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 1e-4)])
-def test_config4_gradients_against_oracle(lt, case4, prec, tol):
+def test_adjoint_d4_n65521_gradients_against_oracle(lt, case4, prec, tol):
     """d = 4, N = 65521, 32 states, 500 steps, checkpoints every 50: the loss,
     u(T), dJ/da (64 coefficients), dJ/dv and dJ/du0 against the FP64 oracle's
     adjoint (stored samples)."""
@@ -156,12 +156,12 @@ def test_config4_gradients_against_oracle(lt, case4, prec, tol):
             "dJ/da": rel(dJda, gold["dJ_da"]),
             "dJ/dv": rel(gv.cpu().numpy()[iv], gold["dJ_dv"]),
             "dJ/du0": rel(g0.cpu().numpy()[:, iu], gold["dJ_du0"])}
-    print(f"config4 {prec}: " + ", ".join(f"{k} {e:.2e}" for k, e in errs.items()), flush=True)
+    print(f"adjoint_d4_n65521 {prec}: " + ", ".join(f"{k} {e:.2e}" for k, e in errs.items()), flush=True)
     for k, e in errs.items():
         assert e < tol, (k, e)
 
 
-def test_config4_central_differences_c128(lt, case4):
+def test_adjoint_d4_n65521_central_differences_c128(lt, case4):
     """dJ/da from the adjoint against central differences, h = 1e-6, every one
     of the 64 coefficients, on the complex128 path."""
     import torch
@@ -179,5 +179,5 @@ def test_config4_central_differences_c128(lt, case4):
         jm, _ = loss_and_grads(lt, c, plan, ((a - e) @ basis).contiguous(), S, target, torch.complex128, False)
         fd[t] = (jp - jm) / (2 * h)
     e = rel(fd, adj)
-    print(f"config4 central differences vs adjoint: rel {e:.2e} (|dJ/da| = {np.linalg.norm(adj):.3e})", flush=True)
+    print(f"adjoint_d4_n65521 central differences vs adjoint: rel {e:.2e} (|dJ/da| = {np.linalg.norm(adj):.3e})", flush=True)
     assert e < 1e-6

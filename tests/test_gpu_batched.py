@@ -12,7 +12,7 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL = {"c128": 1e-11, "c64": 1e-4}
-GOLD = os.path.join(os.path.dirname(__file__), "golden", "config2_oracle_samples.npz")
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "mixed_batch_oracle_samples.npz")
 
 
 def rel(a, b):
@@ -129,19 +129,19 @@ def test_batched_argument_errors(lt, mixed):
 
 
 @pytest.fixture(scope="module")
-def config2(lt):
+def mixed_batch(lt):
     gold = np.load(GOLD)
-    insts = W.config2()
+    insts = W.mixed_batch()
     plans = [lt.lattice_plan(c.Z, c.n, c.I) for c in insts]
     return insts, plans, gold
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
-def test_config2_full_batch(lt, config2, prec):
+def test_mixed_batch_full_batch(lt, mixed_batch, prec):
     """All 256 problems, 200 steps, in the launch configuration the benchmark
     times: the oracle's states at stored sample points of six problems, and the
     norm of every problem (the scheme is unitary)."""
-    insts, plans, gold = config2
+    insts, plans, gold = mixed_batch
     probs = [dict(u0=c.u0, v=c.v, gamma=c.gamma, dt=c.dt, steps=c.steps) for c in insts]
     got = run_batched(lt, plans, probs, prec)
     worst = 0.0
@@ -156,10 +156,10 @@ def test_config2_full_batch(lt, config2, prec):
         assert abs(np.mean(np.abs(g) ** 2) - n0) < 2 * TOL[prec] * n0, i
 
 
-def test_config2_reversible_c128(lt, config2):
+def test_mixed_batch_reversible_c128(lt, mixed_batch):
     """200 steps with dt, then 200 with -dt, batched: every problem returns to u0."""
     import torch
-    insts, plans, _ = config2
+    insts, plans, _ = mixed_batch
     us = [torch.tensor(c.u0, dtype=torch.complex128, device="cuda") for c in insts]
     vs = [torch.tensor(c.v, dtype=torch.float64, device="cuda") for c in insts]
     g = [c.gamma for c in insts]

@@ -1,7 +1,7 @@
 """Full-size parity for the benchmark workload (d = 6, N = 1048573, 1000
 steps) in the launch configuration bench.py times: the GPU state is compared
 with the FP64 oracle at stored sample points (tests/golden/, written by
-make_config1_golden.py, which calls only the oracle) and checked against
+make_cross_d6_n1048573_golden.py, which calls only the oracle) and checked against
 properties that hold at any size (norm, reversibility)."""
 import os
 
@@ -12,7 +12,7 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-GOLD = os.path.join(os.path.dirname(__file__), "golden", "config1_oracle_samples.npz")
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "cross_d6_n1048573_oracle_samples.npz")
 
 
 def rel(a, b):
@@ -23,7 +23,7 @@ def rel(a, b):
 def case(lt):
     import torch
     gold = np.load(GOLD)
-    inst = W.config1(steps=1000)
+    inst = W.cross_d6_n1048573(steps=1000)
     assert np.array_equal(inst.Z[0], gold["z"]), "seeded CBC search changed"
     plan = lt.lattice_plan(inst.Z, inst.n, inst.I)
     v = torch.tensor(inst.v, dtype=torch.float64, device="cuda")
@@ -31,7 +31,7 @@ def case(lt):
 
 
 @pytest.mark.parametrize("prec,tol", [("c128", 1e-11), ("c64", 1e-4)])
-def test_config1_against_oracle_samples(lt, case, prec, tol):
+def test_cross_d6_n1048573_against_oracle_samples(lt, case, prec, tol):
     import torch
     inst, plan, v, gold = case
     dtype = torch.complex128 if prec == "c128" else torch.complex64
@@ -53,7 +53,7 @@ def test_config1_against_oracle_samples(lt, case, prec, tol):
     assert abs(n1000 - float(gold["norm2_1000"])) < 2.0 * tol
 
 
-def test_config1_reversible_c128(lt, case):
+def test_cross_d6_n1048573_reversible_c128(lt, case):
     """1000 steps forward, then 1000 with -dt: back to u0 (symmetric scheme)."""
     import torch
     inst, plan, v, _ = case
@@ -63,14 +63,14 @@ def test_config1_reversible_c128(lt, case):
     assert rel(u.cpu().numpy(), inst.u0) < 1e-11
 
 
-GOLD3 = os.path.join(os.path.dirname(__file__), "golden", "config3_oracle_samples.npz")
+GOLD3 = os.path.join(os.path.dirname(__file__), "golden", "rank2_d10_n4096x256_oracle_samples.npz")
 
 
 @pytest.fixture(scope="module")
 def case3(lt):
     import torch
     gold = np.load(GOLD3)
-    inst = W.config3()
+    inst = W.rank2_d10_n4096x256()
     assert np.array_equal(inst.Z, gold["Z"]), "seeded rank-2 CBC search changed"
     plan = lt.lattice_plan(inst.Z, inst.n, inst.I)
     v = torch.tensor(inst.v, dtype=torch.float64, device="cuda")
@@ -78,7 +78,7 @@ def case3(lt):
 
 
 @pytest.mark.parametrize("prec,tol", [("c128", 1e-11), ("c64", 1e-4)])
-def test_config3_rank2_against_oracle_samples(lt, case3, prec, tol):
+def test_rank2_d10_n4096x256_rank2_against_oracle_samples(lt, case3, prec, tol):
     """Rank-2 lattice n = (4096, 256), d = 10, 500 steps, autotuned kernels."""
     import torch
     inst, plan, v, gold = case3
@@ -99,7 +99,7 @@ def test_config3_rank2_against_oracle_samples(lt, case3, prec, tol):
     assert abs(n500 - float(gold["norm2_500"])) < 2.0 * tol
 
 
-def test_config3_reversible_c128(lt, case3):
+def test_rank2_d10_n4096x256_reversible_c128(lt, case3):
     import torch
     inst, plan, v, _ = case3
     u = torch.tensor(inst.u0, dtype=torch.complex128, device="cuda")

@@ -64,8 +64,8 @@ def check_case(lt, Z, n, v, u0, gamma, dt, steps, precs=("c128", "c64"), I=None,
     return plan
 
 
-def test_config0_resident(lt):
-    c = W.config0()
+def test_box_d2_n1031_resident(lt):
+    c = W.box_d2_n1031()
     check_case(lt, c.Z, c.n, c.v, c.u0, c.gamma, c.dt, c.steps, I=c.I)
 
 

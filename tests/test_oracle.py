@@ -68,11 +68,11 @@ def test_fig1_example_full_minimal_set():
         assert tuple(h[chi]) == best[chi][1]
 
 
-def test_config0_box_keys_and_completion():
+def test_box_d2_n1031_box_keys_and_completion():
     """Def. 2 on the box {-15..16}^2 with z = (1, 32), N = 1031: injective
     (1024 keys), the seven unowned keys are completed with their minimal-l2
     representatives (brute force)."""
-    c = W.config0()
+    c = W.box_d2_n1031()
     k = O.keys(c.Z, c.n, c.I)
     assert np.unique(k).size == 1024
     h, s, fromI = O.index_set(c.Z, c.n, c.I)
@@ -125,7 +125,7 @@ def test_character_property():
 
 
 def test_points_match_workload_numerators():
-    c = W.config0()
+    c = W.box_d2_n1031()
     x = O.points(c.Z, c.n)
     num = W.point_numerators(c.Z, c.n)
     assert np.array_equal(x, num / c.N)
@@ -187,9 +187,9 @@ def _plane_waves(Z, n, hs, coeffs):
     return sum(c * np.exp(2j * PI * (x @ h)) for h, c in zip(hs, coeffs)), x
 
 
-def test_unitarity_config0():
+def test_unitarity_box_d2_n1031():
     """||S||_2 = 1 (proof of Thm. 3; Sec. 3.3): the norm is conserved to rounding."""
-    c = W.config0()
+    c = W.box_d2_n1031()
     _, s, _ = O.index_set(c.Z, c.n, c.I)
     u, hist = O.strang_run(c.n, s, c.v, c.u0, c.gamma, c.dt, c.steps, history=True)
     n0 = np.mean(np.abs(c.u0) ** 2)
@@ -200,7 +200,7 @@ def test_unitarity_config0():
 def test_free_evolution_closed_form():
     """v = 0: every mode evolves by exp(-i 2 pi^2 gamma ||h||^2 t) (eq. (Fourier-ODE)
     with f = 0; the exact propagator of Sec. 2.4 with W = 0)."""
-    c = W.config0()
+    c = W.box_d2_n1031()
     h, s, _ = O.index_set(c.Z, c.n, c.I)
     g = np.random.default_rng(0)
     keys = g.choice(c.N, 12, replace=False)
@@ -216,7 +216,7 @@ def test_free_evolution_closed_form():
 
 def test_constant_potential_global_phase():
     """v = v0 commutes with the Laplacian: an extra phase exp(-i v0 t / gamma)."""
-    c = W.config0()
+    c = W.box_d2_n1031()
     h, s, _ = O.index_set(c.Z, c.n, c.I)
     g = np.random.default_rng(1)
     keys = g.choice(c.N, 8, replace=False)
@@ -419,10 +419,10 @@ def test_projection_error_gaussian_against_direct_integral():
     assert abs(e2 - direct) < 1e-12 * max(1.0, norm2), (e2, direct)
 
 
-def test_config0_second_order_paper_protocol():
+def test_box_d2_n1031_second_order_paper_protocol():
     """Sec. 3.2 protocol: reference at dt = 1e-4, errors at larger dt, T fixed,
     observed order 2 (here T = 0.2 so the reference stays cheap)."""
-    c = W.config0()
+    c = W.box_d2_n1031()
     _, s, _ = O.index_set(c.Z, c.n, c.I)
     T = 0.2
     ref = O.strang_run(c.n, s, c.v, c.u0, c.gamma, 1e-4, int(round(T / 1e-4)))
@@ -482,7 +482,7 @@ def test_rank2_regular_grid_equals_tensor_solver():
 
 def test_reversibility():
     """The Strang scheme is symmetric (Sec. 2.3): S(-dt) S(dt) = I."""
-    c = W.config0()
+    c = W.box_d2_n1031()
     _, s, _ = O.index_set(c.Z, c.n, c.I)
     u = O.strang_run(c.n, s, c.v, c.u0, c.gamma, c.dt, 40)
     back = O.strang_run(c.n, s, c.v, u, c.gamma, -c.dt, 40)
@@ -492,7 +492,7 @@ def test_reversibility():
 def test_diagnostics_single_mode():
     """Sec. 3.3: for u = exp(2 pi i h.x) (h in A), ||u||^2 = 1 and
     <Hu, u> = 2 pi^2 gamma ||h||^2 + mean(v)/gamma."""
-    c = W.config0()
+    c = W.box_d2_n1031()
     h, s, _ = O.index_set(c.Z, c.n, c.I)
     hv = h[123].astype(np.int64)
     x = O.points(c.Z, c.n)

@@ -30,9 +30,9 @@ def _planner_matches_oracle(Z, n, I=None):
     return p
 
 
-def test_planner_fig1_and_config0_bitexact():
+def test_planner_fig1_and_box_d2_n1031_bitexact():
     _planner_matches_oracle(np.array([[1, 34]]), np.array([55]))
-    c = W.config0()
+    c = W.box_d2_n1031()
     p = _planner_matches_oracle(c.Z, c.n, c.I)
     assert p.N == 1031
 
@@ -43,17 +43,17 @@ def test_planner_rank2_bitexact():
     _planner_matches_oracle(Z, np.array([64, 16]), W.hyperbolic_cross(4, 2))
 
 
-def test_planner_config4_lattice_bitexact():
+def test_planner_adjoint_d4_n65521_lattice_bitexact():
     """d = 4, N = 65521, Korobov z, full minimal-l2 set (no user set)."""
     z = W.korobov(65521, 4, W.rng(4, "z"))
     _planner_matches_oracle(z.reshape(1, -1), np.array([65521]))
 
 
 @pytest.mark.slow
-def test_planner_config1_lattice_bitexact():
+def test_planner_cross_d6_n1048573_lattice_bitexact():
     """The benchmark lattice: d = 6, N = 1048573, hyperbolic cross R = 10
     completed with minimal-l2 representatives (bin map bit-exact)."""
-    c1 = W.config1(steps=1)
+    c1 = W.cross_d6_n1048573(steps=1)
     _planner_matches_oracle(c1.Z, c1.n, c1.I)
 
 
@@ -101,7 +101,7 @@ def test_run_argument_errors_before_any_gpu_call():
 
 def test_schedules():
     """Transform layouts: chirp-z for prime N, two passes for long transforms."""
-    c = W.config0()
+    c = W.box_d2_n1031()
     p = C.lattice_plan(c.Z, c.n, c.I)
     assert p.info["bluestein"] == 1 and p.info["passes"] == 1 and p.info["fft_len"] >= 2 * 1031 - 1
     p = C.lattice_plan(np.array([[1, 253]]), np.array([1 << 16]))
@@ -173,14 +173,14 @@ def test_batched_argument_errors_on_host():
 
 
 @pytest.mark.slow
-def test_config2_lattices_bitexact_on_golden_instances():
+def test_mixed_batch_lattices_bitexact_on_golden_instances():
     """Planner bin maps of the batched workload's sampled problems (best-of-8
     Korobov lattices, minimal-l2 full sets) equal the oracle's."""
     import os
-    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "config2_oracle_samples.npz"))
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "mixed_batch_oracle_samples.npz"))
     sel = [int(i) for i in gold["instances"]]
-    shapes = W.config2_shapes()
-    insts = W.config2(shapes=shapes[: max(sel) + 1])
+    shapes = W.mixed_batch_shapes()
+    insts = W.mixed_batch(shapes=shapes[: max(sel) + 1])
     for i in sel:
         _planner_matches_oracle(insts[i].Z, insts[i].n)
 

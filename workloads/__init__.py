@@ -342,7 +342,7 @@ class Instance:
         return int(self.n.size)
 
 
-def config0() -> Instance:
+def box_d2_n1031() -> Instance:
     """d = 2, N = 1031, z = (1, 32), I = {-15..16}^2, gamma = 0.1,
     v = sum_j (1 - cos 2 pi x_j), Gaussian packet at (1/2, 1/2) with k0 = (2, 0),
     dt = 0.01, 100 steps."""
@@ -352,10 +352,10 @@ def config0() -> Instance:
     I = box(-15, 16, 2)
     v = v_sum_one_minus_cos(num, 1031)
     u0 = gaussian_packet(num, 1031, (0.5, 0.5), (2, 0), 0.1)
-    return Instance(2, Z, n, I, 0.1, 0.01, 100, v, u0, {"name": "config0"})
+    return Instance(2, Z, n, I, 0.1, 0.01, 100, v, u0, {"name": "box_d2_n1031"})
 
 
-def config1(steps: int = 1000) -> Instance:
+def cross_d6_n1048573(steps: int = 1000) -> Instance:
     """d = 6, N = 1048573 (prime), z by seeded reconstructing CBC on the
     hyperbolic cross R = 10 (70,173 frequencies), gamma = 0.05,
     v = prod_j (1 + cos(2 pi x_j)/2) - 1, seeded packet, dt = 1e-3."""
@@ -367,7 +367,7 @@ def config1(steps: int = 1000) -> Instance:
     num = point_numerators(Z, n)
     v = v_product(num, N)
     u0 = seeded_packet(num, N, rng(1, "u0"))
-    return Instance(6, Z, n, H, 0.05, 1e-3, steps, v, u0, {"name": "config1", "R": 10})
+    return Instance(6, Z, n, H, 0.05, 1e-3, steps, v, u0, {"name": "cross_d6_n1048573", "R": 10})
 
 
 def smooth7(x: int) -> int:
@@ -407,7 +407,7 @@ def next_prime(x: int) -> int:
     return x
 
 
-def config2_shapes(count: int = 256):
+def mixed_batch_shapes(count: int = 256):
     """(d_i, N_i) for the batched configuration: d ~ U{2..10}, N log-uniform in
     [2^12, 2^18], primes at even i and 7-smooth composites at odd i."""
     g = rng(2, "shapes")
@@ -420,12 +420,12 @@ def config2_shapes(count: int = 256):
     return out
 
 
-def config2(count: int = 256, steps: int = 200, shapes=None) -> List[Instance]:
+def mixed_batch(count: int = 256, steps: int = 200, shapes=None) -> List[Instance]:
     """Batched complex64: per instance the best of 8 seeded Korobov vectors
     (korobov_good), minimal-l2 full index set,
     16-term cosine potential (|h_j| <= 2, a ~ U(-1/2, 1/2)), gamma ~ U(0.02, 0.2),
     seeded packet, dt = 5e-3, 200 steps."""
-    shapes = shapes if shapes is not None else config2_shapes(count)
+    shapes = shapes if shapes is not None else mixed_batch_shapes(count)
     gz, gv, gu, gs = rng(2, "z"), rng(2, "v"), rng(2, "u0"), rng(2, "hidden_v")
     out = []
     for i, (d, N) in enumerate(shapes):
@@ -436,11 +436,11 @@ def config2(count: int = 256, steps: int = 200, shapes=None) -> List[Instance]:
         v = cosine_series(d, 16, gv).at(num, N)
         u0 = seeded_packet(num, N, gu)
         gamma = float(gs.uniform(0.02, 0.2))
-        out.append(Instance(d, Z, n, None, gamma, 5e-3, steps, v, u0, {"name": f"config2[{i}]"}))
+        out.append(Instance(d, Z, n, None, gamma, 5e-3, steps, v, u0, {"name": f"mixed_batch[{i}]"}))
     return out
 
 
-def config3(steps: int = 500) -> Instance:
+def rank2_d10_n4096x256(steps: int = 500) -> Instance:
     """d = 10, rank-2 lattice n = (4096, 256), odd generating vectors by seeded
     rank-2 CBC on the cross {-1,0,1}^10 (59,049 frequencies), completed to
     2^20 keys; gamma = 0.05, 32-term cosine potential, seeded packet, dt = 2e-3."""
@@ -451,7 +451,7 @@ def config3(steps: int = 500) -> Instance:
     N = 4096 * 256
     v = cosine_series(10, 32, rng(3, "v")).at(num, N)
     u0 = seeded_packet(num, N, rng(3, "u0"))
-    return Instance(10, Z, n, H, 0.05, 2e-3, steps, v, u0, {"name": "config3", "R": 1})
+    return Instance(10, Z, n, H, 0.05, 2e-3, steps, v, u0, {"name": "rank2_d10_n4096x256", "R": 1})
 
 
 # Generating vectors the paper prints for its experiments (Sec. 3.1, Table 1):
@@ -470,14 +470,14 @@ def paper_lattice(d: int, n: int):
     return z.reshape(1, -1), np.array([n], dtype=np.int64)
 
 
-def config4_loss_points(N: int, count: int = 2048) -> np.ndarray:
+def adjoint_d4_n65521_loss_points(N: int, count: int = 2048) -> np.ndarray:
     """Seeded sorted point indices on which the differentiation workload's
     misfit is measured (the loss restricted to a sample keeps its stored
     target small)."""
     return np.sort(rng(4, "shapes").choice(N, size=count, replace=False))
 
 
-def config4(batch: int = 32, steps: int = 500):
+def adjoint_d4_n65521(batch: int = 32, steps: int = 500):
     """d = 4, N = 65521 (prime), Korobov z, minimal-l2 full set, batch of
     seeded packets sharing a 64-term cosine potential; a hidden 64-term
     potential defines the target.  gamma = 0.05, dt = 2e-3, checkpoints every 50."""
@@ -491,6 +491,6 @@ def config4(batch: int = 32, steps: int = 500):
     gu = rng(4, "u0")
     u0 = np.stack([seeded_packet(num, N, gu) for _ in range(batch)])
     inst = Instance(d, Z, n, None, 0.05, 2e-3, steps, series.at(num, N), u0,
-                    {"name": "config4", "ckpt_every": 50, "series": series, "hidden": hidden,
+                    {"name": "adjoint_d4_n65521", "ckpt_every": 50, "series": series, "hidden": hidden,
                      "v_hidden": hidden.at(num, N), "num": num})
     return inst
