@@ -18,8 +18,10 @@ must map injectively to keys).  It plays the role of the paper's external
 construction script (Sec. 3.1); both the oracle and the product planner check
 injectivity of its result independently.
 
-Seeds: config i draws from numpy PCG64(SeedSequence(1808_06357 + i)), spawned
-into the sub-streams [z-search, v, u0, batch-shapes, hidden-v].
+Seeds: each workload has a seed index i (box_d2_n1031 0, cross_d6_n1048573 1,
+mixed_batch 2, rank2_d10_n4096x256 3, adjoint_d4_n65521 4) and draws from numpy
+PCG64(SeedSequence(1808_06357 + i)), spawned into the sub-streams [z-search, v,
+u0, batch-shapes, hidden-v].
 """
 from __future__ import annotations
 
@@ -33,8 +35,8 @@ SEED_BASE = 1808_06357
 _STREAMS = {"z": 0, "v": 1, "u0": 2, "shapes": 3, "hidden_v": 4}
 
 
-def rng(config: int, stream: str) -> np.random.Generator:
-    ss = np.random.SeedSequence(SEED_BASE + config).spawn(len(_STREAMS))[_STREAMS[stream]]
+def rng(seed_index: int, stream: str) -> np.random.Generator:
+    ss = np.random.SeedSequence(SEED_BASE + seed_index).spawn(len(_STREAMS))[_STREAMS[stream]]
     return np.random.Generator(np.random.PCG64(ss))
 
 
