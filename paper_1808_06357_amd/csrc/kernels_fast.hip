@@ -261,7 +261,8 @@ __device__ __forceinline__ void tw4_base_step(cx<double> &b, cx<double> &st, int
 // table the run built; MID 1: the chirp-z
 // kinetic step from the table indexed by the squared norm; MID 2: the merged
 // potential step from v in FP64 (runs without a table); MID 3: the angle of
-// a time-dependent potential from two fields.
+// a time-dependent potential from two fields; MID 7: MID 0 plus the store of
+// the step's checkpoint.
 template <typename T, int E, int NT, int MID, int... Rs>
 __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
 {
@@ -335,7 +336,36 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
     } else if constexpr (MID == 6) {
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = conjg(v[e]);
-    } else if constexpr (MID == 0) {
+    } else if constexpr (MID == 0 || MID == 7) {
+        if constexpr (MID == 7) {
+            // checkpoint of the state at this step boundary: the lattice value
+            // u = x exp(-i ck_phase v) of every valid point, in FP64 like the
+            // general pass, stored before the merged step.  The point values
+            // go through LDS (free between the two transforms) so that one
+            // rolled loop, consecutive lanes on consecutive columns, evaluates
+            // the phases without holding them for every element at once.
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int bf = threadIdx.x + j * NT;
+                const int q = F::q_of(bf), t = F::t_of(bf);
+#pragma unroll
+                for (int r = 0; r < R; ++r) s[F::addr(q, t + r * BPS)] = conjg(v[j * R + r]);
+            }
+            __syncthreads();
+            const double *cv = a.ck_v + b * a.v_bs;
+            cx<T> *ck = (cx<T> *)a.ck + b * a.ck_bs;
+#pragma unroll 1
+            for (int i = threadIdx.x; i < C * L1; i += NT) {
+                const int k1 = i / C, q = i - k1 * C;
+                const int64_t n = (int64_t)k1 * L2 + c0 + q;
+                if (n < a.Nvalid) {
+                    double c, sn;
+                    expm_i(a.ck_phase * cv[n], c, sn);
+                    ck[n] = cmul_d(s[F::addr(q, k1)], c, sn);
+                }
+            }
+        }
         // the merged potential step from the per-point table (16 bytes per
         // point: a hi/lo pair of complex floats, or one complex double), every
         // entry of the thread in flight at once.  The whole byte offset sits
@@ -753,7 +783,10 @@ int col_go(const ColArgs &a, int batch, void *stream)
             return timed(LT_KIND_COLUMN, k, dim3(a.L2 / C, batch), dim3(NT), lds_bytes<T, V>(), stream, a);
         }
     }
-    if (a.v) {
+    if (a.ck) {
+        if (!a.v || a.v2 || !a.ptab) return -1;
+        k = k_colf<T, E, NT, MINW, 7, Rs...>;
+    } else if (a.v) {
         if (a.v2) k = k_colf<T, E, NT, MINW, 3, Rs...>;
         else if (a.ptab) k = k_colf<T, E, NT, MINW, 0, Rs...>;
         else if constexpr (sizeof(T) == 8) k = k_colf<T, E, NT, MINW, 2, Rs...>;
@@ -766,6 +799,8 @@ int col_go(const ColArgs &a, int batch, void *stream)
         hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 1, Rs...>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 3, Rs...>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 7, Rs...>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if constexpr (sizeof(T) == 8)
             hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 2, Rs...>,
@@ -928,9 +963,10 @@ int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *st
 {
     // steady-state passes only: the first / last / checkpoint passes of a run
     // and the adjoint passes take the general kernel
-    const bool steady = a.pre_inv && a.post_fwd && !a.in && !a.out && !a.ck && !a.chirp &&
-                        a.scale == 1.0 && !a.adjoint && ((a.v != nullptr) != (a.ktab != nullptr)) &&
-                        (prec == LT_C128 || !a.v || a.ptab || a.v2);
+    const bool steady = a.pre_inv && a.post_fwd && !a.in && !a.out && !a.chirp && a.scale == 1.0 &&
+                        !a.adjoint && ((a.v != nullptr) != (a.ktab != nullptr)) &&
+                        (prec == LT_C128 || !a.v || a.ptab || a.v2) &&
+                        (!a.ck || (a.ptab && a.v && !a.v2 && !a.ck_chirp && a.ck_v));
     if (!steady || !fast_col_fits(prec, variant, a.L1, a.L2, a.C)) return -1;
     if (variant == 3 && a.L1 == 4096)
         return prec == LT_C128 ? go<double, 3, true>(a.L1, a, batch, stream) : go<float, 3, true>(a.L1, a, batch, stream);
