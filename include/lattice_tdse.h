@@ -84,10 +84,10 @@ typedef struct {
     int32_t rows;            /* rows per row-pass workgroup                           */
     int32_t L3;              /* three levels: row length (L = L1*L2*L3); else 0       */
     int32_t swapped;         /* 1: a rank-2 tensor n1 x n2 whose n1-point columns are
-                                long (n1 >= 2048, n2 <= n1/4): strang_run calls without
-                                checkpoints transpose the state and v into the
-                                workspace and run on n2-point columns and n1-point
-                                rows (L1, L2 above describe the untransposed layout) */
+                                long (n1 >= 2048, n2 <= n1/4): strang_run transposes
+                                the state and v into the workspace and runs on
+                                n2-point columns and n1-point rows (L1, L2 above
+                                describe the untransposed layout) */
 } lt_plan_info;
 
 /*
@@ -157,11 +157,11 @@ lt_status strang_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, i
  *          (then the call allocates and frees it stream-ordered).
  * Successive half potential steps are merged into one full step, which
  * equals the literal scheme within rounding.
- * A rank-2 plan with lattice_plan_info.swapped = 1 runs a call without
- * checkpoints on the transposed tensor: u and v are transposed into the
- * workspace, stepped there and u is transposed back (the caller's buffers
- * stay in kappa order; the result equals the untransposed run within
- * rounding).
+ * A rank-2 plan with lattice_plan_info.swapped = 1 runs on the transposed
+ * tensor: u and v are transposed into the workspace, stepped there and u is
+ * transposed back; checkpoints are stored in kappa order (the caller's
+ * buffers stay in kappa order; the result equals the untransposed run
+ * within rounding).
  * With `work` given, and once an earlier call on the plan and precision has
  * built the plan's device tables, the call enqueues kernel launches (and,
  * with checkpoints, one device-to-device copy) on `stream` and nothing else:

@@ -465,7 +465,7 @@ bool conv_available(const lt_plan &p, int which, const Sched &s)
 lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int prec, int batch,
                            const double *v, int64_t v_stride, void *u, double gamma, double dt,
                            int64_t steps, void *ckpt, int64_t ck_every, const double *ktab, void *W,
-                           void *ptab, const void *conv, hipStream_t st)
+                           void *ptab, const void *conv, hipStream_t st, bool ck_transposed = false)
 {
     const int64_t N = p.N;
     const size_t S = esz(prec);
@@ -498,6 +498,7 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
             m.ck_v = v;
             m.ck_phase = half;
             m.ck_chirp = chirpz ? 1 : 0;
+            m.ck_t = ck_transposed ? 1 : 0;
         }
         HIP_TRY(launch_col(prec, s, m, batch, st), "column pass (potential)");
     }
@@ -754,11 +755,13 @@ SwapWork swap_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool
     return w;
 }
 
-// A run without checkpoints of a rank-2 tensor on its swapped schedule: the
-// state and the potential are transposed into the workspace (n2 x n1), the
-// steps run there, and the state is transposed back.
+// A run of a rank-2 tensor on its swapped schedule: the state and the
+// potential are transposed into the workspace (n2 x n1), the steps run there
+// (checkpoints are stored in lattice order by the checkpoint passes), and the
+// state is transposed back.
 lt_status swapped_forward(lt_plan &p, int prec, int batch, const double *v, int64_t v_stride, void *u,
-                          double gamma, double dt, int64_t steps, void *work, size_t work_bytes, void *stream)
+                          double gamma, double dt, int64_t steps, void *ckpt, int64_t ckpt_every, void *work,
+                          size_t work_bytes, void *stream)
 {
     hipStream_t hs = (hipStream_t)stream;
     lt_status st;
@@ -774,11 +777,15 @@ lt_status swapped_forward(lt_plan &p, int prec, int batch, const double *v, int6
     const int n1 = s.L2, n2 = s.L1;
     void *U = at(sc.ptr, L.u);
     double *V = (double *)at(sc.ptr, L.v);
+    if (ckpt)
+        HIP_TRY(hipMemcpyAsync(ckpt, u, (size_t)batch * p.N * esz(prec), hipMemcpyDeviceToDevice, hs),
+                "checkpoint 0");
     HIP_TRY(launch_transpose((int)esz(prec), U, u, batch, n1, n2, p.N, p.N, hs), "state transpose");
     HIP_TRY(launch_transpose(8, V, v, shared ? 1 : batch, n1, n2, p.N, shared ? p.N : v_stride, hs),
             "potential transpose");
-    if ((st = two_pass_forward(p, s, D, prec, batch, V, shared ? 0 : p.N, U, gamma, dt, steps, nullptr, 0, ktab,
-                               at(sc.ptr, L.run.w), at(sc.ptr, L.run.ptab), nullptr, hs)))
+    if ((st = two_pass_forward(p, s, D, prec, batch, V, shared ? 0 : p.N, U, gamma, dt, steps, ckpt,
+                               ckpt ? ckpt_every : 0, ktab, at(sc.ptr, L.run.w), at(sc.ptr, L.run.ptab), nullptr,
+                               hs, true)))
         return st;
     HIP_TRY(launch_transpose((int)esz(prec), u, U, batch, n2, n1, p.N, p.N, hs), "state transpose");
     return LT_OK;
@@ -942,8 +949,9 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
     if (!v || !u) return fail(LT_E_ARG, "v and u must not be NULL");
     if (v_stride != 0 && v_stride < p.N) return fail(LT_E_ARG, "v_stride must be 0 or >= N");
     if (ckpt && ckpt_every < 1) return fail(LT_E_ARG, "ckpt_every must be >= 1 with a checkpoint buffer");
-    if (!ckpt && p.sched[2][prec].ok)
-        return swapped_forward(p, prec, batch, v, v_stride, u, gamma, dt, steps, work, work_bytes, stream);
+    if (p.sched[2][prec].ok)
+        return swapped_forward(p, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every, work,
+                               work_bytes, stream);
     hipStream_t hs = (hipStream_t)stream;
     if ((st = ensure_device_tables(p, 0, prec, stream))) return st;
     const Sched &s = p.sched[0][prec];

@@ -446,7 +446,8 @@ __device__ __forceinline__ void col_checkpoint(cx<T> x, const ColArgs &a, int64_
         c = r;
         sn = i;
     }
-    ((cx<T> *)a.ck)[b * a.ck_bs + n] = cmul_d(x, c, sn);
+    const int64_t nn = a.ck_t ? (n % a.L2) * a.L1 + n / a.L2 : n;
+    ((cx<T> *)a.ck)[b * a.ck_bs + nn] = cmul_d(x, c, sn);
 }
 
 // spectral multiplier of a row pass (see RowArgs)

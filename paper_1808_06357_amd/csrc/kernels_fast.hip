@@ -362,7 +362,7 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
                 if (n < a.Nvalid) {
                     double c, sn;
                     expm_i(a.ck_phase * cv[n], c, sn);
-                    ck[n] = cmul_d(s[F::addr(q, k1)], c, sn);
+                    ck[a.ck_t ? (int64_t)(c0 + q) * L1 + k1 : n] = cmul_d(s[F::addr(q, k1)], c, sn);
                 }
             }
         }

@@ -109,6 +109,8 @@ struct ColArgs {
     const double *ck_v;               // u = x * exp(-i ck_phase ck_v[n]) * conj(c_n)^[ck_chirp]
     double ck_phase;
     int ck_chirp;
+    int ck_t;                         // 1: the tile is a transposed rank-2 tensor, point n = k1 L2 + c
+                                      // is stored at c L1 + k1 (lattice order)
     // adjoint pairing: sequences of vector 0 (state) and vector 1 (cotangent)
     int adjoint;                      // 0: off; 1: first; 2: middle; 3: last
     void *buf2; int64_t buf2_bs;      // cotangent transform buffer

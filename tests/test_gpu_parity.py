@@ -21,6 +21,10 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
+def dtype_np(prec):
+    return np.complex128 if prec == "c128" else np.complex64
+
+
 def _dtype(prec):
     torch = _torch()
     return torch.complex128 if prec == "c128" else torch.complex64
@@ -108,9 +112,9 @@ def test_rank2_resident_and_two_pass(lt):
 @pytest.mark.parametrize("n1,n2,d", [(4096, 256, 6), (2048, 64, 5)])
 def test_rank2_swapped_layout(lt, n1, n2, d):
     """Rank-2 tensors with long columns (n1 >= 2048, n2 <= n1 / 4) run
-    transposed when no checkpoints are asked for: every kernel variant, shared
-    and per-state potentials, then the untransposed run with checkpoints and an
-    autotuned run, against the oracle."""
+    transposed: every kernel variant, shared and per-state potentials, a run
+    with checkpoints (stored in lattice order) and an autotuned run, against
+    the oracle."""
     torch = _torch()
     H = W.hyperbolic_cross(d, 1)
     Z = W.cbc_rank2(H, n1, n2, np.random.default_rng(n1 + n2))
@@ -135,7 +139,7 @@ def test_rank2_swapped_layout(lt, n1, n2, d):
                     e = rel(gpu_run(lt, plan, v, u0, gamma, dt, steps, prec), refs[kind])
                     print(f"  rank-2 {n1}x{n2} col={cv} row={rv} {prec} {kind} rel_l2={e:.2e}", flush=True)
                     assert e < TOL[prec], (cv, rv, prec, kind, e)
-    # checkpoints: the untransposed schedule, same result
+    # checkpoints: written in lattice order by the transposed run's checkpoint passes
     every = 4
     for prec in ("c128", "c64"):
         dtype = _dtype(prec)
@@ -146,8 +150,17 @@ def test_rank2_swapped_layout(lt, n1, n2, d):
         e = rel(u.cpu().numpy().astype(np.complex128), refs["per-state"])
         print(f"  rank-2 {n1}x{n2} with checkpoints {prec} rel_l2={e:.2e}", flush=True)
         assert e < TOL[prec], (prec, e)
-        ck1 = ck.view(-1, 2, N)[1].cpu().numpy().astype(np.complex128)
-        assert rel(ck1, O.strang_run(n, s, vs, u0, gamma, dt, every)) < TOL[prec]
+        cks = ck.view(-1, 2, N).cpu().numpy().astype(np.complex128)
+        assert np.array_equal(cks[0], np.asarray(u0).astype(dtype_np(prec)).astype(np.complex128))
+        assert rel(cks[1], O.strang_run(n, s, vs, u0, gamma, dt, every)) < TOL[prec]
+        # every kernel variant writes the same checkpoint (general and register-staged passes)
+        for cv in (0, 1):
+            lt.lattice_plan_set_kernels(plan, lt.LT_C128 if prec == "c128" else lt.LT_C64, cv, 1)
+            u = torch.tensor(u0, dtype=dtype, device="cuda")
+            ck.zero_()
+            lt.strang_run(plan, torch.tensor(vs, device="cuda"), u, gamma, dt, steps, ckpt=ck, ckpt_every=every)
+            c1 = ck.view(-1, 2, N)[1].cpu().numpy().astype(np.complex128)
+            assert rel(c1, O.strang_run(n, s, vs, u0, gamma, dt, every)) < TOL[prec], (prec, cv)
     for prec, p in (("c64", lt.LT_C64), ("c128", lt.LT_C128)):
         lt.lattice_plan_autotune(plan, p, reps=3)
         e = rel(gpu_run(lt, plan, vs[0], u0, gamma, dt, steps, prec), refs["shared"])
