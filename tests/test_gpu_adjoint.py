@@ -61,6 +61,33 @@ def test_adjoint_matches_oracle(lt, N, d, shared):
         assert e0 < tol and ev < tol
 
 
+def test_adjoint_after_transposed_rank2_forward(lt):
+    """A rank-2 tensor with long columns runs its forward transposed; its
+    checkpoints (lattice order) feed the adjoint sweep, which runs untransposed:
+    the gradients against the oracle's VJP."""
+    import torch
+    n1, n2, d, batch, gamma, dt, steps, every = 2048, 64, 4, 2, 0.05, 2e-3, 13, 5
+    H = W.hyperbolic_cross(d, 1)
+    Z = W.cbc_rank2(H, n1, n2, np.random.default_rng(71))
+    n = np.array([n1, n2])
+    N = n1 * n2
+    num = W.point_numerators(Z, n)
+    g = np.random.default_rng(72)
+    v = W.cosine_series(d, 16, g).at(num, N)
+    u0 = np.stack([W.seeded_packet(num, N, g) for _ in range(batch)])
+    tgt = np.stack([W.seeded_packet(num, N, g) for _ in range(batch)])
+    plan = lt.lattice_plan(Z, n, H)
+    assert plan.info["swapped"] == 1
+    _, s, _ = O.index_set(Z, n, H)
+    uT = O.strang_run(n, s, v, u0, gamma, dt, steps)
+    g0_ref, gv_ref = O.strang_vjp(n, s, v, u0, 2.0 * (uT - tgt) / N, gamma, dt, steps)
+    for dtype, tol in ((torch.complex128, 1e-10), (torch.complex64, 2e-4)):
+        g0, gv = gpu_grad(lt, plan, v, u0, tgt, gamma, dt, steps, every, dtype)
+        e0, ev = rel(g0, g0_ref), rel(gv, gv_ref)
+        print(f"rank-2 {n1}x{n2} {dtype} dJ/du0 rel={e0:.2e} dJ/dv rel={ev:.2e}", flush=True)
+        assert e0 < tol and ev < tol
+
+
 def test_autograd_function(lt):
     import torch
     N, d, batch, gamma, dt, steps = 65521, 4, 3, 0.05, 2e-3, 24
