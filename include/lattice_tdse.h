@@ -91,17 +91,24 @@ typedef struct {
 } lt_plan_info;
 
 /*
- * lattice_plan -- host-side planning (no GPU needed).
+ * lattice_plan -- planning of a lattice and its index set.
  *
  * Builds the lattice of Def. 1 and its anti-aliasing set of full
  * cardinality (Def. 2, Thm. 1):
  *   - H (nh x d, row-major int32, may be NULL with nh = 0) is a user index
  *     set; it must be injective under chi (LT_E_NOT_INJECTIVE otherwise) and
  *     its elements own their keys;
- *   - every key not owned by H gets its minimal-l2 representative
- *     (Lemma 4, eq. (hrepresenter)), ties broken by h lexicographic
- *     (h_1 first, signed ascending), found with the construction of Sec. 3.1
- *     (enumerate a ball, sort by norm, first unseen key wins).
+ *   - complete = 1: every key not owned by H gets its minimal-l2
+ *     representative (Lemma 4, eq. (hrepresenter)), ties broken by h
+ *     lexicographic (h_1 first, signed ascending), found with the
+ *     construction of Sec. 3.1 (enumerate a ball, sort by norm, first unseen
+ *     key wins); complete = 0: H must own all N keys (|H| = N), otherwise
+ *     LT_E_INCOMPLETE; H = NULL always plans the minimal-l2 full set;
+ *   - prec_mask: 0 plans on the host only (no GPU needed; each run builds
+ *     the device tables of its precision on first use); LT_C64 and / or
+ *     LT_C128 also build the device tables a forward run in those precisions
+ *     reads, on the calling thread's current device (LT_E_HIP without one),
+ *     so that later runs with a workspace allocate nothing.
  * Requirements: 1 <= r <= 2 for runs (planning accepts r <= 4), d >= 1,
  * n_{i+1} | n_i (LT_E_NOT_CANONICAL), all N points distinct
  * (LT_E_INCOMPLETE; for rank-1 this is gcd(N, z_1..z_d) = 1).
@@ -110,7 +117,8 @@ typedef struct {
  * On success *out owns the plan; release it with lattice_plan_destroy.
  */
 lt_status lattice_plan(int32_t d, int32_t r, const int64_t *Z, const int64_t *n,
-                       const int32_t *H, int64_t nh, lt_plan **out);
+                       const int32_t *H, int64_t nh, int32_t complete, int32_t prec_mask,
+                       lt_plan **out);
 
 /* Copy the plan's facts into *info. */
 lt_status lattice_plan_info(const lt_plan *p, lt_plan_info *info);

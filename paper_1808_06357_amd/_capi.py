@@ -57,7 +57,7 @@ class PlanInfo(ctypes.Structure):
 
 _P, _i32, _i64, _f64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
 _SIGS = {
-    "lattice_plan": [_i32, _i32, _P, _P, _P, _i64, ctypes.POINTER(_P)],
+    "lattice_plan": [_i32, _i32, _P, _P, _P, _i64, _i32, _i32, ctypes.POINTER(_P)],
     "lattice_plan_info": [_P, ctypes.POINTER(PlanInfo)],
     "lattice_plan_keys": [_P, _P, _P, _P],
     "lattice_plan_points": [_P, _i64, _i64, _P],
@@ -129,9 +129,11 @@ class Plan:
             pass
 
 
-def lattice_plan(Z, n, H=None) -> Plan:
+def lattice_plan(Z, n, H=None, complete: bool = True, prec_mask: int = 0) -> Plan:
     """Plan a rank-r lattice (Z: r x d generating vectors, n: r moduli) with
-    optional index set H (nh x d); see lattice_plan in lattice_tdse.h."""
+    optional index set H (nh x d); complete: give keys H leaves unowned their
+    minimal-l2 representatives; prec_mask: LT_C64 | LT_C128 precisions whose
+    device tables are built now; see lattice_plan in lattice_tdse.h."""
     Z = np.ascontiguousarray(np.atleast_2d(np.asarray(Z, dtype=np.int64)))
     n = np.ascontiguousarray(np.atleast_1d(np.asarray(n, dtype=np.int64)))
     r, d = Z.shape
@@ -139,7 +141,7 @@ def lattice_plan(Z, n, H=None) -> Plan:
         H = np.ascontiguousarray(np.asarray(H, dtype=np.int32).reshape(-1, d))
     out = _P()
     _check(lib.lattice_plan(d, r, _np_ptr(Z), _np_ptr(n), _np_ptr(H), 0 if H is None else H.shape[0],
-                            ctypes.byref(out)), "lattice_plan")
+                            1 if complete else 0, int(prec_mask), ctypes.byref(out)), "lattice_plan")
     return Plan(out.value, d, r)
 
 

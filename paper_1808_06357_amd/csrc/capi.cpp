@@ -735,6 +735,20 @@ lt_status ensure_device_tables(lt_plan &p, int which, int prec, void *stream)
     return LT_OK;
 }
 
+// Device tables a forward run in precision prec reads: its schedule's (the
+// swapped one for a rank-2 tensor with long columns), plus the complex128
+// tables of a two-pass chirp-z lattice, whose convolution spectrum is built
+// in double precision.
+lt_status prepare_forward_tables(lt_plan &p, int prec, void *stream)
+{
+    const int which = p.sched[2][prec].ok ? 2 : 0;
+    lt_status st = ensure_device_tables(p, which, prec, stream);
+    if (st) return st;
+    const Sched &s = p.sched[which][prec];
+    if (s.bluestein && s.passes == 2 && p.sched[0][LT_C128].ok) return ensure_device_tables(p, 0, LT_C128, stream);
+    return LT_OK;
+}
+
 // Workspace of a run on the swapped rank-2 schedule: the run's own layout,
 // then the transposed state (batch x N) and potential (1 or batch x N).
 struct SwapWork {
@@ -796,10 +810,12 @@ lt_status swapped_forward(lt_plan &p, int prec, int batch, const double *v, int6
 extern "C" {
 
 lt_status lattice_plan(int32_t d, int32_t r, const int64_t *Z, const int64_t *n, const int32_t *H,
-                       int64_t nh, lt_plan **out)
+                       int64_t nh, int32_t complete, int32_t prec_mask, lt_plan **out)
 {
     if (!out) return fail(LT_E_ARG, "out is NULL");
     *out = nullptr;
+    if (complete != 0 && complete != 1) return fail(LT_E_ARG, "complete must be 0 or 1");
+    if (prec_mask & ~(LT_C64 | LT_C128)) return fail(LT_E_ARG, "prec_mask must combine LT_C64 and LT_C128");
     if (d < 1 || d > 64) return fail(LT_E_ARG, "d must be in [1, 64]");
     if (r < 1 || r > 4) return fail(LT_E_ARG, "r must be in [1, 4]");
     if (!Z || !n) return fail(LT_E_ARG, "Z and n must not be NULL");
@@ -820,6 +836,7 @@ lt_status lattice_plan(int32_t d, int32_t r, const int64_t *Z, const int64_t *n,
     p->r = r;
     for (int i = 0; i < r; ++i) p->n[i] = n[i];
     p->N = (int64_t)N;
+    p->complete = complete != 0;
     try {
         p->Z.assign(Z, Z + (size_t)r * d);
         if (H) p->H.assign(H, H + (size_t)nh * d);
@@ -837,6 +854,18 @@ lt_status lattice_plan(int32_t d, int32_t r, const int64_t *Z, const int64_t *n,
     } catch (const std::bad_alloc &) {
         delete p;
         return fail(LT_E_NOMEM, "out of host memory while planning");
+    }
+    for (int prec : {LT_C64, LT_C128}) {
+        if (!(prec_mask & prec)) continue;
+        lt_status st = prepare_forward_tables(*p, prec, nullptr);
+        if (st == LT_OK) {
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) st = fail(LT_E_HIP, std::string("table build: ") + hipGetErrorString(e));
+        }
+        if (st != LT_OK) {
+            lattice_plan_destroy(p);
+            return st;
+        }
     }
     *out = p;
     return LT_OK;

@@ -238,6 +238,7 @@ struct lt_plan {
     std::vector<int64_t> s_of_key; // N
     std::vector<int32_t> h_of_key; // N x d
     int64_t n_index = 0, n_completed = 0, max_s = 0;
+    bool complete = true;          // give keys the index set leaves unowned their minimal-l2 representative
     // [0]: the run schedule; [1]: a two-pass schedule (used by the adjoint,
     // identical to [0] when [0] is already two-pass); [2]: the transposed
     // schedule of a rank-2 tensor whose columns are long (ok only then; runs
@@ -254,6 +255,7 @@ lt_status fail(lt_status st, const std::string &msg);
 Sched make_schedule(const lt_plan &p, int prec, bool force_two_pass);
 lt_status plan_index_set(lt_plan &p);
 lt_status ensure_device_tables(lt_plan &p, int which, int prec, void *stream);
+lt_status prepare_forward_tables(lt_plan &p, int prec, void *stream);
 bool factor_radices(int64_t L, Radices &out, int max_log2 = 4);
 int64_t smooth7_at_least(int64_t x);
 }  // namespace lt

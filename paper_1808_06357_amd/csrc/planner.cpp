@@ -133,6 +133,9 @@ lt_status plan_index_set(lt_plan &p)
     }
     p.n_index = nh;
     p.n_completed = N - nh;
+    if (!p.complete && nh > 0 && count < N)
+        return fail(LT_E_INCOMPLETE, "the index set owns " + std::to_string(count) + " of " + std::to_string(N) +
+                    " keys; plan with complete = 1 to give the others their minimal-l2 representatives");
 
     // initial radius: a ball holding about N lattice vectors
     double lg = std::lgamma(0.5 * d + 1.0) + std::log((double)N) - 0.5 * d * std::log(M_PI);

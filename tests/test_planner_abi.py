@@ -78,8 +78,31 @@ def test_plan_errors():
         C.lattice_plan(np.array([[1, 1, 1], [1, 1, 1]]), np.array([4, 4]))  # rank-2 all odd: repeats
     assert e.value.status == "LT_E_INCOMPLETE"
     out = ctypes.c_void_p()
-    assert C.lib.lattice_plan(0, 1, None, None, None, 0, ctypes.byref(out)) == 1
+    assert C.lib.lattice_plan(0, 1, None, None, None, 0, 1, 0, ctypes.byref(out)) == 1
     assert b"d must be" in C.lib.lt_last_error()
+
+
+def test_plan_complete_flag():
+    """complete = 0 accepts an index set only when it owns every key; the
+    config-0 box owns 1024 of 1031 keys (A7) and is rejected, while the full
+    minimal-l2 set of the same lattice, given as H, plans to the same keys."""
+    c = W.box_d2_n1031()
+    with pytest.raises(C.LatticeError) as e:
+        C.lattice_plan(c.Z, c.n, c.I, complete=False)
+    assert e.value.status == "LT_E_INCOMPLETE"
+    assert b"1024 of 1031" in C.lib.lt_last_error()
+    full = C.lattice_plan(c.Z, c.n)
+    _, s_full, h_full = C.lattice_plan_keys(full)
+    again = C.lattice_plan(c.Z, c.n, h_full, complete=False)
+    k, s, h = C.lattice_plan_keys(again)
+    assert again.info["n_completed"] == 0 and again.info["n_index"] == c.N
+    assert np.array_equal(k, np.arange(c.N)) and np.array_equal(s, s_full) and np.array_equal(h, h_full)
+    out = ctypes.c_void_p()
+    Z = np.ascontiguousarray(c.Z, dtype=np.int64)
+    n = np.ascontiguousarray(c.n, dtype=np.int64)
+    assert C.lib.lattice_plan(2, 1, Z.ctypes.data, n.ctypes.data, None, 0, 2, 0, ctypes.byref(out)) == 1
+    assert C.lib.lattice_plan(2, 1, Z.ctypes.data, n.ctypes.data, None, 0, 1, 4, ctypes.byref(out)) == 1
+    assert b"prec_mask" in C.lib.lt_last_error()
 
 
 def test_run_argument_errors_before_any_gpu_call():
@@ -174,12 +197,17 @@ def test_batched_argument_errors_on_host():
 
 @pytest.mark.slow
 def test_mixed_batch_lattices_bitexact_on_golden_instances():
-    """Planner bin maps of the batched workload's sampled problems (best-of-8
+    """Planner bin maps of six problems of the batched workload (best-of-8
     Korobov lattices, minimal-l2 full sets) equal the oracle's."""
-    import os
-    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "mixed_batch_oracle_samples.npz"))
-    sel = [int(i) for i in gold["instances"]]
     shapes = W.mixed_batch_shapes()
+    Ns = np.array([N for _, N in shapes])
+    ds = np.array([d for d, _ in shapes])
+    prime = np.arange(len(shapes)) % 2 == 0
+    # the largest prime and composite N, the smallest N, the first d = 10 and
+    # d = 2 problems, problem 0
+    sel = sorted({int(np.flatnonzero(prime)[np.argmax(Ns[prime])]),
+                  int(np.flatnonzero(~prime)[np.argmax(Ns[~prime])]),
+                  int(np.argmin(Ns)), int(np.flatnonzero(ds == 10)[0]), int(np.flatnonzero(ds == 2)[0]), 0})
     insts = W.mixed_batch(shapes=shapes[: max(sel) + 1])
     for i in sel:
         _planner_matches_oracle(insts[i].Z, insts[i].n)
