@@ -54,7 +54,7 @@ def test_adjoint_matches_oracle(lt, N, d, shared):
     _, s, _ = O.index_set(Z, n)
     uT = O.strang_run(n, s, v, u0, gamma, dt, steps)
     g0_ref, gv_ref = O.strang_vjp(n, s, v, u0, 2.0 * (uT - tgt) / N, gamma, dt, steps)
-    for dtype, tol in ((torch.complex128, 1e-10), (torch.complex64, 2e-4)):
+    for dtype, tol in ((torch.complex128, 1e-11), (torch.complex64, 1e-4)):
         g0, gv = gpu_grad(lt, plan, v, u0, tgt, gamma, dt, steps, every, dtype)
         e0, ev = rel(g0, g0_ref), rel(gv, gv_ref)
         print(f"N={N} {dtype} dJ/du0 rel={e0:.2e} dJ/dv rel={ev:.2e}", flush=True)
@@ -81,7 +81,7 @@ def test_adjoint_after_transposed_rank2_forward(lt):
     _, s, _ = O.index_set(Z, n, H)
     uT = O.strang_run(n, s, v, u0, gamma, dt, steps)
     g0_ref, gv_ref = O.strang_vjp(n, s, v, u0, 2.0 * (uT - tgt) / N, gamma, dt, steps)
-    for dtype, tol in ((torch.complex128, 1e-10), (torch.complex64, 2e-4)):
+    for dtype, tol in ((torch.complex128, 1e-11), (torch.complex64, 1e-4)):
         g0, gv = gpu_grad(lt, plan, v, u0, tgt, gamma, dt, steps, every, dtype)
         e0, ev = rel(g0, g0_ref), rel(gv, gv_ref)
         print(f"rank-2 {n1}x{n2} {dtype} dJ/du0 rel={e0:.2e} dJ/dv rel={ev:.2e}", flush=True)
@@ -103,8 +103,8 @@ def test_autograd_function(lt):
     uT_ref = O.strang_run(n, s, v, u0, gamma, dt, steps)
     g0_ref, gv_ref = O.strang_vjp(n, s, v, u0, 2.0 * (uT_ref - tgt) / N, gamma, dt, steps)
     assert rel(uT.detach().cpu().numpy(), uT_ref) < 1e-11
-    assert rel(u.grad.cpu().numpy(), g0_ref) < 1e-10
-    assert rel(vv.grad.cpu().numpy(), gv_ref) < 1e-10
+    assert rel(u.grad.cpu().numpy(), g0_ref) < 1e-11
+    assert rel(vv.grad.cpu().numpy(), gv_ref) < 1e-11
 
 
 def test_dot_product_identity(lt):
@@ -141,49 +141,58 @@ def case4(lt):
         print(f"adjoint_d4_n65521 kernels {p}: one state {lt.lattice_plan_get_kernels_batch(plan, p, 1)}, "
               f"32 states {lt.lattice_plan_get_kernels_batch(plan, p, 32)}", flush=True)
     basis = torch.tensor(c.meta["series"].basis(c.meta["num"], c.N), dtype=torch.float64, device="cuda")
-    S = torch.tensor(gold["S"], device="cuda")
-    assert np.array_equal(gold["S"], W.adjoint_d4_n65521_loss_points(c.N))
-    return c, plan, basis, S, gold
+    return c, plan, basis, gold
 
 
-def loss_and_grads(lt, c, plan, v, S, target, dtype, grads=True):
-    """J = sum_b (1/N) sum_{k in S} |u_b(T)_k - target_b,k|^2 and, through
-    strang_adjoint, (dJ/dv, dJ/du0)."""
+def target_run(lt, c, plan, dtype):
+    """The target of the loss: u0 run under the hidden potential (on this path,
+    in the precision under test)."""
+    import torch
+    t = torch.tensor(c.u0, dtype=dtype, device="cuda")
+    vh = torch.tensor(c.meta["v_hidden"], dtype=torch.float64, device="cuda")
+    lt.strang_run(plan, vh, t, c.gamma, c.dt, c.steps)
+    return t
+
+
+def loss_and_grads(lt, c, plan, v, target, dtype, grads=True):
+    """J = sum_b (1/N) sum_k |u_b(T)_k - target_b,k|^2 over every point and,
+    through strang_adjoint, (dJ/dv, dJ/du0)."""
     import torch
     N, m, every = c.N, c.steps, c.meta["ckpt_every"]
     u = torch.tensor(c.u0, dtype=dtype, device="cuda")
     B = u.shape[0]
     ck = torch.empty(lt.num_checkpoints(m, every) * B * N, dtype=dtype, device="cuda") if grads else None
     lt.strang_run(plan, v, u, c.gamma, c.dt, m, ckpt=ck, ckpt_every=every if grads else 0)
-    diff = u[:, S].to(torch.complex128) - target
+    diff = u.to(torch.complex128) - target.to(torch.complex128)
     J = float(torch.sum(torch.abs(diff) ** 2).item()) / N
     if not grads:
         return J, u
-    gT = torch.zeros_like(u)
-    gT[:, S] = ((2.0 / N) * diff).to(dtype)
+    gT = ((2.0 / N) * diff).to(dtype)
     g0, gv = lt.strang_adjoint(plan, v, u, gT, c.gamma, c.dt, m, ck, every)
     return J, u, g0, gv
 
 
-@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 1e-4)])
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-11), ("c64", 1e-4)])
 def test_adjoint_d4_n65521_gradients_against_oracle(lt, case4, prec, tol):
-    """d = 4, N = 65521, 32 states, 500 steps, checkpoints every 50: the loss,
-    u(T), dJ/da (64 coefficients), dJ/dv and dJ/du0 against the FP64 oracle's
-    adjoint (stored samples)."""
+    """d = 4, N = 65521, 32 states, 500 steps, checkpoints every 50, the loss
+    over the whole lattice: J, the target run, u(T), dJ/da (64 coefficients),
+    dJ/dv and dJ/du0 against the FP64 oracle's adjoint (stored samples)."""
     import torch
-    c, plan, basis, S, gold = case4
+    c, plan, basis, gold = case4
     dtype = torch.complex128 if prec == "c128" else torch.complex64
     v = torch.tensor(c.v, dtype=torch.float64, device="cuda")
-    target = torch.tensor(gold["target_S"], device="cuda")
-    J, u, g0, gv = loss_and_grads(lt, c, plan, v, S, target, dtype)
+    target = target_run(lt, c, plan, dtype)
+    J, u, g0, gv = loss_and_grads(lt, c, plan, v, target, dtype)
     dJda = (basis @ gv).cpu().numpy()
     iu, iv = gold["idx_u"], gold["idx_v"]
     errs = {"J": abs(J - float(gold["J"])) / abs(float(gold["J"])),
+            "target": rel(target.cpu().numpy()[:, iu], gold["target"]),
             "uT": rel(u.cpu().numpy()[:, iu], gold["uT"]),
             "dJ/da": rel(dJda, gold["dJ_da"]),
             "dJ/dv": rel(gv.cpu().numpy()[iv], gold["dJ_dv"]),
             "dJ/du0": rel(g0.cpu().numpy()[:, iu], gold["dJ_du0"])}
-    print(f"adjoint_d4_n65521 {prec}: " + ", ".join(f"{k} {e:.2e}" for k, e in errs.items()), flush=True)
+    print(f"adjoint_d4_n65521 {prec}: " + ", ".join(f"{k} {e:.2e}" for k, e in errs.items())
+          + f"; max kappa of dJ/da {float(np.max(gold['kappa'])):.1f}", flush=True)
     for k, e in errs.items():
         assert e < tol, (k, e)
 
@@ -192,18 +201,18 @@ def test_adjoint_d4_n65521_central_differences_c128(lt, case4):
     """dJ/da from the adjoint against central differences, h = 1e-6, every one
     of the 64 coefficients, on the complex128 path."""
     import torch
-    c, plan, basis, S, gold = case4
+    c, plan, basis, gold = case4
     a = torch.tensor(c.meta["series"].a, dtype=torch.float64, device="cuda")
-    target = torch.tensor(gold["target_S"], device="cuda")
-    _, _, _, gv = loss_and_grads(lt, c, plan, (a @ basis).contiguous(), S, target, torch.complex128)
+    target = target_run(lt, c, plan, torch.complex128)
+    _, _, _, gv = loss_and_grads(lt, c, plan, (a @ basis).contiguous(), target, torch.complex128)
     adj = (basis @ gv).cpu().numpy()
     h = 1e-6
     fd = np.empty(a.numel())
     for t in range(a.numel()):
         e = torch.zeros_like(a)
         e[t] = h
-        jp, _ = loss_and_grads(lt, c, plan, ((a + e) @ basis).contiguous(), S, target, torch.complex128, False)
-        jm, _ = loss_and_grads(lt, c, plan, ((a - e) @ basis).contiguous(), S, target, torch.complex128, False)
+        jp, _ = loss_and_grads(lt, c, plan, ((a + e) @ basis).contiguous(), target, torch.complex128, False)
+        jm, _ = loss_and_grads(lt, c, plan, ((a - e) @ basis).contiguous(), target, torch.complex128, False)
         fd[t] = (jp - jm) / (2 * h)
     e = rel(fd, adj)
     print(f"adjoint_d4_n65521 central differences vs adjoint: rel {e:.2e} (|dJ/da| = {np.linalg.norm(adj):.3e})", flush=True)

@@ -289,6 +289,25 @@ def paper_g1(num: np.ndarray, N: int, gamma: float, normalize: bool = True) -> n
     return u
 
 
+def paper_g2(num: np.ndarray, N: int, gamma: float, normalize: bool = True) -> np.ndarray:
+    """The paper's hat initial condition g2 (Sec. 3.2) at the lattice points:
+    prod_j max(0, 1 - |y_j| / a) with y_1 = 2 pi x_1 - 3 pi / 2,
+    y_j = 2 pi x_j - pi (j >= 2) and a = pi sqrt(gamma) / 2, the tent whose
+    normalising factor (3 / (pi sqrt(gamma)))^(d/2) makes it unit-norm on
+    [0, 2 pi]^d; scaled to unit lattice-rule norm unless normalize is False.
+    The tent is supported inside the cell for gamma <= 1, so it is periodic,
+    continuous and only Lipschitz (kinks at its peak and edges)."""
+    x = num.astype(np.float64) / N
+    a = 0.5 * np.pi * np.sqrt(gamma)
+    u = np.maximum(0.0, 1.0 - np.abs(2 * np.pi * x[:, 0] - 1.5 * np.pi) / a)
+    for j in range(1, num.shape[1]):
+        u = u * np.maximum(0.0, 1.0 - np.abs(2 * np.pi * x[:, j] - np.pi) / a)
+    u = u.astype(np.complex128)
+    if normalize:
+        u /= np.sqrt(np.mean(np.abs(u) ** 2))
+    return u
+
+
 def paper_g1_coefficients(d: int, gamma: float, kmax: int, nodes: int = 4096):
     """Fourier coefficients of the (unscaled) g1 on [0,1)^d: g1 is a product of
     1-D factors exp(-(2 pi x - c)^2 / gamma) (c = 3 pi / 2 in the first
@@ -472,13 +491,6 @@ def paper_lattice(d: int, n: int):
     return z.reshape(1, -1), np.array([n], dtype=np.int64)
 
 
-def adjoint_d4_n65521_loss_points(N: int, count: int = 2048) -> np.ndarray:
-    """Seeded sorted point indices on which the differentiation workload's
-    misfit is measured (the loss restricted to a sample keeps its stored
-    target small)."""
-    return np.sort(rng(4, "shapes").choice(N, size=count, replace=False))
-
-
 def adjoint_d4_n65521(batch: int = 32, steps: int = 500):
     """d = 4, N = 65521 (prime), Korobov z, minimal-l2 full set, batch of
     seeded packets sharing a 64-term cosine potential; a hidden 64-term
@@ -496,3 +508,49 @@ def adjoint_d4_n65521(batch: int = 32, steps: int = 500):
                     {"name": "adjoint_d4_n65521", "ckpt_every": 50, "series": series, "hidden": hidden,
                      "v_hidden": hidden.at(num, N), "num": num})
     return inst
+
+
+def maxsize_d3(N: int, seed: int = 41) -> Instance:
+    """The largest single lattices of the build: d = 3 rank-1 with N near 2^22
+    (prime 4194301, whose chirp-z length is 2^23, or 2^22 itself), best-of-8
+    Korobov z, 16-term cosine potential, seeded packet, gamma = 0.05,
+    dt = 2e-3, 8 steps."""
+    g = np.random.default_rng(seed)
+    d = 3
+    z = korobov_good(N, d, g)
+    Z, n = z.reshape(1, -1), np.array([N], dtype=np.int64)
+    num = point_numerators(Z, n)
+    v = cosine_series(d, 16, g).at(num, N)
+    u0 = seeded_packet(num, N, g)
+    return Instance(d, Z, n, None, 0.05, 2e-3, 8, v, u0, {"name": f"maxsize_d3_n{N}"})
+
+
+def conservation_d5_n2p20(steps: int = 1000) -> Instance:
+    """The conservation setting of Sec. 3.3: gamma = 0.5, d = 5, the paper's g1
+    and harmonic v2, on a rank-1 lattice of 2^20 points (best of 8 Korobov
+    vectors, seed 33; Table 1 lists no d = 5 vector), dt = 1e-3, checkpoints
+    every 10 steps."""
+    N, d = 1 << 20, 5
+    z = korobov_good(N, d, np.random.default_rng(33))
+    Z, n = z.reshape(1, -1), np.array([N], dtype=np.int64)
+    num = point_numerators(Z, n)
+    return Instance(d, Z, n, None, 0.5, 1e-3, steps, v_harmonic_paper(num, N), paper_g1(num, N, 0.5),
+                    {"name": "conservation_d5_n2p20", "ckpt_every": 10})
+
+
+def table1_run(d: int, n: int, potential: str = "v1", gamma: float = 0.5, dt: float = 1e-3,
+               steps: int = 100, initial: str = "g1") -> Instance:
+    """A Table 1 lattice (Sec. 3.1) with its minimal-l2 index set, the paper's
+    g1 (Gaussian) or g2 (hat) and v1 (smooth) or v2 (harmonic) (Sec. 3.2)."""
+    Z, nn = paper_lattice(d, n)
+    num = point_numerators(Z, nn)
+    vfun = v_smooth_paper if potential == "v1" else v_harmonic_paper
+    gfun = paper_g1 if initial == "g1" else paper_g2
+    return Instance(d, Z, nn, None, gamma, dt, steps, vfun(num, n), gfun(num, n, gamma),
+                    {"name": f"table1_d{d}_n{n}_{initial}_{potential}"})
+
+
+def splitting_modulation(t):
+    """f(t) of the time-dependent potential v(x, t) = v(x) + f(t) v(x) on the
+    benchmark lattice: 0.5 sin(20 t)."""
+    return 0.5 * np.sin(20.0 * np.asarray(t, dtype=np.float64))
