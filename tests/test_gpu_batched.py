@@ -139,21 +139,21 @@ def mixed_batch(lt):
 @pytest.mark.parametrize("prec", ["c64", "c128"])
 def test_mixed_batch_full_batch(lt, mixed_batch, prec):
     """All 256 problems, 200 steps, in the launch configuration the benchmark
-    times: the oracle's states at stored sample points of six problems, and the
-    norm of every problem (the scheme is unitary)."""
+    times: every problem's state against the oracle's at its stored sample
+    points (72 per problem) and its full-vector norm against the oracle's."""
     insts, plans, gold = mixed_batch
     probs = [dict(u0=c.u0, v=c.v, gamma=c.gamma, dt=c.dt, steps=c.steps) for c in insts]
     got = run_batched(lt, plans, probs, prec)
-    worst = 0.0
+    assert len(gold["instances"]) == len(insts)
+    worst, worst_i = 0.0, -1
     for i in gold["instances"]:
         e = rel(got[i][gold[f"idx_{i}"]], gold[f"u_{i}"])
-        worst = max(worst, e)
-        print(f"  {prec} problem {i}: d={insts[i].d} N={insts[i].N} sampled rel_l2={e:.2e}", flush=True)
-        assert e < TOL[prec], (i, e)
+        if e > worst:
+            worst, worst_i = e, int(i)
+        assert e < TOL[prec], (int(i), insts[i].d, insts[i].N, e)
         assert abs(np.mean(np.abs(got[i]) ** 2) - float(gold[f"norm2_{i}"])) < 2 * TOL[prec]
-    for i, (g, c) in enumerate(zip(got, insts)):
-        n0 = np.mean(np.abs(c.u0) ** 2)
-        assert abs(np.mean(np.abs(g) ** 2) - n0) < 2 * TOL[prec] * n0, i
+    print(f"  {prec}: worst sampled rel_l2 over {len(insts)} problems {worst:.2e} (problem {worst_i}, "
+          f"d={insts[worst_i].d} N={insts[worst_i].N})", flush=True)
 
 
 def test_mixed_batch_reversible_c128(lt, mixed_batch):
