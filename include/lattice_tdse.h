@@ -181,6 +181,29 @@ lt_status strang_run(const lt_plan *p, lt_prec prec, int32_t batch, const double
                      void *ckpt, int64_t ckpt_every, void *work, size_t work_bytes, void *stream);
 
 /*
+ * strang_run_sums -- strang_run (same arguments and semantics) that also
+ * records, at every step boundary j = 0..steps, the two point sums of the
+ * state u_j of Sec. 3.3 (norm conservation and the potential part of the
+ * energy <H u, u>, H = -(gamma/2) Laplacian + v/gamma):
+ *   sums[(b (steps+1) + j) 2 + 0] = (1/N) sum_k |u_j(p_k)|^2
+ *   sums[(b (steps+1) + j) 2 + 1] = (1/(gamma N)) sum_k v(p_k) |u_j(p_k)|^2
+ * (sums: device, batch x (steps+1) x 2 doubles, written by the call).
+ * The column pass at each step boundary holds the point values up to a unit
+ * phase and forms the tile sums in FP64 as it passes (one extra read of v per
+ * point); the partials are reduced in a fixed order, so the result is
+ * reproducible run to run.  The kinetic part of the energy needs F u_j, which
+ * no pass of a merged step holds: lattice_diagnostics on checkpoints gives it.
+ *   work   at least strang_run_sums_workspace_size bytes (which depends on
+ *          steps), or NULL.
+ */
+lt_status strang_run_sums_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch,
+                                         int32_t shared_v, int64_t steps, size_t *bytes);
+lt_status strang_run_sums(const lt_plan *p, lt_prec prec, int32_t batch, const double *v,
+                          int64_t v_stride, void *u, double gamma, double dt, int64_t steps,
+                          void *ckpt, int64_t ckpt_every, double *sums, void *work,
+                          size_t work_bytes, void *stream);
+
+/*
  * strang_adjoint -- reverse-mode derivative of u(T) = S^m u(0) for a real
  * loss J, for `batch` states sharing the plan (same v, dt, gamma convention
  * as strang_run).  Gradients use g = dJ/dRe + i dJ/dIm.

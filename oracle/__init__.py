@@ -174,7 +174,8 @@ def strang_run(n, s_of_key, v, u0, gamma, dt, steps, method="auto", history=Fals
 
     n: moduli (rank r); s_of_key: ||h_chi||^2 per key; v: (N,) shared or
     (batch, N); u0: (N,) or (batch, N) complex.  Returns u(T) with the shape
-    of u0, and optionally the (batch, steps+1, 2) norm^2 / energy history."""
+    of u0, and optionally the (batch, steps+1, 3) history of norm^2, energy
+    and the energy's potential term (1/(gamma N)) sum v |u|^2 (Sec. 3.3)."""
     n = np.ascontiguousarray(np.atleast_1d(np.asarray(n, dtype=np.int64)))
     N = int(np.prod(n))
     s = np.ascontiguousarray(s_of_key, dtype=np.int64)
@@ -186,7 +187,7 @@ def strang_run(n, s_of_key, v, u0, gamma, dt, steps, method="auto", history=Fals
     v_stride = 0 if v.ndim == 1 else N
     if v.ndim != 1 and v.shape[0] != batch:
         raise ValueError("v must be (N,) or (batch, N)")
-    hist = np.zeros((batch, steps + 1, 2)) if history else None
+    hist = np.zeros((batch, steps + 1, 3)) if history else None
     _check(_load().or_strang_run(n.size, _p(n), _p(s), batch, _p(v), v_stride, _p(u), float(gamma),
                                  float(dt), int(steps), _METHODS[method],
                                  _p(hist) if history else None), "strang_run")
@@ -284,5 +285,5 @@ def diagnostics(n, s_of_key, v, u, gamma, method="auto"):
     u = np.ascontiguousarray(u, dtype=np.complex128)
     a, b = ctypes.c_double(), ctypes.c_double()
     _check(_load().or_diagnostics(n.size, _p(n), _p(s), _p(v), _p(u), float(gamma),
-                                  _METHODS[method], ctypes.byref(a), ctypes.byref(b)), "diagnostics")
+                                  _METHODS[method], ctypes.byref(a), ctypes.byref(b), None), "diagnostics")
     return a.value, b.value

@@ -64,6 +64,8 @@ _SIGS = {
     "lattice_plan_destroy": [_P],
     "strang_workspace_size": [_P, _i32, _i32, _i32, ctypes.POINTER(_sz)],
     "strang_run": [_P, _i32, _i32, _P, _i64, _P, _f64, _f64, _i64, _P, _i64, _P, _sz, _P],
+    "strang_run_sums_workspace_size": [_P, _i32, _i32, _i32, _i64, ctypes.POINTER(_sz)],
+    "strang_run_sums": [_P, _i32, _i32, _P, _i64, _P, _f64, _f64, _i64, _P, _i64, _P, _P, _sz, _P],
     "strang_adjoint_workspace_size": [_P, _i32, _i32, _i32, ctypes.POINTER(_sz)],
     "strang_adjoint": [_P, _i32, _i32, _P, _i64, _P, _P, _f64, _f64, _i64, _P, _i64, _P, _P, _P, _sz, _P],
     "strang_batched_workspace_size": [_i32, _P, _i32, ctypes.POINTER(_sz)],
@@ -243,6 +245,42 @@ def strang_run(plan: Plan, v, u, gamma: float, dt: float, steps: int, ckpt=None,
                           float(dt), int(steps), _dev_ptr(ckpt), int(ckpt_every), _dev_ptr(work), wb,
                           _stream(stream)), "strang_run")
     return u
+
+
+def strang_run_sums_workspace_size(plan: Plan, prec: int, batch: int, shared_v: bool, steps: int) -> int:
+    n = _sz()
+    _check(lib.strang_run_sums_workspace_size(plan.handle, prec, batch, int(bool(shared_v)), int(steps),
+                                              ctypes.byref(n)), "strang_run_sums_workspace_size")
+    return n.value
+
+
+def strang_run_sums(plan: Plan, v, u, gamma: float, dt: float, steps: int, sums=None, ckpt=None,
+                    ckpt_every: int = 0, work=None, stream=None):
+    """strang_run that also returns the per-step sums (device float64,
+    (batch, steps + 1, 2)): (1/N) sum |u_j|^2 and (1/(gamma N)) sum v |u_j|^2
+    at every step boundary j."""
+    import torch
+    N = plan.N
+    prec = _prec_of(u)
+    batch = u.numel() // N
+    _check_dev(u, "u", numel=batch * N)
+    _check_dev(v, "v", torch.float64)
+    if v.numel() not in (N, batch * N):
+        raise ValueError("v must hold N or batch*N values")
+    v_stride = 0 if v.numel() == N else N
+    if ckpt is not None:
+        _check_dev(ckpt, "ckpt", u.dtype, num_checkpoints(steps, ckpt_every) * batch * N)
+    if sums is None:
+        sums = torch.empty((batch, steps + 1, 2), dtype=torch.float64, device=u.device)
+    _check_dev(sums, "sums", torch.float64, batch * (steps + 1) * 2)
+    wb = 0
+    if work is not None:
+        _check_dev(work, "work")
+        wb = work.numel() * work.element_size()
+    _check(lib.strang_run_sums(plan.handle, prec, batch, _dev_ptr(v), v_stride, _dev_ptr(u), float(gamma),
+                               float(dt), int(steps), _dev_ptr(ckpt), int(ckpt_every), _dev_ptr(sums),
+                               _dev_ptr(work), wb, _stream(stream)), "strang_run_sums")
+    return sums
 
 
 def strang_adjoint(plan: Plan, v, uT, gT, gamma: float, dt: float, steps: int, ckpt, ckpt_every: int,

@@ -459,13 +459,98 @@ bool conv_available(const lt_plan &p, int which, const Sched &s)
     return s.bluestein && s.passes == 2 && d.ok && d.passes == 2 && d.L == s.L && d.L1 == s.L1 && d.L2 == s.L2;
 }
 
+// Per-step sums of a run (Sec. 3.3 norm and potential energy at every step
+// boundary j = 0..steps).  The passes at a boundary write per-tile partials
+// into slot j mod CH of `part` ([slot][b][PT][2], PT bounding the tiles of
+// any column launch of the schedule); every CH steps, and after the last, one
+// launch reduces the filled slots into hist[b][j][2] in a fixed order and the
+// slots are cleared for reuse.  The partial area is capped (kSumBytes).
+constexpr size_t kSumBytes = size_t(64) << 20;
+
+struct SumSink {
+    double *part = nullptr, *hist = nullptr;
+    int PT = 1, batch = 1;
+    int64_t CH = 1, steps = 0, N = 1;
+    double gamma = 1.0;
+    explicit operator bool() const { return hist != nullptr; }
+    double *slot(int64_t j) const { return part + (size_t)(j % CH) * batch * PT * 2; }
+};
+
+// tiles of the widest column launch of a schedule (row length L2, or L2 L3 for
+// the outer pass of three levels): every kernel variant holds at least
+// min(cols, 1024 / L1) columns per tile, and at least one
+int sum_tiles(const Sched &s)
+{
+    const int64_t M = s.passes == 3 ? (int64_t)s.L2 * s.L3 : (int64_t)s.L2;
+    if (s.passes == 1) return 1;
+    int c = std::max(1, std::min(s.cols, s.L1 <= 1024 ? 1024 / s.L1 : 1));
+    return (int)((M + c - 1) / c);
+}
+
+int64_t sum_slots(int batch, int PT, int64_t steps, bool one_launch = false)
+{
+    if (one_launch) return steps + 1;  // a resident run writes every step from one launch
+    const int64_t per = (int64_t)batch * PT * 16;
+    return std::max<int64_t>(1, std::min<int64_t>(steps + 1, (int64_t)(kSumBytes / (size_t)std::max<int64_t>(per, 1))));
+}
+
+size_t sum_bytes(const Sched &s, int batch, int64_t steps)
+{
+    const int PT = sum_tiles(s);
+    return align_up((size_t)sum_slots(batch, PT, steps, s.passes == 1) * batch * PT * 16);
+}
+
+SumSink make_sink(const Sched &s, int batch, int64_t steps, int64_t N, double gamma, void *part, double *hist)
+{
+    SumSink k;
+    if (!hist) return k;
+    k.part = (double *)part;
+    k.hist = hist;
+    k.PT = sum_tiles(s);
+    k.batch = batch;
+    k.steps = steps;
+    k.N = N;
+    k.gamma = gamma;
+    k.CH = sum_slots(batch, k.PT, steps, s.passes == 1);
+    return k;
+}
+
+lt_status sums_begin(const SumSink &k, hipStream_t st)
+{
+    if (!k) return LT_OK;
+    HIP_TRY(launch_zero(k.part, k.CH * k.batch * k.PT * 2, st), "step sums");
+    return LT_OK;
+}
+
+// after the pass that wrote boundary j: reduce a full chunk (or the last one)
+lt_status sums_after(const SumSink &k, int64_t j, hipStream_t st)
+{
+    if (!k) return LT_OK;
+    if ((j + 1) % k.CH != 0 && j != k.steps) return LT_OK;
+    const int64_t j0 = j - j % k.CH;
+    HIP_TRY(launch_step_sums_finish(k.part, k.PT, k.batch, j0, j - j0 + 1, k.steps, 1.0 / (double)k.N,
+                                    1.0 / (k.gamma * (double)k.N), k.hist, st),
+            "step sums");
+    if (j != k.steps) HIP_TRY(launch_zero(k.part, k.CH * k.batch * k.PT * 2, st), "step sums");
+    return LT_OK;
+}
+
+void sums_on(ColArgs &a, const SumSink &k, int64_t j, const double *v)
+{
+    if (!k) return;
+    a.sum_part = k.slot(j);
+    a.sum_pt = k.PT;
+    a.sum_v = v;
+}
+
 // forward run of a state batch through the two-pass sequence; `conv` (chirp-z
 // lattices) is the spectrum from conv_spectrum, or null for the chirp-z DFT
 // pair per step
 lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int prec, int batch,
                            const double *v, int64_t v_stride, void *u, double gamma, double dt,
                            int64_t steps, void *ckpt, int64_t ck_every, const double *ktab, void *W,
-                           void *ptab, const void *conv, hipStream_t st, bool ck_transposed = false)
+                           void *ptab, const void *conv, hipStream_t st, bool ck_transposed = false,
+                           const SumSink &sums = SumSink())
 {
     const int64_t N = p.N;
     const size_t S = esz(prec);
@@ -480,7 +565,11 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
         R.last.chirp = 0;
         R.row.bhat = (const double *)conv;
     }
+    lt_status ls;
+    if ((ls = sums_begin(sums, st))) return ls;
+    sums_on(R.first, sums, 0, v);
     HIP_TRY(launch_col(prec, s, R.first, batch, st), "column pass");
+    if ((ls = sums_after(sums, 0, st))) return ls;
     for (int64_t t = 0; t < steps; ++t) {
         R.row.conj_tab = 0;
         HIP_TRY(launch_row(prec, s, R.row, batch, st), "row pass");
@@ -500,10 +589,13 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
             m.ck_chirp = chirpz ? 1 : 0;
             m.ck_t = ck_transposed ? 1 : 0;
         }
+        sums_on(m, sums, k, v);
         HIP_TRY(launch_col(prec, s, m, batch, st), "column pass (potential)");
+        if ((ls = sums_after(sums, k, st))) return ls;
     }
+    sums_on(R.last, sums, steps, v);
     HIP_TRY(launch_col(prec, s, R.last, batch, st), "column pass (last)");
-    return LT_OK;
+    return sums_after(sums, steps, st);
 }
 
 // Three-level run (power-of-two L of 2^24 points or more, L = L1 L2 L3, M =
@@ -515,7 +607,7 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
 lt_status three_level_forward(lt_plan &p, const Sched &s, const DevTables &D, int prec, int batch,
                               const double *v, int64_t v_stride, void *u, double gamma, double dt,
                               int64_t steps, void *ckpt, int64_t ck_every, const double *ktab, void *ptab,
-                              hipStream_t st)
+                              hipStream_t st, const SumSink &sums = SumSink())
 {
     const int64_t N = p.N, M = (int64_t)s.L2 * s.L3;
     const size_t S = esz(prec);
@@ -588,7 +680,11 @@ lt_status three_level_forward(lt_plan &p, const Sched &s, const DevTables &D, in
     r.ktab_n = D.ktab_n;
     r.twb = D.twb;
     r.rad = s.rb;
+    lt_status ls;
+    if ((ls = sums_begin(sums, st))) return ls;
+    sums_on(first, sums, 0, v);
     HIP_TRY(launch_col(prec, s, first, batch, st), "column pass");
+    if ((ls = sums_after(sums, 0, st))) return ls;
     for (int64_t t = 0; t < steps; ++t) {
         HIP_TRY(launch_col_inner(prec, fwd, blocks, st), "inner column pass");
         HIP_TRY(launch_row(prec, s, r, batch, st), "row pass");
@@ -602,10 +698,13 @@ lt_status three_level_forward(lt_plan &p, const Sched &s, const DevTables &D, in
             m.ck_v = v;
             m.ck_phase = half;
         }
+        sums_on(m, sums, k, v);
         HIP_TRY(launch_col(prec, s, m, batch, st), "column pass (potential)");
+        if ((ls = sums_after(sums, k, st))) return ls;
     }
+    sums_on(last, sums, steps, v);
     HIP_TRY(launch_col(prec, s, last, batch, st), "column pass (last)");
-    return LT_OK;
+    return sums_after(sums, steps, st);
 }
 
 // ---------------------------------------------------------------- batches
@@ -774,8 +873,8 @@ SwapWork swap_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool
 // (checkpoints are stored in lattice order by the checkpoint passes), and the
 // state is transposed back.
 lt_status swapped_forward(lt_plan &p, int prec, int batch, const double *v, int64_t v_stride, void *u,
-                          double gamma, double dt, int64_t steps, void *ckpt, int64_t ckpt_every, void *work,
-                          size_t work_bytes, void *stream)
+                          double gamma, double dt, int64_t steps, void *ckpt, int64_t ckpt_every, double *sums,
+                          void *work, size_t work_bytes, void *stream)
 {
     hipStream_t hs = (hipStream_t)stream;
     lt_status st;
@@ -784,8 +883,10 @@ lt_status swapped_forward(lt_plan &p, int prec, int batch, const double *v, int6
     const DevTables &D = p.dev[2][prec];
     const bool shared = v_stride == 0;
     const SwapWork L = swap_layout(p, s, prec, batch, shared);
+    const size_t need = L.total + (sums ? sum_bytes(s, batch, steps) : 0);
     Scratch sc;
-    if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
+    if ((st = get_work(sc, work, work_bytes, need, hs))) return st;
+    const SumSink sink = make_sink(s, batch, steps, p.N, gamma, at(sc.ptr, L.total), sums);
     double *ktab = (double *)at(sc.ptr, L.run.ktab);
     if ((st = make_ktab(p, s, ktab, gamma, dt, hs))) return st;
     const int n1 = s.L2, n2 = s.L1;
@@ -799,7 +900,7 @@ lt_status swapped_forward(lt_plan &p, int prec, int batch, const double *v, int6
             "potential transpose");
     if ((st = two_pass_forward(p, s, D, prec, batch, V, shared ? 0 : p.N, U, gamma, dt, steps, ckpt,
                                ckpt ? ckpt_every : 0, ktab, at(sc.ptr, L.run.w), at(sc.ptr, L.run.ptab), nullptr,
-                               hs, true)))
+                               hs, true, sink)))
         return st;
     HIP_TRY(launch_transpose((int)esz(prec), u, U, batch, n2, n1, p.N, p.N, hs), "state transpose");
     return LT_OK;
@@ -967,27 +1068,47 @@ lt_status strang_adjoint_workspace_size(const lt_plan *p, lt_prec prec, int32_t 
     return LT_OK;
 }
 
-lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, int64_t v_stride,
-                     void *u, double gamma, double dt, int64_t steps, void *ckpt, int64_t ckpt_every,
-                     void *work, size_t work_bytes, void *stream)
+namespace {
+lt_status run_forward(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, int64_t v_stride, void *u,
+                      double gamma, double dt, int64_t steps, void *ckpt, int64_t ckpt_every, double *sums,
+                      void *work, size_t work_bytes, void *stream)
 {
     lt_status st = check_common(cp, prec, batch, gamma, dt, steps);
     if (st) return st;
     lt_plan &p = *const_cast<lt_plan *>(cp);
-    if (batch == 0 || steps == 0) return LT_OK;
-    if (!v || !u) return fail(LT_E_ARG, "v and u must not be NULL");
+    if (batch == 0) return LT_OK;
+    if (!v || !u) {
+        if (steps == 0 && !sums) return LT_OK;
+        return fail(LT_E_ARG, "v and u must not be NULL");
+    }
     if (v_stride != 0 && v_stride < p.N) return fail(LT_E_ARG, "v_stride must be 0 or >= N");
     if (ckpt && ckpt_every < 1) return fail(LT_E_ARG, "ckpt_every must be >= 1 with a checkpoint buffer");
-    if (p.sched[2][prec].ok)
-        return swapped_forward(p, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every, work,
-                               work_bytes, stream);
     hipStream_t hs = (hipStream_t)stream;
+    if (steps == 0) {
+        if (!sums) return LT_OK;
+        // no step: the sums of u(0) alone
+        if ((st = ensure_device_tables(p, 0, prec, stream))) return st;
+        Scratch sc;
+        const int nb = diag_partials();
+        if ((st = get_work(sc, work, work_bytes, align_up((size_t)batch * nb * 16), hs))) return st;
+        double *pp = (double *)sc.ptr;
+        HIP_TRY(launch_sums(prec, u, p.N, p.N, batch, nullptr, v, v_stride, pp, hs), "step sums");
+        HIP_TRY(launch_step_sums_finish(pp, nb, batch, 0, 1, 0, 1.0 / (double)p.N, 1.0 / (gamma * (double)p.N), sums,
+                                        hs),
+                "step sums");
+        return LT_OK;
+    }
+    if (p.sched[2][prec].ok)
+        return swapped_forward(p, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every, sums, work,
+                               work_bytes, stream);
     if ((st = ensure_device_tables(p, 0, prec, stream))) return st;
     const Sched &s = p.sched[0][prec];
     const DevTables &D = p.dev[0][prec];
     const RunWork L = run_layout(p, s, prec, batch, v_stride == 0);
+    const size_t need = L.total + (sums ? sum_bytes(s, batch, steps) : 0);
     Scratch sc;
-    if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
+    if ((st = get_work(sc, work, work_bytes, need, hs))) return st;
+    const SumSink sink = make_sink(s, batch, steps, p.N, gamma, at(sc.ptr, L.total), sums);
     double *ktab = (double *)at(sc.ptr, L.ktab);
     if ((st = make_ktab(p, s, ktab, gamma, dt, hs))) return st;
     if (s.passes == 1) {
@@ -1016,15 +1137,16 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
         a.ck_every = ckpt ? ckpt_every : 0;
         a.ck_stride = (int64_t)batch * p.N;
         a.batch = batch;
+        a.sum_part = sink.part;
         HIP_TRY(launch_resident(prec, s, a, batch, hs), "resident run");
-        return LT_OK;
+        return sums_after(sink, steps, hs);
     }
     if (ckpt)
         HIP_TRY(hipMemcpyAsync(ckpt, u, (size_t)batch * p.N * esz(prec), hipMemcpyDeviceToDevice, hs),
                 "checkpoint 0");
     if (s.passes == 3)
         return three_level_forward(p, s, D, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every,
-                                   ktab, at(sc.ptr, L.ptab), hs);
+                                   ktab, at(sc.ptr, L.ptab), hs, sink);
     void *conv = nullptr;
     if (steps >= kConvMinSteps && conv_available(p, 0, s)) {
         if ((st = ensure_device_tables(p, 0, LT_C128, stream))) return st;
@@ -1032,7 +1154,46 @@ lt_status strang_run(const lt_plan *cp, lt_prec prec, int32_t batch, const doubl
         if ((st = conv_spectrum(p, 0, ktab, conv, at(sc.ptr, L.conv_tmp), hs))) return st;
     }
     return two_pass_forward(p, s, D, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every,
-                            ktab, at(sc.ptr, L.w), at(sc.ptr, L.ptab), conv, hs);
+                            ktab, at(sc.ptr, L.w), at(sc.ptr, L.ptab), conv, hs, false, sink);
+}
+}  // namespace
+
+lt_status strang_run(const lt_plan *p, lt_prec prec, int32_t batch, const double *v, int64_t v_stride, void *u,
+                     double gamma, double dt, int64_t steps, void *ckpt, int64_t ckpt_every, void *work,
+                     size_t work_bytes, void *stream)
+{
+    return run_forward(p, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every, nullptr, work,
+                       work_bytes, stream);
+}
+
+lt_status strang_run_sums_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch, int32_t shared_v,
+                                         int64_t steps, size_t *bytes)
+{
+    if (!p || !bytes) return fail(LT_E_ARG, "NULL argument");
+    if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
+    if (batch < 0 || steps < 0) return fail(LT_E_ARG, "batch and steps must be >= 0");
+    const int w = p->sched[2][prec].ok ? 2 : 0;
+    size_t run = 0;
+    lt_status st = strang_workspace_size(p, prec, batch, shared_v, &run);
+    if (st) return st;
+    if (steps == 0) {
+        *bytes = align_up((size_t)batch * diag_partials() * 16);
+        return LT_OK;
+    }
+    const size_t base = w == 2 ? swap_layout(*p, p->sched[2][prec], prec, batch, shared_v != 0).total
+                               : run_layout(*p, p->sched[0][prec], prec, batch, shared_v != 0).total;
+    *bytes = base + sum_bytes(p->sched[w][prec], batch, steps);
+    (void)run;
+    return LT_OK;
+}
+
+lt_status strang_run_sums(const lt_plan *p, lt_prec prec, int32_t batch, const double *v, int64_t v_stride,
+                          void *u, double gamma, double dt, int64_t steps, void *ckpt, int64_t ckpt_every,
+                          double *sums, void *work, size_t work_bytes, void *stream)
+{
+    if (!sums) return fail(LT_E_ARG, "sums must not be NULL");
+    return run_forward(p, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every, sums, work, work_bytes,
+                       stream);
 }
 
 lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, int64_t v_stride,

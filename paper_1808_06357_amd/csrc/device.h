@@ -156,6 +156,36 @@ __device__ __forceinline__ FDiv fdiv_make(int d) { return {d, 1.0 / (double)d}; 
 __device__ __forceinline__ int fdiv(int x, const FDiv &f) { return (int)(((double)x + 0.5) * f.r); }
 __device__ __forceinline__ int64_t fdiv64(int64_t x, const FDiv &f) { return (int64_t)(((double)x + 0.5) * f.r); }
 
+// Sum of two per-thread doubles over a workgroup of NT threads (NT a
+// multiple of 64), in a fixed order: a butterfly across each wave, then the
+// waves in order.  The totals land in thread 0; every thread must call it.
+template <int NT>
+__device__ __forceinline__ void block_sum2(double &a, double &b)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    __shared__ double red[2][NT / 64];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = a;
+        red[1][w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = red[0][0];
+        b = red[1][0];
+#pragma unroll
+        for (int i = 1; i < NT / 64; ++i) {
+            a += red[0][i];
+            b += red[1][i];
+        }
+    }
+    __syncthreads();
+}
+
 // chirp c_n = exp(-pi i (n^2 mod 2N) / N), exact integer reduction
 __device__ __forceinline__ void chirp(int64_t n, int64_t N, double &c, double &s)
 {

@@ -166,6 +166,8 @@ __device__ void col_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
     // ---- point-domain work (natural index n)
     const double *vb = a.v ? a.v + b * a.v_bs : nullptr;
     const double *vb2 = a.v && a.v2 ? a.v2 + b * a.v_bs : nullptr;
+    const double *sv = a.sum_part ? a.sum_v + b * a.v_bs : nullptr;
+    double s1 = 0.0, s2 = 0.0;
     for (int e = threadIdx.x; e < L1 * C; e += kThreads) {
         const int n1 = fdiv(e, dC), qc = e - n1 * C;
         if (qc >= cw) continue;
@@ -180,6 +182,11 @@ __device__ void col_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
         }
         if (!a.adjoint) {
             if (a.ck) col_checkpoint(x, a, b, n);
+            if (sv) {
+                const double q = (double)x.x * (double)x.x + (double)x.y * (double)x.y;
+                s1 += q;
+                s2 += sv[n] * q;
+            }
             x = col_mid(x, a, vb, vb2, n);
             if (a.out) ((cx<T> *)a.out)[b * a.out_bs + n] = x;
             else s[e0] = x;
@@ -226,6 +233,14 @@ __device__ void col_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
             }
             s[e0] = cmul_d(x, c, sn);
             s[e0 + C] = cmul_d(y, c, sn);
+        }
+    }
+    if (a.sum_part) {
+        block_sum2<kThreads>(s1, s2);
+        if (threadIdx.x == 0) {
+            double *pb = a.sum_part + ((int64_t)b * a.sum_pt + tile) * 2;
+            pb[0] = s1;
+            pb[1] = s2;
         }
     }
     if (!a.post_fwd) return;
@@ -312,11 +327,28 @@ __device__ void resident_body(const ResArgs &a, int64_t b, cx<T> *s)
     const double *vb = a.v + b * a.v_bs;
     const double *B = a.bhat;
 
+    // per-step sums of |u_j|^2 and v |u_j|^2 (optional)
+    double s1 = 0.0, s2 = 0.0;
+    auto put_sums = [&](int64_t j) {
+        block_sum2<kThreads>(s1, s2);
+        if (threadIdx.x == 0) {
+            double *pb = a.sum_part + (j * a.batch + b) * 2;
+            pb[0] = s1;
+            pb[1] = s2;
+        }
+        s1 = 0.0;
+        s2 = 0.0;
+    };
     // first half potential step (times the chirp for chirp-z)
     for (int n = threadIdx.x; n < L; n += kThreads) {
         cx<T> x = {0, 0};
         if (n < N) {
             x = u[n];
+            if (a.sum_part) {
+                const double q = (double)x.x * (double)x.x + (double)x.y * (double)x.y;
+                s1 += q;
+                s2 += vb[n] * q;
+            }
             if (a.ck) ((cx<T> *)a.ck)[b * N + n] = x;
             double c, sn;
             expm_i(a.phase_half * vb[n], c, sn);
@@ -331,6 +363,7 @@ __device__ void resident_body(const ResArgs &a, int64_t b, cx<T> *s)
         }
         s[n] = x;
     }
+    if (a.sum_part) put_sums(0);
     __syncthreads();
     for (int64_t st = 0; st < a.steps; ++st) {
         res_fft<T, EPT>(s, a);
@@ -364,6 +397,11 @@ __device__ void resident_body(const ResArgs &a, int64_t b, cx<T> *s)
         for (int n = threadIdx.x; n < L; n += kThreads) {
             cx<T> x = conjg(s[n]);
             if (n >= N) { s[n] = {0, 0}; continue; }
+            if (a.sum_part) {
+                const double q = (double)x.x * (double)x.x + (double)x.y * (double)x.y;
+                s1 += q;
+                s2 += vb[n] * q;
+            }
             if (last || ckpt) {
                 double c, sn;
                 expm_i(a.phase_half * vb[n], c, sn);
@@ -380,6 +418,7 @@ __device__ void resident_body(const ResArgs &a, int64_t b, cx<T> *s)
             }
             s[n] = mul_expm_i(x, 2.0 * a.phase_half * vb[n]);
         }
+        if (a.sum_part) put_sums(st + 1);
         __syncthreads();
     }
 }
@@ -672,6 +711,37 @@ __global__ void k_proj_finish(const double *partial, int nblk, int batch, double
     out[2 * b + 1] = s1;
 }
 
+// per-step sums of a run: block (j, b) adds the PT tile partials of slot j
+// (step j0 + j) of state b in a fixed order and writes the norm^2 and the
+// potential energy of that step
+__global__ void __launch_bounds__(256) k_step_sums_finish(const double *part, int PT, int batch, int64_t j0,
+                                                          int64_t steps, double inv_n, double inv_gn,
+                                                          double *hist)
+{
+    const int64_t j = blockIdx.x;
+    const int b = blockIdx.y;
+    const double *pb = part + ((size_t)j * batch + b) * (size_t)PT * 2;
+    double s1 = 0.0, s2 = 0.0;
+    for (int t = threadIdx.x; t < PT; t += 256) {
+        s1 += pb[2 * t];
+        s2 += pb[2 * t + 1];
+    }
+    block_sum2<256>(s1, s2);
+    if (threadIdx.x == 0) {
+        double *h = hist + ((size_t)b * (steps + 1) + j0 + j) * 2;
+        h[0] = s1 * inv_n;
+        h[1] = s2 * inv_gn;
+    }
+}
+
+// a fill kernel instead of a memset, so that the zeroing can sit in a
+// captured graph
+__global__ void k_zero(double *dst, int64_t count)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = 0.0;
+}
+
 __global__ void k_reduce_batch(double *dst, const double *src, int64_t N, int batch)
 {
     for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N;
@@ -710,7 +780,7 @@ int kernels_init()
     static int done = 0;
     if (done) return 0;
     done = 1;
-    const int lim = 160 * 1024;
+    const int lim = kMaxDynLds;
     hipFuncSetAttribute((const void *)k_col<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_col<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     hipFuncSetAttribute((const void *)k_col<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
@@ -816,6 +886,23 @@ int launch_resident_multi(int prec, const ResArgs *d, int ninst, size_t lds, voi
                             stream, d);
     return timed_launch(LT_KIND_RESIDENT, k_resident_multi<float, 16>, dim3(ninst), dim3(kThreads), lds, stream,
                         d);
+}
+
+int launch_step_sums_finish(const double *part, int PT, int batch, int64_t j0, int64_t count, int64_t steps,
+                            double inv_n, double inv_gn, double *hist, void *stream)
+{
+    if (count <= 0) return 0;
+    hipLaunchKernelGGL(k_step_sums_finish, dim3((unsigned)count, batch), dim3(256), 0, (hipStream_t)stream, part, PT,
+                       batch, j0, steps, inv_n, inv_gn, hist);
+    return (int)hipGetLastError();
+}
+
+int launch_zero(double *dst, int64_t count, void *stream)
+{
+    if (count <= 0) return 0;
+    hipLaunchKernelGGL(k_zero, dim3(grid1d(count) > 1024 ? 1024 : grid1d(count)), dim3(256), 0, (hipStream_t)stream,
+                       dst, count);
+    return (int)hipGetLastError();
 }
 
 int launch_fft_single(const Radices &ra, const void *twa, void *buf, int64_t L, void *stream)

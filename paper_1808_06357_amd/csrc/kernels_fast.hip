@@ -353,16 +353,36 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
                 for (int r = 0; r < R; ++r) s[F::addr(q, t + r * BPS)] = conjg(v[j * R + r]);
             }
             __syncthreads();
-            const double *cv = a.ck_v + b * a.v_bs;
-            cx<T> *ck = (cx<T> *)a.ck + b * a.ck_bs;
+            // the same loop forms the step's sums of |u|^2 and v |u|^2 when
+            // asked for (|x| = |u| at the boundary)
+            const double *cv = a.ck ? a.ck_v + b * a.v_bs : nullptr;
+            const double *sv = a.sum_part ? a.sum_v + b * a.v_bs : nullptr;
+            cx<T> *ck = a.ck ? (cx<T> *)a.ck + b * a.ck_bs : nullptr;
+            double s1 = 0.0, s2 = 0.0;
 #pragma unroll 1
             for (int i = threadIdx.x; i < C * L1; i += NT) {
                 const int k1 = i / C, q = i - k1 * C;
                 const int64_t n = (int64_t)k1 * L2 + c0 + q;
                 if (n < a.Nvalid) {
-                    double c, sn;
-                    expm_i(a.ck_phase * cv[n], c, sn);
-                    ck[a.ck_t ? (int64_t)(c0 + q) * L1 + k1 : n] = cmul_d(s[F::addr(q, k1)], c, sn);
+                    const cx<T> x = s[F::addr(q, k1)];
+                    if (ck) {
+                        double c, sn;
+                        expm_i(a.ck_phase * cv[n], c, sn);
+                        ck[a.ck_t ? (int64_t)(c0 + q) * L1 + k1 : n] = cmul_d(x, c, sn);
+                    }
+                    if (sv) {
+                        const double q2 = (double)x.x * (double)x.x + (double)x.y * (double)x.y;
+                        s1 += q2;
+                        s2 += sv[n] * q2;
+                    }
+                }
+            }
+            if (sv) {
+                block_sum2<NT>(s1, s2);
+                if (threadIdx.x == 0) {
+                    double *pb = a.sum_part + ((int64_t)b * a.sum_pt + tile) * 2;
+                    pb[0] = s1;
+                    pb[1] = s2;
                 }
             }
         }
@@ -774,16 +794,16 @@ int col_go(const ColArgs &a, int batch, void *stream)
             static bool attr_io = false;
             if (!attr_io) {
                 hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 5, Rs...>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
                 hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 6, Rs...>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
                 attr_io = true;
             }
             constexpr int C = NT * E / Radix<Rs...>::prod;
             return timed(LT_KIND_COLUMN, k, dim3(a.L2 / C, batch), dim3(NT), lds_bytes<T, V>(), stream, a);
         }
     }
-    if (a.ck) {
+    if (a.ck || a.sum_part) {
         if (!a.v || a.v2 || !a.ptab) return -1;
         k = k_colf<T, E, NT, MINW, 7, Rs...>;
     } else if (a.v) {
@@ -795,16 +815,16 @@ int col_go(const ColArgs &a, int batch, void *stream)
     static bool attr = false;
     if (!attr) {
         hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 0, Rs...>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 1, Rs...>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 3, Rs...>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 7, Rs...>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         if constexpr (sizeof(T) == 8)
             hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 2, Rs...>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         attr = true;
     }
     constexpr int C = NT * E / Radix<Rs...>::prod;
@@ -821,9 +841,9 @@ int row_go(const RowArgs &a, int batch, void *stream)
     static bool attr = false;
     if (!attr) {
         hipFuncSetAttribute((const void *)k_rowf<T, E, NT, MINW, 0, Rs...>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         hipFuncSetAttribute((const void *)k_rowf<T, E, NT, MINW, 1, Rs...>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         attr = true;
     }
     constexpr int RW = NT * E / Radix<Rs...>::prod;
@@ -892,7 +912,7 @@ int col_multi_go(const BatchDesc *d, const int *idx, const int *start, int nmem,
     auto k = k_colf_multi<T, E, NT, MINW, Rs...>;
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         attr = true;
     }
     return timed_multi(LT_KIND_COLUMN, k, dim3(nblocks), dim3(NT), lds_bytes<T, 1>(), stream, d, idx, start, nmem,
@@ -907,7 +927,7 @@ int row_multi_go(const BatchDesc *d, const int *idx, const int *start, int nmem,
     auto k = k_rowf_multi<T, E, NT, MINW, MID, Rs...>;
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         attr = true;
     }
     return timed_multi(LT_KIND_ROW, k, dim3(nblocks), dim3(NT), lds_bytes<T, 1>(), stream, d, idx, start, nmem,
@@ -1013,7 +1033,7 @@ int adj_go(const ColArgs &a, int batch, void *stream)
     auto k = k_colf_adj<T, E, NT, MINW, Rs...>;
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         attr = true;
     }
     constexpr int H = NT * E / Radix<Rs...>::prod / 2;

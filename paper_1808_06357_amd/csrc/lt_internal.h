@@ -16,6 +16,9 @@ constexpr int kThreads = 256;           // workgroup size of every FFT kernel
 constexpr int kMaxStages = 24;
 constexpr int64_t kTileElems = 4096;     // complex elements per workgroup tile
 constexpr int64_t kWideRow = 8192;       // row length of the widest two-pass split (one row per workgroup)
+// dynamic LDS every FFT kernel may request: the 160 KB of a CU less 1 KB for
+// the static arrays of the block reductions (static + dynamic must fit)
+constexpr int kMaxDynLds = 159 * 1024;
 
 // Radix sequence of one sub-transform of length L (product of radices).
 struct Radices {
@@ -120,6 +123,11 @@ struct ColArgs {
     double gcoef;                     // coefficient of Im(conj(mu) a) in the accumulator
     const void *reset; int64_t reset_bs;  // checkpoint replacing the recomputed state, or null
     double reset_phase;               // a = exp(-i reset_phase v) * ckpt (times c_n for chirp-z)
+    // per-step sums at a step boundary (the point values x have |x| = |u_j|):
+    // sum_part[(b sum_pt + tile) 2 + {0, 1}] = (sum |x|^2, sum sum_v[n] |x|^2)
+    // over the tile's valid points; sum_v strided as v (v_bs)
+    double *sum_part; int sum_pt;
+    const double *sum_v;
 };
 
 // Spectral multiplier of a row pass at row-pass position pos = k1 L2 + k2:
@@ -151,6 +159,7 @@ struct ResArgs {
     int64_t steps;
     void *ck; int64_t ck_every; int64_t ck_stride; // checkpoint c at ck + c*ck_stride + b*N
     int64_t batch;
+    double *sum_part;                  // optional: (sum |u_j|^2, sum v |u_j|^2) at ((j batch + b) 2)
 };
 
 // One two-pass problem of a batch: its column / row arguments per role and
@@ -176,6 +185,10 @@ int launch_col(int prec, const Sched &s, const ColArgs &a, int batch, void *stre
 int launch_row(int prec, const Sched &s, const RowArgs &a, int batch, void *stream);
 int launch_resident(int prec, const Sched &s, const ResArgs &a, int batch, void *stream);
 int launch_fft_single(const Radices &ra, const void *twa_c128, void *buf, int64_t L, void *stream);
+// per-step sums: hist[b][j0 + j] = (sum of the PT partials of slot j) * (inv_n, inv_gn), j < count
+int launch_step_sums_finish(const double *part, int PT, int batch, int64_t j0, int64_t count, int64_t steps,
+                            double inv_n, double inv_gn, double *hist, void *stream);
+int launch_zero(double *dst, int64_t count, void *stream);
 int launch_col_multi(int prec, const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks,
                      int off, int64_t g, size_t lds, void *stream);
 int launch_row_multi(int prec, const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks,

@@ -66,7 +66,7 @@ def test_conservation_paper_setting(lt):
     ck = torch.empty(nck * N, dtype=torch.complex128, device="cuda")
     lt.strang_run(plan, vv, u, gamma, dt, steps, ckpt=ck, ckpt_every=every)
     got = lt.lattice_diagnostics(plan, vv, ck.view(nck, N), gamma).cpu().numpy()
-    ref = np.asarray(hist).reshape(-1, 2)[0:steps:every]
+    ref = np.asarray(hist)[0, 0:steps:every, :2]
     assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-11
     norm = got[:, 0]
     delta = (norm.max() - norm.min()) / norm.mean()

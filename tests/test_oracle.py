@@ -502,6 +502,25 @@ def test_diagnostics_single_mode():
     assert abs(E - (2 * PI * PI * c.gamma * (hv @ hv) + np.mean(c.v) / c.gamma)) < 1e-10
 
 
+def test_history_potential_term():
+    """The history's third column is the potential term (1/(gamma N)) sum v |u|^2
+    of <Hu, u> (Sec. 3.3).  A single mode has |u| = 1 at every point and the
+    lattice rule integrates cos(2 pi x_j) to 0 (z_j != 0 mod N), so under
+    v = sum_j (1 - cos 2 pi x_j) the term of u0 is d / gamma; under a constant
+    v0 it is v0 ||u||^2 / gamma at every step."""
+    c = W.box_d2_n1031()
+    h, s, _ = O.index_set(c.Z, c.n, c.I)
+    hv = h[77].astype(np.int64)
+    x = O.points(c.Z, c.n)
+    u0 = np.exp(2j * PI * (x @ hv))
+    _, hist = O.strang_run(c.n, s, c.v, u0, c.gamma, c.dt, 3, history=True)
+    assert abs(hist[0, 0, 2] - 2.0 / c.gamma) < 1e-12
+    assert abs(hist[0, 0, 1] - (2 * PI * PI * c.gamma * (hv @ hv) + 2.0 / c.gamma)) < 1e-9
+    v0 = 0.75
+    _, hist = O.strang_run(c.n, s, np.full(c.N, v0), c.u0, c.gamma, c.dt, 9, history=True)
+    assert np.max(np.abs(hist[0, :, 2] - v0 * hist[0, :, 0] / c.gamma)) < 1e-12
+
+
 # ----------------------------------------------------------------- adjoint
 def _small_problem(batch=1, shared=True):
     Z, n = np.array([[1, 34]]), np.array([55])
