@@ -247,6 +247,46 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
                              size_t work_bytes, void *stream);
 
 /*
+ * Batch objects -- the problems of strang_run_batched planned once, for
+ * callers that advance the same batch again and again (and may capture the
+ * advance into a HIP graph).
+ *
+ * strang_batch_create takes the arguments of strang_run_batched (same
+ * meaning; host arrays of length B holding device pointers).  It allocates
+ * the batch's device memory (workspace and descriptor tables), builds every
+ * member's kinetic table, merged potential table and chirp-z convolution
+ * spectrum from gamma, dt and v on `stream`, and returns once they are built.
+ * The object keeps the device pointers v[b] and u[b]: both buffers must stay
+ * allocated, and v[b] unchanged, until the object is destroyed.
+ *
+ * strang_batch_run advances every u[b] in place by steps[b] Strang steps
+ * (eq. (StrangTDSE) for each member; the same passes as strang_run_batched).
+ * It only enqueues kernels and event operations on `stream`: no allocation,
+ * copy, memset or host wait, so it may be captured into a HIP graph, and each
+ * replay advances the states once more.  Calls on one object must not overlap
+ * (they share the object's workspace).
+ *
+ * strang_batch_autotune times the two register-staged kernel geometries
+ * (256 threads x 16 elements, 512 threads x 8) of every length class of the
+ * batch on scratch copies of the members' buffers (the states are untouched)
+ * and keeps the faster per class; it synchronizes `stream`.
+ * strang_batch_kernels lists the classes: key[i] > 0 is a column class of
+ * column length key[i], key[i] < 0 a row class (-key = 2 L2 + multiplier
+ * kind), variant[i] its geometry (up to cap entries; *ncls gets the count).
+ * strang_batch_destroy waits for the device and frees the object.
+ */
+typedef struct lt_batch lt_batch;
+lt_status strang_batch_create(int32_t B, const lt_plan *const *plans, lt_prec prec,
+                              const double *const *v, void *const *u, const double *gamma,
+                              const double *dt, const int64_t *steps, void *stream,
+                              lt_batch **out);
+lt_status strang_batch_run(const lt_batch *b, void *stream);
+lt_status strang_batch_autotune(lt_batch *b, int32_t reps, void *stream);
+lt_status strang_batch_kernels(const lt_batch *b, int32_t *ncls, int32_t *key, int32_t *variant,
+                               int32_t cap);
+void strang_batch_destroy(lt_batch *b);
+
+/*
  * lattice_projection_error -- the two key sums of the initial (spatial)
  * discretization error of Sec. 3.4: for a function g with Fourier
  * coefficients ghat(h) and its lattice approximation g_a (coefficients

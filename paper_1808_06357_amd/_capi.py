@@ -69,6 +69,11 @@ _SIGS = {
     "strang_adjoint_workspace_size": [_P, _i32, _i32, _i32, ctypes.POINTER(_sz)],
     "strang_adjoint": [_P, _i32, _i32, _P, _i64, _P, _P, _f64, _f64, _i64, _P, _i64, _P, _P, _P, _sz, _P],
     "strang_batched_workspace_size": [_i32, _P, _i32, ctypes.POINTER(_sz)],
+    "strang_batch_create": [_i32, _P, _i32, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_P)],
+    "strang_batch_run": [_P, _P],
+    "strang_batch_autotune": [_P, _i32, _P],
+    "strang_batch_kernels": [_P, ctypes.POINTER(_i32), _P, _P, _i32],
+    "strang_batch_destroy": [_P],
     "strang_run_batched": [_i32, _P, _i32, _P, _P, _P, _P, _P, _P, _sz, _P],
     "lattice_projection_error_workspace_size": [_P, _i32, _i32, ctypes.POINTER(_sz)],
     "lattice_projection_error": [_P, _i32, _i32, _P, _P, _P, _P, _sz, _P],
@@ -88,7 +93,8 @@ _SIGS = {
 for _name, _args in _SIGS.items():
     _fn = getattr(lib, _name)
     _fn.argtypes = _args
-    _fn.restype = ctypes.c_char_p if _name == "lt_last_error" else (None if _name == "lattice_plan_destroy" else ctypes.c_int)
+    _fn.restype = (ctypes.c_char_p if _name == "lt_last_error"
+                   else None if _name in ("lattice_plan_destroy", "strang_batch_destroy") else ctypes.c_int)
 
 
 def header_functions() -> list:
@@ -342,6 +348,67 @@ def strang_run_batched(plans: Sequence[Plan], vs, us, gammas, dts, steps, work=N
     _check(lib.strang_run_batched(B, parr, prec, varr, uarr, _np_ptr(g), _np_ptr(dtt), _np_ptr(st),
                                   _dev_ptr(work), wb, _stream(stream)), "strang_run_batched")
     return us
+
+
+class Batch:
+    """Owner of an lt_batch*: the problems of strang_run_batched planned once.
+    Holds references to the plans, potentials and states it points to."""
+
+    def __init__(self, handle: int, plans, vs, us):
+        self._h = handle
+        self._keep = (list(plans), list(vs), list(us))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            lib.strang_batch_destroy(h)
+
+
+def strang_batch_create(plans: Sequence[Plan], vs, us, gammas, dts, steps, stream=None) -> Batch:
+    """Plan B unrelated problems once (tables built on the device); the
+    returned object advances the states us in place on every strang_batch_run."""
+    import torch
+    B = len(plans)
+    if not (len(vs) == len(us) == len(gammas) == len(dts) == len(steps) == B):
+        raise ValueError("all per-problem sequences must have length B")
+    prec = _prec_of(us[0]) if B else LT_C64
+    for b in range(B):
+        _check_dev(us[b], f"u[{b}]", us[0].dtype, plans[b].N)
+        _check_dev(vs[b], f"v[{b}]", torch.float64, plans[b].N)
+    parr = (_P * max(B, 1))(*[p.handle for p in plans])
+    varr = (_P * max(B, 1))(*[v.data_ptr() for v in vs])
+    uarr = (_P * max(B, 1))(*[u.data_ptr() for u in us])
+    g = np.ascontiguousarray(gammas, dtype=np.float64)
+    dtt = np.ascontiguousarray(dts, dtype=np.float64)
+    st = np.ascontiguousarray(steps, dtype=np.int64)
+    h = _P()
+    _check(lib.strang_batch_create(B, parr, prec, varr, uarr, _np_ptr(g), _np_ptr(dtt), _np_ptr(st),
+                                   _stream(stream), ctypes.byref(h)), "strang_batch_create")
+    return Batch(h.value, plans, vs, us)
+
+
+def strang_batch_run(batch: Batch, stream=None) -> None:
+    _check(lib.strang_batch_run(batch.handle, _stream(stream)), "strang_batch_run")
+
+
+def strang_batch_autotune(batch: Batch, reps: int = 5, stream=None) -> None:
+    _check(lib.strang_batch_autotune(batch.handle, int(reps), _stream(stream)), "strang_batch_autotune")
+
+
+def strang_batch_kernels(batch: Batch):
+    """[(key, variant)] per register-staged class: key > 0 a column class of
+    that column length, key < 0 a row class (-key = 2 L2 + multiplier kind)."""
+    n = _i32()
+    _check(lib.strang_batch_kernels(batch.handle, ctypes.byref(n), None, None, 0), "strang_batch_kernels")
+    key = np.zeros(max(n.value, 1), dtype=np.int32)
+    var = np.zeros(max(n.value, 1), dtype=np.int32)
+    _check(lib.strang_batch_kernels(batch.handle, ctypes.byref(n), _np_ptr(key), _np_ptr(var), n.value),
+           "strang_batch_kernels")
+    return [(int(k), int(v)) for k, v in zip(key[:n.value], var[:n.value])]
 
 
 def splitting_workspace_size(plan: Plan, prec: int, batch: int, shared_v: bool, order: int) -> int:

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -727,6 +728,7 @@ struct MemberList {
     std::vector<int64_t> npass;  // per member
     size_t idx_off = 0, start_off = 0;  // int offsets in the list area
     int act = 0;                 // members still running at the current pass
+    int var = 1;                 // register-staged kernel geometry (1: 256 x 16, 2: 512 x 8)
 };
 
 BatchLayout batch_layout(int32_t B, const lt_plan *const *plans, int prec)
@@ -1068,6 +1070,8 @@ lt_status strang_adjoint_workspace_size(const lt_plan *p, lt_prec prec, int32_t 
     return LT_OK;
 }
 
+}  // extern "C"
+
 namespace {
 lt_status run_forward(const lt_plan *cp, lt_prec prec, int32_t batch, const double *v, int64_t v_stride, void *u,
                       double gamma, double dt, int64_t steps, void *ckpt, int64_t ckpt_every, double *sums,
@@ -1157,6 +1161,8 @@ lt_status run_forward(const lt_plan *cp, lt_prec prec, int32_t batch, const doub
                             ktab, at(sc.ptr, L.w), at(sc.ptr, L.ptab), conv, hs, false, sink);
 }
 }  // namespace
+
+extern "C" {
 
 lt_status strang_run(const lt_plan *p, lt_prec prec, int32_t batch, const double *v, int64_t v_stride, void *u,
                      double gamma, double dt, int64_t steps, void *ckpt, int64_t ckpt_every, void *work,
@@ -1340,9 +1346,32 @@ lt_status strang_batched_workspace_size(int32_t B, const lt_plan *const *plans, 
     return LT_OK;
 }
 
-lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec prec, const double *const *v,
-                             void *const *u, const double *gamma, const double *dt, const int64_t *steps,
-                             void *work, size_t work_bytes, void *stream)
+}  // extern "C"
+
+namespace {
+// Everything the launches of a batch need, built once: host copies of the
+// descriptors (kinetic tables, resident problems, two-pass problems, class
+// lists) and the device-side tables, all pointing into one workspace.
+struct BatchRun {
+    int prec = 0;
+    BatchLayout BL;
+    std::vector<KtabDesc> kd;
+    std::vector<ResArgs> res;
+    std::vector<BatchDesc> two;
+    std::vector<MemberList> cols, rows;  // [0] general kernel, then one per register-staged length
+    std::vector<int> lists;
+    struct ConvJob {
+        lt_plan *p;
+        const double *ktab;
+        void *G, *tmp;
+    };
+    std::vector<ConvJob> conv_jobs;
+    size_t lds_res = 0, lds_col = 0, lds_row = 0;
+    int64_t max_ktab = 0, gmax = 0;
+};
+
+lt_status batch_check(int32_t B, const lt_plan *const *plans, lt_prec prec, const double *const *v, void *const *u,
+                      const double *gamma, const double *dt, const int64_t *steps)
 {
     if (B < 0) return fail(LT_E_ARG, "B must be >= 0");
     if (B == 0) return LT_OK;
@@ -1352,33 +1381,30 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
         if ((st = check_common(plans[i], prec, 1, gamma[i], dt[i], steps[i]))) return st;
         if (steps[i] > 0 && (!v[i] || !u[i])) return fail(LT_E_ARG, "v and u must not be NULL");
     }
-    hipStream_t hs = (hipStream_t)stream;
-    const BatchLayout BL = batch_layout(B, plans, prec);
-    Scratch sc;
-    if ((st = get_work(sc, work, work_bytes, BL.total, hs))) return st;
+    return LT_OK;
+}
+
+// Host descriptors of a batch whose workspace starts at ws; enqueues the
+// members' potential tables (they read only v).
+lt_status batch_build(int32_t B, const lt_plan *const *plans, lt_prec prec, const double *const *v, void *const *u,
+                      const double *gamma, const double *dt, const int64_t *steps, void *ws, BatchRun &R,
+                      hipStream_t hs)
+{
+    lt_status st;
+    R.prec = prec;
+    R.BL = batch_layout(B, plans, prec);
     const size_t S = esz(prec);
-    std::vector<KtabDesc> kd;
-    std::vector<ResArgs> res;
-    std::vector<BatchDesc> two;
-    struct ConvJob {
-        lt_plan *p;
-        const double *ktab;
-        void *G, *tmp;
-    };
-    std::vector<ConvJob> conv_jobs;
-    size_t lds_res = 0, lds_col = 0, lds_row = 0;
-    int64_t max_ktab = 0;
     for (int i = 0; i < B; ++i) {
         if (steps[i] == 0) continue;
         lt_plan &p = *const_cast<lt_plan *>(plans[i]);
-        if ((st = ensure_device_tables(p, 0, prec, stream))) return st;
+        if ((st = ensure_device_tables(p, 0, prec, hs))) return st;
         const Sched &s = p.sched[0][prec];
         const DevTables &D = p.dev[0][prec];
         const RunWork L = run_layout(p, s, prec, 1, true, true, true);
-        char *w = at(sc.ptr, BL.off[i]);
+        char *w = at(ws, R.BL.off[i]);
         double *ktab = (double *)(w + L.ktab);
-        kd.push_back({ktab, p.max_s + 1, kinetic_angle(gamma[i], dt[i]), s.bluestein ? 1.0 : 1.0 / (double)s.L});
-        max_ktab = std::max<int64_t>(max_ktab, p.max_s + 1);
+        R.kd.push_back({ktab, p.max_s + 1, kinetic_angle(gamma[i], dt[i]), s.bluestein ? 1.0 : 1.0 / (double)s.L});
+        R.max_ktab = std::max<int64_t>(R.max_ktab, p.max_s + 1);
         const double half = dt[i] / (2.0 * gamma[i]);
         if (s.passes == 1) {
             ResArgs a;
@@ -1402,8 +1428,8 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
             a.phase_half = half;
             a.steps = steps[i];
             a.batch = 1;
-            res.push_back(a);
-            lds_res = std::max(lds_res, (size_t)s.L * S);
+            R.res.push_back(a);
+            R.lds_res = std::max(R.lds_res, (size_t)s.L * S);
             continue;
         }
         if (s.L2 > kTileElems || s.passes == 3)
@@ -1413,41 +1439,42 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
         void *ptab = steps[i] > 1 ? (void *)(w + L.ptab) : nullptr;
         if (ptab)
             HIP_TRY(launch_phase_table(prec, ptab, v[i], 0, 1, p.N, 2.0 * half, hs), "potential table");
-        Roles R = two_pass_roles(s, D, p.N, v[i], 0, u[i], w + L.w, half, ktab, ptab);
+        Roles Ro = two_pass_roles(s, D, p.N, v[i], 0, u[i], w + L.w, half, ktab, ptab);
         // chirp-z problems of 4 steps or more: the convolution form (spectrum
-        // built below, once the kinetic tables exist)
+        // built once the kinetic tables exist)
         const bool conv = steps[i] >= kConvMinSteps && conv_available(p, 0, s);
         if (conv) {
-            if ((st = ensure_device_tables(p, 0, LT_C128, stream))) return st;
-            conv_jobs.push_back({&p, ktab, w + L.conv, w + L.conv_tmp});
-            R.first.chirp = 0;
-            R.last.chirp = 0;
-            R.row.bhat = (const double *)(w + L.conv);
+            if ((st = ensure_device_tables(p, 0, LT_C128, hs))) return st;
+            R.conv_jobs.push_back({&p, ktab, w + L.conv, w + L.conv_tmp});
+            Ro.first.chirp = 0;
+            Ro.last.chirp = 0;
+            Ro.row.bhat = (const double *)(w + L.conv);
         }
         BatchDesc b;
         std::memset(&b, 0, sizeof(b));
-        b.col[0] = R.first;
-        b.col[1] = R.pot;
-        b.col[2] = R.kin;
-        b.col[3] = R.last;
-        b.row[0] = R.row;
-        b.row[1] = R.row;
+        b.col[0] = Ro.first;
+        b.col[1] = Ro.pot;
+        b.col[2] = Ro.kin;
+        b.col[3] = Ro.last;
+        b.row[0] = Ro.row;
+        b.row[1] = Ro.row;
         b.row[1].conj_tab = 1;
         b.bluestein = (s.bluestein && !conv) ? 1 : 0;
         b.npass = (b.bluestein ? 4 : 2) * steps[i] + 1;
-        two.push_back(b);
-        lds_col = std::max(lds_col, (size_t)R.first.L1 * R.first.C * S);
-        lds_row = std::max(lds_row, (size_t)R.row.rows * R.row.L2 * S);
+        R.two.push_back(b);
+        R.lds_col = std::max(R.lds_col, (size_t)Ro.first.L1 * Ro.first.C * S);
+        R.lds_row = std::max(R.lds_row, (size_t)Ro.row.rows * Ro.row.L2 * S);
     }
-    if (kd.empty()) return LT_OK;
     // longest schedules first: the problems still running at pass g are a prefix
-    std::stable_sort(two.begin(), two.end(),
+    std::stable_sort(R.two.begin(), R.two.end(),
                      [](const BatchDesc &a, const BatchDesc &b) { return a.npass > b.npass; });
-    const int n2 = (int)two.size();
+    const int n2 = (int)R.two.size();
+    R.gmax = n2 ? R.two[0].npass : 0;
     // column and row kernel classes: register-staged passes where the length
     // has one (two passes per step only), the general kernel otherwise
-    std::vector<MemberList> cols(1), rows(1);
-    cols[0].key = rows[0].key = -1;
+    R.cols.assign(1, MemberList());
+    R.rows.assign(1, MemberList());
+    R.cols[0].key = R.rows[0].key = -1;
     auto list_for = [](std::vector<MemberList> &ls, int key) -> MemberList & {
         for (auto &l : ls)
             if (l.key == key) return l;
@@ -1456,97 +1483,324 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
         return ls.back();
     };
     for (int i = 0; i < n2; ++i) {
-        const BatchDesc &b = two[i];
+        const BatchDesc &b = R.two[i];
         const ColArgs &pc = b.col[1];
         const RowArgs &pr = b.row[0];
         const bool fc = !b.bluestein && pc.v && fast_col_fits(prec, 1, pc.L1, pc.L2, pc.C);
         const bool fr = !b.bluestein && fast_row_fits(prec, 1, pr.L1, pr.L2, pr.rows);
-        MemberList &lc = fc ? list_for(cols, pc.L1) : cols[0];
-        MemberList &lr = fr ? list_for(rows, 2 * pr.L2 + (pr.bhat ? 0 : 1)) : rows[0];
+        MemberList &lc = fc ? list_for(R.cols, pc.L1) : R.cols[0];
+        MemberList &lr = fr ? list_for(R.rows, 2 * pr.L2 + (pr.bhat ? 0 : 1)) : R.rows[0];
         lc.mem.push_back(i);
         lc.npass.push_back(b.npass);
         lr.mem.push_back(i);
         lr.npass.push_back(b.npass);
     }
-    if ((int)(cols.size() + rows.size()) > kMaxBatchLists) return fail(LT_E_UNSUPPORTED, "too many kernel classes");
-    std::vector<int> lists;
-    for (auto *ls : {&cols, &rows}) {
-        const bool is_col = ls == &cols;
+    if ((int)(R.cols.size() + R.rows.size()) > kMaxBatchLists) return fail(LT_E_UNSUPPORTED, "too many kernel classes");
+    for (auto *ls : {&R.cols, &R.rows}) {
+        const bool is_col = ls == &R.cols;
         for (auto &l : *ls) {
             l.start.assign(1, 0);
             for (int i : l.mem)
-                l.start.push_back(l.start.back() + (is_col ? two[i].col[0].ntiles : two[i].row[0].nblk));
-            l.idx_off = lists.size();
-            lists.insert(lists.end(), l.mem.begin(), l.mem.end());
-            l.start_off = lists.size();
-            lists.insert(lists.end(), l.start.begin(), l.start.end());
+                l.start.push_back(l.start.back() + (is_col ? R.two[i].col[0].ntiles : R.two[i].row[0].nblk));
+            l.idx_off = R.lists.size();
+            R.lists.insert(R.lists.end(), l.mem.begin(), l.mem.end());
+            l.start_off = R.lists.size();
+            R.lists.insert(R.lists.end(), l.start.begin(), l.start.end());
             l.act = (int)l.mem.size();
         }
     }
-    std::vector<char> blob(BL.desc_bytes, 0);
-    std::memcpy(blob.data() + BL.d_ktab, kd.data(), kd.size() * sizeof(KtabDesc));
-    if (!res.empty()) std::memcpy(blob.data() + BL.d_res, res.data(), res.size() * sizeof(ResArgs));
-    if (n2) std::memcpy(blob.data() + BL.d_two, two.data(), two.size() * sizeof(BatchDesc));
-    std::memcpy(blob.data() + BL.d_lists, lists.data(), lists.size() * sizeof(int));
-    char *dd = at(sc.ptr, BL.desc);
-    if ((st = upload_async(dd, blob.data(), blob.size(), hs))) return st;
-    HIP_TRY(launch_ktab_multi((const KtabDesc *)(dd + BL.d_ktab), (int)kd.size(), max_ktab, hs),
+    return LT_OK;
+}
+
+// the descriptor block as uploaded
+std::vector<char> batch_blob(const BatchRun &R)
+{
+    std::vector<char> blob(R.BL.desc_bytes, 0);
+    std::memcpy(blob.data() + R.BL.d_ktab, R.kd.data(), R.kd.size() * sizeof(KtabDesc));
+    if (!R.res.empty()) std::memcpy(blob.data() + R.BL.d_res, R.res.data(), R.res.size() * sizeof(ResArgs));
+    if (!R.two.empty()) std::memcpy(blob.data() + R.BL.d_two, R.two.data(), R.two.size() * sizeof(BatchDesc));
+    std::memcpy(blob.data() + R.BL.d_lists, R.lists.data(), R.lists.size() * sizeof(int));
+    return blob;
+}
+
+// kinetic tables and convolution spectra (after the descriptor upload)
+lt_status batch_tables(const BatchRun &R, char *dd, hipStream_t hs)
+{
+    lt_status st;
+    HIP_TRY(launch_ktab_multi((const KtabDesc *)(dd + R.BL.d_ktab), (int)R.kd.size(), R.max_ktab, hs),
             "kinetic tables");
-    for (const ConvJob &j : conv_jobs)
+    for (const auto &j : R.conv_jobs)
         if ((st = conv_spectrum(*j.p, 0, j.ktab, j.G, j.tmp, hs))) return st;
-    // problems that fit one workgroup: their whole step loop in one launch,
-    // overlapped with the pass-by-pass launches of the others
-    hipStream_t rs = hs;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    if (!res.empty() && n2) {
-        if ((st = side_stream(&rs))) return st;
-        HIP_TRY(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming), "event");
-        HIP_TRY(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming), "event");
+    return LT_OK;
+}
+
+// The pass launches of one batch run.  Problems that fit one workgroup run
+// their whole step loop in one launch on rs (a second stream joined through
+// the two events, or hs itself), overlapped with the pass-by-pass launches of
+// the others on hs.  Enqueues kernels and event operations only.
+lt_status batch_passes(const BatchRun &R, char *dd, hipStream_t hs, hipStream_t rs, hipEvent_t ev_fork,
+                       hipEvent_t ev_join)
+{
+    const int prec = R.prec;
+    const int n2 = (int)R.two.size();
+    const bool fork = !R.res.empty() && n2 && rs != hs;
+    if (fork) {
         HIP_TRY(hipEventRecord(ev_fork, hs), "event record");
         HIP_TRY(hipStreamWaitEvent(rs, ev_fork, 0), "stream wait");
     }
-    if (!res.empty())
-        HIP_TRY(launch_resident_multi(prec, (const ResArgs *)(dd + BL.d_res), (int)res.size(), lds_res, rs),
+    if (!R.res.empty())
+        HIP_TRY(launch_resident_multi(prec, (const ResArgs *)(dd + R.BL.d_res), (int)R.res.size(), R.lds_res,
+                                      fork ? rs : hs),
                 "resident batch");
-    const BatchDesc *dtwo = (const BatchDesc *)(dd + BL.d_two);
-    const int *dl = (const int *)(dd + BL.d_lists);
-    const int64_t gmax = n2 ? two[0].npass : 0;
+    const BatchDesc *dtwo = (const BatchDesc *)(dd + R.BL.d_two);
+    const int *dl = (const int *)(dd + R.BL.d_lists);
+    std::vector<MemberList> cols = R.cols, rows = R.rows;  // act counts down per run
     int herr = 0;
-    for (int64_t g = 0; g < gmax && !herr; ++g) {
+    for (int64_t g = 0; g < R.gmax && !herr; ++g) {
         const bool col = !(g & 1);
         for (auto &l : col ? cols : rows) {
             while (l.act > 0 && l.npass[l.act - 1] <= g) --l.act;
             if (herr || l.act == 0) continue;
             const int *idx = dl + l.idx_off, *start = dl + l.start_off;
             if (!col) {
-                herr = l.key < 0 ? launch_row_multi(prec, dtwo, idx, start, l.act, l.start[l.act], 0, g, lds_row, hs)
-                                 : launch_row_fast_multi(prec, l.key / 2, l.key % 2, dtwo, idx, start, l.act,
+                herr = l.key < 0 ? launch_row_multi(prec, dtwo, idx, start, l.act, l.start[l.act], 0, g, R.lds_row, hs)
+                                 : launch_row_fast_multi(prec, l.var, l.key / 2, l.key % 2, dtwo, idx, start, l.act,
                                                          l.start[l.act], 0, g, hs);
                 continue;
             }
             if (l.key < 0 || g == 0) {  // general kernel: every role (the first pass of every member)
-                herr = launch_col_multi(prec, dtwo, idx, start, l.act, l.start[l.act], 0, g, lds_col, hs);
+                herr = launch_col_multi(prec, dtwo, idx, start, l.act, l.start[l.act], 0, g, R.lds_col, hs);
                 continue;
             }
             // register-staged interior passes, then the general kernel for the
             // members whose last pass this is (a contiguous range [a, act))
-            herr = launch_col_fast_multi(prec, l.key, dtwo, idx, start, l.act, l.start[l.act], 0, g, hs);
+            herr = launch_col_fast_multi(prec, l.var, l.key, dtwo, idx, start, l.act, l.start[l.act], 0, g, hs);
             int a = l.act;
             while (a > 0 && l.npass[a - 1] == g + 1) --a;
             if (!herr && a < l.act)
                 herr = launch_col_multi(prec, dtwo, idx, start, l.act, l.start[l.act] - l.start[a], l.start[a], g,
-                                        lds_col, hs);
+                                        R.lds_col, hs);
         }
     }
-    if (ev_fork) {  // join even after a failed launch: the workspace must outlive the side stream's work
-        if (!herr) herr = (int)hipEventRecord(ev_join, rs);
-        if (!herr) herr = (int)hipStreamWaitEvent(hs, ev_join, 0);
-        else hipStreamSynchronize(rs);
-        hipEventDestroy(ev_fork);
-        hipEventDestroy(ev_join);
+    if (fork) {  // join even after a failed launch: the workspace must outlive the second stream's work
+        int e = (int)hipEventRecord(ev_join, rs);
+        if (!e) e = (int)hipStreamWaitEvent(hs, ev_join, 0);
+        if (e) hipStreamSynchronize(rs);
+        if (!herr) herr = e;
     }
     HIP_TRY(herr, "batched pass");
     return LT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec prec, const double *const *v,
+                             void *const *u, const double *gamma, const double *dt, const int64_t *steps,
+                             void *work, size_t work_bytes, void *stream)
+{
+    lt_status st = batch_check(B, plans, prec, v, u, gamma, dt, steps);
+    if (st || B == 0) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    const BatchLayout BL = batch_layout(B, plans, prec);
+    Scratch sc;
+    if ((st = get_work(sc, work, work_bytes, BL.total, hs))) return st;
+    BatchRun R;
+    if ((st = batch_build(B, plans, prec, v, u, gamma, dt, steps, sc.ptr, R, hs))) return st;
+    if (R.kd.empty()) return LT_OK;
+    const std::vector<char> blob = batch_blob(R);
+    char *dd = at(sc.ptr, BL.desc);
+    if ((st = upload_async(dd, blob.data(), blob.size(), hs))) return st;
+    if ((st = batch_tables(R, dd, hs))) return st;
+    hipStream_t rs = hs;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    if (!R.res.empty() && !R.two.empty()) {
+        if ((st = side_stream(&rs))) return st;
+        HIP_TRY(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming), "event");
+        HIP_TRY(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming), "event");
+    }
+    st = batch_passes(R, dd, hs, rs, ev_fork, ev_join);
+    if (ev_fork) hipEventDestroy(ev_fork);
+    if (ev_join) hipEventDestroy(ev_join);
+    return st;
+}
+
+// ---------------------------------------------------------------- batch objects
+struct lt_batch {
+    BatchRun R;
+    void *mem = nullptr;    // workspace and descriptor block (device, owned)
+    char *dd = nullptr;     // descriptor block
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int device = -1;
+};
+
+lt_status strang_batch_create(int32_t B, const lt_plan *const *plans, lt_prec prec, const double *const *v,
+                              void *const *u, const double *gamma, const double *dt, const int64_t *steps,
+                              void *stream, lt_batch **out)
+{
+    if (!out) return fail(LT_E_ARG, "out is NULL");
+    *out = nullptr;
+    lt_status st = batch_check(B, plans, prec, v, u, gamma, dt, steps);
+    if (st) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    std::unique_ptr<lt_batch> b(new (std::nothrow) lt_batch());
+    if (!b) return fail(LT_E_NOMEM, "batch object");
+    HIP_TRY(hipGetDevice(&b->device), "device query");
+    if (B > 0) {
+        const BatchLayout BL = batch_layout(B, plans, prec);
+        HIP_TRY(hipMalloc(&b->mem, BL.total), "batch workspace");
+        auto release = [&]() {
+            hipFree(b->mem);
+            b->mem = nullptr;
+        };
+        if ((st = batch_build(B, plans, prec, v, u, gamma, dt, steps, b->mem, b->R, hs))) {
+            hipStreamSynchronize(hs);
+            release();
+            return st;
+        }
+        b->dd = at(b->mem, BL.desc);
+        if (!b->R.kd.empty()) {
+            const std::vector<char> blob = batch_blob(b->R);
+            hipError_t e = hipMemcpyAsync(b->dd, blob.data(), blob.size(), hipMemcpyHostToDevice, hs);
+            if (e == hipSuccess) st = batch_tables(b->R, b->dd, hs);
+            const hipError_t e2 = hipStreamSynchronize(hs);  // blob is host memory of this frame
+            if (e == hipSuccess) e = e2;
+            if (!st && e != hipSuccess) st = fail(LT_E_HIP, std::string("batch tables: ") + hipGetErrorString(e));
+            if (st) {
+                release();
+                return st;
+            }
+        }
+        if (!b->R.res.empty() && !b->R.two.empty()) {
+            HIP_TRY(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking), "stream");
+            HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming), "event");
+            HIP_TRY(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming), "event");
+        }
+    }
+    *out = b.release();
+    return LT_OK;
+}
+
+lt_status strang_batch_run(const lt_batch *b, void *stream)
+{
+    if (!b) return fail(LT_E_ARG, "batch is NULL");
+    if (b->R.kd.empty()) return LT_OK;
+    hipStream_t hs = (hipStream_t)stream;
+    return batch_passes(b->R, b->dd, hs, b->side ? b->side : hs, b->ev_fork, b->ev_join);
+}
+
+lt_status strang_batch_autotune(lt_batch *b, int32_t reps, void *stream)
+{
+    if (!b) return fail(LT_E_ARG, "batch is NULL");
+    if (reps < 1) return fail(LT_E_ARG, "reps must be >= 1");
+    BatchRun &R = b->R;
+    if (R.two.empty()) return LT_OK;
+    hipStream_t hs = (hipStream_t)stream;
+    const size_t S = esz(R.prec);
+    // a copy of the two-pass descriptors whose transform buffers point into
+    // scratch, so that timing the passes leaves the members' states alone
+    std::vector<BatchDesc> tune = R.two;
+    size_t bytes = 0;
+    std::vector<size_t> off(tune.size());
+    for (size_t i = 0; i < tune.size(); ++i) {
+        off[i] = bytes;
+        bytes += align_up((size_t)tune[i].col[0].L1 * tune[i].col[0].L2 * S);
+    }
+    const size_t dsz = align_up(tune.size() * sizeof(BatchDesc));
+    const size_t lsz = align_up(R.lists.size() * sizeof(int));
+    void *scratch = nullptr;
+    HIP_TRY(hipMalloc(&scratch, bytes + dsz + lsz), "autotune scratch");
+    lt_status st = LT_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int herr = (int)hipMemsetAsync(scratch, 0, bytes, hs);
+    for (size_t i = 0; i < tune.size(); ++i) {
+        void *buf = at(scratch, off[i]);
+        for (auto &c : tune[i].col) {
+            c.buf = buf;
+            c.buf_bs = 0;
+            c.out = nullptr;  // first / last roles never run below
+        }
+        for (auto &r : tune[i].row) {
+            r.buf = buf;
+            r.buf_bs = 0;
+        }
+    }
+    BatchDesc *dtwo = (BatchDesc *)at(scratch, bytes);
+    int *dl = (int *)at(scratch, bytes + dsz);
+    if (!herr) herr = (int)hipMemcpyAsync(dtwo, tune.data(), tune.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, hs);
+    if (!herr) herr = (int)hipMemcpyAsync(dl, R.lists.data(), R.lists.size() * sizeof(int), hipMemcpyHostToDevice, hs);
+    if (!herr) herr = (int)hipEventCreate(&e0);
+    if (!herr) herr = (int)hipEventCreate(&e1);
+    if (!herr) herr = (int)hipStreamSynchronize(hs);
+    // every member at an interior pass: column g = 2, row g = 1 (members with a
+    // single step have no interior column pass and skip it inside the kernel)
+    for (int which = 0; which < 2 && !herr; ++which) {
+        auto &ls = which == 0 ? R.cols : R.rows;
+        for (auto &l : ls) {
+            if (l.key < 0 || l.mem.empty() || herr) continue;
+            const int *idx = dl + l.idx_off, *start = dl + l.start_off;
+            const int nm = (int)l.mem.size(), nb = l.start[nm];
+            float best_ms = 0.0f;
+            int best = 1;
+            for (int var = 1; var <= 2 && !herr; ++var) {
+                auto go = [&]() {
+                    return which == 0 ? launch_col_fast_multi(R.prec, var, l.key, dtwo, idx, start, nm, nb, 0, 2, hs)
+                                      : launch_row_fast_multi(R.prec, var, l.key / 2, l.key % 2, dtwo, idx, start, nm,
+                                                              nb, 0, 1, hs);
+                };
+                herr = go();  // warm-up
+                if (!herr) herr = (int)hipEventRecord(e0, hs);
+                for (int k = 0; k < reps && !herr; ++k) herr = go();
+                if (!herr) herr = (int)hipEventRecord(e1, hs);
+                if (!herr) herr = (int)hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (!herr) herr = (int)hipEventElapsedTime(&ms, e0, e1);
+                if (!herr && (var == 1 || ms < best_ms)) {
+                    best_ms = ms;
+                    best = var;
+                }
+            }
+            l.var = best;
+        }
+    }
+    if (herr) st = fail(LT_E_HIP, std::string("batch autotune: ") + hipGetErrorString((hipError_t)herr));
+    hipStreamSynchronize(hs);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(scratch);
+    return st;
+}
+
+lt_status strang_batch_kernels(const lt_batch *b, int32_t *ncls, int32_t *key, int32_t *variant, int32_t cap)
+{
+    if (!b || !ncls) return fail(LT_E_ARG, "NULL argument");
+    int n = 0;
+    for (int which = 0; which < 2; ++which)
+        for (const auto &l : which == 0 ? b->R.cols : b->R.rows) {
+            if (l.key < 0 || l.mem.empty()) continue;
+            if (n < cap && key && variant) {
+                key[n] = which == 0 ? l.key : -l.key;
+                variant[n] = l.var;
+            }
+            ++n;
+        }
+    *ncls = n;
+    return LT_OK;
+}
+
+void strang_batch_destroy(lt_batch *b)
+{
+    if (!b) return;
+    int cur = -1;
+    hipGetDevice(&cur);
+    if (b->device >= 0) hipSetDevice(b->device);
+    if (b->mem) hipFree(b->mem);  // waits for the work of the device
+    if (b->ev_fork) hipEventDestroy(b->ev_fork);
+    if (b->ev_join) hipEventDestroy(b->ev_join);
+    if (b->side) hipStreamDestroy(b->side);
+    if (cur >= 0) hipSetDevice(cur);
+    delete b;
 }
 
 // ---------------------------------------------------------------- compositions

@@ -145,6 +145,12 @@ __device__ __forceinline__ int find_member(const int *start, int n, int bid)
     return lo;
 }
 
+// Work item of block b in a grid of n blocks (n a multiple of 8).  Blocks are
+// dealt round-robin to the 8 XCDs (block b to XCD b mod 8), each with its own
+// L2; this hands every XCD a contiguous range of work items, so that
+// neighbouring column tiles, which share cache lines, meet in one L2.
+__device__ __forceinline__ int xcd_block(int b, int n) { return (b & 7) * (n >> 3) + (b >> 3); }
+
 // floor(x / d) by a double reciprocal, for 0 <= x < 2^50 and d >= 1: the
 // quotient (x + 1/2) / d lies at least 1/(2d) from an integer, far beyond the
 // relative error 2^-52 of the two roundings

@@ -440,10 +440,13 @@ __global__ void __launch_bounds__(kThreads) k_resident(ResArgs a)
 //                         spectrum), g = 2 mod 4 kinetic, g = 0 mod 4 potential, last g last.
 template <typename T, int EPT>
 __global__ void __launch_bounds__(kThreads) k_col_multi(const BatchDesc *d, const int *idx, const int *start,
-                                                        int nmem, int off, int64_t g)
+                                                        int nmem, int nblocks, int off, int64_t g)
 {
     extern __shared__ char smem_raw[];
-    const int bid = blockIdx.x + off;
+    // the grid is padded to a multiple of 8 blocks (XCD-contiguous tiles)
+    const int w = xcd_block(blockIdx.x, gridDim.x);
+    if (w >= nblocks) return;
+    const int bid = w + off;
     const int k = find_member(start, nmem, bid);
     const BatchDesc &p = d[idx[k]];
     if (g >= p.npass || (g & 1)) return;
@@ -853,11 +856,12 @@ int launch_resident(int prec, const Sched &s, const ResArgs &a, int batch, void 
 int launch_col_multi(int prec, const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks,
                      int off, int64_t g, size_t lds, void *stream)
 {
+    const int grid = (nblocks + 7) / 8 * 8;
     if (prec == LT_C128)
-        return timed_launch(LT_KIND_COLUMN, k_col_multi<double, 16>, dim3(nblocks), dim3(kThreads), lds, stream,
-                            d, idx, start, nmem, off, g);
-    return timed_launch(LT_KIND_COLUMN, k_col_multi<float, 16>, dim3(nblocks), dim3(kThreads), lds, stream, d,
-                        idx, start, nmem, off, g);
+        return timed_launch(LT_KIND_COLUMN, k_col_multi<double, 16>, dim3(grid), dim3(kThreads), lds, stream,
+                            d, idx, start, nmem, nblocks, off, g);
+    return timed_launch(LT_KIND_COLUMN, k_col_multi<float, 16>, dim3(grid), dim3(kThreads), lds, stream, d,
+                        idx, start, nmem, nblocks, off, g);
 }
 
 int launch_row_multi(int prec, const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks,

@@ -604,10 +604,13 @@ __global__ void __launch_bounds__(NT, MINW) k_colf_adj(ColArgs a)
 // column passes take the general kernel.
 template <typename T, int E, int NT, int MINW, int... Rs>
 __global__ void __launch_bounds__(NT, MINW) k_colf_multi(const BatchDesc *d, const int *idx, const int *start,
-                                                          int nmem, int off, int64_t g)
+                                                          int nmem, int nblocks, int off, int64_t g)
 {
     extern __shared__ char smem_raw[];
-    const int bid = blockIdx.x + off;
+    // the grid is padded to a multiple of 8 blocks
+    const int w = xcd_block(blockIdx.x, gridDim.x);
+    if (w >= nblocks) return;
+    const int bid = w + off;
     const int k = find_member(start, nmem, bid);
     const BatchDesc &p = d[idx[k]];
     if (g == 0 || (g & 1) || g >= p.npass - 1) return;
@@ -713,9 +716,10 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
 // table, as in k_rowf.
 template <typename T, int E, int NT, int MINW, int MID, int... Rs>
 __global__ void __launch_bounds__(NT, MINW) k_rowf_multi(const BatchDesc *d, const int *idx, const int *start,
-                                                          int nmem, int off, int64_t g)
+                                                          int nmem, int nblocks, int off, int64_t g)
 {
     extern __shared__ char smem_raw[];
+    if ((int)blockIdx.x >= nblocks) return;
     const int bid = blockIdx.x + off;
     const int k = find_member(start, nmem, bid);
     const BatchDesc &p = d[idx[k]];
@@ -904,55 +908,78 @@ int go(int L, const A &a, int batch, void *stream)
 
 bool fast_len(int L) { return L >= 64 && L <= 4096 && (L & (L - 1)) == 0; }
 
-template <typename T, int... Rs>
+template <typename T, int V, int... Rs>
 int col_multi_go(const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks, int off, int64_t g,
                  void *stream)
 {
-    constexpr int NT = Geo<1>::NT, E = Geo<1>::E, MINW = Geo<1>::MINW;
+    constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW;
     auto k = k_colf_multi<T, E, NT, MINW, Rs...>;
     static bool attr = false;
     if (!attr) {
         hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         attr = true;
     }
-    return timed_multi(LT_KIND_COLUMN, k, dim3(nblocks), dim3(NT), lds_bytes<T, 1>(), stream, d, idx, start, nmem,
-                       off, g);
+    const int grid = (nblocks + 7) / 8 * 8;
+    return timed_multi(LT_KIND_COLUMN, k, dim3(grid), dim3(NT), lds_bytes<T, V>(), stream, d, idx, start, nmem,
+                       nblocks, off, g);
 }
 
-template <typename T, int MID, int... Rs>
+template <typename T, int V, int MID, int... Rs>
 int row_multi_go(const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks, int off, int64_t g,
                  void *stream)
 {
-    constexpr int NT = Geo<1>::NT, E = Geo<1>::E, MINW = Geo<1>::MINW;
+    constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW;
     auto k = k_rowf_multi<T, E, NT, MINW, MID, Rs...>;
     static bool attr = false;
     if (!attr) {
         hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         attr = true;
     }
-    return timed_multi(LT_KIND_ROW, k, dim3(nblocks), dim3(NT), lds_bytes<T, 1>(), stream, d, idx, start, nmem,
-                       off, g);
+    return timed_multi(LT_KIND_ROW, k, dim3(nblocks), dim3(NT), lds_bytes<T, V>(), stream, d, idx, start, nmem,
+                       nblocks, off, g);
 }
 
-// radix sequences of the 16-elements-per-thread geometry (as in go<T, 1, ...>)
-template <typename T, bool COL, int MID>
-int multi_go(int L, const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks, int off,
-             int64_t g, void *stream)
+// radix sequences per length of the two 4096-element-tile geometries (as in
+// go<T, 1 or 2, ...>): variant 1 (256 threads x 16) and 2 (512 threads x 8)
+template <typename T, bool COL, int MID, int V>
+int multi_go_v(int L, const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks, int off,
+               int64_t g, void *stream)
 {
 #define LT_MULTI(...)                                                                              \
-    (COL ? col_multi_go<T, __VA_ARGS__>(d, idx, start, nmem, nblocks, off, g, stream)              \
-         : row_multi_go<T, MID, __VA_ARGS__>(d, idx, start, nmem, nblocks, off, g, stream))
-    switch (L) {
-    case 64: return LT_MULTI(8, 8);
-    case 128: return LT_MULTI(8, 2, 8);
-    case 256: return LT_MULTI(16, 16);
-    case 512: return LT_MULTI(8, 8, 8);
-    case 1024: return LT_MULTI(16, 4, 16);
-    case 2048: return LT_MULTI(16, 8, 16);
-    case 4096: return LT_MULTI(16, 16, 16);
-    default: return -1;
+    (COL ? col_multi_go<T, V, __VA_ARGS__>(d, idx, start, nmem, nblocks, off, g, stream)           \
+         : row_multi_go<T, V, MID, __VA_ARGS__>(d, idx, start, nmem, nblocks, off, g, stream))
+    if constexpr (V == 1) {
+        switch (L) {
+        case 64: return LT_MULTI(8, 8);
+        case 128: return LT_MULTI(8, 2, 8);
+        case 256: return LT_MULTI(16, 16);
+        case 512: return LT_MULTI(8, 8, 8);
+        case 1024: return LT_MULTI(16, 4, 16);
+        case 2048: return LT_MULTI(16, 8, 16);
+        case 4096: return LT_MULTI(16, 16, 16);
+        default: return -1;
+        }
+    } else {
+        switch (L) {
+        case 64: return LT_MULTI(8, 8);
+        case 128: return LT_MULTI(8, 2, 8);
+        case 256: return LT_MULTI(4, 4, 4, 4);
+        case 512: return LT_MULTI(8, 8, 8);
+        case 1024: return LT_MULTI(8, 4, 4, 8);
+        case 2048: return LT_MULTI(8, 4, 8, 8);
+        case 4096: return LT_MULTI(8, 8, 8, 8);
+        default: return -1;
+        }
     }
 #undef LT_MULTI
+}
+
+template <typename T, bool COL, int MID>
+int multi_go(int variant, int L, const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks,
+             int off, int64_t g, void *stream)
+{
+    if (variant == 2) return multi_go_v<T, COL, MID, 2>(L, d, idx, start, nmem, nblocks, off, g, stream);
+    return multi_go_v<T, COL, MID, 1>(L, d, idx, start, nmem, nblocks, off, g, stream);
 }
 constexpr int kTile = 4096;
 }  // namespace
@@ -1063,21 +1090,21 @@ int launch_col_fast_adjoint(int prec, int variant, const ColArgs &a, int batch, 
     return adj_dispatch<float>(a, batch, stream);
 }
 
-int launch_col_fast_multi(int prec, int L1, const BatchDesc *d, const int *idx, const int *start, int nmem,
-                          int nblocks, int off, int64_t g, void *stream)
-{
-    if (prec == LT_C128) return multi_go<double, true, 0>(L1, d, idx, start, nmem, nblocks, off, g, stream);
-    return multi_go<float, true, 0>(L1, d, idx, start, nmem, nblocks, off, g, stream);
-}
-
-int launch_row_fast_multi(int prec, int L2, int mid, const BatchDesc *d, const int *idx, const int *start,
+int launch_col_fast_multi(int prec, int variant, int L1, const BatchDesc *d, const int *idx, const int *start,
                           int nmem, int nblocks, int off, int64_t g, void *stream)
 {
+    if (prec == LT_C128) return multi_go<double, true, 0>(variant, L1, d, idx, start, nmem, nblocks, off, g, stream);
+    return multi_go<float, true, 0>(variant, L1, d, idx, start, nmem, nblocks, off, g, stream);
+}
+
+int launch_row_fast_multi(int prec, int variant, int L2, int mid, const BatchDesc *d, const int *idx,
+                          const int *start, int nmem, int nblocks, int off, int64_t g, void *stream)
+{
     if (prec == LT_C128)
-        return mid ? multi_go<double, false, 1>(L2, d, idx, start, nmem, nblocks, off, g, stream)
-                   : multi_go<double, false, 0>(L2, d, idx, start, nmem, nblocks, off, g, stream);
-    return mid ? multi_go<float, false, 1>(L2, d, idx, start, nmem, nblocks, off, g, stream)
-               : multi_go<float, false, 0>(L2, d, idx, start, nmem, nblocks, off, g, stream);
+        return mid ? multi_go<double, false, 1>(variant, L2, d, idx, start, nmem, nblocks, off, g, stream)
+                   : multi_go<double, false, 0>(variant, L2, d, idx, start, nmem, nblocks, off, g, stream);
+    return mid ? multi_go<float, false, 1>(variant, L2, d, idx, start, nmem, nblocks, off, g, stream)
+               : multi_go<float, false, 0>(variant, L2, d, idx, start, nmem, nblocks, off, g, stream);
 }
 
 }  // namespace lt

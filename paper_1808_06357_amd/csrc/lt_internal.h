@@ -197,10 +197,12 @@ int launch_row_multi(int prec, const BatchDesc *d, const int *idx, const int *st
 int launch_col_fast_adjoint(int prec, int variant, const ColArgs &a, int batch, void *stream);
 // register-staged multi-member passes (kernels_fast.hip); -1 when the length
 // has no such pass
-int launch_col_fast_multi(int prec, int L1, const BatchDesc *d, const int *idx, const int *start, int nmem,
-                          int nblocks, int off, int64_t g, void *stream);
-int launch_row_fast_multi(int prec, int L2, int mid, const BatchDesc *d, const int *idx, const int *start,
+// (variant 1: 256 threads x 16 elements, 2: 512 threads x 8; both on the
+// members' 4096-element tiles)
+int launch_col_fast_multi(int prec, int variant, int L1, const BatchDesc *d, const int *idx, const int *start,
                           int nmem, int nblocks, int off, int64_t g, void *stream);
+int launch_row_fast_multi(int prec, int variant, int L2, int mid, const BatchDesc *d, const int *idx,
+                          const int *start, int nmem, int nblocks, int off, int64_t g, void *stream);
 int launch_resident_multi(int prec, const ResArgs *d, int ninst, size_t lds, void *stream);
 int launch_ktab_multi(const KtabDesc *d, int count, int64_t max_len, void *stream);
 int launch_permute_c128(void *dst, const void *src_nat, int64_t L, int L1, int L2, int transposed,

@@ -168,3 +168,108 @@ def test_mixed_batch_reversible_c128(lt, mixed_batch):
     lt.strang_run_batched(plans, vs, us, g, [-c.dt for c in insts], st)
     for u, c in zip(us, insts):
         assert rel(u.cpu().numpy(), c.u0) < 1e-11
+
+
+# ---------------------------------------------------------------- batch objects
+def make_states(probs, dtype):
+    import torch
+    us = [torch.tensor(p["u0"], dtype=dtype, device="cuda") for p in probs]
+    vs = [torch.tensor(p["v"], dtype=torch.float64, device="cuda") for p in probs]
+    return us, vs
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_batch_object_equals_run_batched(lt, mixed, prec):
+    """strang_batch_create + strang_batch_run runs the launches of
+    strang_run_batched: the same states, bit for bit, run after run."""
+    import torch
+    probs, plans, refs = mixed
+    dtype = torch.complex128 if prec == "c128" else torch.complex64
+    us, vs = make_states(probs, dtype)
+    g, dts, st = [p["gamma"] for p in probs], [p["dt"] for p in probs], [p["steps"] for p in probs]
+    bo = lt.strang_batch_create(plans, vs, us, g, dts, st)
+    ur, vr = make_states(probs, dtype)
+    for run in range(2):
+        lt.strang_batch_run(bo)
+        lt.strang_run_batched(plans, vr, ur, g, dts, st)
+        torch.cuda.synchronize()
+        for i in range(len(probs)):
+            assert torch.equal(us[i], ur[i]), (run, i)
+    e = max(rel(us[i].cpu().numpy().astype(np.complex128), O.strang_run(
+        probs[i]["n"], O.index_set(probs[i]["Z"], probs[i]["n"], probs[i]["I"])[1], probs[i]["v"], refs[i],
+        probs[i]["gamma"], probs[i]["dt"], probs[i]["steps"])) for i in range(len(probs)))
+    print(f"  {prec}: two advances vs the oracle's 2m steps: max rel_l2 {e:.2e}", flush=True)
+    assert e < 2 * TOL[prec]
+
+
+def test_batch_object_graph_replay(lt, mixed):
+    """strang_batch_run only enqueues launches: captured into a HIP graph, each
+    replay advances every state once more, equal to eager advances of a second
+    batch object, with eager work and synchronisations between the replays."""
+    import torch
+    probs, plans, _ = mixed
+    g, dts, st = [p["gamma"] for p in probs], [p["dt"] for p in probs], [p["steps"] for p in probs]
+    for dtype in (torch.complex64, torch.complex128):
+        ug, vg = make_states(probs, dtype)
+        ue, ve = make_states(probs, dtype)
+        bg = lt.strang_batch_create(plans, vg, ug, g, dts, st)
+        be = lt.strang_batch_create(plans, ve, ue, g, dts, st)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            lt.strang_batch_run(bg)
+        torch.cuda.synchronize()
+        for rep in range(3):
+            graph.replay()
+            torch.cuda.synchronize()
+            lt.strang_batch_run(be)
+            torch.cuda.synchronize()
+            same = all(torch.equal(a, b) for a, b in zip(ug, ue))
+            print(f"  {dtype} replay {rep}: equal to eager {same}", flush=True)
+            assert same, rep
+        del graph
+
+
+def test_batch_object_autotune_and_errors(lt, mixed):
+    import torch
+    probs, plans, refs = mixed
+    us, vs = make_states(probs, torch.complex128)
+    g, dts, st = [p["gamma"] for p in probs], [p["dt"] for p in probs], [p["steps"] for p in probs]
+    bo = lt.strang_batch_create(plans, vs, us, g, dts, st)
+    lt.strang_batch_autotune(bo, reps=2)
+    ks = lt.strang_batch_kernels(bo)
+    print(f"  classes (key, variant): {ks}", flush=True)
+    assert ks and all(v in (1, 2) for _, v in ks)
+    lt.strang_batch_run(bo)
+    torch.cuda.synchronize()
+    for i, (u, r) in enumerate(zip(us, refs)):  # the tuner leaves the states alone
+        assert rel(u.cpu().numpy(), r) < TOL["c128"], i
+    with pytest.raises(Exception):
+        lt.strang_batch_create(plans[:1], vs[:1], us[:1], [-1.0], [1e-3], [3])
+    empty = lt.strang_batch_create([], [], [], [], [], [])
+    lt.strang_batch_run(empty)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_mixed_batch_full_batch_object_autotuned(lt, mixed_batch, prec):
+    """All 256 problems through an autotuned batch object (the benchmark's
+    launch configuration): every problem against the oracle's samples."""
+    import torch
+    insts, plans, gold = mixed_batch
+    dtype = torch.complex128 if prec == "c128" else torch.complex64
+    us = [torch.tensor(c.u0, dtype=dtype, device="cuda") for c in insts]
+    vs = [torch.tensor(c.v, dtype=torch.float64, device="cuda") for c in insts]
+    bo = lt.strang_batch_create(plans, vs, us, [c.gamma for c in insts], [c.dt for c in insts],
+                                [c.steps for c in insts])
+    lt.strang_batch_autotune(bo, reps=2)
+    for u, c in zip(us, insts):  # the tuner leaves the states alone
+        u.copy_(torch.tensor(c.u0, dtype=dtype, device="cuda"))
+    lt.strang_batch_run(bo)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i in gold["instances"]:
+        got = us[i].cpu().numpy().astype(np.complex128)
+        e = rel(got[gold[f"idx_{i}"]], gold[f"u_{i}"])
+        worst = max(worst, e)
+        assert e < TOL[prec], (int(i), e)
+    print(f"  {prec}: classes {lt.strang_batch_kernels(bo)}, worst sampled rel_l2 {worst:.2e}", flush=True)
