@@ -118,6 +118,22 @@ def kernel_summary(lt, fn, K):
     return out
 
 
+def golden(name):
+    """A stored FP64 oracle result (tests/golden/*.npz, written by scripts that
+    call only the oracle), or None."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", name + ".npz")
+    return np.load(path) if os.path.exists(path) else None
+
+
+def sampled_rel(u, idx, ref):
+    """Relative L2 error of a device state at stored sample points."""
+    import numpy as np
+    import torch
+    got = u.reshape(-1)[torch.from_numpy(np.asarray(idx)).to(u.device)].cpu().numpy().astype(np.complex128)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
 def wall(fn, K, W):
     import torch
     for _ in range(W):
@@ -131,9 +147,12 @@ def wall(fn, K, W):
 
 
 def bench_batched(lt, torch, K, W):
-    """256 unrelated problems (d 2..10, N 2^12..2^18, 200 steps each):
-    strang_run_batched in complex64 vs. the single-state complex128 path
-    (strang_run per problem, one after another)."""
+    """256 unrelated problems (d 2..10, N 2^12..2^18, 200 steps each) as one
+    autotuned batch object (descriptors and tables built once; each advance
+    only enqueues launches), eager and replayed from a HIP graph, in complex64
+    and complex128, against the single-state complex128 path (strang_run per
+    problem, one after another); every problem's complex64 state against the
+    oracle's stored samples."""
     import numpy as np
 
     import workloads as W_
@@ -147,17 +166,41 @@ def bench_batched(lt, torch, K, W):
     dts = [c.dt for c in insts]
     st = [c.steps for c in insts]
     pt_steps = sum(c.N * c.steps for c in insts)
+    gold = golden("mixed_batch_oracle_samples")
     res = {}
     for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
-        prec = lt.LT_C64 if name == "c64" else lt.LT_C128
         us = [torch.tensor(c.u0, dtype=dtype, device=dev) for c in insts]
-        work = torch.empty(lt.strang_batched_workspace_size(plans, prec), dtype=torch.uint8, device=dev)
-        run = lambda: lt.strang_run_batched(plans, vs, us, gam, dts, st, work=work)  # noqa: E731
+        t = time.perf_counter()
+        bo = lt.strang_batch_create(plans, vs, us, gam, dts, st)
+        lt.strang_batch_autotune(bo, reps=3)
+        t_setup = time.perf_counter() - t
+        # accuracy: one advance from u0, every problem against the oracle
+        acc = None
+        if gold is not None:
+            lt.strang_batch_run(bo)
+            torch.cuda.synchronize()
+            errs = [sampled_rel(us[int(i)], gold[f"idx_{i}"], gold[f"u_{i}"]) for i in gold["instances"]]
+            acc = {"max_sampled_rel_l2_vs_oracle": max(errs), "problems": len(errs)}
+        run = lambda: lt.strang_batch_run(bo)  # noqa: E731
         sec = wall(run, K, W)
-        res[f"batched_{name}"] = {"value": pt_steps / sec, "ms_per_call": sec * 1e3,
-                                  "kernels": kernel_summary(lt, run, 1)}
-        log(f"batched {name}: {pt_steps / sec:.3e} pt-steps/s, {sec * 1e3:.1f} ms per batch")
-        del us, work
+        r = {"value": pt_steps / sec, "ms_per_call": sec * 1e3, "setup_s": t_setup,
+             "classes": lt.strang_batch_kernels(bo), "kernels": kernel_summary(lt, run, 1), "accuracy": acc}
+        try:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                lt.strang_batch_run(bo)
+            g_sec = wall(g.replay, K, W)
+            r["graph"] = {"value": pt_steps / g_sec, "ms_per_call": g_sec * 1e3}
+            del g
+        except RuntimeError as e:
+            torch.cuda.synchronize()
+            r["graph"] = {"error": str(e)[:200]}
+        res[f"batched_{name}"] = r
+        log(f"batched {name}: {pt_steps / sec:.3e} pt-steps/s, {sec * 1e3:.1f} ms per batch"
+            + (f", graph {r['graph'].get('ms_per_call', float('nan')):.1f} ms" if 'graph' in r else "")
+            + (f", max sampled error vs oracle {acc['max_sampled_rel_l2_vs_oracle']:.2e}" if acc else ""))
+        del bo, us
+        torch.cuda.empty_cache()
     # the plain single-state complex128 path over the same problems
     us = [torch.tensor(c.u0, dtype=torch.complex128, device=dev) for c in insts]
     wmax = max(lt.strang_workspace_size(p, lt.LT_C128, 1, True) for p in plans)
@@ -169,19 +212,6 @@ def bench_batched(lt, torch, K, W):
     sec = wall(singles, 1, 1)
     res["single_c128"] = {"value": pt_steps / sec, "ms_per_call": sec * 1e3}
     log(f"single-state c128: {pt_steps / sec:.3e} pt-steps/s, {sec * 1e3:.1f} ms")
-    # accuracy of the batched complex64 result against stored FP64 oracle samples
-    gold_path = os.path.join(ROOT, "tests", "golden", "mixed_batch_oracle_samples.npz")
-    acc = None
-    if os.path.exists(gold_path):
-        gold = np.load(gold_path)
-        us = [torch.tensor(c.u0, dtype=torch.complex64, device=dev) for c in insts]
-        lt.strang_run_batched(plans, vs, us, gam, dts, st)
-        errs = []
-        for i in gold["instances"]:
-            got = us[int(i)].cpu().numpy().astype(np.complex128)[gold[f"idx_{i}"]]
-            ref = gold[f"u_{i}"]
-            errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
-        acc = {"c64_max_sampled_rel_l2_vs_oracle": max(errs), "problems_sampled": len(errs)}
     Ns = [c.N for c in insts]
     return {
         "workload": f"{len(insts)} unrelated rank-1 problems, d in 2..10, N in [{min(Ns)}, {max(Ns)}] "
@@ -191,7 +221,7 @@ def bench_batched(lt, torch, K, W):
         "unit": "lattice-point-steps/s",
         "value_c64": res["batched_c64"]["value"],
         "speedup_c64_batched_vs_single_state_c128": res["batched_c64"]["value"] / res["single_c128"]["value"],
-        **res, "accuracy": acc,
+        **res,
     }
 
 
@@ -211,9 +241,12 @@ def bench_rank2(lt, torch, K, W):
         u = torch.tensor(c.u0, dtype=dtype, device=dev)
         work = torch.empty(lt.strang_workspace_size(plan, prec, 1, True), dtype=torch.uint8, device=dev)
         run = lambda: lt.strang_run(plan, v, u, c.gamma, c.dt, c.steps, work=work)  # noqa: E731
+        run()
+        gold = golden("rank2_d10_n4096x256_oracle_samples")
+        err = sampled_rel(u, gold["idx"], gold[f"u{c.steps}"]) if gold is not None else None
         sec = wall(run, K, W)
         out[name] = {"value": c.N * c.steps / sec, "ms_per_run": sec * 1e3, "kernel_variants": list(kernels),
-                     "kernels": kernel_summary(lt, run, 1)}
+                     "sampled_rel_l2_vs_oracle": err, "kernels": kernel_summary(lt, run, 1)}
         log(f"rank-2 {name}: {c.N * c.steps / sec:.3e} pt-steps/s, {sec * 1e3:.1f} ms per run")
     return out
 
@@ -227,8 +260,13 @@ def bench_adjoint(lt, torch, K, W):
     dev = torch.device("cuda:0")
     v = torch.tensor(c.v, dtype=torch.float64, device=dev)
     B, N, m, every = c.u0.shape[0], c.N, c.steps, c.meta["ckpt_every"]
+    import numpy as np
+    vh = torch.tensor(c.meta["v_hidden"], dtype=torch.float64, device=dev)
+    basis = torch.tensor(c.meta["series"].basis(c.meta["num"], N), dtype=torch.float64, device=dev)
+    gold = golden("adjoint_d4_n65521_oracle_grad")
     out = {"workload": f"rank-1 d=4 N={N} (prime), {B} states sharing a 64-term cosine potential, "
-                       f"gamma=0.05, dt=2e-3, {m} steps, checkpoints every {every}",
+                       f"gamma=0.05, dt=2e-3, {m} steps, checkpoints every {every}; loss: the full lattice "
+                       "misfit to the states run under a hidden 64-term potential",
            "unit": "lattice-point-steps/s (forward + adjoint)"}
     for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
         prec = lt.LT_C64 if name == "c64" else lt.LT_C128
@@ -243,14 +281,31 @@ def bench_adjoint(lt, torch, K, W):
         def fwd():
             u.copy_(u0)
             lt.strang_run(plan, v, u, c.gamma, c.dt, m, ckpt=ck, ckpt_every=every, work=fw)
+        # the target: u0 run under the hidden potential
+        tgt.copy_(u0)
+        lt.strang_run(plan, vh, tgt, c.gamma, c.dt, m, work=fw)
         fwd()
         gT = (2.0 / N) * (u - tgt)
+        res = {}
 
         def adj():
-            lt.strang_adjoint(plan, v, u, gT, c.gamma, c.dt, m, ck, every, work=aw)
+            res["g"] = lt.strang_adjoint(plan, v, u, gT, c.gamma, c.dt, m, ck, every, work=aw)
+        adj()
+        errs = None
+        if gold is not None:
+            g0, gv = res["g"]
+            errs = {"dJ_da": float(torch.linalg.vector_norm((basis @ gv).cpu() - torch.from_numpy(gold["dJ_da"]))
+                                   / np.linalg.norm(gold["dJ_da"])),
+                    "dJ_dv": sampled_rel(gv, gold["idx_v"], gold["dJ_dv"]),
+                    "dJ_du0": float(np.linalg.norm(g0.cpu().numpy()[:, gold["idx_u"]] - gold["dJ_du0"])
+                                    / np.linalg.norm(gold["dJ_du0"])),
+                    "uT": float(np.linalg.norm(u.cpu().numpy()[:, gold["idx_u"]] - gold["uT"])
+                                / np.linalg.norm(gold["uT"]))}
         tf = wall(fwd, K, W)
         ta = wall(adj, K, W)
         out[name] = {"value": B * N * m / (tf + ta), "forward_ms": tf * 1e3, "adjoint_ms": ta * 1e3,
+                     "forward_value": B * N * m / tf, "adjoint_value": B * N * m / ta,
+                     "rel_l2_vs_oracle": errs,
                      "variants": {"one_state": lt.lattice_plan_get_kernels_batch(plan, prec, 1),
                                   f"{B}_states": lt.lattice_plan_get_kernels_batch(plan, prec, B)},
                      "adjoint_kernels": kernel_summary(lt, adj, 1)}
@@ -261,53 +316,56 @@ def bench_adjoint(lt, torch, K, W):
 
 def bench_conservation(lt, torch, K, W):
     """The conservation setting of Sec. 3.3 (gamma = 0.5, d = 5, g1, harmonic
-    v2) on a 2^20-point lattice: 1000 steps with checkpoints every 10, norm and
-    energy of every checkpoint by lattice_diagnostics, delta = (max-min)/mean."""
-    import numpy as np
-
+    v2) on a 2^20-point lattice, 1000 steps: the norm and the potential part of
+    the energy at every step, summed inside the step passes (strang_run_sums),
+    and the full energy (kinetic part included) of checkpoints every 10 steps
+    by lattice_diagnostics; delta = (max - min) / mean over the run."""
     import workloads as W_
-    N, d, gamma, dt, steps, every = 1 << 20, 5, 0.5, 1e-3, 1000, 10
-    z = W_.korobov_good(N, d, np.random.default_rng(33))
-    Z, n = z.reshape(1, -1), np.array([N])
-    num = W_.point_numerators(Z, n)
-    plan = lt.lattice_plan(Z, n)
+    c = W_.conservation_d5_n2p20()
+    N, gamma, dt, steps, every = c.N, c.gamma, c.dt, c.steps, c.meta["ckpt_every"]
+    plan = lt.lattice_plan(c.Z, c.n)
     dev = torch.device("cuda:0")
-    v = torch.tensor(W_.v_harmonic_paper(num, N), device=dev)
-    u0 = W_.paper_g1(num, N, gamma)
-    out = {"workload": f"Sec. 3.3 setting: rank-1 d={d} N=2^20 (best-of-8 Korobov), gamma={gamma}, g1, "
-                       f"harmonic v2, dt={dt}, {steps} steps, norm and energy every {every} steps"}
+    v = torch.tensor(c.v, device=dev)
+    out = {"workload": f"Sec. 3.3 setting: rank-1 d={c.d} N=2^20 (best-of-8 Korobov), gamma={gamma}, g1, "
+                       f"harmonic v2, dt={dt}, {steps} steps; per-step norm and potential energy fused into "
+                       f"the step passes, full energy of checkpoints every {every} steps"}
     nck = lt.num_checkpoints(steps, every)
     for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
-        u = torch.tensor(u0, dtype=dtype, device=dev)
+        prec = lt.LT_C64 if name == "c64" else lt.LT_C128
+        u = torch.tensor(c.u0, dtype=dtype, device=dev)
         ck = torch.empty(nck * N, dtype=dtype, device=dev)
-        # one untimed run first (the plan's tables and first-use setup)
-        lt.strang_run(plan, v, u, gamma, dt, steps, ckpt=ck, ckpt_every=every)
-        lt.lattice_diagnostics(plan, v, ck.view(nck, N), gamma)
-        u.copy_(torch.tensor(u0, dtype=dtype, device=dev))
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        lt.strang_run(plan, v, u, gamma, dt, steps, ckpt=ck, ckpt_every=every)
-        torch.cuda.synchronize()
-        t_run = time.perf_counter() - t
+        work = torch.empty(lt.strang_run_sums_workspace_size(plan, prec, 1, True, steps), dtype=torch.uint8,
+                           device=dev)
+        sums = torch.empty((1, steps + 1, 2), dtype=torch.float64, device=dev)
+        plain = lambda: lt.strang_run(plan, v, u, gamma, dt, steps, work=work)  # noqa: E731
+        fused = lambda: lt.strang_run_sums(plan, v, u, gamma, dt, steps, sums=sums, work=work)  # noqa: E731
+        t_plain, t_fused = wall(plain, K, W), wall(fused, K, W)
+        # the reported run: from u0, with checkpoints for the full energy
+        u.copy_(torch.tensor(c.u0, dtype=dtype, device=dev))
+        lt.strang_run_sums(plan, v, u, gamma, dt, steps, sums=sums, ckpt=ck, ckpt_every=every)
         diag = lt.lattice_diagnostics(plan, v, ck.view(nck, N), gamma)
         torch.cuda.synchronize()
-        t = time.perf_counter() - t
-        h = diag.cpu().numpy()
-        out[name] = {"norm_delta": float((h[:, 0].max() - h[:, 0].min()) / h[:, 0].mean()),
-                     "energy_delta": float((h[:, 1].max() - h[:, 1].min()) / h[:, 1].mean()),
-                     "energy_0": float(h[0, 1]), "ms_run_plus_diagnostics": t * 1e3,
-                     "ms_run": t_run * 1e3, "ms_diagnostics": (t - t_run) * 1e3}
-        log(f"conservation {name}: norm delta {out[name]['norm_delta']:.2e}, "
-            f"energy delta {out[name]['energy_delta']:.2e}, {t * 1e3:.1f} ms")
-        del u, ck
+        h = sums.cpu().numpy()[0]
+        e = diag.cpu().numpy()
+        delta = lambda x: float((x.max() - x.min()) / x.mean())  # noqa: E731
+        out[name] = {"norm_delta_every_step": delta(h[:, 0]), "potential_energy_delta_every_step": delta(h[:, 1]),
+                     "norm_delta_checkpoints": delta(e[:, 0]), "energy_delta_checkpoints": delta(e[:, 1]),
+                     "energy_0": float(e[0, 1]),
+                     "ms_run": t_plain * 1e3, "ms_run_with_step_sums": t_fused * 1e3,
+                     "step_sums_overhead": t_fused / t_plain - 1.0}
+        log(f"conservation {name}: norm delta per step {out[name]['norm_delta_every_step']:.2e}, energy delta "
+            f"{out[name]['energy_delta_checkpoints']:.2e}; run {t_plain * 1e3:.1f} ms, with step sums "
+            f"{t_fused * 1e3:.1f} ms")
+        del u, ck, work
     return out
 
 
 def bench_convergence(lt, torch, K, W):
-    """Time-step convergence on a lattice of the paper's Table 1 (d = 3,
-    n = 2^22, z = (1, 1737355, 261247)) with g1, gamma = 0.5, T = 1, for the
-    smooth v1 and the harmonic v2: reference dt = 1/10000, errors for dt = 1/m
-    (complex128)."""
+    """The time-step convergence protocol of Sec. 3.2 on a lattice of the
+    paper's Table 1 (d = 3, n = 2^22, z = (1, 1737355, 261247)), gamma = 0.5,
+    T = 1: the Gaussian g1 and the hat g2 under the smooth v1 and the harmonic
+    v2, errors of dt = 1/m for m = 5 ... 1000 against a reference with
+    dt = 1e-4 (complex128)."""
     import numpy as np
 
     import workloads as W_
@@ -317,31 +375,33 @@ def bench_convergence(lt, torch, K, W):
     gamma = 0.5
     plan = lt.lattice_plan(Z, n)
     dev = torch.device("cuda:0")
-    u0 = torch.tensor(W_.paper_g1(num, N, gamma), dtype=torch.complex128, device=dev)
-    out = {"workload": "paper Table 1 lattice d=3 n=2^22 z=(1,1737355,261247), minimal-l2 index set, g1, "
+    out = {"workload": "paper Table 1 lattice d=3 n=2^22 z=(1,1737355,261247), minimal-l2 index set, "
                        "gamma=0.5, T=1, reference dt=1e-4, complex128"}
-    for name, vfun in (("v1", W_.v_smooth_paper), ("v2", W_.v_harmonic_paper)):
-        v = torch.tensor(vfun(num, N), device=dev)
+    ms = [5, 10, 20, 50, 100, 200, 500, 1000]
+    for gname, gfun in (("g1", W_.paper_g1), ("g2", W_.paper_g2)):
+        u0 = torch.tensor(gfun(num, N, gamma), dtype=torch.complex128, device=dev)
+        for name, vfun in (("v1", W_.v_smooth_paper), ("v2", W_.v_harmonic_paper)):
+            v = torch.tensor(vfun(num, N), device=dev)
 
-        def solve(m):
-            u = u0.clone()
-            lt.strang_run(plan, v, u, gamma, 1.0 / m, m)
-            return u
+            def solve(m):
+                u = u0.clone()
+                lt.strang_run(plan, v, u, gamma, 1.0 / m, m)
+                return u
 
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        ref = solve(10000)
-        torch.cuda.synchronize()
-        t = time.perf_counter() - t
-        ms = [10, 20, 40, 80, 160, 320, 640]
-        errs = [float(torch.sqrt(torch.mean(torch.abs(solve(m) - ref) ** 2)).item()) for m in ms]
-        orders = [float(np.log2(errs[i] / errs[i + 1])) for i in range(len(ms) - 1)]
-        fit = float(np.polyfit(np.log(1.0 / np.asarray(ms, dtype=float)), np.log(errs), 1)[0])
-        log(f"convergence {name}: errors {['%.2e' % e for e in errs]}, orders {['%.2f' % o for o in orders]}, "
-            f"fitted {fit:.2f}")
-        out[name] = {"m": ms, "l2_error": errs, "observed_order": orders, "fitted_order": fit,
-                     "reference_run": {"value": N * 10000 / t, "unit": "lattice-point-steps/s", "seconds": t}}
-        del ref
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ref = solve(10000)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t
+            errs = [float(torch.sqrt(torch.mean(torch.abs(solve(m) - ref) ** 2)).item()) for m in ms]
+            orders = [float(np.log2(errs[i] / errs[i + 1]) / np.log2(ms[i + 1] / ms[i])) for i in range(len(ms) - 1)]
+            fit = float(np.polyfit(np.log(1.0 / np.asarray(ms, dtype=float)), np.log(errs), 1)[0])
+            log(f"convergence {gname} {name}: errors {['%.2e' % e for e in errs]}, orders "
+                f"{['%.2f' % o for o in orders]}, fitted {fit:.2f}")
+            out[f"{gname}_{name}"] = {"m": ms, "l2_error": errs, "observed_order": orders, "fitted_order": fit,
+                                      "reference_run": {"value": N * 10000 / t, "unit": "lattice-point-steps/s",
+                                                        "seconds": t}}
+            del ref
     return out
 
 
@@ -368,10 +428,16 @@ def bench_wide(lt, torch, K, W):
         kernels = lt.lattice_plan_autotune(plan, prec, reps=3)
         u = torch.tensor(u0, dtype=dtype, device=dev)
         work = torch.empty(lt.strang_workspace_size(plan, prec, 1, True), dtype=torch.uint8, device=dev)
+        err = None
+        gold = golden("wide_oracle_samples")
+        if gold is not None and "table1_d6_u" in gold.files:
+            lt.strang_run(plan, v, u, gamma, dt, int(gold["steps"]), work=work)
+            err = sampled_rel(u, gold["table1_d6_idx"], gold["table1_d6_u"])
+            u.copy_(torch.tensor(u0, dtype=dtype, device=dev))
         run = lambda: lt.strang_run(plan, v, u, gamma, dt, m, work=work)  # noqa: E731
         sec = wall(run, K, W)
         out[name] = {"value": N * m / sec, "ms_per_run": sec * 1e3, "kernel_variants": list(kernels),
-                     "kernels": kernel_summary(lt, run, 1)}
+                     "sampled_rel_l2_vs_oracle_after_4_steps": err, "kernels": kernel_summary(lt, run, 1)}
         log(f"wide {name}: {N * m / sec:.3e} pt-steps/s, {sec * 1e3:.1f} ms per {m}-step run")
         del u, work
         torch.cuda.empty_cache()
@@ -402,6 +468,10 @@ def bench_hbm(lt, torch, K, W):
         u = torch.tensor(np.tile(inst.u0, (B, 1)), dtype=dtype, device=dev)
         work = torch.empty(lt.strang_workspace_size(plan, prec, B, True), dtype=torch.uint8, device=dev)
         run = lambda: lt.strang_run(plan, v, u, inst.gamma, inst.dt, m, work=work)  # noqa: E731
+        run()
+        gold = golden("cross_d6_n1048573_oracle_samples")
+        err = (max(sampled_rel(u[b], gold["idx"], gold["u100"]) for b in range(B))
+               if gold is not None and m == 100 else None)
         sec = wall(run, K, W)
         ks = kernel_summary(lt, run, 1)
         col_b, row_b = pass_bytes(info, N, m, S)
@@ -410,7 +480,7 @@ def bench_hbm(lt, torch, K, W):
         row_steady = B * (2 * L * S) + 16 * L
         resident = B * (N * S + L * S) + 16 * N + 16 * L
         out[name] = {"value": B * N * m / sec, "states": B, "ms_per_run": sec * 1e3,
-                     "working_set_MB": resident / 1e6,
+                     "working_set_MB": resident / 1e6, "max_sampled_rel_l2_vs_oracle": err,
                      "column_us": ks["column"]["avg_us"], "row_us": ks["row"]["avg_us"],
                      "column_GBs": col_steady / (ks["column"]["avg_us"] * 1e-6) / 1e9,
                      "row_GBs": row_steady / (ks["row"]["avg_us"] * 1e-6) / 1e9}
@@ -509,13 +579,13 @@ def bench_splitting(lt, torch, K, W):
     return out
 
 
-def cpu_baseline(inst, seconds):
-    import numpy as np
-
+def cpu_worker(seconds):
+    """One oracle process: Strang steps of the benchmark workload for about
+    `seconds`; prints its step count and time as JSON."""
     import oracle as O
-    t = time.perf_counter()
+    import workloads as W_
+    inst = W_.cross_d6_n1048573(steps=1)
     _, s, _ = O.index_set(inst.Z, inst.n, inst.I)
-    log(f"oracle index set {time.perf_counter() - t:.1f}s")
     u = inst.u0.copy()
     steps, spent = 0, 0.0
     while spent < seconds:
@@ -523,10 +593,58 @@ def cpu_baseline(inst, seconds):
         u = O.strang_run(inst.n, s, inst.v, u, inst.gamma, inst.dt, 1)
         spent += time.perf_counter() - t
         steps += 1
-    return {"value": inst.N * steps / spent, "unit": "lattice-point-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{steps} Strang steps of the benchmark workload (N={inst.N}, d=6) in the FP64 "
-                      f"C oracle (radix-2 chirp-z FFTs), single thread, {spent:.1f}s"}
+    print(json.dumps({"steps": steps, "seconds": spent, "N": inst.N}), flush=True)
+
+
+def host_cpu():
+    """CPU model and the cores this process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(seconds):
+    """The FP64 C oracle on the host: one process per usable core (at most 16,
+    the host share of one GPU), each running Strang steps of the benchmark
+    workload on its own state for about `seconds`, started as child processes
+    of this one; plus the single-core rate of the first worker."""
+    import subprocess
+    host = host_cpu()
+    P = max(1, min(16, host["usable_cpus"] or 1))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    t = time.perf_counter()
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(seconds)],
+                              stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, env=env, text=True)
+             for _ in range(P)]
+    res = []
+    for p in procs:
+        o, _ = p.communicate()
+        lines = [x for x in o.splitlines() if x.startswith("{")]
+        if p.returncode == 0 and lines:
+            res.append(json.loads(lines[-1]))
+    wall_s = time.perf_counter() - t
+    if not res:
+        return {"value": None, "unit": "lattice-point-steps/s", "cores": 0, "kind": "oracle", "error": "no worker"}
+    N = res[0]["N"]
+    rate_all = sum(N * r["steps"] / r["seconds"] for r in res)
+    one = res[0]
+    return {"value": rate_all, "unit": "lattice-point-steps/s", "cores": len(res), "kind": "oracle",
+            "sample": f"{len(res)} processes (one per core, single-threaded), each {one['steps']} or so Strang "
+                      f"steps of the benchmark workload (N={N}, d=6) in the FP64 C oracle (radix-2 chirp-z FFTs) "
+                      f"on its own state for about {seconds:.0f}s; value = sum of the per-process rates",
+            "single_core": {"value": N * one["steps"] / one["seconds"], "steps": one["steps"],
+                            "seconds": one["seconds"]},
+            "host": host, "wall_s": wall_s}
 
 
 def main():
@@ -543,9 +661,13 @@ def main():
     ap.add_argument("--only", choices=["batched", "rank2", "adjoint", "conservation", "convergence", "splitting",
                                        "wide", "hbm", "initial"],
                     help="run one companion workload alone (profiling)")
+    ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device (counter calibration for the traffic figure)")
     args = ap.parse_args()
+    if args.cpu_worker is not None:
+        cpu_worker(args.cpu_worker)
+        return
     if args.copy_calibration:
         import torch
         a = torch.ones(32 * 1024 * 1024, dtype=torch.complex64, device="cuda:0")
@@ -638,11 +760,24 @@ def main():
     head = results["c64"]
     dom_name = max(head["kinds"], key=lambda k: head["kinds"][k]["total_ms"])
     dom = head["kinds"][dom_name]
+    # accuracy: the run from u0 against the FP64 oracle's state at stored points
     acc = {"norm2_after_run_c64": float(np.mean(np.abs(head["uT"]) ** 2))}
+    gold = golden("cross_d6_n1048573_oracle_samples")
+    for name_, r_ in results.items():
+        if gold is not None and f"u{m}" in gold.files:
+            ref = gold[f"u{m}"]
+            acc[f"{name_}_sampled_rel_l2_vs_oracle"] = float(np.linalg.norm(r_["uT"][gold["idx"]] - ref)
+                                                              / np.linalg.norm(ref))
     if "c128" in results:
         ref = results["c128"]["uT"]
         acc["c64_vs_c128_rel_l2_after_run"] = float(np.linalg.norm(head["uT"] - ref) / np.linalg.norm(ref))
         acc["norm2_after_run_c128"] = float(np.mean(np.abs(ref) ** 2))
+    # roofline on the method's floor: per Strang step the state is read and
+    # written once and the two diagonal tables are read (4 S bytes per point)
+    step_s = head["ms_per_step"] * 1e-3 / m
+    floor_step = 4 * 8 * N
+    col_t, row_t = pmc_traffic("column"), pmc_traffic("row")
+    sched_step = (sum(pass_bytes(info, N, m, 8)[0]) + sum(pass_bytes(info, N, m, 8)[1])) / m
 
     out = {
         "metric": METRIC,
@@ -662,14 +797,24 @@ def main():
                                "+ minimal-l2 completion, gamma=0.05, dt=1e-3, "
                                f"{m} Strang steps per run, complex64 with FP64 phases",
                    "N": N, "d": 6, "time_steps_per_run": m, "fft_len": info["fft_len"]},
-        "roofline": {"bound": "hbm", "kernel": f"k_{'row' if dom_name == 'row' else 'col'} (c64)",
-                     "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom["achieved_GBs"] / HBM_PEAK_GBS if dom["achieved_GBs"] else None,
-                     "traffic": pmc_traffic() if dom_name == "column" else None,
-                     "traffic_note": "HBM bytes per steady-state column launch from rocprofv3 FETCH_SIZE x2 + "
-                                     "WRITE_SIZE x1 (factors from a 256 MiB copy)",
-                     "avg_launch_us": dom["avg_us"],
-                     "bytes_per_launch": dom["bytes_per_launch"],
+        "roofline": {"bound": "hbm", "kernel": "one Strang step: k_colf + k_rowf (c64)",
+                     "achieved": floor_step / step_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": floor_step / step_s / 1e9 / HBM_PEAK_GBS,
+                     "traffic": (col_t + row_t) if (col_t and row_t) else None,
+                     "basis": "achieved = the method's floor (32 B per point-step in complex64: the state read "
+                              "and written once, the potential and kinetic diagonals read once) x N per step, "
+                              "divided by the timed per-step time (run time / steps); traffic = counter-measured "
+                              "HBM bytes of one steady-state column plus one row launch (rocprofv3 FETCH_SIZE x2 "
+                              "+ WRITE_SIZE x1, factors from a 256 MiB copy)",
+                     "bytes_per_step": {"floor": floor_step, "schedule": sched_step,
+                                        "counter": (col_t + row_t) if (col_t and row_t) else None},
+                     "us_per_step": step_s * 1e6,
+                     "dominant_kernel": {"name": f"k_{'rowf' if dom_name == 'row' else 'colf'} (c64)",
+                                         "avg_launch_us": dom["avg_us"],
+                                         "schedule_bytes_per_launch": dom["bytes_per_launch"],
+                                         "achieved_GBs": dom["achieved_GBs"],
+                                         "frac_of_schedule_bytes": dom["achieved_GBs"] / HBM_PEAK_GBS
+                                         if dom["achieved_GBs"] else None},
                      "instrumented_ms_per_run": head["instrumented_ms_per_run"]},
         "bytes_per_point_step": {
             name_: {"algorithmic_floor": 4 * S_,
@@ -694,7 +839,7 @@ def main():
             out[name] = fn(lt, torch, args.steps, args.warmup)
             torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
