@@ -181,6 +181,26 @@ lt_status strang_run(const lt_plan *p, lt_prec prec, int32_t batch, const double
                      void *ckpt, int64_t ckpt_every, void *work, size_t work_bytes, void *stream);
 
 /*
+ * strang_run_noalloc -- strang_run (same arguments, no checkpoints) for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  The run's workspace is a static
+ * device array of the library, one per GPU, held until the process ends; the
+ * call allocates nothing (no hipMalloc, no stream-ordered allocation) and
+ * only enqueues kernels on `stream`.
+ *   - The plan's device tables for `prec` must exist (lattice_plan with prec
+ *     in prec_mask, or an earlier run): otherwise LT_E_ARG, before any launch.
+ *   - A run whose workspace (strang_workspace_size) exceeds the array
+ *     (strang_run_noalloc_capacity: 128 MiB) fails with LT_E_ARG.
+ *   - Every call on one GPU shares that GPU's array, and the array keeps the
+ *     last call's contents (a run rebuilds everything it reads from it), so
+ *     calls that overlap on one GPU (other streams, other threads) race.
+ */
+lt_status strang_run_noalloc_capacity(size_t *bytes);
+lt_status strang_run_noalloc(const lt_plan *p, lt_prec prec, int32_t batch, const double *v,
+                             int64_t v_stride, void *u, double gamma, double dt, int64_t steps,
+                             void *stream);
+
+/*
  * strang_run_sums -- strang_run (same arguments and semantics) that also
  * records, at every step boundary j = 0..steps, the two point sums of the
  * state u_j of Sec. 3.3 (norm conservation and the potential part of the

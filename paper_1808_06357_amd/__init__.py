@@ -16,7 +16,8 @@ from ._capi import (LT_C64, LT_C128, LT_KIND_COLUMN, LT_KIND_RESIDENT, LT_KIND_R
                     strang_adjoint_workspace_size, strang_batched_workspace_size, strang_run,
                     strang_run_batched, strang_run_sums, strang_run_sums_workspace_size,
                     strang_workspace_size, Batch, strang_batch_create, strang_batch_run,
-                    strang_batch_autotune, strang_batch_kernels)
+                    strang_batch_autotune, strang_batch_kernels, strang_run_noalloc,
+                    strang_run_noalloc_capacity)
 from .autograd import LatticeStrang, lattice_strang
 
 __all__ = ["LT_C64", "LT_C128", "LatticeError", "Plan", "lattice_plan", "lattice_plan_info",
@@ -29,4 +30,5 @@ __all__ = ["LT_C64", "LT_C128", "LatticeError", "Plan", "lattice_plan", "lattice
            "lattice_diagnostics_workspace_size",
            "splitting_run", "splitting_workspace_size", "splitting_times", "lattice_projection_error",
            "lattice_projection_error_workspace_size", "strang_run_sums", "strang_run_sums_workspace_size",
-           "Batch", "strang_batch_create", "strang_batch_run", "strang_batch_autotune", "strang_batch_kernels"]
+           "Batch", "strang_batch_create", "strang_batch_run", "strang_batch_autotune", "strang_batch_kernels",
+           "strang_run_noalloc", "strang_run_noalloc_capacity"]

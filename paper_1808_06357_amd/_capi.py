@@ -65,6 +65,8 @@ _SIGS = {
     "strang_workspace_size": [_P, _i32, _i32, _i32, ctypes.POINTER(_sz)],
     "strang_run": [_P, _i32, _i32, _P, _i64, _P, _f64, _f64, _i64, _P, _i64, _P, _sz, _P],
     "strang_run_sums_workspace_size": [_P, _i32, _i32, _i32, _i64, ctypes.POINTER(_sz)],
+    "strang_run_noalloc_capacity": [ctypes.POINTER(_sz)],
+    "strang_run_noalloc": [_P, _i32, _i32, _P, _i64, _P, _f64, _f64, _i64, _P],
     "strang_run_sums": [_P, _i32, _i32, _P, _i64, _P, _f64, _f64, _i64, _P, _i64, _P, _P, _sz, _P],
     "strang_adjoint_workspace_size": [_P, _i32, _i32, _i32, ctypes.POINTER(_sz)],
     "strang_adjoint": [_P, _i32, _i32, _P, _i64, _P, _P, _f64, _f64, _i64, _P, _i64, _P, _P, _P, _sz, _P],
@@ -250,6 +252,29 @@ def strang_run(plan: Plan, v, u, gamma: float, dt: float, steps: int, ckpt=None,
     _check(lib.strang_run(plan.handle, prec, batch, _dev_ptr(v), v_stride, _dev_ptr(u), float(gamma),
                           float(dt), int(steps), _dev_ptr(ckpt), int(ckpt_every), _dev_ptr(work), wb,
                           _stream(stream)), "strang_run")
+    return u
+
+
+def strang_run_noalloc_capacity() -> int:
+    n = _sz()
+    _check(lib.strang_run_noalloc_capacity(ctypes.byref(n)), "strang_run_noalloc_capacity")
+    return n.value
+
+
+def strang_run_noalloc(plan: Plan, v, u, gamma: float, dt: float, steps: int, stream=None):
+    """strang_run on the library's static per-GPU scratch: allocates nothing
+    (the plan's tables must exist: prec_mask at planning, or an earlier run)."""
+    import torch
+    N = plan.N
+    prec = _prec_of(u)
+    batch = u.numel() // N
+    _check_dev(u, "u", numel=batch * N)
+    _check_dev(v, "v", torch.float64)
+    if v.numel() not in (N, batch * N):
+        raise ValueError("v must hold N or batch*N values")
+    v_stride = 0 if v.numel() == N else N
+    _check(lib.strang_run_noalloc(plan.handle, prec, batch, _dev_ptr(v), v_stride, _dev_ptr(u), float(gamma),
+                                  float(dt), int(steps), _stream(stream)), "strang_run_noalloc")
     return u
 
 

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(LIBDIR, "liblattice_tdse.so")
-SOURCES = ["planner.cpp", "capi.cpp", "timing.cpp", "kernels.hip", "kernels_fast.hip"]
+SOURCES = ["planner.cpp", "capi.cpp", "timing.cpp", "kernels.hip", "kernels_fast.hip", "noalloc.hip"]
 HEADERS = ["lt_internal.h", os.path.join("..", "..", "include", "lattice_tdse.h")]
 ARCH = os.environ.get("LT_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",

@@ -836,6 +836,18 @@ lt_status ensure_device_tables(lt_plan &p, int which, int prec, void *stream)
     return LT_OK;
 }
 
+// Whether the device tables a forward run in precision prec reads exist
+// (then a run with a caller workspace allocates nothing).
+bool forward_tables_ready(lt_plan &p, int prec)
+{
+    std::lock_guard<std::mutex> lock(p.mu);
+    const int which = p.sched[2][prec].ok ? 2 : 0;
+    if (!p.dev[which][prec].built) return false;
+    const Sched &s = p.sched[which][prec];
+    if (s.bluestein && s.passes == 2 && p.sched[0][LT_C128].ok) return p.dev[0][LT_C128].built;
+    return true;
+}
+
 // Device tables a forward run in precision prec reads: its schedule's (the
 // swapped one for a rank-2 tensor with long columns), plus the complex128
 // tables of a two-pass chirp-z lattice, whose convolution spectrum is built

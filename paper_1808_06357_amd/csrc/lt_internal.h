@@ -271,6 +271,7 @@ Sched make_schedule(const lt_plan &p, int prec, bool force_two_pass);
 lt_status plan_index_set(lt_plan &p);
 lt_status ensure_device_tables(lt_plan &p, int which, int prec, void *stream);
 lt_status prepare_forward_tables(lt_plan &p, int prec, void *stream);
+bool forward_tables_ready(lt_plan &p, int prec);
 bool factor_radices(int64_t L, Radices &out, int max_log2 = 4);
 int64_t smooth7_at_least(int64_t x);
 }  // namespace lt
