@@ -78,7 +78,7 @@ def _load():
                 "or_strang_run": (ctypes.c_int, [ctypes.c_int, P, P, i64, P, i64, P, f64, f64, i64,
                                                  ctypes.c_int, P]),
                 "or_strang_vjp": (ctypes.c_int, [ctypes.c_int, P, P, i64, P, i64, P, P, f64, f64, i64,
-                                                 ctypes.c_int, P, P]),
+                                                 ctypes.c_int, P, P, P]),
             }
             for name, (res, args) in sig.items():
                 fn = getattr(lib, name)
@@ -195,10 +195,11 @@ def strang_run(n, s_of_key, v, u0, gamma, dt, steps, method="auto", history=Fals
     return (u, hist) if history else u
 
 
-def strang_vjp(n, s_of_key, v, u0, gT, gamma, dt, steps, method="auto"):
+def strang_vjp(n, s_of_key, v, u0, gT, gamma, dt, steps, method="auto", return_abs=False):
     """Reverse-mode derivative of u(T) = S^m u0: returns (g0, gv) given the
     cotangent gT = dJ/dRe u(T) + i dJ/dIm u(T).  gv is summed over the batch
-    when v is shared."""
+    when v is shared.  return_abs: also return gv_abs, the same sums of the
+    terms' absolute values (gv_abs / |gv| is the conditioning of each sum)."""
     n = np.ascontiguousarray(np.atleast_1d(np.asarray(n, dtype=np.int64)))
     N = int(np.prod(n))
     s = np.ascontiguousarray(s_of_key, dtype=np.int64)
@@ -212,10 +213,14 @@ def strang_vjp(n, s_of_key, v, u0, gT, gamma, dt, steps, method="auto"):
     v_stride = 0 if v.ndim == 1 else N
     g0 = np.empty_like(u0)
     gv = np.zeros((1 if v_stride == 0 else batch, N))
+    ga = np.zeros_like(gv) if return_abs else None
     _check(_load().or_strang_vjp(n.size, _p(n), _p(s), batch, _p(v), v_stride, _p(u0), _p(gT),
                                  float(gamma), float(dt), int(steps), _METHODS[method], _p(g0),
-                                 _p(gv)), "strang_vjp")
-    return g0.reshape(shape), (gv[0] if v_stride == 0 else gv)
+                                 _p(gv), _p(ga) if return_abs else None), "strang_vjp")
+    out = (g0.reshape(shape), (gv[0] if v_stride == 0 else gv))
+    if return_abs:
+        out = out + ((ga[0] if v_stride == 0 else ga),)
+    return out
 
 
 def composition_weights(order):

@@ -534,6 +534,36 @@ def _small_problem(batch=1, shared=True):
     return n, s, v, u0
 
 
+def test_vjp_abs_sums_single_step_dense():
+    """gv_abs (the conditioning output of the VJP) on one step, N = 55: with
+    dense matrices (DFT matrix F, K, P), a = P u0, b = F^H K F a,
+    y = conj(P) gT, mu = F^H conj(K) F y, the two terms per point are
+    t1 = c Im(conj(y) b) and t2 = c Im(conj(mu) a) (c = dt / (2 gamma)):
+    gv = t1 + t2 and gv_abs = |t1| + |t2|; over several steps and states
+    gv_abs >= |gv|."""
+    n, s, v, u0 = _small_problem(batch=1)
+    N, gamma, dt = 55, 0.3, 0.07
+    g = np.random.default_rng(12)
+    gT = g.standard_normal(N) + 1j * g.standard_normal(N)
+    _, gv, ga = O.strang_vjp(n, s, v, u0[0], gT, gamma, dt, 1, return_abs=True)
+    k = np.arange(N)
+    F = np.exp(-2j * PI * np.outer(k, k) / N) / np.sqrt(N)
+    K = np.exp(-1j * 2 * PI * PI * gamma * dt * s)
+    P = np.exp(-1j * dt * v / (2 * gamma))
+    c = dt / (2 * gamma)
+    a = P * u0[0]
+    b = F.conj().T @ (K * (F @ a))
+    y = np.conj(P) * gT
+    mu = F.conj().T @ (np.conj(K) * (F @ y))
+    t1, t2 = c * np.imag(np.conj(y) * b), c * np.imag(np.conj(mu) * a)
+    assert np.max(np.abs(gv - (t1 + t2))) < 1e-13
+    assert np.max(np.abs(ga - (np.abs(t1) + np.abs(t2)))) < 1e-13
+    n, s, v, u0 = _small_problem(batch=3)
+    gT = g.standard_normal(u0.shape) + 1j * g.standard_normal(u0.shape)
+    _, gv, ga = O.strang_vjp(n, s, v, u0, gT, gamma, dt, 9, return_abs=True)
+    assert np.all(ga >= np.abs(gv) - 1e-15) and np.max(ga - np.abs(gv)) > 0
+
+
 def test_vjp_dot_product():
     """The state map is linear: Re<y, S^m x> = Re<(S^m)^H y, x>."""
     n, s, v, u0 = _small_problem(batch=2)
