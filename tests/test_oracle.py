@@ -502,6 +502,41 @@ def test_diagnostics_single_mode():
     assert abs(E - (2 * PI * PI * c.gamma * (hv @ hv) + np.mean(c.v) / c.gamma)) < 1e-10
 
 
+def test_bluestein_steps_against_long_double():
+    """A prime lattice (N = 4099, Bluestein transforms) stepped 400 times
+    against the same steps in long double (the kinetic part of a step as the
+    cyclic convolution with the kernel F^-1 K F, evaluated by long-double FFTs
+    through scipy.fft): the chirp-z tables enter every transform, so their
+    rounding adds up over the steps unless they are exact to double
+    precision; the drift stays at the level of the double data path."""
+    import scipy.fft as sf
+    N, d, m, gamma, dt = 4099, 3, 400, 0.05, 2e-3
+    g = np.random.default_rng(3)
+    z = W.korobov(N, d, g)
+    Z, n = z.reshape(1, -1), np.array([N])
+    num = W.point_numerators(Z, n)
+    _, s, _ = O.index_set(Z, n)
+    v = W.cosine_series(d, 16, g).at(num, N)
+    u0 = W.seeded_packet(num, N, g)
+    L = 16384
+    pil = np.longdouble("3.14159265358979323846264338327950288")
+    th = 2 * pil ** 2 * np.longdouble(gamma) * np.longdouble(dt)
+    k = sf.ifft(np.exp(-1j * (th * s.astype(np.longdouble))).astype(np.clongdouble))
+    gk = np.zeros(L, np.clongdouble)
+    gk[:N] = k
+    gk[L - N + 1:] = k[1:]
+    G = sf.fft(gk)
+    P = np.exp(-1j * (np.longdouble(dt) * v.astype(np.longdouble) / (2 * np.longdouble(gamma))))
+    x = u0.astype(np.clongdouble)
+    for _ in range(m):
+        xp = np.zeros(L, np.clongdouble)
+        xp[:N] = x * P
+        x = sf.ifft(sf.fft(xp) * G)[:N] * P
+    got = O.strang_run(n, s, v, u0, gamma, dt, m)
+    e = float(np.linalg.norm(got - x) / np.linalg.norm(x))
+    assert e < 1.5e-13, e
+
+
 def test_history_potential_term():
     """The history's third column is the potential term (1/(gamma N)) sum v |u|^2
     of <Hu, u> (Sec. 3.3).  A single mode has |u| = 1 at every point and the
