@@ -262,7 +262,8 @@ __device__ __forceinline__ void tw4_base_step(cx<double> &b, cx<double> &st, int
 // kinetic step from the table indexed by the squared norm; MID 2: the merged
 // potential step from v in FP64 (runs without a table); MID 3: the angle of
 // a time-dependent potential from two fields; MID 7: MID 0 plus the store of
-// the step's checkpoint.
+// the step's checkpoint (and the step's sums when asked for); MID 8: MID 0
+// plus the step's sums of |u|^2 and v |u|^2.
 template <typename T, int E, int NT, int MID, int... Rs>
 __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
 {
@@ -290,7 +291,7 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
     // thread, the table entries of the first group are loaded with the state
     // (halving the burst of table loads after the inverse DFT), the rest
     // after the inverse DFT
-    constexpr bool kPreP = MID == 0 && sizeof(T) == 4 && J > 1;
+    constexpr bool kPreP = (MID == 0 || MID == 8) && sizeof(T) == 4 && J > 1;
     constexpr uint32_t ps = (uint32_t)(sizeof(Tw<T>) / sizeof(cx<T>));
     Tw<T> pre[kPreP ? R : 1];
     if constexpr (kPreP) {
@@ -336,7 +337,7 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
     } else if constexpr (MID == 6) {
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = conjg(v[e]);
-    } else if constexpr (MID == 0 || MID == 7) {
+    } else if constexpr (MID == 0 || MID == 7 || MID == 8) {
         if constexpr (MID == 7) {
             // checkpoint of the state at this step boundary: the lattice value
             // u = x exp(-i ck_phase v) of every valid point, in FP64 like the
@@ -384,6 +385,38 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
                     pb[0] = s1;
                     pb[1] = s2;
                 }
+            }
+        }
+        if constexpr (MID == 8) {
+            // the step's sums of |u|^2 and v |u|^2 over the tile (|x| = |u|
+            // at the boundary), in registers: v of each element at the
+            // element's offset scaled to 8 bytes; the zero padding
+            // (n >= Nvalid) is masked by its offset
+            const rsrc_t rv = make_rsrc(a.sum_v + b * a.v_bs, a.Nvalid * (int64_t)sizeof(double));
+            constexpr uint32_t vdiv = (uint32_t)(sizeof(cx<T>) / sizeof(double));
+            const uint32_t lim = (uint32_t)a.Nvalid * (uint32_t)sizeof(cx<T>);
+            double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                double vv[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    vv[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                           rv, (voff[j] + r * rstep) / vdiv, 0, 0));
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const cx<T> x = v[j * R + r];  // conj of the point value: same modulus
+                    const double q2 = voff[j] + r * rstep < lim ? (double)x.x * (double)x.x + (double)x.y * (double)x.y
+                                                                 : 0.0;
+                    s1 += q2;
+                    s2 += vv[r] * q2;
+                }
+            }
+            block_sum2<NT>(s1, s2);
+            if (threadIdx.x == 0) {
+                double *pb = a.sum_part + ((int64_t)b * a.sum_pt + tile) * 2;
+                pb[0] = s1;
+                pb[1] = s2;
             }
         }
         // the merged potential step from the per-point table (16 bytes per
@@ -807,9 +840,12 @@ int col_go(const ColArgs &a, int batch, void *stream)
             return timed(LT_KIND_COLUMN, k, dim3(a.L2 / C, batch), dim3(NT), lds_bytes<T, V>(), stream, a);
         }
     }
-    if (a.ck || a.sum_part) {
+    if (a.ck) {  // checkpoint pass (and the step's sums, when asked for)
         if (!a.v || a.v2 || !a.ptab) return -1;
         k = k_colf<T, E, NT, MINW, 7, Rs...>;
+    } else if (a.sum_part) {  // merged step plus the step's sums in registers
+        if (!a.v || a.v2 || !a.ptab || !a.sum_v) return -1;
+        k = k_colf<T, E, NT, MINW, 8, Rs...>;
     } else if (a.v) {
         if (a.v2) k = k_colf<T, E, NT, MINW, 3, Rs...>;
         else if (a.ptab) k = k_colf<T, E, NT, MINW, 0, Rs...>;
@@ -825,6 +861,8 @@ int col_go(const ColArgs &a, int batch, void *stream)
         hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 3, Rs...>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 7, Rs...>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+        hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 8, Rs...>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         if constexpr (sizeof(T) == 8)
             hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 2, Rs...>,
@@ -1013,7 +1051,8 @@ int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *st
     const bool steady = a.pre_inv && a.post_fwd && !a.in && !a.out && !a.chirp && a.scale == 1.0 &&
                         !a.adjoint && ((a.v != nullptr) != (a.ktab != nullptr)) &&
                         (prec == LT_C128 || !a.v || a.ptab || a.v2) &&
-                        (!a.ck || (a.ptab && a.v && !a.v2 && !a.ck_chirp && a.ck_v));
+                        (!a.ck || (a.ptab && a.v && !a.v2 && !a.ck_chirp && a.ck_v)) &&
+                        (!a.sum_part || (a.ptab && a.v && !a.v2 && a.sum_v));
     if (!steady || !fast_col_fits(prec, variant, a.L1, a.L2, a.C)) return -1;
     if (variant == 3 && a.L1 == 4096)
         return prec == LT_C128 ? go<double, 3, true>(a.L1, a, batch, stream) : go<float, 3, true>(a.L1, a, batch, stream);
