@@ -523,35 +523,45 @@ __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
 
 // Interior merge pass of the adjoint sweep (no checkpoint reset, no chirp):
 // the tile holds C/2 state columns (sequences q < C/2, buffer buf) and the
-// same C/2 cotangent columns (sequences q >= C/2, buffer buf2).  After the
-// inverse column DFTs the two values of each point meet through LDS:
-// a = state, mu = cotangent; dJ/dv[n] += gcoef Im(conj(mu) a); both are
-// multiplied by exp(-i phase v[n]); then the forward column DFTs.
+// same C/2 cotangent columns (sequences q >= C/2, buffer buf2, which follows
+// buf in the same allocation).  After the inverse column DFTs the two values
+// of each point meet through LDS: a = state, mu = cotangent;
+// dJ/dv[n] += gcoef Im(conj(mu) a); both are multiplied by exp(-i phase v[n])
+// from the sweep's table; then the forward column DFTs.  Both vectors are
+// addressed through one buffer resource (the cotangent at a fixed element
+// offset), and every accumulator and table entry a thread touches is loaded
+// before the first use.
 template <typename T, int E, int NT, int MINW, int... Rs>
 __global__ void __launch_bounds__(NT, MINW) k_colf_adj(ColArgs a)
 {
     using F = Fft<T, E, NT, true, Rs...>;
     constexpr int C = F::SEQ, H = C / 2, J = F::J, R = F::R, BPS = F::BPS, L1 = F::L;
     static_assert(C % 2 == 0, "state and cotangent columns pair up");
+    constexpr int IT = H * L1 / NT;  // points per thread in the pairing step
+    static_assert((H * L1) % NT == 0, "whole pairing iterations");
     extern __shared__ char smem_raw[];
     cx<T> *s = reinterpret_cast<cx<T> *>(smem_raw);
     const int L2 = a.L2;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t b = blockIdx.y;
     const int c0 = tile * H;
-    cx<T> *buf0 = (cx<T> *)a.buf + b * a.buf_bs;
-    cx<T> *buf1 = (cx<T> *)a.buf2 + b * a.buf2_bs;
+    cx<T> *base = (cx<T> *)a.buf + b * a.buf_bs;
+    const uint32_t delta = (uint32_t)((cx<T> *)a.buf2 - (cx<T> *)a.buf);  // cotangent offset, elements
+    const rsrc_t rb = make_rsrc(base, ((int64_t)delta + (int64_t)L1 * L2) * (int64_t)sizeof(cx<T>));
+    constexpr uint32_t S = (uint32_t)sizeof(cx<T>);
+    const uint32_t rstep = (uint32_t)BPS * (uint32_t)L2 * S;
     typename F::Bases B;
     F::load_bases(B, (const Tw<T> *)a.twa);
+    uint32_t voff[J];
     cx<T> v[E];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int bf = threadIdx.x + j * NT;
         const int q = F::q_of(bf), t = F::t_of(bf);
-        const int n2 = c0 + (q < H ? q : q - H);
-        cx<T> *bq = q < H ? buf0 : buf1;
+        const uint32_t n2 = (uint32_t)(c0 + (q < H ? q : q - H));
+        voff[j] = ((uint32_t)t * (uint32_t)L2 + n2 + (q < H ? 0u : delta)) * S;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[j * R + r] = bq[(int64_t)(t + r * BPS) * L2 + n2];
+        for (int r = 0; r < R; ++r) v[j * R + r] = bload<T>(rb, voff[j], r * rstep);
     }
     const bool tw = a.twiddle != 0;
     cx<double> tb[J], ts[J];
@@ -584,31 +594,42 @@ __global__ void __launch_bounds__(NT, MINW) k_colf_adj(ColArgs a)
 #pragma unroll
         for (int r = 0; r < R; ++r) s[F::addr(q, t + r * BPS)] = conjg(v[j * R + r]);
     }
-    __syncthreads();
-    const double *vb = a.v + b * a.v_bs;
-    double *gb = a.gacc + b * a.gacc_bs;
-    for (int i = threadIdx.x; i < H * L1; i += NT) {
+    // the accumulator and table entries of this thread's points, all in flight
+    // at once (point n = k1 L2 + c0 + q of iteration it; the buffers' range
+    // checks read the zero padding n >= Nvalid as 0 and drop its stores)
+    const rsrc_t rg = make_rsrc(a.gacc + b * a.gacc_bs, a.Nvalid * (int64_t)sizeof(double));
+    const rsrc_t rp = make_rsrc((const Tw<T> *)a.ptab + b * a.ptab_bs, a.Nvalid * (int64_t)sizeof(Tw<T>));
+    double g_in[IT];
+    Tw<T> pw[IT];
+    uint32_t nn[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int i = threadIdx.x + it * NT;
         const int k1 = i / H, q = i - k1 * H;
-        const int64_t n = (int64_t)k1 * L2 + c0 + q;
+        nn[it] = (uint32_t)k1 * (uint32_t)L2 + (uint32_t)(c0 + q);
+        g_in[it] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rg, nn[it] * 8u, 0, 0));
+        pw[it] = __builtin_bit_cast(Tw<T>, __builtin_amdgcn_raw_buffer_load_b128(
+                                               rp, nn[it] * (uint32_t)sizeof(Tw<T>), 0, 0));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int i = threadIdx.x + it * NT;
+        const int k1 = i / H, q = i - k1 * H;
         const int ax = F::addr(q, k1), ay = F::addr(q + H, k1);
-        if (n >= a.Nvalid) {
+        if ((int64_t)nn[it] >= a.Nvalid) {
             s[ax] = {0, 0};
             s[ay] = {0, 0};
             continue;
         }
         const cx<T> x = s[ax], y = s[ay];
         const double im = (double)y.x * (double)x.y - (double)y.y * (double)x.x;
-        gb[n] += a.gcoef * im;
-        double c, sn;
-        if (a.ptab) {  // the sweep's table of exp(-i phase v[n])
-            const cx<double> w = tw_d(((const Tw<T> *)a.ptab)[b * a.ptab_bs + n]);
-            c = w.x;
-            sn = w.y;
-        } else {
-            expm_i(a.phase * vb[n], c, sn);
-        }
-        s[ax] = cmul_d(x, c, sn);
-        s[ay] = cmul_d(y, c, sn);
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(rg, 0, 0, 0)), g_in[it] + a.gcoef * im),
+            rg, nn[it] * 8u, 0, 0);
+        const cx<double> w = tw_d(pw[it]);  // the sweep's table of exp(-i phase v[n])
+        s[ax] = cmul_d(x, w.x, w.y);
+        s[ay] = cmul_d(y, w.x, w.y);
     }
     __syncthreads();
 #pragma unroll
@@ -621,13 +642,9 @@ __global__ void __launch_bounds__(NT, MINW) k_colf_adj(ColArgs a)
     F::run(v, s, B, true);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        const int bf = threadIdx.x + j * NT;
-        const int q = F::q_of(bf), t = F::t_of(bf);
-        const int n2 = c0 + (q < H ? q : q - H);
-        cx<T> *bq = q < H ? buf0 : buf1;
         if (tw) apply_series<T, R>(&v[j * R], tb[j], ts[j]);
 #pragma unroll
-        for (int r = 0; r < R; ++r) bq[(int64_t)(t + r * BPS) * L2 + n2] = v[j * R + r];
+        for (int r = 0; r < R; ++r) bstore(v[j * R + r], rb, voff[j], r * rstep);
     }
 }
 
@@ -1123,8 +1140,14 @@ int adj_dispatch(const ColArgs &a, int batch, void *stream)
 int launch_col_fast_adjoint(int prec, int variant, const ColArgs &a, int batch, void *stream)
 {
     if (variant < 1 || a.adjoint != 2 || a.reset || a.chirp || !a.pre_inv || !a.post_fwd || a.in || a.out ||
-        !fast_len(a.L1) || a.L1 > 2048 || a.C != kTile / a.L1 / 2 || a.L2 % a.C)
+        !fast_len(a.L1) || a.L1 > 2048 || a.C != kTile / a.L1 / 2 || a.L2 % a.C || !a.ptab)
         return -1;
+    // one buffer resource spans a state and its cotangent (which follows the
+    // states in the same allocation): offsets stay below 2^31 bytes
+    const int64_t S = prec == LT_C128 ? 16 : 8;
+    if (a.buf2_bs != a.buf_bs) return -1;
+    const int64_t delta = ((const char *)a.buf2 - (const char *)a.buf) / S;
+    if (delta < 0 || (delta + (int64_t)batch * a.buf_bs + (int64_t)a.L1 * a.L2) * S >= (int64_t(1) << 31)) return -1;
     if (prec == LT_C128) return adj_dispatch<double>(a, batch, stream);
     return adj_dispatch<float>(a, batch, stream);
 }
