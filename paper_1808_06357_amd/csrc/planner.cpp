@@ -12,6 +12,8 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
+#include <vector>
 
 #include "lt_internal.h"
 
@@ -75,20 +77,33 @@ static bool points_distinct(const lt_plan &p)
 }
 
 namespace {
-// Lexicographic enumeration of {h : lo < ||h||^2 <= hi}, h_1 outermost.
+// Lexicographic enumeration of {h : lo < ||h||^2 <= hi} with h_1 in
+// [x0, x1] (h_1 outermost), carrying the key's partial dot products
+// sum_{j' < j} h_j' z_{i,j'} mod n_i down the recursion, so that a vector's
+// key costs one multiply-add per level.
 struct Shell {
-    int d;
+    const lt_plan *p;
+    int d, r;
     int64_t lo, hi;
-    std::vector<int32_t> h;
-    int64_t limit = INT64_MAX, seen = 0;  // the walk stops after `limit` vectors
-    template <class F> void walk(F &&f) { h.assign(d, 0); seen = 0; rec(0, 0, f); }
+    int32_t x0, x1;
+    int32_t h[64];
+    int64_t part[4][64];  // [component][level]
+    template <class F> void walk(F &&f)
+    {
+        for (int i = 0; i < r; ++i) part[i][0] = 0;
+        rec(0, 0, f);
+    }
     template <class F> void rec(int j, int64_t used, F &f)
     {
-        if (seen >= limit) return;
         if (j == d) {
             if (used > lo) {
-                f(h.data(), used);
-                ++seen;
+                int64_t chi = 0;
+                for (int i = 0; i < r; ++i) {
+                    int64_t xi = part[i][d] % p->n[i];
+                    if (xi < 0) xi += p->n[i];
+                    chi = chi * p->n[i] + xi;
+                }
+                f(h, used, chi);
             }
             return;
         }
@@ -96,12 +111,49 @@ struct Shell {
         int32_t a = (int32_t)std::floor(std::sqrt((double)rem));
         while ((int64_t)(a + 1) * (a + 1) <= rem) ++a;
         while ((int64_t)a * a > rem) --a;
-        for (int32_t x = -a; x <= a; ++x) {
+        int32_t from = -a, to = a;
+        if (j == 0) {
+            from = std::max(from, x0);
+            to = std::min(to, x1);
+        }
+        for (int32_t x = from; x <= to; ++x) {
             h[j] = x;
+            for (int i = 0; i < r; ++i)
+                part[i][j + 1] = (part[i][j] + (int64_t)x * zr[i][j]) % p->n[i];
             rec(j + 1, used + (int64_t)x * x, f);
         }
     }
+    int64_t zr[4][64];  // z_{i,j} mod n_i
 };
+
+// first-coordinate ranges for T threads over [-a, a], balanced by the
+// volume of the remaining (d-1)-ball
+std::vector<std::pair<int32_t, int32_t>> split_first(int d, int64_t hi, int T)
+{
+    int32_t a = (int32_t)std::floor(std::sqrt((double)hi));
+    while ((int64_t)(a + 1) * (a + 1) <= hi) ++a;
+    while ((int64_t)a * a > hi) --a;
+    std::vector<double> w;
+    double tot = 0;
+    for (int32_t x = -a; x <= a; ++x) {
+        const double rem = (double)(hi - (int64_t)x * x);
+        const double wx = d > 1 ? std::pow(std::max(rem, 0.0) + 1.0, 0.5 * (d - 1)) : 1.0;
+        w.push_back(wx);
+        tot += wx;
+    }
+    std::vector<std::pair<int32_t, int32_t>> out;
+    double acc = 0;
+    int32_t start = -a;
+    for (int32_t x = -a; x <= a; ++x) {
+        acc += w[(size_t)(x + a)];
+        if ((int)out.size() < T - 1 && acc >= tot * (double)(out.size() + 1) / T) {
+            out.push_back({start, x});
+            start = x + 1;
+        }
+    }
+    if (start <= a) out.push_back({start, a});
+    return out;
+}
 }  // namespace
 
 lt_status plan_index_set(lt_plan &p)
@@ -147,19 +199,60 @@ lt_status plan_index_set(lt_plan &p)
     // host memory.
     const int64_t budget = std::max<int64_t>(int64_t(1) << 26, 64 * N);
     int64_t enumerated = 0;
+    if (d > 64 || p.r > 4) return fail(LT_E_UNSUPPORTED, "at most 64 dimensions and rank 4");
+    Shell proto;
+    proto.p = &p;
+    proto.d = d;
+    proto.r = p.r;
+    for (int i = 0; i < p.r; ++i)
+        for (int j = 0; j < d; ++j) {
+            int64_t zz = p.Z[(size_t)i * d + j] % p.n[i];
+            proto.zr[i][j] = zz < 0 ? zz + p.n[i] : zz;
+        }
+    const int T = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
     while (count < N) {
-        // count the shell per norm, then place vectors in (norm, lex) order
-        Shell sh{d, lo, hi, {}};
-        sh.limit = budget - enumerated + 1;
-        std::vector<int64_t> per((size_t)(hi - (lo < 0 ? 0 : lo) + 2), 0);
+        // the vectors of the range (lo, hi], placed in (norm, lex) order: each
+        // thread walks a contiguous range of first coordinates (so its
+        // vectors of one norm are a contiguous lex range), counts them per
+        // norm, then writes them at offsets ordered by (norm, thread)
         const int64_t base = lo < 0 ? 0 : lo + 1;
+        const size_t nn = (size_t)(hi - base + 1);
+        const auto parts = split_first(d, hi, T);
+        const int P = (int)parts.size();
+        std::vector<std::vector<int64_t>> cnt((size_t)P, std::vector<int64_t>(nn, 0));
+        std::vector<int32_t> amax_t((size_t)P, 0);
+        auto run = [&](auto &&body) {
+            std::vector<std::thread> th;
+            for (int t = 0; t < P; ++t) th.emplace_back([&, t]() { body(t); });
+            for (auto &x : th) x.join();
+        };
+        run([&](int t) {
+            Shell sh = proto;
+            sh.lo = lo;
+            sh.hi = hi;
+            sh.x0 = parts[(size_t)t].first;
+            sh.x1 = parts[(size_t)t].second;
+            int64_t *c = cnt[(size_t)t].data();
+            int32_t am = 0;
+            sh.walk([&](const int32_t *h, int64_t sn, int64_t) {
+                ++c[sn - base];
+                for (int j = 0; j < d; ++j) am = std::max(am, std::abs(h[j]));
+            });
+            amax_t[(size_t)t] = am;
+        });
         int64_t total = 0;
         int32_t amax = 0;
-        sh.walk([&](const int32_t *h, int64_t s) {
-            ++per[(size_t)(s - base)];
-            ++total;
-            for (int j = 0; j < d; ++j) amax = std::max(amax, std::abs(h[j]));
-        });
+        std::vector<std::vector<int64_t>> off((size_t)P, std::vector<int64_t>(nn, 0));
+        std::vector<int64_t> norm_start(nn + 1, 0);
+        for (size_t k = 0; k < nn; ++k) {
+            norm_start[k] = total;
+            for (int t = 0; t < P; ++t) {
+                off[(size_t)t][k] = total;
+                total += cnt[(size_t)t][k];
+            }
+        }
+        norm_start[nn] = total;
+        for (int t = 0; t < P; ++t) amax = std::max(amax, amax_t[(size_t)t]);
         enumerated += total;
         if (enumerated > budget)
             return fail(LT_E_UNSUPPORTED,
@@ -167,31 +260,38 @@ lt_status plan_index_set(lt_plan &p)
                             " frequency vectors (" + std::to_string(N - count) +
                             " keys still uncovered at squared radius " + std::to_string(lo < 0 ? 0 : lo) +
                             "): the generating vector has short dual vectors; choose a better lattice");
-        std::vector<int64_t> off(per.size() + 1, 0);
-        for (size_t t = 0; t < per.size(); ++t) off[t + 1] = off[t] + per[t];
-        std::vector<int64_t> fill(off.begin(), off.end() - 1);
         const bool narrow = amax <= 127;
         std::vector<int8_t> h8(narrow ? (size_t)total * d : 0);
         std::vector<int32_t> h32(narrow ? 0 : (size_t)total * d);
-        std::vector<int64_t> snorm((size_t)total);
-        sh.walk([&](const int32_t *h, int64_t s) {
-            int64_t at = fill[(size_t)(s - base)]++;
-            snorm[(size_t)at] = s;
-            for (int j = 0; j < d; ++j) {
-                if (narrow) h8[(size_t)at * d + j] = (int8_t)h[j];
-                else h32[(size_t)at * d + j] = h[j];
-            }
+        std::vector<int64_t> keys((size_t)total);
+        run([&](int t) {
+            Shell sh = proto;
+            sh.lo = lo;
+            sh.hi = hi;
+            sh.x0 = parts[(size_t)t].first;
+            sh.x1 = parts[(size_t)t].second;
+            std::vector<int64_t> &o = off[(size_t)t];
+            sh.walk([&](const int32_t *h, int64_t sn, int64_t chi) {
+                const int64_t at = o[(size_t)(sn - base)]++;
+                keys[(size_t)at] = chi;
+                for (int j = 0; j < d; ++j) {
+                    if (narrow) h8[(size_t)at * d + j] = (int8_t)h[j];
+                    else h32[(size_t)at * d + j] = h[j];
+                }
+            });
         });
-        std::vector<int32_t> hv(d);
-        for (int64_t at = 0; at < total && count < N; ++at) {
-            for (int j = 0; j < d; ++j)
-                hv[j] = narrow ? h8[(size_t)at * d + j] : h32[(size_t)at * d + j];
-            int64_t chi = key_of(p, hv.data());
-            if (owned[(size_t)chi]) continue;
-            owned[(size_t)chi] = 1;
-            p.s_of_key[(size_t)chi] = snorm[(size_t)at];
-            std::memcpy(&p.h_of_key[(size_t)chi * d], hv.data(), (size_t)d * sizeof(int32_t));
-            ++count;
+        // first vector in (norm, lex) order wins each key
+        for (size_t k = 0; k < nn && count < N; ++k) {
+            const int64_t sn = base + (int64_t)k;
+            for (int64_t at = norm_start[k]; at < norm_start[k + 1] && count < N; ++at) {
+                const int64_t chi = keys[(size_t)at];
+                if (owned[(size_t)chi]) continue;
+                owned[(size_t)chi] = 1;
+                p.s_of_key[(size_t)chi] = sn;
+                int32_t *dst = &p.h_of_key[(size_t)chi * d];
+                for (int j = 0; j < d; ++j) dst[j] = narrow ? h8[(size_t)at * d + j] : h32[(size_t)at * d + j];
+                ++count;
+            }
         }
         lo = hi;
         hi = hi + hi / 3 + 1;
