@@ -145,3 +145,52 @@ def test_three_level_checkpoints_match_shorter_runs(lt):
         e = float(torch.linalg.vector_norm(ck[c] - w) / torch.linalg.vector_norm(w))
         print(f"  checkpoint {c}: rel_l2={e:.2e}", flush=True)
         assert e < 1e-13, (c, e)
+
+
+# the Table 1 lattices of d = 4 ... 12 with n = 2^25 (Sec. 3.1; z the first d
+# components of the d = 12 vector), each under one of the paper's initial
+# conditions and potentials (Sec. 3.2), as stored by make_wide_golden.py
+TABLE1_HIGH = {4: ("g2", "v2"), 6: ("g1", "v1"), 8: ("g1", "v2"), 10: ("g2", "v1"), 12: ("g1", "v2")}
+
+
+@pytest.mark.parametrize("d", sorted(TABLE1_HIGH))
+def test_table1_high_dimensions_against_oracle_samples(lt, d):
+    """Planning the minimal-l2 set of 2^25 keys in d dimensions (d = 12 is the
+    largest the planner builds) and 4 steps on the three-level layout, both
+    precisions, against the oracle's state at stored sample points."""
+    import time
+
+    import torch
+    gold = np.load(GOLD)
+    name = f"table1_d{d}"
+    g, pot = TABLE1_HIGH[d]
+    c = W.table1_run(d, 1 << 25, potential=pot, gamma=GAMMA, dt=DT, steps=STEPS, initial=g)
+    assert np.array_equal(c.Z[0], gold[f"{name}_z"])
+    t = time.time()
+    plan = lt.lattice_plan(c.Z, c.n)
+    info = plan.info
+    print(f"  {name} ({g}, {pot}): planned in {time.time() - t:.1f}s, max |h|^2 = {info['max_s']}, "
+          f"layout {info['L1']} x {info['L2']} x {info['L3']}", flush=True)
+    assert info["passes"] == 3 and info["n_index"] + info["n_completed"] == 1 << 25
+    v = torch.tensor(c.v, device="cuda")
+    idx = torch.from_numpy(gold[f"{name}_idx"]).to("cuda")
+    for prec in ("c128", "c64"):
+        u = torch.tensor(c.u0, dtype=_dtype(prec), device="cuda")
+        lt.strang_run(plan, v, u, GAMMA, DT, STEPS)
+        torch.cuda.synchronize()
+        norm2 = float(torch.mean(torch.abs(u.to(torch.complex128)) ** 2))
+        got = u[idx].cpu().numpy().astype(np.complex128)
+        ref = gold[f"{name}_u"]
+        e_samples = rel(got, ref)
+        # the relative L2 error of the whole state, estimated from the
+        # uniform sample (numerator) and the stored norm of the whole state
+        # (denominator): the concentrated g1 and g2 of high d leave most
+        # sampled values near zero, which inflates the samples' own ratio
+        e = float(np.linalg.norm(got - ref) / np.sqrt(len(idx) * float(gold[f"{name}_norm2"])))
+        print(f"    {prec}: relative L2 error of the state (sampled) {e:.2e} (over the samples alone "
+              f"{e_samples:.2e}), norm2 {norm2:.15f}", flush=True)
+        assert e < TOL[prec], (d, prec, e)
+        assert abs(norm2 - float(gold[f"{name}_norm2"])) < 2.0 * TOL[prec]
+        del u
+    del v, plan
+    torch.cuda.empty_cache()
