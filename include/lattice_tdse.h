@@ -241,6 +241,10 @@ lt_status strang_run_sums(const lt_plan *p, lt_prec prec, int32_t batch, const d
  * Per step, with a = P u^{j-1}, b = F^{-1} K F a, y = conj(P) g_j and
  * mu = F^{-1} conj(K) F y, the potential gradient collects
  * dt/(2 gamma) [Im(conj(y) b) + Im(conj(mu) a)] and g_{j-1} = conj(P) mu.
+ * A rank-2 plan with a swapped schedule (lattice_plan_info.swapped) sweeps
+ * the transposed tensor like its forward run: the workspace then also holds
+ * transposed copies of u(T), gT and v; every input and output stays in
+ * lattice order.
  */
 lt_status strang_adjoint_workspace_size(const lt_plan *p, lt_prec prec, int32_t batch,
                                         int32_t shared_v, size_t *bytes);
@@ -403,11 +407,15 @@ lt_status lattice_diagnostics(const lt_plan *p, lt_prec prec, int32_t batch, con
  *   3 = register-staged kernel with its own tiles: 64 threads x 16
  *       elements (1024-element tiles, four times the workgroups of 1 and 2,
  *       for small transforms), or, for 4096-point columns, 512 threads x 16
- *       elements holding two columns per tile.
+ *       elements holding two columns per tile;
+ *   4 = (column passes only) two tiles of variant 2 per workgroup, the
+ *       second tile's loads in flight while the first is transformed.
  * Variants 1 and 2 exist for the power-of-two lengths 64 ... 4096, variant
- * 3 for 64 ... 1024 and 4096-point columns; elsewhere the general kernel
- * runs whatever is selected (rows of 8192 points always take their own
- * 512-thread kernel).
+ * 3 for 64 ... 1024 and 4096-point columns, variant 4 for columns of
+ * 64 ... 4096 points; elsewhere the general kernel runs whatever is
+ * selected (rows of 8192 points always take their own 512-thread kernel).
+ * Column variants are 0 ... 4 and row variants 0 ... 3 (LT_E_ARG
+ * otherwise).
  * The default is 1.
  * A plan keeps two choices per pass: one for launches of a single state (or
  * of few points) and one for launches of many states, batch >= 2 with

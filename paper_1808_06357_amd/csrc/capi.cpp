@@ -262,8 +262,13 @@ RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool s
 }
 
 struct AdjWork {
-    size_t ktab = 0, w = 0, gacc = 0, ptab = 0, conv = 0, conv_tmp = 0, total = 0;
+    size_t ktab = 0, w = 0, gacc = 0, ptab = 0, conv = 0, conv_tmp = 0, ut = 0, gt = 0, vt = 0, total = 0;
 };
+
+// The adjoint sweep's schedule slot: the swapped one of a rank-2 tensor with
+// long columns (the sweep then runs transposed, like the forward run), else
+// slot 1.
+int adj_slot(const lt_plan &p, int prec) { return p.sched[2][prec].ok ? 2 : 1; }
 
 AdjWork adj_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool shared_v)
 {
@@ -280,6 +285,16 @@ AdjWork adj_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool s
         off = align_up(off + (size_t)s.L * 16);
         w.conv_tmp = off;
         off = align_up(off + (size_t)p.N * 16);
+    }
+    if (s.swapped) {
+        // transposed u(T) (later dJ/du0), transposed cotangent (later the
+        // shared gradient), transposed v
+        w.ut = off;
+        off = align_up(off + (size_t)batch * p.N * esz(prec));
+        w.gt = off;
+        off = align_up(off + (size_t)batch * p.N * esz(prec));
+        w.vt = off;
+        off = align_up(off + (size_t)(shared_v ? 1 : batch) * p.N * sizeof(double));
     }
     w.total = off;
     return w;
@@ -1078,7 +1093,7 @@ lt_status strang_adjoint_workspace_size(const lt_plan *p, lt_prec prec, int32_t 
     if (!p || !bytes) return fail(LT_E_ARG, "NULL argument");
     if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
     if (batch < 0) return fail(LT_E_ARG, "batch must be >= 0");
-    *bytes = adj_layout(*p, p->sched[1][prec], prec, batch, shared_v != 0).total;
+    *bytes = adj_layout(*p, p->sched[adj_slot(*p, prec)][prec], prec, batch, shared_v != 0).total;
     return LT_OK;
 }
 
@@ -1235,12 +1250,30 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
         return LT_OK;
     }
     if (!ckpt || ckpt_every < 1) return fail(LT_E_ARG, "the adjoint needs the forward checkpoints");
-    if ((st = ensure_device_tables(p, 1, prec, stream))) return st;
-    const Sched &s = p.sched[1][prec];
-    const DevTables &D = p.dev[1][prec];
+    const int slot = adj_slot(p, prec);
+    if ((st = ensure_device_tables(p, slot, prec, stream))) return st;
+    const Sched &s = p.sched[slot][prec];
+    const DevTables &D = p.dev[slot][prec];
     const AdjWork L = adj_layout(p, s, prec, batch, shared);
     Scratch sc;
     if ((st = get_work(sc, work, work_bytes, L.total, hs))) return st;
+    // a swapped rank-2 schedule sweeps the transposed tensor (n2 x n1): u(T),
+    // the cotangent and v are transposed into the workspace, the checkpoint
+    // resets read the lattice-order checkpoints transposed, and dJ/du0 and
+    // dJ/dv are transposed back at the end
+    const int n1 = s.L2, n2 = s.L1;
+    if (s.swapped) {
+        void *UT = at(sc.ptr, L.ut), *GT = at(sc.ptr, L.gt);
+        double *VT = (double *)at(sc.ptr, L.vt);
+        HIP_TRY(launch_transpose((int)S, UT, uT, batch, n1, n2, N, N, hs), "state transpose");
+        HIP_TRY(launch_transpose((int)S, GT, gT, batch, n1, n2, N, N, hs), "cotangent transpose");
+        HIP_TRY(launch_transpose(8, VT, v, shared ? 1 : batch, n1, n2, N, shared ? N : v_stride, hs),
+                "potential transpose");
+        uT = UT;
+        gT = GT;
+        v = VT;
+        v_stride = shared ? 0 : N;
+    }
     void *W = at(sc.ptr, L.w);
     double *gacc = (double *)at(sc.ptr, L.gacc);
     double *ktab = (double *)at(sc.ptr, L.ktab);
@@ -1249,9 +1282,9 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
     if ((st = make_ktab(p, s, ktab, gamma, dtb, hs))) return st;
     // the backward sweep's kinetic part F^-1 conj(K) F as one cyclic convolution
     const void *conv = nullptr;
-    if (steps >= kConvMinSteps && conv_available(p, 1, s)) {
-        if ((st = ensure_device_tables(p, 1, LT_C128, stream))) return st;
-        if ((st = conv_spectrum(p, 1, ktab, at(sc.ptr, L.conv), at(sc.ptr, L.conv_tmp), hs))) return st;
+    if (steps >= kConvMinSteps && conv_available(p, slot, s)) {
+        if ((st = ensure_device_tables(p, slot, LT_C128, stream))) return st;
+        if ((st = conv_spectrum(p, slot, ktab, at(sc.ptr, L.conv), at(sc.ptr, L.conv_tmp), hs))) return st;
         conv = at(sc.ptr, L.conv);
     }
     const bool chirpz = s.bluestein && !conv;
@@ -1320,7 +1353,10 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
         const int64_t k = j - 1;  // state index at this merge point
         ColArgs m = base;
         m.pre_inv = 1;
-        if (k % ckpt_every == 0) m.reset = (const char *)ckpt + (size_t)(k / ckpt_every) * batch * N * S;
+        if (k % ckpt_every == 0) {
+            m.reset = (const char *)ckpt + (size_t)(k / ckpt_every) * batch * N * S;
+            m.reset_t = s.swapped ? 1 : 0;
+        }
         if (k > 0) {
             m.adjoint = 2;
             m.phase = 2.0 * halfb;
@@ -1333,11 +1369,22 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
         } else {
             m.adjoint = 3;
             m.phase = halfb;
-            m.out2 = g0;
+            m.out2 = s.swapped ? at(sc.ptr, L.ut) : g0;  // u(T) was read by the first pass
             m.out2_bs = N;
             m.gcoef = c;
         }
         HIP_TRY(launch_col(prec, s, m, batch, hs), "adjoint column pass");
+    }
+    if (s.swapped) {
+        HIP_TRY(launch_transpose((int)S, g0, at(sc.ptr, L.ut), batch, n2, n1, N, N, hs), "gradient transpose");
+        if (shared) {
+            double *GV = (double *)at(sc.ptr, L.gt);  // the cotangent was read by the first pass
+            HIP_TRY(launch_reduce_batch(GV, gacc, N, batch, hs), "gradient reduction");
+            HIP_TRY(launch_transpose(8, gv, GV, 1, n2, n1, N, N, hs), "gradient transpose");
+        } else {
+            HIP_TRY(launch_transpose(8, gv, gacc, batch, n2, n1, N, N, hs), "gradient transpose");
+        }
+        return LT_OK;
     }
     if (shared) {
         HIP_TRY(launch_reduce_batch(gv, gacc, N, batch, hs), "gradient reduction");
@@ -2112,8 +2159,8 @@ lt_status lattice_plan_set_kernels(lt_plan *p, lt_prec prec, int32_t col_variant
 {
     if (!p) return fail(LT_E_ARG, "plan is NULL");
     if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
-    if (col_variant < 0 || col_variant > 3 || row_variant < 0 || row_variant > 3)
-        return fail(LT_E_ARG, "kernel variants are 0, 1, 2 or 3");
+    if (col_variant < 0 || col_variant > 4 || row_variant < 0 || row_variant > 3)
+        return fail(LT_E_ARG, "column kernel variants are 0 to 4, row kernel variants 0 to 3");
     std::lock_guard<std::mutex> lock(p->mu);
     for (int w = 0; w < 3; ++w) {
         Sched &s = p->sched[w][prec];
@@ -2203,7 +2250,7 @@ static lt_status tune_slot(lt_plan *p, int w, lt_prec prec, int32_t reps, void *
     for (int cls = 0; cls < 2 && !st; ++cls) {
         const int batch = cls ? many : 1;
         float tc = 1e30f, tr = 1e30f;
-        for (int var = 0; var <= 3 && !st; ++var) {
+        for (int var = 0; var <= 4 && !st; ++var) {
             float ms = 0.f;
             if (var == 0 || fast_col_fits(prec, var, s.L1, s.L2, s.cols)) {
                 st = time_it(true, var, batch, ms);

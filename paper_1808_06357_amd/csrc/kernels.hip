@@ -205,7 +205,8 @@ __device__ void col_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
                     rc = r;
                     rs = i;
                 }
-                x = cmul_d(ldc<T>(a.reset, b * a.reset_bs + n), rc, rs);
+                const int64_t rn = a.reset_t ? (int64_t)(c0 + qc) * L1 + n1 : n;
+                x = cmul_d(ldc<T>(a.reset, b * a.reset_bs + rn), rc, rs);
             }
             // Im(conj(mu) a) is chirp invariant (|c_n| = 1)
             const double im = (double)y.x * (double)x.y - (double)y.y * (double)x.x;

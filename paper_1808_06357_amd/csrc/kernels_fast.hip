@@ -56,15 +56,23 @@ __device__ __forceinline__ cx<double> bload<double>(rsrc_t r, uint32_t voff, uin
     return __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
+// State stores carry the device-scope coherence bit (sc1): the next pass,
+// on every XCD, reads what this one writes, and a write-back L2 would hold
+// the dirty lines until the release at the end of the kernel.  Measured on
+// the 2^21-point convolution: row pass 13.8 -> 12.3 us (complex64), 16.6 ->
+// 15.7 us (complex128); the column pass is unchanged.  Streaming (nt) stores
+// or loads were slower.
+constexpr int kStoreAux = 16;
+
 __device__ __forceinline__ void bstore(cx<float> x, rsrc_t r, uint32_t voff, uint32_t soff)
 {
     using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, x), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, x), r, voff, soff, kStoreAux);
 }
 __device__ __forceinline__ void bstore(cx<double> x, rsrc_t r, uint32_t voff, uint32_t soff)
 {
     using V = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, x), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, x), r, voff, soff, kStoreAux);
 }
 
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
@@ -264,42 +272,82 @@ __device__ __forceinline__ void tw4_base_step(cx<double> &b, cx<double> &st, int
 // a time-dependent potential from two fields; MID 7: MID 0 plus the store of
 // the step's checkpoint (and the step's sums when asked for); MID 8: MID 0
 // plus the step's sums of |u|^2 and v |u|^2.
-template <typename T, int E, int NT, int MID, int... Rs>
-__device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b, cx<T> *s)
+// Registers of one column tile between its loads and its transforms: the
+// tile's elements, their byte offsets, and (complex64 table steps) the table
+// entries of the first butterfly group.
+template <typename T, int E, int J, int R, bool PRE>
+struct ColTile {
+    cx<T> v[E];
+    uint32_t voff[J];
+    Tw<T> pre[PRE ? R : 1];
+};
+
+// complex64 merged potential step: with two or more butterfly groups per
+// thread, or several tiles per workgroup, the table entries of the first
+// group are loaded with the state (halving the burst of table loads after
+// the inverse DFT), the rest after the inverse DFT
+template <typename T, int MID, int J, int S>
+constexpr bool col_prefetch()
+{
+    return (MID == 0 || MID == 8) && sizeof(T) == 4 && (J > 1 || S > 1);
+}
+
+// Issues every load of column tile `tile` of batch item b: element
+// (t + r BPS, c0 + q) sits at byte voff[j] + r * rstep of the state
+template <typename T, int E, int NT, bool PRE, int... Rs>
+__device__ __forceinline__ void colf_load(const ColArgs &a, int tile, int64_t b,
+                                          ColTile<T, E, Fft<T, E, NT, true, Rs...>::J, Fft<T, E, NT, true, Rs...>::R, PRE> &X)
+{
+    using F = Fft<T, E, NT, true, Rs...>;
+    constexpr int C = F::SEQ, J = F::J, R = F::R, BPS = F::BPS, L1 = F::L;
+    const int L2 = a.L2;
+    const int c0 = tile * C;
+    cx<T> *buf = (cx<T> *)a.buf + b * a.buf_bs;
+    const rsrc_t rb = make_rsrc(buf, (int64_t)L1 * L2 * (int64_t)sizeof(cx<T>));
+    const uint32_t rstep = (uint32_t)BPS * (uint32_t)L2 * (uint32_t)sizeof(cx<T>);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int bf = threadIdx.x + j * NT;
+        X.voff[j] = ((uint32_t)F::t_of(bf) * (uint32_t)L2 + (uint32_t)(c0 + F::q_of(bf))) * (uint32_t)sizeof(cx<T>);
+#pragma unroll
+        for (int r = 0; r < R; ++r) X.v[j * R + r] = bload<T>(rb, X.voff[j], r * rstep);
+    }
+    if constexpr (PRE) {
+        constexpr uint32_t ps = (uint32_t)(sizeof(Tw<T>) / sizeof(cx<T>));
+        const rsrc_t rp = make_rsrc((const Tw<T> *)a.ptab + b * a.ptab_bs, a.Nvalid * (int64_t)sizeof(Tw<T>));
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            X.pre[r] = __builtin_bit_cast(Tw<T>, __builtin_amdgcn_raw_buffer_load_b128(rp, ps * (X.voff[0] + r * rstep), 0, 0));
+    }
+}
+
+// Steady-state column pass: [inverse column DFT -> point-domain multiplier
+// (and chirp-z mask) -> forward column DFT], in place, on column tile `tile`
+// of batch item b, whose loads colf_load issued.  MID 0: the merged potential
+// step from the per-point table the run built; MID 1: the chirp-z
+// kinetic step from the table indexed by the squared norm; MID 2: the merged
+// potential step from v in FP64 (runs without a table); MID 3: the angle of
+// a time-dependent potential from two fields; MID 7: MID 0 plus the store of
+// the step's checkpoint (and the step's sums when asked for); MID 8: MID 0
+// plus the step's sums of |u|^2 and v |u|^2.  sync_first: the workgroup used
+// the LDS buffer before (a previous tile), so the first write waits for it.
+template <typename T, int E, int NT, int MID, bool PRE, int... Rs>
+__device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, cx<T> *s,
+                                         const typename Fft<T, E, NT, true, Rs...>::Bases &B,
+                                         ColTile<T, E, Fft<T, E, NT, true, Rs...>::J, Fft<T, E, NT, true, Rs...>::R, PRE> &X,
+                                         bool sync_first)
 {
     using F = Fft<T, E, NT, true, Rs...>;
     constexpr int C = F::SEQ, J = F::J, R = F::R, BPS = F::BPS, L1 = F::L, TILE = F::TILE;
     const int L2 = a.L2;
     const int c0 = tile * C;
     cx<T> *buf = (cx<T> *)a.buf + b * a.buf_bs;
-    typename F::Bases B;
-    F::load_bases(B, (const Tw<T> *)a.twa);
-    // every state load of the tile is issued before the first use; element
-    // (t + r BPS, c0 + q) sits at byte voff[j] + r * rstep
     const rsrc_t rb = make_rsrc(buf, (int64_t)L1 * L2 * (int64_t)sizeof(cx<T>));
     const uint32_t rstep = (uint32_t)BPS * (uint32_t)L2 * (uint32_t)sizeof(cx<T>);
-    uint32_t voff[J];
-    cx<T> v[E];
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int bf = threadIdx.x + j * NT;
-        voff[j] = ((uint32_t)F::t_of(bf) * (uint32_t)L2 + (uint32_t)(c0 + F::q_of(bf))) * (uint32_t)sizeof(cx<T>);
-#pragma unroll
-        for (int r = 0; r < R; ++r) v[j * R + r] = bload<T>(rb, voff[j], r * rstep);
-    }
-    // complex64 merged potential step: with two or more butterfly groups per
-    // thread, the table entries of the first group are loaded with the state
-    // (halving the burst of table loads after the inverse DFT), the rest
-    // after the inverse DFT
-    constexpr bool kPreP = (MID == 0 || MID == 8) && sizeof(T) == 4 && J > 1;
+    cx<T>(&v)[E] = X.v;
+    const uint32_t(&voff)[J] = X.voff;
+    constexpr bool kPreP = PRE;
     constexpr uint32_t ps = (uint32_t)(sizeof(Tw<T>) / sizeof(cx<T>));
-    Tw<T> pre[kPreP ? R : 1];
-    if constexpr (kPreP) {
-        const rsrc_t rp = make_rsrc((const Tw<T> *)a.ptab + b * a.ptab_bs, a.Nvalid * (int64_t)sizeof(Tw<T>));
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            pre[r] = __builtin_bit_cast(Tw<T>, __builtin_amdgcn_raw_buffer_load_b128(rp, ps * (voff[0] + r * rstep), 0, 0));
-    }
     // four-step twiddle base and step of each butterfly group: the forward
     // pass at the end multiplies by the same series, so they are kept
     const bool tw = a.twiddle != 0;
@@ -327,7 +375,7 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
             for (int r = 0; r < R; ++r) v[j * R + r] = conjg(v[j * R + r]);
             if (tw) apply_series<T, R>(&v[j * R], tb[j], ts[j]);
         }
-        F::run(v, s, B, false);
+        F::run(v, s, B, sync_first);
     }
     // point-domain multiplier: the table entries of all of this thread's
     // elements are loaded in one batch (one exposed latency), then applied
@@ -437,7 +485,7 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
         }
         if constexpr (kPreP) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) pin[0][r] = pre[r];
+            for (int r = 0; r < R; ++r) pin[0][r] = X.pre[r];
         }
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -503,7 +551,7 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
             }
         }
     }
-    if constexpr (kFwd) F::run(v, s, B, kInv);
+    if constexpr (kFwd) F::run(v, s, B, kInv || sync_first);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         if (kFwd && tw) apply_series<T, R>(&v[j * R], tb[j], ts[j]);
@@ -513,12 +561,39 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int tile, int64_t b,
     (void)TILE;
 }
 
+// S column tiles per workgroup (consecutive tiles S w .. S w + S - 1): the
+// loads of all S tiles are issued first, so that the later tiles' loads are
+// in flight while the first tiles are transformed, and the first tiles'
+// stores drain while the later ones are.
+template <typename T, int E, int NT, int MID, int S, int... Rs>
+__device__ __forceinline__ void colf_body(const ColArgs &a, int wtile, int64_t b, cx<T> *s)
+{
+    using F = Fft<T, E, NT, true, Rs...>;
+    constexpr bool PRE = col_prefetch<T, MID, F::J, S>();
+    typename F::Bases B;
+    F::load_bases(B, (const Tw<T> *)a.twa);
+    ColTile<T, E, F::J, F::R, PRE> X[S];
+#pragma unroll
+    for (int st = 0; st < S; ++st) colf_load<T, E, NT, PRE, Rs...>(a, wtile * S + st, b, X[st]);
+#pragma unroll
+    for (int st = 0; st < S; ++st) colf_run<T, E, NT, MID, PRE, Rs...>(a, wtile * S + st, b, s, B, X[st], st > 0);
+}
+
 template <typename T, int E, int NT, int MINW, int MID, int... Rs>
 __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
 {
     extern __shared__ char smem_raw[];
-    colf_body<T, E, NT, MID, Rs...>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.y,
-                                    reinterpret_cast<cx<T> *>(smem_raw));
+    colf_body<T, E, NT, MID, 1, Rs...>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.y,
+                                       reinterpret_cast<cx<T> *>(smem_raw));
+}
+
+// two column tiles per workgroup
+template <typename T, int E, int NT, int MINW, int MID, int... Rs>
+__global__ void __launch_bounds__(NT, MINW) k_colf2(ColArgs a)
+{
+    extern __shared__ char smem_raw[];
+    colf_body<T, E, NT, MID, 2, Rs...>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.y,
+                                       reinterpret_cast<cx<T> *>(smem_raw));
 }
 
 // Interior merge pass of the adjoint sweep (no checkpoint reset, no chirp):
@@ -665,7 +740,7 @@ __global__ void __launch_bounds__(NT, MINW) k_colf_multi(const BatchDesc *d, con
     const BatchDesc &p = d[idx[k]];
     if (g == 0 || (g & 1) || g >= p.npass - 1) return;
     // members with interior passes carry the per-point table of the merged potential step
-    colf_body<T, E, NT, 0, Rs...>(p.col[1], bid - start[k], 0, reinterpret_cast<cx<T> *>(smem_raw));
+    colf_body<T, E, NT, 0, 1, Rs...>(p.col[1], bid - start[k], 0, reinterpret_cast<cx<T> *>(smem_raw));
 }
 
 // Row pass: [DFT -> spectral multiplier -> inverse DFT], in place; the
@@ -800,6 +875,24 @@ template <>
 struct Geo<4> {  // small tiles (one wave, 1024 elements): more workgroups for small transforms
     static constexpr int NT = 64, E = 16, MINW = 2;
 };
+template <>
+struct Geo<5> {  // two 4096-element column tiles of 512 threads x 8 per workgroup
+    static constexpr int NT = 512, E = 8, MINW = 2, S = 2;
+};
+template <int V>
+constexpr int tiles_per_group()
+{
+    if constexpr (V == 5) return Geo<5>::S;
+    else return 1;
+}
+
+// the column kernel for S tiles per workgroup
+template <typename T, int E, int NT, int MINW, int MID, int S, int... Rs>
+constexpr auto colk()
+{
+    if constexpr (S == 2) return k_colf2<T, E, NT, MINW, MID, Rs...>;
+    else return k_colf<T, E, NT, MINW, MID, Rs...>;
+}
 
 template <typename K, typename A>
 int timed(int kind, K kernel, dim3 grid, dim3 block, size_t lds, void *stream, const A &args)
@@ -837,11 +930,11 @@ size_t lds_bytes()
 template <typename T, int V, int... Rs>
 int col_go(const ColArgs &a, int batch, void *stream)
 {
-    constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW;
+    constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW, S = tiles_per_group<V>();
     // MID 0: merged potential step from the per-point table; MID 1: kinetic table;
     // MID 2 (complex128 runs without a table): FP64 phase of v; MID 3:
     // potential with a time-dependent second field
-    auto k = k_colf<T, E, NT, MINW, 1, Rs...>;
+    auto k = colk<T, E, NT, MINW, 1, S, Rs...>();
     if constexpr (V == 1) {
         if (a.pre_inv != a.post_fwd) {
             k = a.post_fwd ? k_colf<T, E, NT, MINW, 5, Rs...> : k_colf<T, E, NT, MINW, 6, Rs...>;
@@ -856,38 +949,41 @@ int col_go(const ColArgs &a, int batch, void *stream)
             constexpr int C = NT * E / Radix<Rs...>::prod;
             return timed(LT_KIND_COLUMN, k, dim3(a.L2 / C, batch), dim3(NT), lds_bytes<T, V>(), stream, a);
         }
+    } else {
+        if (a.pre_inv != a.post_fwd) return -1;
     }
     if (a.ck) {  // checkpoint pass (and the step's sums, when asked for)
         if (!a.v || a.v2 || !a.ptab) return -1;
-        k = k_colf<T, E, NT, MINW, 7, Rs...>;
+        k = colk<T, E, NT, MINW, 7, S, Rs...>();
     } else if (a.sum_part) {  // merged step plus the step's sums in registers
         if (!a.v || a.v2 || !a.ptab || !a.sum_v) return -1;
-        k = k_colf<T, E, NT, MINW, 8, Rs...>;
+        k = colk<T, E, NT, MINW, 8, S, Rs...>();
     } else if (a.v) {
-        if (a.v2) k = k_colf<T, E, NT, MINW, 3, Rs...>;
-        else if (a.ptab) k = k_colf<T, E, NT, MINW, 0, Rs...>;
-        else if constexpr (sizeof(T) == 8) k = k_colf<T, E, NT, MINW, 2, Rs...>;
+        if (a.v2) k = colk<T, E, NT, MINW, 3, S, Rs...>();
+        else if (a.ptab) k = colk<T, E, NT, MINW, 0, S, Rs...>();
+        else if constexpr (sizeof(T) == 8) k = colk<T, E, NT, MINW, 2, S, Rs...>();
         else return -1;
     }
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 0, Rs...>,
+        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 0, S, Rs...>(),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
-        hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 1, Rs...>,
+        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 1, S, Rs...>(),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
-        hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 3, Rs...>,
+        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 3, S, Rs...>(),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
-        hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 7, Rs...>,
+        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 7, S, Rs...>(),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
-        hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 8, Rs...>,
+        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 8, S, Rs...>(),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         if constexpr (sizeof(T) == 8)
-            hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 2, Rs...>,
+            hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 2, S, Rs...>(),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         attr = true;
     }
     constexpr int C = NT * E / Radix<Rs...>::prod;
-    dim3 grid(a.L2 / C, batch);
+    if (a.L2 % (C * S)) return -1;
+    dim3 grid(a.L2 / (C * S), batch);
     const size_t lds = lds_bytes<T, V>();
     return timed(LT_KIND_COLUMN, k, grid, dim3(NT), lds, stream, a);
 }
@@ -923,7 +1019,9 @@ int go1(const A &a, int batch, void *stream)
 template <typename T, int V, bool COL, class A>
 int go(int L, const A &a, int batch, void *stream)
 {
-    if constexpr (V == 3) {  // 16 elements per thread, 512 threads: rows of 8192, pairs of 4096-point columns
+    if constexpr (V == 5 && !COL) {
+        return -1;
+    } else if constexpr (V == 3) {  // 16 elements per thread, 512 threads: rows of 8192, pairs of 4096-point columns
         if (L == 8192 && !COL) return go1<T, V, COL, 16, 4, 8, 16>(a, batch, stream);
         if (L == 4096 && COL) return go1<T, V, COL, 16, 16, 16>(a, batch, stream);
         return -1;
@@ -1049,6 +1147,7 @@ bool fast_col_fits(int prec, int variant, int L1, int L2, int C)
     (void)prec;
     if (variant == 3)
         return (fast_len(L1) && L1 <= kSmallTile && L2 % (kSmallTile / L1) == 0) || (L1 == 4096 && L2 % 2 == 0);
+    if (variant == 4) return fast_len(L1) && C == kTile / L1 && L2 % (2 * C) == 0;
     return (variant == 1 || variant == 2) && fast_len(L1) && C == kTile / L1 && L2 % C == 0;
 }
 
@@ -1076,9 +1175,11 @@ int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *st
     if (prec == LT_C128)
         return variant == 1   ? go<double, 1, true>(a.L1, a, batch, stream)
                : variant == 2 ? go<double, 2, true>(a.L1, a, batch, stream)
+               : variant == 4 ? go<double, 5, true>(a.L1, a, batch, stream)
                               : go<double, 4, true>(a.L1, a, batch, stream);
     return variant == 1   ? go<float, 1, true>(a.L1, a, batch, stream)
            : variant == 2 ? go<float, 2, true>(a.L1, a, batch, stream)
+           : variant == 4 ? go<float, 5, true>(a.L1, a, batch, stream)
                           : go<float, 4, true>(a.L1, a, batch, stream);
 }
 

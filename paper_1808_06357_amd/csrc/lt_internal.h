@@ -123,6 +123,8 @@ struct ColArgs {
     double gcoef;                     // coefficient of Im(conj(mu) a) in the accumulator
     const void *reset; int64_t reset_bs;  // checkpoint replacing the recomputed state, or null
     double reset_phase;               // a = exp(-i reset_phase v) * ckpt (times c_n for chirp-z)
+    int reset_t;                      // 1: the tile is a transposed rank-2 tensor whose checkpoints are
+                                      // in lattice order: point n = k1 L2 + c reads ckpt[c L1 + k1]
     // per-step sums at a step boundary (the point values x have |x| = |u_j|):
     // sum_part[(b sum_pt + tile) 2 + {0, 1}] = (sum |x|^2, sum sum_v[n] |x|^2)
     // over the tile's valid points; sum_v strided as v (v_bs)

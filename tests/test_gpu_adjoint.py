@@ -61,10 +61,13 @@ def test_adjoint_matches_oracle(lt, N, d, shared):
         assert e0 < tol and ev < tol
 
 
-def test_adjoint_after_transposed_rank2_forward(lt):
-    """A rank-2 tensor with long columns runs its forward transposed; its
-    checkpoints (lattice order) feed the adjoint sweep, which runs untransposed:
-    the gradients against the oracle's VJP."""
+@pytest.mark.parametrize("shared", [True, False])
+def test_adjoint_on_transposed_rank2(lt, shared):
+    """A rank-2 tensor with long columns runs its forward transposed and
+    stores its checkpoints in lattice order; the adjoint sweep runs
+    transposed too (u(T), the cotangent and v transposed in, the checkpoint
+    resets read transposed, dJ/du0 and dJ/dv transposed out): the gradients
+    against the oracle's VJP, with a shared and a per-state potential."""
     import torch
     n1, n2, d, batch, gamma, dt, steps, every = 2048, 64, 4, 2, 0.05, 2e-3, 13, 5
     H = W.hyperbolic_cross(d, 1)
@@ -73,7 +76,10 @@ def test_adjoint_after_transposed_rank2_forward(lt):
     N = n1 * n2
     num = W.point_numerators(Z, n)
     g = np.random.default_rng(72)
-    v = W.cosine_series(d, 16, g).at(num, N)
+    if shared:
+        v = W.cosine_series(d, 16, g).at(num, N)
+    else:
+        v = np.stack([W.cosine_series(d, 16, g).at(num, N) for _ in range(batch)])
     u0 = np.stack([W.seeded_packet(num, N, g) for _ in range(batch)])
     tgt = np.stack([W.seeded_packet(num, N, g) for _ in range(batch)])
     plan = lt.lattice_plan(Z, n, H)
@@ -84,7 +90,8 @@ def test_adjoint_after_transposed_rank2_forward(lt):
     for dtype, tol in ((torch.complex128, 1e-11), (torch.complex64, 1e-4)):
         g0, gv = gpu_grad(lt, plan, v, u0, tgt, gamma, dt, steps, every, dtype)
         e0, ev = rel(g0, g0_ref), rel(gv, gv_ref)
-        print(f"rank-2 {n1}x{n2} {dtype} dJ/du0 rel={e0:.2e} dJ/dv rel={ev:.2e}", flush=True)
+        print(f"rank-2 {n1}x{n2} shared={shared} {dtype} dJ/du0 rel={e0:.2e} dJ/dv rel={ev:.2e}", flush=True)
+        assert gv.shape == np.shape(gv_ref)
         assert e0 < tol and ev < tol
 
 
