@@ -408,14 +408,17 @@ lt_status lattice_diagnostics(const lt_plan *p, lt_prec prec, int32_t batch, con
  *       elements (1024-element tiles, four times the workgroups of 1 and 2,
  *       for small transforms), or, for 4096-point columns, 512 threads x 16
  *       elements holding two columns per tile;
- *   4 = (column passes only) two tiles of variant 2 per workgroup, the
- *       second tile's loads in flight while the first is transformed.
+ *   4 = 512 threads x 8 elements with twice the registers of variant 2
+ *       (two waves per SIMD); a column workgroup takes two tiles, the
+ *       second tile's loads in flight while the first is transformed;
+ *   5 = 256 threads x 8 elements on 2048-element tiles (twice the
+ *       workgroups of 1, 2 and 4, two waves per SIMD).
  * Variants 1 and 2 exist for the power-of-two lengths 64 ... 4096, variant
  * 3 for 64 ... 1024 and 4096-point columns, variant 4 for columns of
- * 64 ... 4096 points; elsewhere the general kernel runs whatever is
- * selected (rows of 8192 points always take their own 512-thread kernel).
- * Column variants are 0 ... 4 and row variants 0 ... 3 (LT_E_ARG
- * otherwise).
+ * 64 ... 4096 points and rows of 64 ... 4096, variant 5 for 64 ... 2048;
+ * elsewhere the general kernel runs whatever is selected (rows of 8192
+ * points always take their own 512-thread kernel).  Variants outside
+ * 0 ... 5 give LT_E_ARG.
  * The default is 1.
  * A plan keeps two choices per pass: one for launches of a single state (or
  * of few points) and one for launches of many states, batch >= 2 with

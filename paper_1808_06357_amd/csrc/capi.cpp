@@ -2159,8 +2159,8 @@ lt_status lattice_plan_set_kernels(lt_plan *p, lt_prec prec, int32_t col_variant
 {
     if (!p) return fail(LT_E_ARG, "plan is NULL");
     if (prec != LT_C64 && prec != LT_C128) return fail(LT_E_ARG, "bad precision");
-    if (col_variant < 0 || col_variant > 4 || row_variant < 0 || row_variant > 3)
-        return fail(LT_E_ARG, "column kernel variants are 0 to 4, row kernel variants 0 to 3");
+    if (col_variant < 0 || col_variant > 5 || row_variant < 0 || row_variant > 5)
+        return fail(LT_E_ARG, "kernel variants are 0 to 5");
     std::lock_guard<std::mutex> lock(p->mu);
     for (int w = 0; w < 3; ++w) {
         Sched &s = p->sched[w][prec];
@@ -2250,7 +2250,7 @@ static lt_status tune_slot(lt_plan *p, int w, lt_prec prec, int32_t reps, void *
     for (int cls = 0; cls < 2 && !st; ++cls) {
         const int batch = cls ? many : 1;
         float tc = 1e30f, tr = 1e30f;
-        for (int var = 0; var <= 4 && !st; ++var) {
+        for (int var = 0; var <= 5 && !st; ++var) {
             float ms = 0.f;
             if (var == 0 || fast_col_fits(prec, var, s.L1, s.L2, s.cols)) {
                 st = time_it(true, var, batch, ms);

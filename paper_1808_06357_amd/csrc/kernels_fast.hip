@@ -876,8 +876,14 @@ struct Geo<4> {  // small tiles (one wave, 1024 elements): more workgroups for s
     static constexpr int NT = 64, E = 16, MINW = 2;
 };
 template <>
-struct Geo<5> {  // two 4096-element column tiles of 512 threads x 8 per workgroup
+struct Geo<5> {  // 512 threads x 8 with the register budget of two waves per SIMD: two
+                 // 4096-element column tiles per workgroup, or one row tile
     static constexpr int NT = 512, E = 8, MINW = 2, S = 2;
+};
+template <>
+struct Geo<6> {  // 256 threads x 8 (2048-element tiles): twice the workgroups of
+                 // 1, 2 and 4 at two waves per SIMD, for transforms of 2^20 points
+    static constexpr int NT = 256, E = 8, MINW = 2;
 };
 template <int V>
 constexpr int tiles_per_group()
@@ -1019,9 +1025,7 @@ int go1(const A &a, int batch, void *stream)
 template <typename T, int V, bool COL, class A>
 int go(int L, const A &a, int batch, void *stream)
 {
-    if constexpr (V == 5 && !COL) {
-        return -1;
-    } else if constexpr (V == 3) {  // 16 elements per thread, 512 threads: rows of 8192, pairs of 4096-point columns
+    if constexpr (V == 3) {  // 16 elements per thread, 512 threads: rows of 8192, pairs of 4096-point columns
         if (L == 8192 && !COL) return go1<T, V, COL, 16, 4, 8, 16>(a, batch, stream);
         if (L == 4096 && COL) return go1<T, V, COL, 16, 16, 16>(a, batch, stream);
         return -1;
@@ -1049,11 +1053,13 @@ int go(int L, const A &a, int batch, void *stream)
         switch (L) {
         case 64: return go1<T, V, COL, 8, 8>(a, batch, stream);
         case 128: return go1<T, V, COL, 8, 2, 8>(a, batch, stream);
-        case 256: return go1<T, V, COL, 4, 4, 4, 4>(a, batch, stream);
+        case 256: return go1<T, V, COL, 8, 4, 8>(a, batch, stream);
         case 512: return go1<T, V, COL, 8, 8, 8>(a, batch, stream);
         case 1024: return go1<T, V, COL, 8, 4, 4, 8>(a, batch, stream);
         case 2048: return go1<T, V, COL, 8, 4, 8, 8>(a, batch, stream);
-        case 4096: return go1<T, V, COL, 8, 8, 8, 8>(a, batch, stream);
+        case 4096:
+            if constexpr (V != 6) return go1<T, V, COL, 8, 8, 8, 8>(a, batch, stream);
+            else return -1;  // longer than the 2048-element tile
         default: return -1;
         }
     }
@@ -1116,7 +1122,7 @@ int multi_go_v(int L, const BatchDesc *d, const int *idx, const int *start, int 
         switch (L) {
         case 64: return LT_MULTI(8, 8);
         case 128: return LT_MULTI(8, 2, 8);
-        case 256: return LT_MULTI(4, 4, 4, 4);
+        case 256: return LT_MULTI(8, 4, 8);
         case 512: return LT_MULTI(8, 8, 8);
         case 1024: return LT_MULTI(8, 4, 4, 8);
         case 2048: return LT_MULTI(8, 4, 8, 8);
@@ -1148,6 +1154,7 @@ bool fast_col_fits(int prec, int variant, int L1, int L2, int C)
     if (variant == 3)
         return (fast_len(L1) && L1 <= kSmallTile && L2 % (kSmallTile / L1) == 0) || (L1 == 4096 && L2 % 2 == 0);
     if (variant == 4) return fast_len(L1) && C == kTile / L1 && L2 % (2 * C) == 0;
+    if (variant == 5) return fast_len(L1) && L1 <= kTile / 2 && L2 % (kTile / 2 / L1) == 0;
     return (variant == 1 || variant == 2) && fast_len(L1) && C == kTile / L1 && L2 % C == 0;
 }
 
@@ -1155,9 +1162,10 @@ bool fast_row_fits(int prec, int variant, int L1, int L2, int rows)
 {
     (void)prec;
     // rows of kWideRow points: one per workgroup, the 512-thread kernel (variants 1 and 2)
-    if (L2 == kWideRow) return rows == 1 && (variant == 1 || variant == 2);
+    if (L2 == kWideRow) return rows == 1 && (variant == 1 || variant == 2 || variant == 4);
     if (variant == 3) return fast_len(L2) && L2 <= kSmallTile && L1 % (kSmallTile / L2) == 0;
-    return (variant == 1 || variant == 2) && fast_len(L2) && rows == kTile / L2 && L1 % rows == 0;
+    if (variant == 5) return fast_len(L2) && L2 <= kTile / 2 && L1 % (kTile / 2 / L2) == 0;
+    return (variant == 1 || variant == 2 || variant == 4) && fast_len(L2) && rows == kTile / L2 && L1 % rows == 0;
 }
 
 int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *stream)
@@ -1176,10 +1184,12 @@ int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *st
         return variant == 1   ? go<double, 1, true>(a.L1, a, batch, stream)
                : variant == 2 ? go<double, 2, true>(a.L1, a, batch, stream)
                : variant == 4 ? go<double, 5, true>(a.L1, a, batch, stream)
+               : variant == 5 ? go<double, 6, true>(a.L1, a, batch, stream)
                               : go<double, 4, true>(a.L1, a, batch, stream);
     return variant == 1   ? go<float, 1, true>(a.L1, a, batch, stream)
            : variant == 2 ? go<float, 2, true>(a.L1, a, batch, stream)
            : variant == 4 ? go<float, 5, true>(a.L1, a, batch, stream)
+           : variant == 5 ? go<float, 6, true>(a.L1, a, batch, stream)
                           : go<float, 4, true>(a.L1, a, batch, stream);
 }
 
@@ -1196,7 +1206,7 @@ int launch_col_inner(int prec, const ColArgs &a, int batch, void *stream)
 int launch_row_fast(int prec, int variant, const RowArgs &a, int batch, void *stream)
 {
     if (a.fft_only) return -1;
-    if (a.L2 == kWideRow && a.rows == 1 && (variant == 1 || variant == 2)) {
+    if (a.L2 == kWideRow && a.rows == 1 && (variant == 1 || variant == 2 || variant == 4)) {
         if (prec == LT_C128) return go<double, 3, false>(a.L2, a, batch, stream);
         return go<float, 3, false>(a.L2, a, batch, stream);
     }
@@ -1204,9 +1214,13 @@ int launch_row_fast(int prec, int variant, const RowArgs &a, int batch, void *st
     if (prec == LT_C128)
         return variant == 1   ? go<double, 1, false>(a.L2, a, batch, stream)
                : variant == 2 ? go<double, 2, false>(a.L2, a, batch, stream)
+               : variant == 4 ? go<double, 5, false>(a.L2, a, batch, stream)
+               : variant == 5 ? go<double, 6, false>(a.L2, a, batch, stream)
                               : go<double, 4, false>(a.L2, a, batch, stream);
     return variant == 1   ? go<float, 1, false>(a.L2, a, batch, stream)
            : variant == 2 ? go<float, 2, false>(a.L2, a, batch, stream)
+           : variant == 4 ? go<float, 5, false>(a.L2, a, batch, stream)
+           : variant == 5 ? go<float, 6, false>(a.L2, a, batch, stream)
                           : go<float, 4, false>(a.L2, a, batch, stream);
 }
 

@@ -130,8 +130,8 @@ def test_rank2_swapped_layout(lt, n1, n2, d):
     _, s, _ = O.index_set(Z, n, H)
     refs = {"shared": O.strang_run(n, s, vs[0], u0, gamma, dt, steps),
             "per-state": O.strang_run(n, s, vs, u0, gamma, dt, steps)}
-    for cv in (0, 1, 2, 3, 4):
-        for rv in (0, 1, 3):
+    for cv in (0, 1, 2, 3, 4, 5):
+        for rv in (0, 1, 3, 4, 5):
             for prec in ("c128", "c64"):
                 p = lt.LT_C128 if prec == "c128" else lt.LT_C64
                 lt.lattice_plan_set_kernels(plan, p, cv, rv)
@@ -225,8 +225,8 @@ def test_every_kernel_variant(lt, N, d):
     plan = lt.lattice_plan(Z, n)
     _, s, _ = O.index_set(Z, n)
     ref = O.strang_run(n, s, v, u0, gamma, dt, steps)
-    # column variant 4 (two tiles per workgroup) has no row counterpart
-    pairs = [(cv, rv) for cv in (0, 1, 2, 3) for rv in (0, 1, 2, 3)] + [(4, 0), (4, 1)]
+    pairs = [(cv, rv) for cv in (0, 1, 2, 3) for rv in (0, 1, 2, 3)] + [(4, 0), (4, 1), (0, 4), (1, 4), (4, 4),
+                                                                         (5, 0), (5, 1), (1, 5), (5, 5)]
     for cv, rv in pairs:
         for prec in ("c128", "c64"):
             p = lt.LT_C128 if prec == "c128" else lt.LT_C64
@@ -236,10 +236,10 @@ def test_every_kernel_variant(lt, N, d):
             assert e < TOL[prec], (cv, rv, prec, e)
     for prec in (lt.LT_C64, lt.LT_C128):
         chosen = lt.lattice_plan_autotune(plan, prec, reps=3)
-        assert chosen[0] in (0, 1, 2, 3, 4) and chosen[1] in (0, 1, 2, 3)
+        assert chosen[0] in range(6) and chosen[1] in range(6)
         assert lt.lattice_plan_get_kernels_batch(plan, prec, 1) == tuple(chosen)
         cm, rm = lt.lattice_plan_get_kernels_batch(plan, prec, 64)
-        assert cm in (0, 1, 2, 3, 4) and rm in (0, 1, 2, 3)
+        assert cm in range(6) and rm in range(6)
     # a batch large enough for the many-state choice the autotuner made
     L = plan.info["fft_len"]
     batch = max(2, -(-(1 << 20) // L))

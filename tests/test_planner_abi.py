@@ -147,9 +147,9 @@ def test_schedules():
         assert C.lattice_plan_get_kernels_batch(c1, C.LT_C64, batch) == (2, 0)
     assert C.lattice_plan_get_kernels_batch(c1, C.LT_C128, 64) == (1, 1)
     with pytest.raises(C.LatticeError):
-        C.lattice_plan_set_kernels(c1, C.LT_C64, 5, 0)
+        C.lattice_plan_set_kernels(c1, C.LT_C64, 6, 0)
     with pytest.raises(C.LatticeError):
-        C.lattice_plan_set_kernels(c1, C.LT_C64, 1, 4)
+        C.lattice_plan_set_kernels(c1, C.LT_C64, 1, 6)
     with pytest.raises(C.LatticeError):
         C.lattice_plan_get_kernels_batch(c1, C.LT_C64, 0)
 
