@@ -290,10 +290,11 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
  * replay advances the states once more.  Calls on one object must not overlap
  * (they share the object's workspace).
  *
- * strang_batch_autotune times the two register-staged kernel geometries
- * (256 threads x 16 elements, 512 threads x 8) of every length class of the
- * batch on scratch copies of the members' buffers (the states are untouched)
- * and keeps the faster per class; it synchronizes `stream`.
+ * strang_batch_autotune times the register-staged kernel geometries
+ * (variants 1, 2 and, for lengths up to 2048, 5 of lattice_plan_set_kernels)
+ * of every length class of the batch on scratch copies of the members'
+ * buffers (the states are untouched) and keeps the fastest per class; it
+ * synchronizes `stream`.
  * strang_batch_kernels lists the classes: key[i] > 0 is a column class of
  * column length key[i], key[i] < 0 a row class (-key = 2 L2 + multiplier
  * kind), variant[i] its geometry (up to cap entries; *ncls gets the count).

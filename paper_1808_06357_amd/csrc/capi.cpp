@@ -743,7 +743,8 @@ struct MemberList {
     std::vector<int64_t> npass;  // per member
     size_t idx_off = 0, start_off = 0;  // int offsets in the list area
     int act = 0;                 // members still running at the current pass
-    int var = 1;                 // register-staged kernel geometry (1: 256 x 16, 2: 512 x 8)
+    int var = 1;                 // register-staged kernel geometry (1: 256 x 16, 2: 512 x 8, 5: 256 x 8
+                                 // on 2048-element tiles)
 };
 
 BatchLayout batch_layout(int32_t B, const lt_plan *const *plans, int prec)
@@ -1802,7 +1803,12 @@ lt_status strang_batch_autotune(lt_batch *b, int32_t reps, void *stream)
             const int nm = (int)l.mem.size(), nb = l.start[nm];
             float best_ms = 0.0f;
             int best = 1;
-            for (int var = 1; var <= 2 && !herr; ++var) {
+            // 256 x 16 and 512 x 8 on 4096-element tiles; 256 x 8 on
+            // 2048-element tiles for lengths up to 2048
+            const int len = which == 0 ? l.key : l.key / 2;
+            for (int var : {1, 2, 5}) {
+                if (herr) break;
+                if (var == 5 && len > 2048) continue;
                 auto go = [&]() {
                     return which == 0 ? launch_col_fast_multi(R.prec, var, l.key, dtwo, idx, start, nm, nb, 0, 2, hs)
                                       : launch_row_fast_multi(R.prec, var, l.key / 2, l.key % 2, dtwo, idx, start, nm,

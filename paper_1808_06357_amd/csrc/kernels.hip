@@ -809,8 +809,10 @@ int launch_col(int prec, const Sched &s, const ColArgs &a, int batch, void *stre
 {
     const int var = col_variant_of(s, batch);
     if (var > 0) {
-        const int r = a.adjoint ? launch_col_fast_adjoint(prec, var, a, batch, stream)
-                                : launch_col_fast(prec, var, a, batch, stream);
+        ColArgs f = a;
+        f.wt = cache_resident(s, esize(prec), batch) ? 1 : 0;
+        const int r = a.adjoint ? launch_col_fast_adjoint(prec, var, f, batch, stream)
+                                : launch_col_fast(prec, var, f, batch, stream);
         if (r >= 0) return r;
     }
     const int nvec = a.adjoint ? 2 : 1;
@@ -830,7 +832,9 @@ int launch_row(int prec, const Sched &s, const RowArgs &a, int batch, void *stre
 {
     const int var = row_variant_of(s, batch);
     if (var > 0 && !a.fft_only) {
-        const int r = launch_row_fast(prec, var, a, batch, stream);
+        RowArgs f = a;
+        f.wt = cache_resident(s, esize(prec), batch) ? 1 : 0;
+        const int r = launch_row_fast(prec, var, f, batch, stream);
         if (r >= 0) return r;
     }
     const size_t lds = (size_t)a.rows * a.L2 * esize(prec);

@@ -56,23 +56,29 @@ __device__ __forceinline__ cx<double> bload<double>(rsrc_t r, uint32_t voff, uin
     return __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
-// State stores carry the device-scope coherence bit (sc1): the next pass,
-// on every XCD, reads what this one writes, and a write-back L2 would hold
-// the dirty lines until the release at the end of the kernel.  Measured on
-// the 2^21-point convolution: row pass 13.8 -> 12.3 us (complex64), 16.6 ->
-// 15.7 us (complex128); the column pass is unchanged.  Streaming (nt) stores
-// or loads were slower.
-constexpr int kStoreAux = 16;
+// State stores: SA is the instruction's cache-policy operand.  A pass whose
+// working set fits the Infinity Cache stores with the device-scope coherence
+// bit (kWriteThrough, sc1): the next pass, on every XCD, reads what this one
+// writes, and a write-back L2 would hold the dirty lines until the release at
+// the end of the kernel.  Measured on the 2^21-point convolution (67 MB per
+// pass): row pass 13.8 -> 12.3 us (complex64), 16.6 -> 15.7 us (complex128),
+// rank-2 2^20 points 4.7e10 -> 6.3e10 pt-steps/s.  Beyond the cache
+// (working sets of 270-450 MB) the plain write-back stores are 2-4 % faster,
+// so launches choose by their working set.  Streaming (nt) stores or loads
+// were slower in both regimes.
+constexpr int kWriteThrough = 16;
 
+template <int SA = 0>
 __device__ __forceinline__ void bstore(cx<float> x, rsrc_t r, uint32_t voff, uint32_t soff)
 {
     using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, x), r, voff, soff, kStoreAux);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, x), r, voff, soff, SA);
 }
+template <int SA = 0>
 __device__ __forceinline__ void bstore(cx<double> x, rsrc_t r, uint32_t voff, uint32_t soff)
 {
     using V = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, x), r, voff, soff, kStoreAux);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, x), r, voff, soff, SA);
 }
 
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
@@ -331,7 +337,7 @@ __device__ __forceinline__ void colf_load(const ColArgs &a, int tile, int64_t b,
 // the step's checkpoint (and the step's sums when asked for); MID 8: MID 0
 // plus the step's sums of |u|^2 and v |u|^2.  sync_first: the workgroup used
 // the LDS buffer before (a previous tile), so the first write waits for it.
-template <typename T, int E, int NT, int MID, bool PRE, int... Rs>
+template <typename T, int E, int NT, int MID, bool PRE, int SA, int... Rs>
 __device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, cx<T> *s,
                                          const typename Fft<T, E, NT, true, Rs...>::Bases &B,
                                          ColTile<T, E, Fft<T, E, NT, true, Rs...>::J, Fft<T, E, NT, true, Rs...>::R, PRE> &X,
@@ -556,7 +562,7 @@ __device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, 
     for (int j = 0; j < J; ++j) {
         if (kFwd && tw) apply_series<T, R>(&v[j * R], tb[j], ts[j]);
 #pragma unroll
-        for (int r = 0; r < R; ++r) bstore(v[j * R + r], rb, voff[j], r * rstep);
+        for (int r = 0; r < R; ++r) bstore<SA>(v[j * R + r], rb, voff[j], r * rstep);
     }
     (void)TILE;
 }
@@ -565,7 +571,7 @@ __device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, 
 // loads of all S tiles are issued first, so that the later tiles' loads are
 // in flight while the first tiles are transformed, and the first tiles'
 // stores drain while the later ones are.
-template <typename T, int E, int NT, int MID, int S, int... Rs>
+template <typename T, int E, int NT, int MID, int S, int SA, int... Rs>
 __device__ __forceinline__ void colf_body(const ColArgs &a, int wtile, int64_t b, cx<T> *s)
 {
     using F = Fft<T, E, NT, true, Rs...>;
@@ -576,24 +582,24 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int wtile, int64_t b
 #pragma unroll
     for (int st = 0; st < S; ++st) colf_load<T, E, NT, PRE, Rs...>(a, wtile * S + st, b, X[st]);
 #pragma unroll
-    for (int st = 0; st < S; ++st) colf_run<T, E, NT, MID, PRE, Rs...>(a, wtile * S + st, b, s, B, X[st], st > 0);
+    for (int st = 0; st < S; ++st) colf_run<T, E, NT, MID, PRE, SA, Rs...>(a, wtile * S + st, b, s, B, X[st], st > 0);
 }
 
-template <typename T, int E, int NT, int MINW, int MID, int... Rs>
+template <typename T, int E, int NT, int MINW, int MID, int SA, int... Rs>
 __global__ void __launch_bounds__(NT, MINW) k_colf(ColArgs a)
 {
     extern __shared__ char smem_raw[];
-    colf_body<T, E, NT, MID, 1, Rs...>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.y,
-                                       reinterpret_cast<cx<T> *>(smem_raw));
+    colf_body<T, E, NT, MID, 1, SA, Rs...>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.y,
+                                           reinterpret_cast<cx<T> *>(smem_raw));
 }
 
 // two column tiles per workgroup
-template <typename T, int E, int NT, int MINW, int MID, int... Rs>
+template <typename T, int E, int NT, int MINW, int MID, int SA, int... Rs>
 __global__ void __launch_bounds__(NT, MINW) k_colf2(ColArgs a)
 {
     extern __shared__ char smem_raw[];
-    colf_body<T, E, NT, MID, 2, Rs...>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.y,
-                                       reinterpret_cast<cx<T> *>(smem_raw));
+    colf_body<T, E, NT, MID, 2, SA, Rs...>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.y,
+                                           reinterpret_cast<cx<T> *>(smem_raw));
 }
 
 // Interior merge pass of the adjoint sweep (no checkpoint reset, no chirp):
@@ -726,26 +732,29 @@ __global__ void __launch_bounds__(NT, MINW) k_colf_adj(ColArgs a)
 // Pass g of the batch members listed in idx (prefix sums of their column
 // tiles in start, block offset off): the merged potential step of each
 // member whose schedule is at an interior column pass; first and last
-// column passes take the general kernel.
-template <typename T, int E, int NT, int MINW, int... Rs>
+// column passes take the general kernel.  The members' tiles are counted in
+// 4096-element tiles; a kernel with Q times smaller tiles runs Q blocks per
+// counted tile.
+template <typename T, int E, int NT, int MINW, int Q, int... Rs>
 __global__ void __launch_bounds__(NT, MINW) k_colf_multi(const BatchDesc *d, const int *idx, const int *start,
                                                           int nmem, int nblocks, int off, int64_t g)
 {
     extern __shared__ char smem_raw[];
     // the grid is padded to a multiple of 8 blocks
     const int w = xcd_block(blockIdx.x, gridDim.x);
-    if (w >= nblocks) return;
-    const int bid = w + off;
+    if (w >= nblocks * Q) return;
+    const int bid = w / Q + off;
     const int k = find_member(start, nmem, bid);
     const BatchDesc &p = d[idx[k]];
     if (g == 0 || (g & 1) || g >= p.npass - 1) return;
     // members with interior passes carry the per-point table of the merged potential step
-    colf_body<T, E, NT, 0, 1, Rs...>(p.col[1], bid - start[k], 0, reinterpret_cast<cx<T> *>(smem_raw));
+    colf_body<T, E, NT, 0, 1, 0, Rs...>(p.col[1], (bid - start[k]) * Q + w % Q, 0,
+                                     reinterpret_cast<cx<T> *>(smem_raw));
 }
 
 // Row pass: [DFT -> spectral multiplier -> inverse DFT], in place; the
 // multiplier (chirp-z kernel spectrum or kinetic table) is applied in registers.
-template <typename T, int E, int NT, int MID, int... Rs>
+template <typename T, int E, int NT, int MID, int SA, int... Rs>
 __device__ __forceinline__ void rowf_body(const RowArgs &a, int blk, int64_t b, cx<T> *s)
 {
     using F = Fft<T, E, NT, false, Rs...>;
@@ -825,31 +834,33 @@ __device__ __forceinline__ void rowf_body(const RowArgs &a, int blk, int64_t b, 
 #pragma unroll
     for (int j = 0; j < J; ++j) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) bstore(conjg(v[j * R + r]), rb, voff[j], r * rstep);
+        for (int r = 0; r < R; ++r) bstore<SA>(conjg(v[j * R + r]), rb, voff[j], r * rstep);
     }
 }
 
-template <typename T, int E, int NT, int MINW, int MID, int... Rs>
+template <typename T, int E, int NT, int MINW, int MID, int SA, int... Rs>
 __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
 {
     extern __shared__ char smem_raw[];
-    rowf_body<T, E, NT, MID, Rs...>(a, blockIdx.x, blockIdx.y, reinterpret_cast<cx<T> *>(smem_raw));
+    rowf_body<T, E, NT, MID, SA, Rs...>(a, blockIdx.x, blockIdx.y, reinterpret_cast<cx<T> *>(smem_raw));
 }
 
 // Row pass g of the batch members listed in idx (prefix sums of their row
 // blocks in start, block offset off); MID 0: spectrum table, MID 1: kinetic
-// table, as in k_rowf.
-template <typename T, int E, int NT, int MINW, int MID, int... Rs>
+// table, as in k_rowf.  Q blocks per counted 4096-element block, as in
+// k_colf_multi.
+template <typename T, int E, int NT, int MINW, int MID, int Q, int... Rs>
 __global__ void __launch_bounds__(NT, MINW) k_rowf_multi(const BatchDesc *d, const int *idx, const int *start,
                                                           int nmem, int nblocks, int off, int64_t g)
 {
     extern __shared__ char smem_raw[];
-    if ((int)blockIdx.x >= nblocks) return;
-    const int bid = blockIdx.x + off;
+    if ((int)blockIdx.x >= nblocks * Q) return;
+    const int bid = (int)blockIdx.x / Q + off;
     const int k = find_member(start, nmem, bid);
     const BatchDesc &p = d[idx[k]];
     if (!(g & 1) || g >= p.npass) return;
-    rowf_body<T, E, NT, MID, Rs...>(p.row[0], bid - start[k], 0, reinterpret_cast<cx<T> *>(smem_raw));
+    rowf_body<T, E, NT, MID, 0, Rs...>(p.row[0], (bid - start[k]) * Q + (int)blockIdx.x % Q, 0,
+                                    reinterpret_cast<cx<T> *>(smem_raw));
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -857,6 +868,8 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf_multi(const BatchDesc *d, con
 // x 8 elements (radix 8 / 4, twice the waves per CU).  Both hold a
 // 4096-element tile, so they share the plan's layout and are interchangeable.
 namespace {
+constexpr int kTile = 4096;  // elements of the tile a plan counts its column and row tiles in
+
 template <int V>
 struct Geo;
 template <>
@@ -892,12 +905,12 @@ constexpr int tiles_per_group()
     else return 1;
 }
 
-// the column kernel for S tiles per workgroup
-template <typename T, int E, int NT, int MINW, int MID, int S, int... Rs>
+// the column kernel for S tiles per workgroup and store policy SA
+template <typename T, int E, int NT, int MINW, int MID, int S, int SA, int... Rs>
 constexpr auto colk()
 {
-    if constexpr (S == 2) return k_colf2<T, E, NT, MINW, MID, Rs...>;
-    else return k_colf<T, E, NT, MINW, MID, Rs...>;
+    if constexpr (S == 2) return k_colf2<T, E, NT, MINW, MID, SA, Rs...>;
+    else return k_colf<T, E, NT, MINW, MID, SA, Rs...>;
 }
 
 template <typename K, typename A>
@@ -940,15 +953,15 @@ int col_go(const ColArgs &a, int batch, void *stream)
     // MID 0: merged potential step from the per-point table; MID 1: kinetic table;
     // MID 2 (complex128 runs without a table): FP64 phase of v; MID 3:
     // potential with a time-dependent second field
-    auto k = colk<T, E, NT, MINW, 1, S, Rs...>();
+    auto k = colk<T, E, NT, MINW, 1, S, 0, Rs...>();
     if constexpr (V == 1) {
         if (a.pre_inv != a.post_fwd) {
-            k = a.post_fwd ? k_colf<T, E, NT, MINW, 5, Rs...> : k_colf<T, E, NT, MINW, 6, Rs...>;
+            k = a.post_fwd ? k_colf<T, E, NT, MINW, 5, 0, Rs...> : k_colf<T, E, NT, MINW, 6, 0, Rs...>;
             static bool attr_io = false;
             if (!attr_io) {
-                hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 5, Rs...>,
+                hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 5, 0, Rs...>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
-                hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 6, Rs...>,
+                hipFuncSetAttribute((const void *)k_colf<T, E, NT, MINW, 6, 0, Rs...>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
                 attr_io = true;
             }
@@ -960,31 +973,36 @@ int col_go(const ColArgs &a, int batch, void *stream)
     }
     if (a.ck) {  // checkpoint pass (and the step's sums, when asked for)
         if (!a.v || a.v2 || !a.ptab) return -1;
-        k = colk<T, E, NT, MINW, 7, S, Rs...>();
+        k = colk<T, E, NT, MINW, 7, S, 0, Rs...>();
     } else if (a.sum_part) {  // merged step plus the step's sums in registers
         if (!a.v || a.v2 || !a.ptab || !a.sum_v) return -1;
-        k = colk<T, E, NT, MINW, 8, S, Rs...>();
+        k = a.wt ? colk<T, E, NT, MINW, 8, S, kWriteThrough, Rs...>() : colk<T, E, NT, MINW, 8, S, 0, Rs...>();
     } else if (a.v) {
-        if (a.v2) k = colk<T, E, NT, MINW, 3, S, Rs...>();
-        else if (a.ptab) k = colk<T, E, NT, MINW, 0, S, Rs...>();
-        else if constexpr (sizeof(T) == 8) k = colk<T, E, NT, MINW, 2, S, Rs...>();
+        if (a.v2) k = colk<T, E, NT, MINW, 3, S, 0, Rs...>();
+        else if (a.ptab)
+            k = a.wt ? colk<T, E, NT, MINW, 0, S, kWriteThrough, Rs...>() : colk<T, E, NT, MINW, 0, S, 0, Rs...>();
+        else if constexpr (sizeof(T) == 8) k = colk<T, E, NT, MINW, 2, S, 0, Rs...>();
         else return -1;
     }
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 0, S, Rs...>(),
+        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 0, S, 0, Rs...>(),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
-        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 1, S, Rs...>(),
+        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 1, S, 0, Rs...>(),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
-        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 3, S, Rs...>(),
+        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 3, S, 0, Rs...>(),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
-        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 7, S, Rs...>(),
+        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 7, S, 0, Rs...>(),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
-        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 8, S, Rs...>(),
+        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 8, S, 0, Rs...>(),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         if constexpr (sizeof(T) == 8)
-            hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 2, S, Rs...>(),
+            hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 2, S, 0, Rs...>(),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 0, S, kWriteThrough, Rs...>(),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+        hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 8, S, kWriteThrough, Rs...>(),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         attr = true;
     }
     constexpr int C = NT * E / Radix<Rs...>::prod;
@@ -998,12 +1016,18 @@ template <typename T, int V, int... Rs>
 int row_go(const RowArgs &a, int batch, void *stream)
 {
     constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW;
-    auto k = a.bhat ? k_rowf<T, E, NT, MINW, 0, Rs...> : k_rowf<T, E, NT, MINW, 1, Rs...>;
+    auto k = a.bhat ? k_rowf<T, E, NT, MINW, 0, 0, Rs...> : k_rowf<T, E, NT, MINW, 1, 0, Rs...>;
+    if (a.wt)
+        k = a.bhat ? k_rowf<T, E, NT, MINW, 0, kWriteThrough, Rs...> : k_rowf<T, E, NT, MINW, 1, kWriteThrough, Rs...>;
     static bool attr = false;
     if (!attr) {
-        hipFuncSetAttribute((const void *)k_rowf<T, E, NT, MINW, 0, Rs...>,
+        hipFuncSetAttribute((const void *)k_rowf<T, E, NT, MINW, 0, 0, Rs...>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
-        hipFuncSetAttribute((const void *)k_rowf<T, E, NT, MINW, 1, Rs...>,
+        hipFuncSetAttribute((const void *)k_rowf<T, E, NT, MINW, 1, 0, Rs...>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+        hipFuncSetAttribute((const void *)k_rowf<T, E, NT, MINW, 0, kWriteThrough, Rs...>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+        hipFuncSetAttribute((const void *)k_rowf<T, E, NT, MINW, 1, kWriteThrough, Rs...>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         attr = true;
     }
@@ -1071,14 +1095,14 @@ template <typename T, int V, int... Rs>
 int col_multi_go(const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks, int off, int64_t g,
                  void *stream)
 {
-    constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW;
-    auto k = k_colf_multi<T, E, NT, MINW, Rs...>;
+    constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW, Q = kTile / (NT * E);
+    auto k = k_colf_multi<T, E, NT, MINW, Q, Rs...>;
     static bool attr = false;
     if (!attr) {
         hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         attr = true;
     }
-    const int grid = (nblocks + 7) / 8 * 8;
+    const int grid = (nblocks * Q + 7) / 8 * 8;
     return timed_multi(LT_KIND_COLUMN, k, dim3(grid), dim3(NT), lds_bytes<T, V>(), stream, d, idx, start, nmem,
                        nblocks, off, g);
 }
@@ -1087,14 +1111,14 @@ template <typename T, int V, int MID, int... Rs>
 int row_multi_go(const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks, int off, int64_t g,
                  void *stream)
 {
-    constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW;
-    auto k = k_rowf_multi<T, E, NT, MINW, MID, Rs...>;
+    constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW, Q = kTile / (NT * E);
+    auto k = k_rowf_multi<T, E, NT, MINW, MID, Q, Rs...>;
     static bool attr = false;
     if (!attr) {
         hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
         attr = true;
     }
-    return timed_multi(LT_KIND_ROW, k, dim3(nblocks), dim3(NT), lds_bytes<T, V>(), stream, d, idx, start, nmem,
+    return timed_multi(LT_KIND_ROW, k, dim3(nblocks * Q), dim3(NT), lds_bytes<T, V>(), stream, d, idx, start, nmem,
                        nblocks, off, g);
 }
 
@@ -1126,7 +1150,9 @@ int multi_go_v(int L, const BatchDesc *d, const int *idx, const int *start, int 
         case 512: return LT_MULTI(8, 8, 8);
         case 1024: return LT_MULTI(8, 4, 4, 8);
         case 2048: return LT_MULTI(8, 4, 8, 8);
-        case 4096: return LT_MULTI(8, 8, 8, 8);
+        case 4096:
+            if constexpr (V != 6) return LT_MULTI(8, 8, 8, 8);
+            else return -1;  // longer than the 2048-element tile
         default: return -1;
         }
     }
@@ -1138,9 +1164,9 @@ int multi_go(int variant, int L, const BatchDesc *d, const int *idx, const int *
              int off, int64_t g, void *stream)
 {
     if (variant == 2) return multi_go_v<T, COL, MID, 2>(L, d, idx, start, nmem, nblocks, off, g, stream);
+    if (variant == 5) return multi_go_v<T, COL, MID, 6>(L, d, idx, start, nmem, nblocks, off, g, stream);
     return multi_go_v<T, COL, MID, 1>(L, d, idx, start, nmem, nblocks, off, g, stream);
 }
-constexpr int kTile = 4096;
 }  // namespace
 
 constexpr int kSmallTile = Geo<4>::NT * Geo<4>::E;

@@ -64,6 +64,15 @@ struct Sched {
 constexpr int64_t kManyPoints = int64_t(1) << 20;
 inline bool many_states(const Sched &s, int batch) { return batch > 1 && batch * s.L >= kManyPoints; }
 inline int col_variant_of(const Sched &s, int batch) { return many_states(s, batch) ? s.col_var_m : s.col_var; }
+
+// A pass whose working set (the states plus at most 32 bytes of tables per
+// transform point) fits the 256 MB Infinity Cache with room to spare stores
+// the state with write-through; larger ones keep the write-back L2.
+constexpr int64_t kCacheResident = int64_t(192) << 20;
+inline bool cache_resident(const Sched &s, int64_t state_bytes, int batch)
+{
+    return (int64_t)batch * s.L * state_bytes + 32 * s.L <= kCacheResident;
+}
 inline int row_variant_of(const Sched &s, int batch) { return many_states(s, batch) ? s.row_var_m : s.row_var; }
 
 // Device tables of a plan for one precision (built lazily, then immutable).
@@ -130,6 +139,8 @@ struct ColArgs {
     // over the tile's valid points; sum_v strided as v (v_bs)
     double *sum_part; int sum_pt;
     const double *sum_v;
+    int wt;                           // register-staged passes: store the state with write-through
+                                      // (set by launch_col from the launch's working set)
 };
 
 // Spectral multiplier of a row pass at row-pass position pos = k1 L2 + k2:
@@ -144,6 +155,8 @@ struct RowArgs {
     int fft_only;
     const void *twb;                  // Tw<T> table of W_{L2}
     Radices rad;
+    int wt;                           // register-staged passes: store the state with write-through
+                                      // (set by launch_row from the launch's working set)
 };
 
 struct ResArgs {

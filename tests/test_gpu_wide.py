@@ -69,12 +69,12 @@ def test_wide_rows_against_oracle_samples(lt, name):
             assert abs(norm2 - float(gold[f"{name}_norm2"])) < 2.0 * TOL[prec]
             del u
     if info["L2"] == 8192:
-        # the autotuner times the 8192-point row kernel (variants 1 and 2), not
+        # the autotuner times the 8192-point row kernel (variants 1, 2 and 4 select it), not
         # only the general one, and keeps it (2.5x faster per row pass)
         for prec, p in (("c64", lt.LT_C64), ("c128", lt.LT_C128)):
             cv, rv = lt.lattice_plan_autotune(plan, p, reps=2)
             print(f"  {name} autotuned {prec}: column {cv}, row {rv}", flush=True)
-            assert rv in (1, 2), (prec, cv, rv)
+            assert rv in (1, 2, 4), (prec, cv, rv)
             u = torch.tensor(u0, dtype=_dtype(prec), device="cuda")
             lt.strang_run(plan, v, u, GAMMA, DT, STEPS)
             got = u[torch.from_numpy(idx).to("cuda")].cpu().numpy().astype(np.complex128)
