@@ -281,28 +281,40 @@ __device__ __forceinline__ void tw4_base_step(cx<double> &b, cx<double> &st, int
 // Registers of one column tile between its loads and its transforms: the
 // tile's elements, their byte offsets, and (complex64 table steps) the table
 // entries of the first butterfly group.
-template <typename T, int E, int J, int R, bool PRE>
+template <typename T, int E, int J, int R, bool PRE, bool PV>
 struct ColTile {
     cx<T> v[E];
     uint32_t voff[J];
     Tw<T> pre[PRE ? R : 1];
+    double sv[PV ? E : 1];  // v of every element for the step's sums (MID 8, eight elements or fewer)
 };
+
+// MID 8 with at most eight elements per thread: v of the tile's elements is
+// loaded with the state (its latency then hides behind the inverse DFT
+// instead of stalling the sums between the transforms)
+template <int MID, int E>
+constexpr bool col_prefetch_v()
+{
+    return MID == 8 && E <= 8;
+}
 
 // complex64 merged potential step: with two or more butterfly groups per
 // thread, or several tiles per workgroup, the table entries of the first
 // group are loaded with the state (halving the burst of table loads after
-// the inverse DFT), the rest after the inverse DFT
+// the inverse DFT), the rest after the inverse DFT.  Not with the step's
+// sums and two groups per thread: holding those entries through the sums
+// spills.
 template <typename T, int MID, int J, int S>
 constexpr bool col_prefetch()
 {
-    return (MID == 0 || MID == 8) && sizeof(T) == 4 && (J > 1 || S > 1);
+    return sizeof(T) == 4 && ((MID == 0 && (J > 1 || S > 1)) || (MID == 8 && J == 1 && S > 1));
 }
 
 // Issues every load of column tile `tile` of batch item b: element
 // (t + r BPS, c0 + q) sits at byte voff[j] + r * rstep of the state
-template <typename T, int E, int NT, bool PRE, int... Rs>
+template <typename T, int E, int NT, bool PRE, bool PV, int... Rs>
 __device__ __forceinline__ void colf_load(const ColArgs &a, int tile, int64_t b,
-                                          ColTile<T, E, Fft<T, E, NT, true, Rs...>::J, Fft<T, E, NT, true, Rs...>::R, PRE> &X)
+                                          ColTile<T, E, Fft<T, E, NT, true, Rs...>::J, Fft<T, E, NT, true, Rs...>::R, PRE, PV> &X)
 {
     using F = Fft<T, E, NT, true, Rs...>;
     constexpr int C = F::SEQ, J = F::J, R = F::R, BPS = F::BPS, L1 = F::L;
@@ -317,6 +329,19 @@ __device__ __forceinline__ void colf_load(const ColArgs &a, int tile, int64_t b,
         X.voff[j] = ((uint32_t)F::t_of(bf) * (uint32_t)L2 + (uint32_t)(c0 + F::q_of(bf))) * (uint32_t)sizeof(cx<T>);
 #pragma unroll
         for (int r = 0; r < R; ++r) X.v[j * R + r] = bload<T>(rb, X.voff[j], r * rstep);
+    }
+    if constexpr (PV) {
+        // v at the element's offset scaled to 8 bytes; the zero padding
+        // (n >= Nvalid) lies beyond the buffer's range and reads 0
+        const rsrc_t rv = make_rsrc(a.sum_v + b * a.v_bs, a.Nvalid * (int64_t)sizeof(double));
+        constexpr uint32_t vdiv = (uint32_t)(sizeof(cx<T>) / sizeof(double));
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                X.sv[j * R + r] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(rv, (X.voff[j] + r * rstep) / vdiv, 0, 0));
+        }
     }
     if constexpr (PRE) {
         constexpr uint32_t ps = (uint32_t)(sizeof(Tw<T>) / sizeof(cx<T>));
@@ -337,10 +362,10 @@ __device__ __forceinline__ void colf_load(const ColArgs &a, int tile, int64_t b,
 // the step's checkpoint (and the step's sums when asked for); MID 8: MID 0
 // plus the step's sums of |u|^2 and v |u|^2.  sync_first: the workgroup used
 // the LDS buffer before (a previous tile), so the first write waits for it.
-template <typename T, int E, int NT, int MID, bool PRE, int SA, int... Rs>
+template <typename T, int E, int NT, int MID, bool PRE, bool PV, int SA, int... Rs>
 __device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, cx<T> *s,
                                          const typename Fft<T, E, NT, true, Rs...>::Bases &B,
-                                         ColTile<T, E, Fft<T, E, NT, true, Rs...>::J, Fft<T, E, NT, true, Rs...>::R, PRE> &X,
+                                         ColTile<T, E, Fft<T, E, NT, true, Rs...>::J, Fft<T, E, NT, true, Rs...>::R, PRE, PV> &X,
                                          bool sync_first)
 {
     using F = Fft<T, E, NT, true, Rs...>;
@@ -454,9 +479,12 @@ __device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, 
             for (int j = 0; j < J; ++j) {
                 double vv[R];
 #pragma unroll
-                for (int r = 0; r < R; ++r)
-                    vv[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                                           rv, (voff[j] + r * rstep) / vdiv, 0, 0));
+                for (int r = 0; r < R; ++r) {
+                    if constexpr (PV) vv[r] = X.sv[j * R + r];
+                    else
+                        vv[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                               rv, (voff[j] + r * rstep) / vdiv, 0, 0));
+                }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const cx<T> x = v[j * R + r];  // conj of the point value: same modulus
@@ -576,13 +604,15 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int wtile, int64_t b
 {
     using F = Fft<T, E, NT, true, Rs...>;
     constexpr bool PRE = col_prefetch<T, MID, F::J, S>();
+    constexpr bool PV = col_prefetch_v<MID, E>();
     typename F::Bases B;
     F::load_bases(B, (const Tw<T> *)a.twa);
-    ColTile<T, E, F::J, F::R, PRE> X[S];
+    ColTile<T, E, F::J, F::R, PRE, PV> X[S];
 #pragma unroll
-    for (int st = 0; st < S; ++st) colf_load<T, E, NT, PRE, Rs...>(a, wtile * S + st, b, X[st]);
+    for (int st = 0; st < S; ++st) colf_load<T, E, NT, PRE, PV, Rs...>(a, wtile * S + st, b, X[st]);
 #pragma unroll
-    for (int st = 0; st < S; ++st) colf_run<T, E, NT, MID, PRE, SA, Rs...>(a, wtile * S + st, b, s, B, X[st], st > 0);
+    for (int st = 0; st < S; ++st)
+        colf_run<T, E, NT, MID, PRE, PV, SA, Rs...>(a, wtile * S + st, b, s, B, X[st], st > 0);
 }
 
 template <typename T, int E, int NT, int MINW, int MID, int SA, int... Rs>
