@@ -226,7 +226,10 @@ def bench_batched(lt, torch, K, W):
 
 
 def bench_rank2(lt, torch, K, W):
-    """d = 10 rank-2 lattice n = (4096, 256), 500 steps."""
+    """d = 10 rank-2 lattice n = (4096, 256), 500 steps; also a forward run
+    with checkpoints plus the adjoint sweep (both on the transposed tensor)."""
+    import numpy as np
+
     import workloads as W_
     c = W_.rank2_d10_n4096x256()
     plan = lt.lattice_plan(c.Z, c.n, c.I)
@@ -248,6 +251,30 @@ def bench_rank2(lt, torch, K, W):
         out[name] = {"value": c.N * c.steps / sec, "ms_per_run": sec * 1e3, "kernel_variants": list(kernels),
                      "sampled_rel_l2_vs_oracle": err, "kernels": kernel_summary(lt, run, 1)}
         log(f"rank-2 {name}: {c.N * c.steps / sec:.3e} pt-steps/s, {sec * 1e3:.1f} ms per run")
+        # forward with checkpoints every 50 steps plus the adjoint sweep (on the
+        # transposed tensor), for the loss ||u(T) - u0||^2 / N
+        every = 50
+        ck = torch.empty(lt.num_checkpoints(c.steps, every) * c.N, dtype=dtype, device=dev)
+        aw = torch.empty(lt.strang_adjoint_workspace_size(plan, prec, 1, True), dtype=torch.uint8, device=dev)
+        u0 = torch.tensor(c.u0, dtype=dtype, device=dev)
+        uT = u0.clone()
+        fwd = lambda: lt.strang_run(plan, v, uT.copy_(u0), c.gamma, c.dt, c.steps, ckpt=ck, ckpt_every=every,  # noqa: E731
+                                    work=work)
+        fwd()
+        gT = ((2.0 / c.N) * (uT - u0)).contiguous()
+        grads = {}
+        adj = lambda: grads.__setitem__("g", lt.strang_adjoint(plan, v, uT, gT, c.gamma, c.dt, c.steps, ck,  # noqa: E731
+                                                                every, work=aw))
+        t_f, t_a = wall(fwd, K, W), wall(adj, K, W)
+        out[name]["adjoint"] = {"forward_with_checkpoints_ms": t_f * 1e3, "adjoint_ms": t_a * 1e3,
+                                "value": c.N * c.steps / (t_f + t_a),
+                                "gv": grads["g"][1].cpu().numpy()}
+        log(f"rank-2 {name}: forward with checkpoints {t_f * 1e3:.1f} ms, adjoint {t_a * 1e3:.1f} ms")
+        del ck, aw, work
+    # the two precisions' potential gradients agree to the complex64 rounding
+    # (a consistency figure: no stored oracle gradient for this lattice)
+    g64, g128 = out["c64"]["adjoint"].pop("gv"), out["c128"]["adjoint"].pop("gv")
+    out["adjoint_c64_vs_c128_rel_l2_dJ_dv"] = float(np.linalg.norm(g64 - g128) / np.linalg.norm(g128))
     return out
 
 
