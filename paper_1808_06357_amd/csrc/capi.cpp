@@ -235,7 +235,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // runs in u itself), and for two-pass runs the merged potential multiplier
 // exp(-i dt v / gamma) per point (one table per distinct potential)
 struct RunWork {
-    size_t ktab = 0, w = 0, ptab = 0, conv = 0, conv_tmp = 0, total = 0;
+    size_t ktab = 0, w = 0, ptab = 0, conv = 0, conv_tmp = 0, conv_f = 0, total = 0;
 };
 
 RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool shared_v = true,
@@ -256,6 +256,10 @@ RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool s
         off = align_up(off + (size_t)s.L * 16);
         w.conv_tmp = off;
         off = align_up(off + (size_t)p.N * 16);
+        if (prec == LT_C64) {  // the spectrum rounded to complex float for the complex64 rows
+            w.conv_f = off;
+            off = align_up(off + (size_t)s.L * 8);
+        }
     }
     w.total = off;
     return w;
@@ -561,12 +565,15 @@ void sums_on(ColArgs &a, const SumSink &k, int64_t j, const double *v)
 
 // forward run of a state batch through the two-pass sequence; `conv` (chirp-z
 // lattices) is the spectrum from conv_spectrum, or null for the chirp-z DFT
-// pair per step
+// pair per step.  A complex64 run given `conv_f` (L complex floats) rounds the
+// spectrum into it once, and its register-staged rows read that copy: half
+// the spectrum's bytes, applied in float (complex64 arithmetic, like the
+// state); the general first and last passes keep the double spectrum.
 lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int prec, int batch,
                            const double *v, int64_t v_stride, void *u, double gamma, double dt,
                            int64_t steps, void *ckpt, int64_t ck_every, const double *ktab, void *W,
                            void *ptab, const void *conv, hipStream_t st, bool ck_transposed = false,
-                           const SumSink &sums = SumSink())
+                           const SumSink &sums = SumSink(), void *conv_f = nullptr)
 {
     const int64_t N = p.N;
     const size_t S = esz(prec);
@@ -580,6 +587,10 @@ lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int p
         R.first.chirp = 0;
         R.last.chirp = 0;
         R.row.bhat = (const double *)conv;
+        if (conv_f && prec == LT_C64) {
+            HIP_TRY(launch_spectrum_f32(conv_f, conv, s.L, st), "convolution spectrum (complex float)");
+            R.row.bhat_f = (const float *)conv_f;
+        }
     }
     lt_status ls;
     if ((ls = sums_begin(sums, st))) return ls;
@@ -1186,7 +1197,8 @@ lt_status run_forward(const lt_plan *cp, lt_prec prec, int32_t batch, const doub
         if ((st = conv_spectrum(p, 0, ktab, conv, at(sc.ptr, L.conv_tmp), hs))) return st;
     }
     return two_pass_forward(p, s, D, prec, batch, v, v_stride, u, gamma, dt, steps, ckpt, ckpt_every,
-                            ktab, at(sc.ptr, L.w), at(sc.ptr, L.ptab), conv, hs, false, sink);
+                            ktab, at(sc.ptr, L.w), at(sc.ptr, L.ptab), conv, hs, false, sink,
+                            conv && prec == LT_C64 ? at(sc.ptr, L.conv_f) : nullptr);
 }
 }  // namespace
 

@@ -585,6 +585,15 @@ __global__ void k_conv_embed(cx<double> *g, const cx<double> *src, int64_t N, in
     }
 }
 
+// the convolution spectrum of a complex64 run, rounded once to complex float
+// (count complex entries)
+__global__ void k_spectrum_f32(cx<float> *dst, const cx<double> *src, int64_t count)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < count;
+         j += (int64_t)gridDim.x * blockDim.x)
+        dst[j] = {(float)src[j].x, (float)src[j].y};
+}
+
 // per-point multiplier exp(-i phase v[n]) as a Tw<T> entry (complex double, or
 // hi/lo complex floats), angle formed and reduced in FP64
 template <typename T>
@@ -961,6 +970,13 @@ int launch_conv_embed(void *g, const void *src, int64_t N, int64_t L, double sca
 {
     hipLaunchKernelGGL(k_conv_embed, dim3(grid1d(L)), dim3(256), 0, (hipStream_t)stream, (cx<double> *)g,
                        (const cx<double> *)src, N, L, scale);
+    return (int)hipGetLastError();
+}
+
+int launch_spectrum_f32(void *dst, const void *src, int64_t count, void *stream)
+{
+    hipLaunchKernelGGL(k_spectrum_f32, dim3(grid1d(count) > 2048 ? 2048 : grid1d(count)), dim3(256), 0,
+                       (hipStream_t)stream, (cx<float> *)dst, (const cx<double> *)src, count);
     return (int)hipGetLastError();
 }
 

@@ -846,6 +846,24 @@ __device__ __forceinline__ void rowf_body(const RowArgs &a, int blk, int64_t b, 
                 v[j * R + r] = conjg(cmul_d(v[j * R + r], w.x, a.conj_tab ? -w.y : w.y));
             }
         }
+    } else if constexpr (MID == 2) {
+        // complex64: the spectrum rounded once to complex float, 8 bytes per
+        // element at the element's own offset, applied in float
+        static_assert(sizeof(T) == 4, "complex-float spectrum rows are complex64 only");
+        const rsrc_t rg = make_rsrc(a.bhat_f + 2 * p0, (int64_t)TILE * 8);
+        cx<float> g[E];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) g[j * R + r] = bload<float>(rg, voff[j], r * rstep);
+        }
+        const float sg = a.conj_tab ? -1.0f : 1.0f;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const cx<T> x = v[e];
+            const float gx = g[e].x, gy = sg * g[e].y;
+            v[e] = conjg(cx<T>{x.x * gx - x.y * gy, x.x * gy + x.y * gx});
+        }
     } else {
         // kinetic table indexed by the squared norm (a small table, cached):
         // every entry of the thread in flight at once
@@ -1049,6 +1067,18 @@ int row_go(const RowArgs &a, int batch, void *stream)
     auto k = a.bhat ? k_rowf<T, E, NT, MINW, 0, 0, Rs...> : k_rowf<T, E, NT, MINW, 1, 0, Rs...>;
     if (a.wt)
         k = a.bhat ? k_rowf<T, E, NT, MINW, 0, kWriteThrough, Rs...> : k_rowf<T, E, NT, MINW, 1, kWriteThrough, Rs...>;
+    if constexpr (sizeof(T) == 4) {
+        // complex64 with the spectrum in complex float
+        if (a.bhat_f) k = a.wt ? k_rowf<T, E, NT, MINW, 2, kWriteThrough, Rs...> : k_rowf<T, E, NT, MINW, 2, 0, Rs...>;
+        static bool attr_f = false;
+        if (!attr_f) {
+            hipFuncSetAttribute((const void *)k_rowf<T, E, NT, MINW, 2, 0, Rs...>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+            hipFuncSetAttribute((const void *)k_rowf<T, E, NT, MINW, 2, kWriteThrough, Rs...>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+            attr_f = true;
+        }
+    }
     static bool attr = false;
     if (!attr) {
         hipFuncSetAttribute((const void *)k_rowf<T, E, NT, MINW, 0, 0, Rs...>,

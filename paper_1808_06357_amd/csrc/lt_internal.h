@@ -150,6 +150,8 @@ struct RowArgs {
     void *buf; int64_t buf_bs;
     int L1, L2, rows, nblk;
     const double *bhat; int conj_tab;
+    const float *bhat_f;              // complex64 register-staged rows: the same spectrum rounded once
+                                      // to complex float (interleaved pairs), or null
     const int32_t *s; const double *ktab;
     int64_t ktab_n;                   // entries of ktab (its squared-norm range)
     int fft_only;
@@ -240,6 +242,7 @@ int launch_diag_finish(const double *pp, const double *ps, int batch, int64_t N,
                        double *out, void *stream);
 int launch_conv_input(void *dst, const int32_t *s, const double *ktab, int64_t N, void *stream);
 int launch_conv_embed(void *g, const void *src, int64_t N, int64_t L, double scale, void *stream);
+int launch_spectrum_f32(void *dst, const void *src, int64_t count, void *stream);
 int launch_phase_table(int prec, void *dst, const double *v, int64_t v_bs, int nv, int64_t N, double phase,
                        void *stream);
 // fast register-staged variants (kernels_fast.hip); return -1 when the variant does not fit
