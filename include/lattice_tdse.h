@@ -27,7 +27,10 @@
  *     P = diag(exp(-i dt v_kappa / (2 gamma))) and
  *     K = diag(exp(-i 2 pi^2 gamma dt ||h_chi||^2)) (eqs. (Dn), (Vn),
  *     (StrangTDSE)).  The phase arguments are formed and reduced mod 2 pi in
- *     double precision in both precisions.
+ *     double precision in both precisions.  Prime (chirp-z) lengths run
+ *     F^{-1} K F as one zero-padded cyclic convolution (runs of 4 steps or
+ *     more); its kernel spectrum is built in double, and LT_C64 runs apply
+ *     it rounded once to complex float, like the rest of their arithmetic.
  *
  * Memory: every pointer documented "device" is device memory owned by the
  * caller, who must keep it alive until the work queued on `stream` has

@@ -1436,6 +1436,8 @@ struct BatchRun {
         lt_plan *p;
         const double *ktab;
         void *G, *tmp;
+        void *Gf;  // complex64 batches: the spectrum rounded to complex float, or null
+        int64_t L;
     };
     std::vector<ConvJob> conv_jobs;
     size_t lds_res = 0, lds_col = 0, lds_row = 0;
@@ -1517,7 +1519,9 @@ lt_status batch_build(int32_t B, const lt_plan *const *plans, lt_prec prec, cons
         const bool conv = steps[i] >= kConvMinSteps && conv_available(p, 0, s);
         if (conv) {
             if ((st = ensure_device_tables(p, 0, LT_C128, hs))) return st;
-            R.conv_jobs.push_back({&p, ktab, w + L.conv, w + L.conv_tmp});
+            void *Gf = prec == LT_C64 ? (void *)(w + L.conv_f) : nullptr;
+            R.conv_jobs.push_back({&p, ktab, w + L.conv, w + L.conv_tmp, Gf, s.L});
+            if (Gf) Ro.row.bhat_f = (const float *)Gf;
             Ro.first.chirp = 0;
             Ro.last.chirp = 0;
             Ro.row.bhat = (const double *)(w + L.conv);
@@ -1584,6 +1588,16 @@ lt_status batch_build(int32_t B, const lt_plan *const *plans, lt_prec prec, cons
     return LT_OK;
 }
 
+// multiplier of a register-staged row class (key = 2 L2 + kind): 1 the kinetic
+// table; 0 the convolution spectrum, which complex64 batches read in complex
+// float (every member of such a class has the convolution form and its
+// rounded copy, batch_build)
+int row_mid(int prec, int key)
+{
+    const int kind = key % 2;
+    return kind == 0 && prec == LT_C64 ? 2 : kind;
+}
+
 // the descriptor block as uploaded
 std::vector<char> batch_blob(const BatchRun &R)
 {
@@ -1601,8 +1615,10 @@ lt_status batch_tables(const BatchRun &R, char *dd, hipStream_t hs)
     lt_status st;
     HIP_TRY(launch_ktab_multi((const KtabDesc *)(dd + R.BL.d_ktab), (int)R.kd.size(), R.max_ktab, hs),
             "kinetic tables");
-    for (const auto &j : R.conv_jobs)
+    for (const auto &j : R.conv_jobs) {
         if ((st = conv_spectrum(*j.p, 0, j.ktab, j.G, j.tmp, hs))) return st;
+        if (j.Gf) HIP_TRY(launch_spectrum_f32(j.Gf, j.G, j.L, hs), "convolution spectrum (complex float)");
+    }
     return LT_OK;
 }
 
@@ -1636,7 +1652,7 @@ lt_status batch_passes(const BatchRun &R, char *dd, hipStream_t hs, hipStream_t 
             const int *idx = dl + l.idx_off, *start = dl + l.start_off;
             if (!col) {
                 herr = l.key < 0 ? launch_row_multi(prec, dtwo, idx, start, l.act, l.start[l.act], 0, g, R.lds_row, hs)
-                                 : launch_row_fast_multi(prec, l.var, l.key / 2, l.key % 2, dtwo, idx, start, l.act,
+                                 : launch_row_fast_multi(prec, l.var, l.key / 2, row_mid(prec, l.key), dtwo, idx, start, l.act,
                                                          l.start[l.act], 0, g, hs);
                 continue;
             }
@@ -1823,7 +1839,7 @@ lt_status strang_batch_autotune(lt_batch *b, int32_t reps, void *stream)
                 if (var == 5 && len > 2048) continue;
                 auto go = [&]() {
                     return which == 0 ? launch_col_fast_multi(R.prec, var, l.key, dtwo, idx, start, nm, nb, 0, 2, hs)
-                                      : launch_row_fast_multi(R.prec, var, l.key / 2, l.key % 2, dtwo, idx, start, nm,
+                                      : launch_row_fast_multi(R.prec, var, l.key / 2, row_mid(R.prec, l.key), dtwo, idx, start, nm,
                                                               nb, 0, 1, hs);
                 };
                 herr = go();  // warm-up

@@ -895,7 +895,7 @@ __global__ void __launch_bounds__(NT, MINW) k_rowf(RowArgs a)
 
 // Row pass g of the batch members listed in idx (prefix sums of their row
 // blocks in start, block offset off); MID 0: spectrum table, MID 1: kinetic
-// table, as in k_rowf.  Q blocks per counted 4096-element block, as in
+// table, MID 2: spectrum in complex float, as in k_rowf.  Q blocks per counted 4096-element block, as in
 // k_colf_multi.
 template <typename T, int E, int NT, int MINW, int MID, int Q, int... Rs>
 __global__ void __launch_bounds__(NT, MINW) k_rowf_multi(const BatchDesc *d, const int *idx, const int *start,
@@ -1363,9 +1363,14 @@ int launch_col_fast_multi(int prec, int variant, int L1, const BatchDesc *d, con
 int launch_row_fast_multi(int prec, int variant, int L2, int mid, const BatchDesc *d, const int *idx,
                           const int *start, int nmem, int nblocks, int off, int64_t g, void *stream)
 {
-    if (prec == LT_C128)
+    // mid 0: spectrum (complex double), 1: kinetic table, 2: spectrum in
+    // complex float (complex64 only; every member's row carries bhat_f)
+    if (prec == LT_C128) {
+        if (mid == 2) return -1;
         return mid ? multi_go<double, false, 1>(variant, L2, d, idx, start, nmem, nblocks, off, g, stream)
                    : multi_go<double, false, 0>(variant, L2, d, idx, start, nmem, nblocks, off, g, stream);
+    }
+    if (mid == 2) return multi_go<float, false, 2>(variant, L2, d, idx, start, nmem, nblocks, off, g, stream);
     return mid ? multi_go<float, false, 1>(variant, L2, d, idx, start, nmem, nblocks, off, g, stream)
                : multi_go<float, false, 0>(variant, L2, d, idx, start, nmem, nblocks, off, g, stream);
 }
