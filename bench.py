@@ -48,15 +48,16 @@ def pass_bytes(plan_info, N, m, S):
     is one zero-padded cyclic convolution of length L): each pass reads and
     writes the state once and reads the tables its step needs -- v (FP64,
     8 B per point) in the first and last passes, the merged potential step
-    exp(-i dt v / gamma) per point in the middle ones (16 B: a hi/lo pair of
-    complex floats for complex64, one complex double for complex128), and the
-    convolution spectrum (complex double, 16 B per bin) in the row pass."""
+    exp(-i dt v / gamma) per point in the middle ones, and the convolution
+    spectrum per bin in the row pass; both tables are as wide as a state
+    element (S bytes: complex float for complex64, complex double for
+    complex128)."""
     L = plan_info["fft_len"]
-    pot = 16 * N
+    pot = S * N
     col = [N * S + 8 * N + L * S]                 # first: u, v in; transform out
     col += [2 * L * S + pot] * (m - 1)            # merged potential steps P^2
     col += [L * S + 8 * N + N * S]                # last: transform in, v in, u out
-    row = [2 * L * S + 16 * L] * m                # state in/out + convolution spectrum
+    row = [2 * L * S + S * L] * m                 # state in/out + convolution spectrum
     return col, row
 
 

@@ -594,23 +594,16 @@ __global__ void k_spectrum_f32(cx<float> *dst, const cx<double> *src, int64_t co
         dst[j] = {(float)src[j].x, (float)src[j].y};
 }
 
-// per-point multiplier exp(-i phase v[n]) as a Tw<T> entry (complex double, or
-// hi/lo complex floats), angle formed and reduced in FP64
+// per-point multiplier exp(-i phase v[n]) in the run's precision (complex
+// double, or rounded once to complex float), angle formed and reduced in FP64
 template <typename T>
-__global__ void k_phase_table(Tw<T> *dst, const double *v, int64_t v_bs, int nv, int64_t N, double phase)
+__global__ void k_phase_table(cx<T> *dst, const double *v, int64_t v_bs, int nv, int64_t N, double phase)
 {
     const int b = blockIdx.y;
     for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
         double c, s;
         expm_i(phase * v[b * v_bs + n], c, s);
-        Tw<T> t;
-        if constexpr (sizeof(T) == 8) {
-            t.w = {c, s};
-        } else {
-            t.hi = {(float)c, (float)s};
-            t.lo = {(float)(c - (double)t.hi.x), (float)(s - (double)t.hi.y)};
-        }
-        dst[b * N + n] = t;
+        dst[b * N + n] = {(T)c, (T)s};
     }
 }
 
@@ -985,10 +978,10 @@ int launch_phase_table(int prec, void *dst, const double *v, int64_t v_bs, int n
 {
     dim3 grid(grid1d(N) > 2048 ? 2048 : grid1d(N), nv);
     if (prec == LT_C128)
-        hipLaunchKernelGGL(k_phase_table<double>, grid, dim3(256), 0, (hipStream_t)stream, (Tw<double> *)dst, v,
+        hipLaunchKernelGGL(k_phase_table<double>, grid, dim3(256), 0, (hipStream_t)stream, (cx<double> *)dst, v,
                            v_bs, nv, N, phase);
     else
-        hipLaunchKernelGGL(k_phase_table<float>, grid, dim3(256), 0, (hipStream_t)stream, (Tw<float> *)dst, v,
+        hipLaunchKernelGGL(k_phase_table<float>, grid, dim3(256), 0, (hipStream_t)stream, (cx<float> *)dst, v,
                            v_bs, nv, N, phase);
     return (int)hipGetLastError();
 }

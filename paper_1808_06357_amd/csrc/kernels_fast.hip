@@ -83,6 +83,44 @@ __device__ __forceinline__ void bstore(cx<double> x, rsrc_t r, uint32_t voff, ui
 
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 
+// Entry of the per-point table of the merged potential step exp(-i phase v):
+// complex64 runs keep it rounded once to complex float (the phase itself is
+// formed and reduced in double), complex128 runs in complex double.  Either
+// way one entry is as wide as one state element, so it sits at the element's
+// own byte offset.
+template <typename T>
+struct PTabT;
+template <>
+struct PTabT<float> {
+    using type = cx<float>;
+};
+template <>
+struct PTabT<double> {
+    using type = Tw<double>;
+};
+template <typename T>
+using PTab = typename PTabT<T>::type;
+
+template <typename T>
+__device__ __forceinline__ PTab<T> pload(rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ PTab<float> pload<float>(rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(cx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ PTab<double> pload<double>(rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(Tw<double>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ cx<float> ptmul(cx<float> a, cx<float> t)
+{
+    return {a.x * t.x - a.y * t.y, a.x * t.y + a.y * t.x};
+}
+__device__ __forceinline__ cx<double> ptmul(cx<double> a, const Tw<double> &t) { return twmul(a, t); }
+__device__ __forceinline__ cx<double> pt_d(cx<float> t) { return {(double)t.x, (double)t.y}; }
+__device__ __forceinline__ cx<double> pt_d(const Tw<double> &t) { return t.w; }
+
 // x[r] *= w^r for r = 1..R-1, w in double: two running powers (odd and even
 // exponents, each stepped by w^2), multiplied and applied in turn, so that
 // only three complex doubles stay live and the two chains overlap.  Each
@@ -285,7 +323,7 @@ template <typename T, int E, int J, int R, bool PRE, bool PV>
 struct ColTile {
     cx<T> v[E];
     uint32_t voff[J];
-    Tw<T> pre[PRE ? R : 1];
+    PTab<T> pre[PRE ? R : 1];
     double sv[PV ? E : 1];  // v of every element for the step's sums (MID 8, eight elements or fewer)
 };
 
@@ -344,11 +382,9 @@ __device__ __forceinline__ void colf_load(const ColArgs &a, int tile, int64_t b,
         }
     }
     if constexpr (PRE) {
-        constexpr uint32_t ps = (uint32_t)(sizeof(Tw<T>) / sizeof(cx<T>));
-        const rsrc_t rp = make_rsrc((const Tw<T> *)a.ptab + b * a.ptab_bs, a.Nvalid * (int64_t)sizeof(Tw<T>));
+        const rsrc_t rp = make_rsrc((const PTab<T> *)a.ptab + b * a.ptab_bs, a.Nvalid * (int64_t)sizeof(PTab<T>));
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            X.pre[r] = __builtin_bit_cast(Tw<T>, __builtin_amdgcn_raw_buffer_load_b128(rp, ps * (X.voff[0] + r * rstep), 0, 0));
+        for (int r = 0; r < R; ++r) X.pre[r] = pload<T>(rp, X.voff[0] + r * rstep);
     }
 }
 
@@ -378,7 +414,6 @@ __device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, 
     cx<T>(&v)[E] = X.v;
     const uint32_t(&voff)[J] = X.voff;
     constexpr bool kPreP = PRE;
-    constexpr uint32_t ps = (uint32_t)(sizeof(Tw<T>) / sizeof(cx<T>));
     // four-step twiddle base and step of each butterfly group: the forward
     // pass at the end multiplies by the same series, so they are kept
     const bool tw = a.twiddle != 0;
@@ -501,21 +536,18 @@ __device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, 
                 pb[1] = s2;
             }
         }
-        // the merged potential step from the per-point table (16 bytes per
-        // point: a hi/lo pair of complex floats, or one complex double), every
-        // entry of the thread in flight at once.  The whole byte offset sits
-        // in the per-lane register, so the buffer's range check reads the
-        // entries of the zero padding (n >= Nvalid) as 0, which zeroes those
-        // points.
-        const rsrc_t rp = make_rsrc((const Tw<T> *)a.ptab + b * a.ptab_bs, a.Nvalid * (int64_t)sizeof(Tw<T>));
+        // the merged potential step from the per-point table (one entry as
+        // wide as the element, at its offset), every entry of the thread in
+        // flight at once.  The whole byte offset sits in the per-lane
+        // register, so the buffer's range check reads the entries of the zero
+        // padding (n >= Nvalid) as 0, which zeroes those points.
+        const rsrc_t rp = make_rsrc((const PTab<T> *)a.ptab + b * a.ptab_bs, a.Nvalid * (int64_t)sizeof(PTab<T>));
         constexpr int j0 = kPreP ? 1 : 0;
-        Tw<T> pin[J][R];
+        PTab<T> pin[J][R];
 #pragma unroll
         for (int j = j0; j < J; ++j) {
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                pin[j][r] = __builtin_bit_cast(
-                    Tw<T>, __builtin_amdgcn_raw_buffer_load_b128(rp, ps * (voff[j] + r * rstep), 0, 0));
+            for (int r = 0; r < R; ++r) pin[j][r] = pload<T>(rp, voff[j] + r * rstep);
         }
         if constexpr (kPreP) {
 #pragma unroll
@@ -524,7 +556,7 @@ __device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, 
 #pragma unroll
         for (int j = 0; j < J; ++j) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[j * R + r] = twmul(conjg(v[j * R + r]), pin[j][r]);
+            for (int r = 0; r < R; ++r) v[j * R + r] = ptmul(conjg(v[j * R + r]), pin[j][r]);
         }
     } else if constexpr (MID == 0 || MID == 2 || MID == 3) {
         // passes without a table: exp(-i phase v) in FP64 on the fly.  MID 3: the angle
@@ -709,9 +741,9 @@ __global__ void __launch_bounds__(NT, MINW) k_colf_adj(ColArgs a)
     // at once (point n = k1 L2 + c0 + q of iteration it; the buffers' range
     // checks read the zero padding n >= Nvalid as 0 and drop its stores)
     const rsrc_t rg = make_rsrc(a.gacc + b * a.gacc_bs, a.Nvalid * (int64_t)sizeof(double));
-    const rsrc_t rp = make_rsrc((const Tw<T> *)a.ptab + b * a.ptab_bs, a.Nvalid * (int64_t)sizeof(Tw<T>));
+    const rsrc_t rp = make_rsrc((const PTab<T> *)a.ptab + b * a.ptab_bs, a.Nvalid * (int64_t)sizeof(PTab<T>));
     double g_in[IT];
-    Tw<T> pw[IT];
+    PTab<T> pw[IT];
     uint32_t nn[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -719,8 +751,7 @@ __global__ void __launch_bounds__(NT, MINW) k_colf_adj(ColArgs a)
         const int k1 = i / H, q = i - k1 * H;
         nn[it] = (uint32_t)k1 * (uint32_t)L2 + (uint32_t)(c0 + q);
         g_in[it] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rg, nn[it] * 8u, 0, 0));
-        pw[it] = __builtin_bit_cast(Tw<T>, __builtin_amdgcn_raw_buffer_load_b128(
-                                               rp, nn[it] * (uint32_t)sizeof(Tw<T>), 0, 0));
+        pw[it] = pload<T>(rp, nn[it] * (uint32_t)sizeof(PTab<T>));
     }
     __syncthreads();
 #pragma unroll
@@ -738,7 +769,7 @@ __global__ void __launch_bounds__(NT, MINW) k_colf_adj(ColArgs a)
         __builtin_amdgcn_raw_buffer_store_b64(
             __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(rg, 0, 0, 0)), g_in[it] + a.gcoef * im),
             rg, nn[it] * 8u, 0, 0);
-        const cx<double> w = tw_d(pw[it]);  // the sweep's table of exp(-i phase v[n])
+        const cx<double> w = pt_d(pw[it]);  // the sweep's table of exp(-i phase v[n])
         s[ax] = cmul_d(x, w.x, w.y);
         s[ay] = cmul_d(y, w.x, w.y);
     }

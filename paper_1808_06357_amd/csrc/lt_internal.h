@@ -113,7 +113,7 @@ struct ColArgs {
     int64_t Nchirp;
     double scale;
     const double *tw4hi, *tw4lo;      // four-step twiddle tables (complex double)
-    const void *ptab; int64_t ptab_bs;// merged potential step exp(-i phase v[n]) per point, Tw<T>
+    const void *ptab; int64_t ptab_bs;// merged potential step exp(-i phase v[n]) per point, cx<T>
                                       // (fast passes; the general kernel uses v and phase)
     const void *twa;                  // Tw<T> table of W_{L1}
     Radices rad;
