@@ -68,6 +68,29 @@ def test_fig1_example_full_minimal_set():
         assert tuple(h[chi]) == best[chi][1]
 
 
+def test_box_d2_n1031_initial_condition_is_projected_onto_the_index_set():
+    """Config 0's u0 is the Gaussian packet projected onto I: its lattice DFT
+    vanishes on the seven completed keys and carries, on each key of I, the
+    packet's closed-form Fourier coefficient (the transform of a Gaussian,
+    shifted to the centre and the carrier k0), up to the common scale."""
+    c = W.box_d2_n1031()
+    N = int(c.n[0])
+    coef = np.fft.fft(c.u0) / N  # u_k = sum_xi coef_xi exp(2 pi i xi k / N)
+    k = O.keys(c.Z, c.n, c.I)
+    others = np.setdiff1d(np.arange(N), k)
+    assert others.size == 7
+    assert np.max(np.abs(coef[others])) < 1e-14 * np.max(np.abs(coef))
+    sigma, centre, k0 = 0.1, np.array([0.5, 0.5]), np.array([2, 0])
+    dh = c.I.astype(np.float64) - k0
+    exact = np.prod(sigma * np.sqrt(2 * np.pi) * np.exp(-2 * np.pi ** 2 * sigma ** 2 * dh ** 2), axis=1) \
+        * np.exp(-2j * np.pi * dh @ centre)
+    ratio = coef[k] / exact
+    big = np.abs(exact) > 1e-4 * np.abs(exact).max()
+    assert big.sum() > 50 and np.allclose(ratio[big], ratio[big][0], rtol=1e-11, atol=0)
+    # unit lattice-rule norm
+    assert abs(np.mean(np.abs(c.u0) ** 2) - 1.0) < 1e-14
+
+
 def test_box_d2_n1031_box_keys_and_completion():
     """Def. 2 on the box {-15..16}^2 with z = (1, 32), N = 1031: injective
     (1024 keys), the seven unowned keys are completed with their minimal-l2

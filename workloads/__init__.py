@@ -271,6 +271,30 @@ def gaussian_packet(num: np.ndarray, N: int, center, k0, sigma: float = 0.1) -> 
     return u.astype(np.complex128)
 
 
+def projected_packet(Z: np.ndarray, n: np.ndarray, I: np.ndarray, center, k0, sigma: float = 0.1) -> np.ndarray:
+    """The periodised Gaussian packet of gaussian_packet projected onto the
+    span of exp(2 pi i h.x), h in I: its exact Fourier coefficients
+    prod_j sigma sqrt(2 pi) exp(-2 pi^2 sigma^2 (h_j - k0_j)^2)
+    exp(-2 pi i (h_j - k0_j) c_j) on I (zero elsewhere), summed at the
+    lattice points (Def. 1, rank 1 or 2) and scaled so that
+    (1/N) sum_k |u_k|^2 = 1."""
+    Z = np.asarray(Z, dtype=np.int64)
+    n = np.asarray(n, dtype=np.int64)
+    I = np.asarray(I, dtype=np.int64)
+    N = int(np.prod(n))
+    num = point_numerators(Z, n)
+    dh = I - np.asarray(k0, dtype=np.int64)[None, :]
+    c = np.asarray(center, dtype=np.float64)
+    coef = np.prod(sigma * np.sqrt(2.0 * np.pi) * np.exp(-2.0 * np.pi ** 2 * sigma ** 2 * dh.astype(np.float64) ** 2),
+                   axis=1) * np.exp(-2j * np.pi * (dh.astype(np.float64) @ c))
+    u = np.zeros(num.shape[0], dtype=np.complex128)
+    for t in range(I.shape[0]):
+        ph = (num @ I[t]) % N  # h.x_k = (h.num_k mod N) / N for the point numerators
+        u += coef[t] * np.exp(2j * np.pi * ph.astype(np.float64) / N)
+    u /= np.sqrt(np.mean(np.abs(u) ** 2))
+    return u
+
+
 def seeded_packet(num: np.ndarray, N: int, g: np.random.Generator, sigma: float = 0.1):
     d = num.shape[1]
     c = g.uniform(0.3, 0.7, size=d)
@@ -365,14 +389,14 @@ class Instance:
 
 def box_d2_n1031() -> Instance:
     """d = 2, N = 1031, z = (1, 32), I = {-15..16}^2, gamma = 0.1,
-    v = sum_j (1 - cos 2 pi x_j), Gaussian packet at (1/2, 1/2) with k0 = (2, 0),
-    dt = 0.01, 100 steps."""
+    v = sum_j (1 - cos 2 pi x_j), Gaussian packet at (1/2, 1/2) with k0 = (2, 0)
+    projected onto I, dt = 0.01, 100 steps."""
     Z = np.array([[1, 32]], dtype=np.int64)
     n = np.array([1031], dtype=np.int64)
     num = point_numerators(Z, n)
     I = box(-15, 16, 2)
     v = v_sum_one_minus_cos(num, 1031)
-    u0 = gaussian_packet(num, 1031, (0.5, 0.5), (2, 0), 0.1)
+    u0 = projected_packet(Z, n, I, (0.5, 0.5), (2, 0), 0.1)
     return Instance(2, Z, n, I, 0.1, 0.01, 100, v, u0, {"name": "box_d2_n1031"})
 
 
