@@ -266,7 +266,8 @@ RunWork run_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool s
 }
 
 struct AdjWork {
-    size_t ktab = 0, w = 0, gacc = 0, ptab = 0, conv = 0, conv_tmp = 0, ut = 0, gt = 0, vt = 0, total = 0;
+    size_t ktab = 0, w = 0, gacc = 0, ptab = 0, conv = 0, conv_tmp = 0, conv_f = 0, ut = 0, gt = 0, vt = 0,
+           total = 0;
 };
 
 // The adjoint sweep's schedule slot: the swapped one of a rank-2 tensor with
@@ -289,6 +290,10 @@ AdjWork adj_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool s
         off = align_up(off + (size_t)s.L * 16);
         w.conv_tmp = off;
         off = align_up(off + (size_t)p.N * 16);
+        if (prec == LT_C64) {  // the spectrum rounded to complex float for the complex64 rows
+            w.conv_f = off;
+            off = align_up(off + (size_t)s.L * 8);
+        }
     }
     if (s.swapped) {
         // transposed u(T) (later dJ/du0), transposed cotangent (later the
@@ -1342,6 +1347,10 @@ lt_status strang_adjoint(const lt_plan *cp, lt_prec prec, int32_t batch, const d
     r.buf_bs = s.L;
     if (conv) {
         r.bhat = (const double *)conv;
+        if (prec == LT_C64) {  // as in the forward run: the complex64 rows read it in complex float
+            HIP_TRY(launch_spectrum_f32(at(sc.ptr, L.conv_f), conv, s.L, hs), "convolution spectrum (complex float)");
+            r.bhat_f = (const float *)at(sc.ptr, L.conv_f);
+        }
     } else if (s.bluestein) {
         r.bhat = D.bhat;
     } else {
