@@ -1911,7 +1911,7 @@ void strang_batch_destroy(lt_batch *b)
 // kinetic table and (chirp-z) a convolution spectrum, per boundary a merged
 // potential table (complex64), the transform buffer (chirp-z) and scratch.
 struct ComposedWork {
-    size_t ktab[3] = {}, conv[3] = {}, ptab[3] = {}, w = 0, tmp = 0, total = 0;
+    size_t ktab[3] = {}, conv[3] = {}, conv_f[3] = {}, ptab[3] = {}, w = 0, tmp = 0, total = 0;
 };
 
 ComposedWork composed_layout(const lt_plan &p, const Sched &s, int prec, int batch, bool shared_v, int P)
@@ -1924,6 +1924,10 @@ ComposedWork composed_layout(const lt_plan &p, const Sched &s, int prec, int bat
         if (s.bluestein) {
             c.conv[i] = off;
             off = align_up(off + (size_t)s.L * 16);
+            if (prec == LT_C64) {  // the spectrum rounded to complex float for the complex64 rows
+                c.conv_f[i] = off;
+                off = align_up(off + (size_t)s.L * 8);
+            }
         }
         c.ptab[i] = off;
         off = align_up(off + (size_t)(shared_v ? 1 : batch) * p.N * 16);
@@ -2177,7 +2181,14 @@ lt_status splitting_run(const lt_plan *cp, lt_prec prec, int32_t batch, const do
         R[i].pot.phase = merged;
         R[i].first.chirp = 0;
         R[i].last.chirp = 0;
-        if (conv) R[i].row.bhat = (const double *)conv;
+        if (conv) {
+            R[i].row.bhat = (const double *)conv;
+            if (prec == LT_C64) {
+                void *cf = at(sc.ptr, L.conv_f[i]);
+                HIP_TRY(launch_spectrum_f32(cf, conv, s.L, hs), "convolution spectrum (complex float)");
+                R[i].row.bhat_f = (const float *)cf;
+            }
+        }
         if (v1) R[i].first.v2 = R[i].pot.v2 = R[i].last.v2 = v1;
     }
     // time-dependent field: the angle at substep boundary j carries f[j] v1
