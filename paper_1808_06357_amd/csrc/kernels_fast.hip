@@ -307,15 +307,6 @@ __device__ __forceinline__ void tw4_base_step(cx<double> &b, cx<double> &st, int
     st = tw4mul(one, n2, BPS, L2, hi, lo);
 }
 
-// Steady-state column pass: [inverse column DFT -> point-domain multiplier
-// (and chirp-z mask) -> forward column DFT], in place, on column tile `tile`
-// of batch item b.  MID 0: the merged potential step from the per-point
-// table the run built; MID 1: the chirp-z
-// kinetic step from the table indexed by the squared norm; MID 2: the merged
-// potential step from v in FP64 (runs without a table); MID 3: the angle of
-// a time-dependent potential from two fields; MID 7: MID 0 plus the store of
-// the step's checkpoint (and the step's sums when asked for); MID 8: MID 0
-// plus the step's sums of |u|^2 and v |u|^2.
 // Registers of one column tile between its loads and its transforms: the
 // tile's elements, their byte offsets, and (complex64 table steps) the table
 // entries of the first butterfly group.
@@ -350,7 +341,9 @@ constexpr bool col_prefetch()
 
 // Issues every load of column tile `tile` of batch item b: element
 // (t + r BPS, c0 + q) sits at byte voff[j] + r * rstep of the state
-template <typename T, int E, int NT, bool PRE, bool PV, int... Rs>
+// (IN: from the run's input vector, whose zero padding n >= Nvalid lies
+// beyond its range and reads 0)
+template <typename T, int E, int NT, bool PRE, bool PV, bool IN, int... Rs>
 __device__ __forceinline__ void colf_load(const ColArgs &a, int tile, int64_t b,
                                           ColTile<T, E, Fft<T, E, NT, true, Rs...>::J, Fft<T, E, NT, true, Rs...>::R, PRE, PV> &X)
 {
@@ -358,8 +351,8 @@ __device__ __forceinline__ void colf_load(const ColArgs &a, int tile, int64_t b,
     constexpr int C = F::SEQ, J = F::J, R = F::R, BPS = F::BPS, L1 = F::L;
     const int L2 = a.L2;
     const int c0 = tile * C;
-    cx<T> *buf = (cx<T> *)a.buf + b * a.buf_bs;
-    const rsrc_t rb = make_rsrc(buf, (int64_t)L1 * L2 * (int64_t)sizeof(cx<T>));
+    const cx<T> *src = IN ? (const cx<T> *)a.in + b * a.in_bs : (const cx<T> *)a.buf + b * a.buf_bs;
+    const rsrc_t rb = make_rsrc(src, (IN ? a.Nvalid : (int64_t)L1 * L2) * (int64_t)sizeof(cx<T>));
     const uint32_t rstep = (uint32_t)BPS * (uint32_t)L2 * (uint32_t)sizeof(cx<T>);
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -388,6 +381,46 @@ __device__ __forceinline__ void colf_load(const ColArgs &a, int tile, int64_t b,
     }
 }
 
+// The step's sums of |u|^2 and v |u|^2 over column tile `tile` of batch item
+// b, from the tile's values x in registers (|x| = |u| at a step boundary): v
+// of each element at the element's offset scaled to 8 bytes (or from sv, when
+// it was loaded with the state); the zero padding (n >= Nvalid) is masked by
+// its offset.  One partial pair per tile.
+template <typename T, int E, int NT, int J, int R, bool PV>
+__device__ __forceinline__ void tile_sums(const ColArgs &a, int tile, int64_t b, const cx<T> (&v)[E],
+                                          const uint32_t (&voff)[J], uint32_t rstep, const double *sv)
+{
+    const rsrc_t rv = make_rsrc(a.sum_v + b * a.v_bs, a.Nvalid * (int64_t)sizeof(double));
+    constexpr uint32_t vdiv = (uint32_t)(sizeof(cx<T>) / sizeof(double));
+    const uint32_t lim = (uint32_t)a.Nvalid * (uint32_t)sizeof(cx<T>);
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        double vv[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if constexpr (PV) vv[r] = sv[j * R + r];
+            else
+                vv[r] = __builtin_bit_cast(double,
+                                           __builtin_amdgcn_raw_buffer_load_b64(rv, (voff[j] + r * rstep) / vdiv, 0, 0));
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const cx<T> x = v[j * R + r];
+            const double q2 =
+                voff[j] + r * rstep < lim ? (double)x.x * (double)x.x + (double)x.y * (double)x.y : 0.0;
+            s1 += q2;
+            s2 += vv[r] * q2;
+        }
+    }
+    block_sum2<NT>(s1, s2);
+    if (threadIdx.x == 0) {
+        double *pb = a.sum_part + ((int64_t)b * a.sum_pt + tile) * 2;
+        pb[0] = s1;
+        pb[1] = s2;
+    }
+}
+
 // Steady-state column pass: [inverse column DFT -> point-domain multiplier
 // (and chirp-z mask) -> forward column DFT], in place, on column tile `tile`
 // of batch item b, whose loads colf_load issued.  MID 0: the merged potential
@@ -396,8 +429,12 @@ __device__ __forceinline__ void colf_load(const ColArgs &a, int tile, int64_t b,
 // potential step from v in FP64 (runs without a table); MID 3: the angle of
 // a time-dependent potential from two fields; MID 7: MID 0 plus the store of
 // the step's checkpoint (and the step's sums when asked for); MID 8: MID 0
-// plus the step's sums of |u|^2 and v |u|^2.  sync_first: the workgroup used
-// the LDS buffer before (a previous tile), so the first write waits for it.
+// plus the step's sums of |u|^2 and v |u|^2.  MID 9: the first pass of a run
+// (the half potential step exp(-i phase v) on the input vector, then the
+// forward column DFT), MID 10: the last (inverse column DFT, half potential
+// step, store to the output vector); both in FP64 from v, with the step's
+// sums when asked for.  sync_first: the workgroup used the LDS buffer before
+// (a previous tile), so the first write waits for it.
 template <typename T, int E, int NT, int MID, bool PRE, bool PV, int SA, int... Rs>
 __device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, cx<T> *s,
                                          const typename Fft<T, E, NT, true, Rs...>::Bases &B,
@@ -408,8 +445,10 @@ __device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, 
     constexpr int C = F::SEQ, J = F::J, R = F::R, BPS = F::BPS, L1 = F::L, TILE = F::TILE;
     const int L2 = a.L2;
     const int c0 = tile * C;
-    cx<T> *buf = (cx<T> *)a.buf + b * a.buf_bs;
-    const rsrc_t rb = make_rsrc(buf, (int64_t)L1 * L2 * (int64_t)sizeof(cx<T>));
+    // MID 10 stores into the output vector; its zero padding (n >= Nvalid)
+    // lies beyond that range and is dropped
+    cx<T> *dst = MID == 10 ? (cx<T> *)a.out + b * a.out_bs : (cx<T> *)a.buf + b * a.buf_bs;
+    const rsrc_t rb = make_rsrc(dst, (MID == 10 ? a.Nvalid : (int64_t)L1 * L2) * (int64_t)sizeof(cx<T>));
     const uint32_t rstep = (uint32_t)BPS * (uint32_t)L2 * (uint32_t)sizeof(cx<T>);
     cx<T>(&v)[E] = X.v;
     const uint32_t(&voff)[J] = X.voff;
@@ -432,8 +471,9 @@ __device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, 
     }
     // MID 5: forward DFT only (then the four-step twiddle); MID 6: inverse
     // DFT only (the conjugated twiddle first) -- the inner passes of a
-    // three-level transform
-    constexpr bool kInv = MID != 5, kFwd = MID != 6;
+    // three-level transform; MIDs 9 and 10 likewise for a run's first and
+    // last passes
+    constexpr bool kInv = MID != 5 && MID != 9, kFwd = MID != 6 && MID != 10;
     if constexpr (kInv) {
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -501,41 +541,8 @@ __device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, 
                 }
             }
         }
-        if constexpr (MID == 8) {
-            // the step's sums of |u|^2 and v |u|^2 over the tile (|x| = |u|
-            // at the boundary), in registers: v of each element at the
-            // element's offset scaled to 8 bytes; the zero padding
-            // (n >= Nvalid) is masked by its offset
-            const rsrc_t rv = make_rsrc(a.sum_v + b * a.v_bs, a.Nvalid * (int64_t)sizeof(double));
-            constexpr uint32_t vdiv = (uint32_t)(sizeof(cx<T>) / sizeof(double));
-            const uint32_t lim = (uint32_t)a.Nvalid * (uint32_t)sizeof(cx<T>);
-            double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-            for (int j = 0; j < J; ++j) {
-                double vv[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if constexpr (PV) vv[r] = X.sv[j * R + r];
-                    else
-                        vv[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                                               rv, (voff[j] + r * rstep) / vdiv, 0, 0));
-                }
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const cx<T> x = v[j * R + r];  // conj of the point value: same modulus
-                    const double q2 = voff[j] + r * rstep < lim ? (double)x.x * (double)x.x + (double)x.y * (double)x.y
-                                                                 : 0.0;
-                    s1 += q2;
-                    s2 += vv[r] * q2;
-                }
-            }
-            block_sum2<NT>(s1, s2);
-            if (threadIdx.x == 0) {
-                double *pb = a.sum_part + ((int64_t)b * a.sum_pt + tile) * 2;
-                pb[0] = s1;
-                pb[1] = s2;
-            }
-        }
+        // the values are conjugates of the point values: same modulus
+        if constexpr (MID == 8) tile_sums<T, E, NT, J, R, PV>(a, tile, b, v, voff, rstep, X.sv);
         // the merged potential step from the per-point table (one entry as
         // wide as the element, at its offset), every entry of the thread in
         // flight at once.  The whole byte offset sits in the per-lane
@@ -558,9 +565,12 @@ __device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, 
 #pragma unroll
             for (int r = 0; r < R; ++r) v[j * R + r] = ptmul(conjg(v[j * R + r]), pin[j][r]);
         }
-    } else if constexpr (MID == 0 || MID == 2 || MID == 3) {
+    } else if constexpr (MID == 2 || MID == 3 || MID == 9 || MID == 10) {
         // passes without a table: exp(-i phase v) in FP64 on the fly.  MID 3: the angle
         // phase v[n] + phase2 v2[n] of a time-dependent potential, both fields in FP64
+        if constexpr (MID == 9 || MID == 10) {
+            if (a.sum_part) tile_sums<T, E, NT, J, R, false>(a, tile, b, v, voff, rstep, nullptr);
+        }
         double pin[J][R];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -592,7 +602,10 @@ __device__ __forceinline__ void colf_run(const ColArgs &a, int tile, int64_t b, 
             for (int r = 0; r < R; ++r) {
                 const int64_t n = (int64_t)(t + r * BPS) * L2 + c0 + q;
                 const double ang = MID == 3 ? pin[j][r] : a.phase * pin[j][r];
-                v[j * R + r] = n < a.Nvalid ? mul_expm_i(conjg(v[j * R + r]), ang) : cx<T>{0, 0};
+                // MID 9 holds the input's point values, the others the
+                // conjugates left by the inverse DFT
+                const cx<T> x = MID == 9 ? v[j * R + r] : conjg(v[j * R + r]);
+                v[j * R + r] = n < a.Nvalid ? mul_expm_i(x, ang) : cx<T>{0, 0};
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -641,7 +654,7 @@ __device__ __forceinline__ void colf_body(const ColArgs &a, int wtile, int64_t b
     F::load_bases(B, (const Tw<T> *)a.twa);
     ColTile<T, E, F::J, F::R, PRE, PV> X[S];
 #pragma unroll
-    for (int st = 0; st < S; ++st) colf_load<T, E, NT, PRE, PV, Rs...>(a, wtile * S + st, b, X[st]);
+    for (int st = 0; st < S; ++st) colf_load<T, E, NT, PRE, PV, MID == 9, Rs...>(a, wtile * S + st, b, X[st]);
 #pragma unroll
     for (int st = 0; st < S; ++st)
         colf_run<T, E, NT, MID, PRE, PV, SA, Rs...>(a, wtile * S + st, b, s, B, X[st], st > 0);
@@ -1033,6 +1046,23 @@ int col_go(const ColArgs &a, int batch, void *stream)
     // MID 2 (complex128 runs without a table): FP64 phase of v; MID 3:
     // potential with a time-dependent second field
     auto k = colk<T, E, NT, MINW, 1, S, 0, Rs...>();
+    if (a.pre_inv != a.post_fwd && a.v) {
+        // a run's first (forward only) or last (inverse only) pass: the half
+        // potential step from v in FP64, and the step's sums when asked for
+        if (a.v2 || a.ptab || a.ktab || a.ck || a.chirp || (a.sum_part && !a.sum_v)) return -1;
+        k = a.post_fwd ? colk<T, E, NT, MINW, 9, S, 0, Rs...>() : colk<T, E, NT, MINW, 10, S, 0, Rs...>();
+        static bool attr_end = false;
+        if (!attr_end) {
+            hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 9, S, 0, Rs...>(),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+            hipFuncSetAttribute((const void *)colk<T, E, NT, MINW, 10, S, 0, Rs...>(),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
+            attr_end = true;
+        }
+        constexpr int C = NT * E / Radix<Rs...>::prod;
+        if (a.L2 % (C * S)) return -1;
+        return timed(LT_KIND_COLUMN, k, dim3(a.L2 / (C * S), batch), dim3(NT), lds_bytes<T, V>(), stream, a);
+    }
     if constexpr (V == 1) {
         if (a.pre_inv != a.post_fwd) {
             k = a.post_fwd ? k_colf<T, E, NT, MINW, 5, 0, Rs...> : k_colf<T, E, NT, MINW, 6, 0, Rs...>;
@@ -1287,14 +1317,20 @@ bool fast_row_fits(int prec, int variant, int L1, int L2, int rows)
 
 int launch_col_fast(int prec, int variant, const ColArgs &a, int batch, void *stream)
 {
-    // steady-state passes only: the first / last / checkpoint passes of a run
-    // and the adjoint passes take the general kernel
+    // steady-state passes, and the first and last passes of runs without the
+    // chirp-z pair form (the first reads the input vector, the last writes
+    // the output vector); the adjoint passes and the general first / last
+    // passes (chirp-z pair, scaled, time-dependent) take the general kernel
     const bool steady = a.pre_inv && a.post_fwd && !a.in && !a.out && !a.chirp && a.scale == 1.0 &&
                         !a.adjoint && ((a.v != nullptr) != (a.ktab != nullptr)) &&
                         (prec == LT_C128 || !a.v || a.ptab || a.v2) &&
                         (!a.ck || (a.ptab && a.v && !a.v2 && !a.ck_chirp && a.ck_v)) &&
                         (!a.sum_part || (a.ptab && a.v && !a.v2 && a.sum_v));
-    if (!steady || !fast_col_fits(prec, variant, a.L1, a.L2, a.C)) return -1;
+    const bool first = !a.pre_inv && a.post_fwd && a.in && !a.out;
+    const bool last = a.pre_inv && !a.post_fwd && !a.in && a.out;
+    const bool ends = (first || last) && a.v && !a.v2 && !a.ptab && !a.ktab && !a.ck && !a.chirp &&
+                      a.scale == 1.0 && !a.adjoint && (!a.sum_part || a.sum_v);
+    if (!(steady || ends) || !fast_col_fits(prec, variant, a.L1, a.L2, a.C)) return -1;
     if (variant == 3 && a.L1 == 4096)
         return prec == LT_C128 ? go<double, 3, true>(a.L1, a, batch, stream) : go<float, 3, true>(a.L1, a, batch, stream);
     if (prec == LT_C128)
