@@ -226,6 +226,23 @@ def bench_batched(lt, torch, K, W):
     }
 
 
+# kernel variants given on the command line (--kernels), per precision name;
+# empty: every leg autotunes
+FORCED_KERNELS = {}
+
+
+def choose_kernels(lt, plan, prec, name, reps):
+    """The (column, row) variants a leg runs: those given with --kernels for
+    this precision, else the autotuner's pick.  The override is for profiling
+    runs, where the profiler's per-dispatch overhead swamps the tuner's
+    timings."""
+    if name in FORCED_KERNELS:
+        cv, rv = FORCED_KERNELS[name]
+        lt.lattice_plan_set_kernels(plan, prec, cv, rv)
+        return (cv, rv)
+    return tuple(lt.lattice_plan_autotune(plan, prec, reps=reps))
+
+
 def bench_rank2(lt, torch, K, W):
     """d = 10 rank-2 lattice n = (4096, 256), 500 steps; also a forward run
     with checkpoints plus the adjoint sweep (both on the transposed tensor)."""
@@ -241,7 +258,7 @@ def bench_rank2(lt, torch, K, W):
            "unit": "lattice-point-steps/s"}
     for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
         prec = lt.LT_C64 if name == "c64" else lt.LT_C128
-        kernels = lt.lattice_plan_autotune(plan, prec, reps=10)
+        kernels = choose_kernels(lt, plan, prec, name, 10)
         u = torch.tensor(c.u0, dtype=dtype, device=dev)
         work = torch.empty(lt.strang_workspace_size(plan, prec, 1, True), dtype=torch.uint8, device=dev)
         run = lambda: lt.strang_run(plan, v, u, c.gamma, c.dt, c.steps, work=work)  # noqa: E731
@@ -689,10 +706,17 @@ def main():
     ap.add_argument("--only", choices=["batched", "rank2", "adjoint", "conservation", "convergence", "splitting",
                                        "wide", "hbm", "initial"],
                     help="run one companion workload alone (profiling)")
+    ap.add_argument("--kernels", default="",
+                    help="fixed kernel variants instead of the autotuner for the main and rank-2 legs, "
+                         "e.g. 'c64=2,4;c128=5,4' (profiling runs)")
     ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device (counter calibration for the traffic figure)")
     args = ap.parse_args()
+    for item in filter(None, args.kernels.split(";")):
+        name, pair = item.split("=")
+        cv, rv = (int(x) for x in pair.split(","))
+        FORCED_KERNELS[name.strip()] = (cv, rv)
     if args.cpu_worker is not None:
         cpu_worker(args.cpu_worker)
         return
@@ -742,8 +766,8 @@ def main():
             continue
         u = torch.tensor(inst.u0, dtype=dtype, device=dev)
         prec = lt.LT_C64 if name == "c64" else lt.LT_C128
-        kernels = lt.lattice_plan_autotune(plan, prec, reps=20)
-        log(f"{name}: autotuned kernel variants (column, row) = {kernels}")
+        kernels = choose_kernels(lt, plan, prec, name, 20)
+        log(f"{name}: kernel variants (column, row) = {kernels}")
         work = torch.empty(lt.strang_workspace_size(plan, prec, 1, True), dtype=torch.uint8, device=dev)
         # one run from u0 for the accuracy indicators
         lt.strang_run(plan, v, u, inst.gamma, inst.dt, m, work=work)

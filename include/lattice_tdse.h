@@ -296,8 +296,9 @@ lt_status strang_run_batched(int32_t B, const lt_plan *const *plans, lt_prec pre
  * strang_batch_autotune times the register-staged kernel geometries
  * (variants 1, 2 and, for lengths up to 2048, 5 of lattice_plan_set_kernels)
  * of every length class of the batch on scratch copies of the members'
- * buffers (the states are untouched) and keeps the fastest per class; it
- * synchronizes `stream`.
+ * buffers (the states are untouched; reps launches per timing, three
+ * interleaved rounds of which the fastest counts) and keeps the fastest per
+ * class; it synchronizes `stream`.
  * strang_batch_kernels lists the classes: key[i] > 0 is a column class of
  * column length key[i], key[i] < 0 a row class (-key = 2 L2 + multiplier
  * kind), variant[i] its geometry (up to cap entries; *ncls gets the count).
@@ -432,9 +433,10 @@ lt_status lattice_diagnostics(const lt_plan *p, lt_prec prec, int32_t batch, con
  * that overlap, and the fastest variant differs between the two.
  * lattice_plan_autotune times every applicable variant of the plan's
  * steady-state column and row passes on `stream`, once on one state and
- * once on max(2, ceil(2^22 / L)) states sharing v (reps launches each, on a
- * scratch buffer it allocates and frees), and keeps the fastest of each
- * class; it must not run concurrently with runs of the same plan.
+ * once on max(2, ceil(2^22 / L)) states sharing v (reps launches each, in
+ * three interleaved rounds of which the fastest counts, on a scratch buffer
+ * it allocates and frees), and keeps the fastest of each class; it must not
+ * run concurrently with runs of the same plan.
  * One-workgroup and three-level schedules have nothing to tune (the latter
  * run the default variant 1).
  * lattice_plan_set_kernels sets both classes to the given variants;

@@ -1838,32 +1838,36 @@ lt_status strang_batch_autotune(lt_batch *b, int32_t reps, void *stream)
             if (l.key < 0 || l.mem.empty() || herr) continue;
             const int *idx = dl + l.idx_off, *start = dl + l.start_off;
             const int nm = (int)l.mem.size(), nb = l.start[nm];
-            float best_ms = 0.0f;
-            int best = 1;
             // 256 x 16 and 512 x 8 on 4096-element tiles; 256 x 8 on
-            // 2048-element tiles for lengths up to 2048
+            // 2048-element tiles for lengths up to 2048; three interleaved
+            // rounds, the fastest of each variant counts
             const int len = which == 0 ? l.key : l.key / 2;
-            for (int var : {1, 2, 5}) {
-                if (herr) break;
-                if (var == 5 && len > 2048) continue;
-                auto go = [&]() {
-                    return which == 0 ? launch_col_fast_multi(R.prec, var, l.key, dtwo, idx, start, nm, nb, 0, 2, hs)
-                                      : launch_row_fast_multi(R.prec, var, l.key / 2, row_mid(R.prec, l.key), dtwo, idx, start, nm,
-                                                              nb, 0, 1, hs);
-                };
-                herr = go();  // warm-up
-                if (!herr) herr = (int)hipEventRecord(e0, hs);
-                for (int k = 0; k < reps && !herr; ++k) herr = go();
-                if (!herr) herr = (int)hipEventRecord(e1, hs);
-                if (!herr) herr = (int)hipEventSynchronize(e1);
-                float ms = 0.0f;
-                if (!herr) herr = (int)hipEventElapsedTime(&ms, e0, e1);
-                if (!herr && (var == 1 || ms < best_ms)) {
-                    best_ms = ms;
-                    best = var;
+            const int vars[3] = {1, 2, 5};
+            float t[3] = {1e30f, 1e30f, 1e30f};
+            for (int round = 0; round < 3 && !herr; ++round) {
+                for (int i = 0; i < 3 && !herr; ++i) {
+                    const int var = vars[i];
+                    if (var == 5 && len > 2048) continue;
+                    auto go = [&]() {
+                        return which == 0
+                                   ? launch_col_fast_multi(R.prec, var, l.key, dtwo, idx, start, nm, nb, 0, 2, hs)
+                                   : launch_row_fast_multi(R.prec, var, l.key / 2, row_mid(R.prec, l.key), dtwo, idx,
+                                                           start, nm, nb, 0, 1, hs);
+                    };
+                    herr = go();  // warm-up
+                    if (!herr) herr = (int)hipEventRecord(e0, hs);
+                    for (int k = 0; k < reps && !herr; ++k) herr = go();
+                    if (!herr) herr = (int)hipEventRecord(e1, hs);
+                    if (!herr) herr = (int)hipEventSynchronize(e1);
+                    float ms = 0.0f;
+                    if (!herr) herr = (int)hipEventElapsedTime(&ms, e0, e1);
+                    if (!herr) t[i] = std::min(t[i], ms);
                 }
             }
-            l.var = best;
+            int best = 0;
+            for (int i = 1; i < 3; ++i)
+                if (t[i] < t[best]) best = i;
+            l.var = vars[best];
         }
     }
     if (herr) st = fail(LT_E_HIP, std::string("batch autotune: ") + hipGetErrorString((hipError_t)herr));
@@ -2300,20 +2304,31 @@ static lt_status tune_slot(lt_plan *p, int w, lt_prec prec, int32_t reps, void *
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "event");
         return LT_OK;
     };
+    // every candidate is timed in kTuneRounds interleaved rounds and its
+    // fastest round counts, so that a transient slowdown (clock ramp, another
+    // stream's work) does not decide the pick
+    constexpr int kTuneRounds = 3;
     best_c[0] = best_c[1] = best_r[0] = best_r[1] = 0;
     for (int cls = 0; cls < 2 && !st; ++cls) {
         const int batch = cls ? many : 1;
-        float tc = 1e30f, tr = 1e30f;
-        for (int var = 0; var <= 5 && !st; ++var) {
-            float ms = 0.f;
-            if (var == 0 || fast_col_fits(prec, var, s.L1, s.L2, s.cols)) {
-                st = time_it(true, var, batch, ms);
-                if (!st && ms < tc) { tc = ms; best_c[cls] = var; }
+        float tc[6], tr[6];
+        for (int var = 0; var <= 5; ++var) tc[var] = tr[var] = 1e30f;
+        for (int round = 0; round < kTuneRounds && !st; ++round) {
+            for (int var = 0; var <= 5 && !st; ++var) {
+                float ms = 0.f;
+                if (var == 0 || fast_col_fits(prec, var, s.L1, s.L2, s.cols)) {
+                    st = time_it(true, var, batch, ms);
+                    if (!st) tc[var] = std::min(tc[var], ms);
+                }
+                if (!st && (var == 0 || fast_row_fits(prec, var, s.L1, s.L2, s.rows))) {
+                    st = time_it(false, var, batch, ms);
+                    if (!st) tr[var] = std::min(tr[var], ms);
+                }
             }
-            if (!st && (var == 0 || fast_row_fits(prec, var, s.L1, s.L2, s.rows))) {
-                st = time_it(false, var, batch, ms);
-                if (!st && ms < tr) { tr = ms; best_r[cls] = var; }
-            }
+        }
+        for (int var = 1; var <= 5; ++var) {
+            if (tc[var] < tc[best_c[cls]]) best_c[cls] = var;
+            if (tr[var] < tr[best_r[cls]]) best_r[cls] = var;
         }
     }
     hipEventDestroy(e0);
