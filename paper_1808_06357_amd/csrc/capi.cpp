@@ -1665,18 +1665,22 @@ lt_status batch_passes(const BatchRun &R, char *dd, hipStream_t hs, hipStream_t 
                                                          l.start[l.act], 0, g, hs);
                 continue;
             }
-            if (l.key < 0 || g == 0) {  // general kernel: every role (the first pass of every member)
+            if (l.key < 0) {  // general kernel: every role
                 herr = launch_col_multi(prec, dtwo, idx, start, l.act, l.start[l.act], 0, g, R.lds_col, hs);
                 continue;
             }
-            // register-staged interior passes, then the general kernel for the
-            // members whose last pass this is (a contiguous range [a, act))
-            herr = launch_col_fast_multi(prec, l.var, l.key, dtwo, idx, start, l.act, l.start[l.act], 0, g, hs);
+            if (g == 0) {  // every member's first pass
+                herr = launch_col_fast_multi(prec, l.var, l.key, 9, dtwo, idx, start, l.act, l.start[l.act], 0, g, hs);
+                continue;
+            }
+            // register-staged interior passes, then the last pass of the
+            // members whose schedules end here (a contiguous range [a, act))
+            herr = launch_col_fast_multi(prec, l.var, l.key, 0, dtwo, idx, start, l.act, l.start[l.act], 0, g, hs);
             int a = l.act;
             while (a > 0 && l.npass[a - 1] == g + 1) --a;
             if (!herr && a < l.act)
-                herr = launch_col_multi(prec, dtwo, idx, start, l.act, l.start[l.act] - l.start[a], l.start[a], g,
-                                        R.lds_col, hs);
+                herr = launch_col_fast_multi(prec, l.var, l.key, 10, dtwo, idx, start, l.act,
+                                             l.start[l.act] - l.start[a], l.start[a], g, hs);
         }
     }
     if (fork) {  // join even after a failed launch: the workspace must outlive the second stream's work
@@ -1850,7 +1854,7 @@ lt_status strang_batch_autotune(lt_batch *b, int32_t reps, void *stream)
                     if (var == 5 && len > 2048) continue;
                     auto go = [&]() {
                         return which == 0
-                                   ? launch_col_fast_multi(R.prec, var, l.key, dtwo, idx, start, nm, nb, 0, 2, hs)
+                                   ? launch_col_fast_multi(R.prec, var, l.key, 0, dtwo, idx, start, nm, nb, 0, 2, hs)
                                    : launch_row_fast_multi(R.prec, var, l.key / 2, row_mid(R.prec, l.key), dtwo, idx,
                                                            start, nm, nb, 0, 1, hs);
                     };

@@ -804,12 +804,12 @@ __global__ void __launch_bounds__(NT, MINW) k_colf_adj(ColArgs a)
 }
 
 // Pass g of the batch members listed in idx (prefix sums of their column
-// tiles in start, block offset off): the merged potential step of each
-// member whose schedule is at an interior column pass; first and last
-// column passes take the general kernel.  The members' tiles are counted in
-// 4096-element tiles; a kernel with Q times smaller tiles runs Q blocks per
-// counted tile.
-template <typename T, int E, int NT, int MINW, int Q, int... Rs>
+// tiles in start, block offset off).  MID 0: the merged potential step of
+// each member whose schedule is at an interior column pass; MID 9: the
+// members' first pass (g = 0); MID 10: the last pass of each member whose
+// schedule ends at g.  The members' tiles are counted in 4096-element tiles;
+// a kernel with Q times smaller tiles runs Q blocks per counted tile.
+template <typename T, int E, int NT, int MINW, int MID, int Q, int... Rs>
 __global__ void __launch_bounds__(NT, MINW) k_colf_multi(const BatchDesc *d, const int *idx, const int *start,
                                                           int nmem, int nblocks, int off, int64_t g)
 {
@@ -820,10 +820,17 @@ __global__ void __launch_bounds__(NT, MINW) k_colf_multi(const BatchDesc *d, con
     const int bid = w / Q + off;
     const int k = find_member(start, nmem, bid);
     const BatchDesc &p = d[idx[k]];
-    if (g == 0 || (g & 1) || g >= p.npass - 1) return;
-    // members with interior passes carry the per-point table of the merged potential step
-    colf_body<T, E, NT, 0, 1, 0, Rs...>(p.col[1], (bid - start[k]) * Q + w % Q, 0,
-                                     reinterpret_cast<cx<T> *>(smem_raw));
+    if constexpr (MID == 9) {
+        if (g != 0) return;
+    } else if constexpr (MID == 10) {
+        if (g != p.npass - 1) return;
+    } else {
+        if (g == 0 || (g & 1) || g >= p.npass - 1) return;
+    }
+    // members with interior passes carry the per-point table of the merged
+    // potential step (col[1]); col[0] and col[3] are the first and last roles
+    colf_body<T, E, NT, MID, 1, 0, Rs...>(p.col[MID == 9 ? 0 : MID == 10 ? 3 : 1], (bid - start[k]) * Q + w % Q, 0,
+                                       reinterpret_cast<cx<T> *>(smem_raw));
 }
 
 // Row pass: [DFT -> spectral multiplier -> inverse DFT], in place; the
@@ -1212,12 +1219,12 @@ int go(int L, const A &a, int batch, void *stream)
 
 bool fast_len(int L) { return L >= 64 && L <= 4096 && (L & (L - 1)) == 0; }
 
-template <typename T, int V, int... Rs>
+template <typename T, int V, int MID, int... Rs>
 int col_multi_go(const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks, int off, int64_t g,
                  void *stream)
 {
     constexpr int NT = Geo<V>::NT, E = Geo<V>::E, MINW = Geo<V>::MINW, Q = kTile / (NT * E);
-    auto k = k_colf_multi<T, E, NT, MINW, Q, Rs...>;
+    auto k = k_colf_multi<T, E, NT, MINW, MID, Q, Rs...>;
     static bool attr = false;
     if (!attr) {
         hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
@@ -1250,7 +1257,7 @@ int multi_go_v(int L, const BatchDesc *d, const int *idx, const int *start, int 
                int64_t g, void *stream)
 {
 #define LT_MULTI(...)                                                                              \
-    (COL ? col_multi_go<T, V, __VA_ARGS__>(d, idx, start, nmem, nblocks, off, g, stream)           \
+    (COL ? col_multi_go<T, V, MID, __VA_ARGS__>(d, idx, start, nmem, nblocks, off, g, stream)      \
          : row_multi_go<T, V, MID, __VA_ARGS__>(d, idx, start, nmem, nblocks, off, g, stream))
     if constexpr (V == 1) {
         switch (L) {
@@ -1420,10 +1427,18 @@ int launch_col_fast_adjoint(int prec, int variant, const ColArgs &a, int batch, 
     return adj_dispatch<float>(a, batch, stream);
 }
 
-int launch_col_fast_multi(int prec, int variant, int L1, const BatchDesc *d, const int *idx, const int *start,
-                          int nmem, int nblocks, int off, int64_t g, void *stream)
+int launch_col_fast_multi(int prec, int variant, int L1, int mid, const BatchDesc *d, const int *idx,
+                          const int *start, int nmem, int nblocks, int off, int64_t g, void *stream)
 {
-    if (prec == LT_C128) return multi_go<double, true, 0>(variant, L1, d, idx, start, nmem, nblocks, off, g, stream);
+    // mid 0: interior passes, 9: first passes, 10: last passes
+    if (mid != 0 && mid != 9 && mid != 10) return -1;
+    if (prec == LT_C128) {
+        if (mid == 9) return multi_go<double, true, 9>(variant, L1, d, idx, start, nmem, nblocks, off, g, stream);
+        if (mid == 10) return multi_go<double, true, 10>(variant, L1, d, idx, start, nmem, nblocks, off, g, stream);
+        return multi_go<double, true, 0>(variant, L1, d, idx, start, nmem, nblocks, off, g, stream);
+    }
+    if (mid == 9) return multi_go<float, true, 9>(variant, L1, d, idx, start, nmem, nblocks, off, g, stream);
+    if (mid == 10) return multi_go<float, true, 10>(variant, L1, d, idx, start, nmem, nblocks, off, g, stream);
     return multi_go<float, true, 0>(variant, L1, d, idx, start, nmem, nblocks, off, g, stream);
 }
 

@@ -216,8 +216,10 @@ int launch_col_fast_adjoint(int prec, int variant, const ColArgs &a, int batch, 
 // has no such pass
 // (variant 1: 256 threads x 16 elements, 2: 512 threads x 8; both on the
 // members' 4096-element tiles)
-int launch_col_fast_multi(int prec, int variant, int L1, const BatchDesc *d, const int *idx, const int *start,
-                          int nmem, int nblocks, int off, int64_t g, void *stream);
+// (columns: mid 0 the interior passes, 9 the members' first passes, 10 the
+// last passes of the members whose schedules end at g)
+int launch_col_fast_multi(int prec, int variant, int L1, int mid, const BatchDesc *d, const int *idx,
+                          const int *start, int nmem, int nblocks, int off, int64_t g, void *stream);
 int launch_row_fast_multi(int prec, int variant, int L2, int mid, const BatchDesc *d, const int *idx,
                           const int *start, int nmem, int nblocks, int off, int64_t g, void *stream);
 int launch_resident_multi(int prec, const ResArgs *d, int ninst, size_t lds, void *stream);
