@@ -1250,15 +1250,22 @@ int row_multi_go(const BatchDesc *d, const int *idx, const int *start, int nmem,
                        nblocks, off, g);
 }
 
+// one multi-member launch: the column or the row kernel of the pass kind MID
+template <typename T, bool COL, int MID, int V, int... Rs>
+int multi_one(const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks, int off, int64_t g,
+              void *stream)
+{
+    if constexpr (COL) return col_multi_go<T, V, MID, Rs...>(d, idx, start, nmem, nblocks, off, g, stream);
+    else return row_multi_go<T, V, MID, Rs...>(d, idx, start, nmem, nblocks, off, g, stream);
+}
+
 // radix sequences per length of the two 4096-element-tile geometries (as in
 // go<T, 1 or 2, ...>): variant 1 (256 threads x 16) and 2 (512 threads x 8)
 template <typename T, bool COL, int MID, int V>
 int multi_go_v(int L, const BatchDesc *d, const int *idx, const int *start, int nmem, int nblocks, int off,
                int64_t g, void *stream)
 {
-#define LT_MULTI(...)                                                                              \
-    (COL ? col_multi_go<T, V, MID, __VA_ARGS__>(d, idx, start, nmem, nblocks, off, g, stream)      \
-         : row_multi_go<T, V, MID, __VA_ARGS__>(d, idx, start, nmem, nblocks, off, g, stream))
+#define LT_MULTI(...) multi_one<T, COL, MID, V, __VA_ARGS__>(d, idx, start, nmem, nblocks, off, g, stream)
     if constexpr (V == 1) {
         switch (L) {
         case 64: return LT_MULTI(8, 8);
