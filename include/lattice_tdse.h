@@ -424,7 +424,9 @@ lt_status lattice_diagnostics(const lt_plan *p, lt_prec prec, int32_t batch, con
  * elsewhere the general kernel runs whatever is selected (rows of 8192
  * points always take their own 512-thread kernel).  Variants outside
  * 0 ... 5 give LT_E_ARG.
- * The default is 1.
+ * The default is 1, except for complex128 column passes of at most 2048
+ * points, which default to 5 (the geometry that holds the step's fused
+ * sums of strang_run_sums without spilling registers).
  * A plan keeps two choices per pass: one for launches of a single state (or
  * of few points) and one for launches of many states, batch >= 2 with
  * batch * L >= 2^20 points (L = the schedule's transform length).  A

@@ -998,6 +998,13 @@ lt_status lattice_plan(int32_t d, int32_t r, const int64_t *Z, const int64_t *n,
                                                               : make_schedule(*p, prec, true);
             p->sched[2][prec] = swapped_schedule(p->sched[0][prec]);
         }
+        // complex128 column passes default to the 256 x 8 geometry on
+        // 2048-element tiles where it fits: with the step's fused sums the
+        // 16-element geometries run out of registers and spill
+        for (int w = 0; w < 3; ++w) {
+            Sched &s = p->sched[w][LT_C128];
+            if (s.ok && s.passes == 2 && fast_col_fits(LT_C128, 5, s.L1, s.L2, s.cols)) s.col_var = s.col_var_m = 5;
+        }
     } catch (const std::bad_alloc &) {
         delete p;
         return fail(LT_E_NOMEM, "out of host memory while planning");

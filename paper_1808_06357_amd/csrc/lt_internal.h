@@ -39,7 +39,8 @@ struct Sched {
     int rows = 1;            // rows per row-pass workgroup
     int ept = 16;            // max complex elements per thread (register budget)
     int col_var = 1;         // column-pass kernel: 0 general, 1 fast 256x16, 2 fast 512x8,
-                             // 3 fast 64x16 (1024-element tiles)
+                             // 3 fast 64x16 (1024-element tiles), 4 fast 512x8 with two
+                             // waves per SIMD, 5 fast 256x8 (2048-element tiles)
     int row_var = 1;         // row-pass kernel (same codes)
     int col_var_m = 1;       // the same choices for launches of many states
     int row_var_m = 1;       // (see many_states)

@@ -145,7 +145,9 @@ def test_schedules():
     # a forced choice holds for single-state and many-state launches alike
     for batch in (1, 2, 8, 64, 4096):
         assert C.lattice_plan_get_kernels_batch(c1, C.LT_C64, batch) == (2, 0)
-    assert C.lattice_plan_get_kernels_batch(c1, C.LT_C128, 64) == (1, 1)
+    # complex128 columns of at most 2048 points default to variant 5
+    assert c1.info["L1"] <= 2048
+    assert C.lattice_plan_get_kernels_batch(c1, C.LT_C128, 64) == (5, 1)
     with pytest.raises(C.LatticeError):
         C.lattice_plan_set_kernels(c1, C.LT_C64, 6, 0)
     with pytest.raises(C.LatticeError):
