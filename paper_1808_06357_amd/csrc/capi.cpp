@@ -573,7 +573,7 @@ void sums_on(ColArgs &a, const SumSink &k, int64_t j, const double *v)
 // pair per step.  A complex64 run given `conv_f` (L complex floats) rounds the
 // spectrum into it once, and its register-staged rows read that copy: half
 // the spectrum's bytes, applied in float (complex64 arithmetic, like the
-// state); the general first and last passes keep the double spectrum.
+// state); the general row kernel, where one runs, reads the double spectrum.
 lt_status two_pass_forward(lt_plan &p, const Sched &s, const DevTables &D, int prec, int batch,
                            const double *v, int64_t v_stride, void *u, double gamma, double dt,
                            int64_t steps, void *ckpt, int64_t ck_every, const double *ktab, void *W,
