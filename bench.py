@@ -491,7 +491,7 @@ def bench_wide(lt, torch, K, W):
 
 def bench_hbm(lt, torch, K, W):
     """The benchmark lattice with a batch of states sharing v (16 in complex64,
-    8 in complex128: about 500 and 450 MB of states, transform buffers and
+    8 in complex128: about 440 and 460 MB of states, transform buffers and
     tables, beyond the 256 MB Infinity Cache), 100 steps: the same
     steady-state passes as the headline run, with a working set that has to
     stream from HBM."""
@@ -521,9 +521,11 @@ def bench_hbm(lt, torch, K, W):
         ks = kernel_summary(lt, run, 1)
         col_b, row_b = pass_bytes(info, N, m, S)
         L = info["fft_len"]
-        col_steady = B * (2 * L * S) + 16 * N   # the shared table is read once per launch
-        row_steady = B * (2 * L * S) + 16 * L
-        resident = B * (N * S + L * S) + 16 * N + 16 * L
+        # the shared tables (the merged potential step per point, the
+        # convolution spectrum per bin; S bytes each) are read once per launch
+        col_steady = B * (2 * L * S) + S * N
+        row_steady = B * (2 * L * S) + S * L
+        resident = B * (N * S + L * S) + S * N + S * L + 8 * N
         out[name] = {"value": B * N * m / sec, "states": B, "ms_per_run": sec * 1e3,
                      "working_set_MB": resident / 1e6, "max_sampled_rel_l2_vs_oracle": err,
                      "column_us": ks["column"]["avg_us"], "row_us": ks["row"]["avg_us"],
