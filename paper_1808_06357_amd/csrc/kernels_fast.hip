@@ -393,24 +393,33 @@ __device__ __forceinline__ void tile_sums(const ColArgs &a, int tile, int64_t b,
     const rsrc_t rv = make_rsrc(a.sum_v + b * a.v_bs, a.Nvalid * (int64_t)sizeof(double));
     constexpr uint32_t vdiv = (uint32_t)(sizeof(cx<T>) / sizeof(double));
     const uint32_t lim = (uint32_t)a.Nvalid * (uint32_t)sizeof(cx<T>);
+    // v is loaded in chunks of at most eight elements (sixteen registers in
+    // flight), which keeps the 16-element geometries from spilling; the
+    // accumulation order is that of the elements either way
+    constexpr int CH = R > 8 ? 8 : R;
     double s1 = 0.0, s2 = 0.0;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        double vv[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if constexpr (PV) vv[r] = sv[j * R + r];
-            else
-                vv[r] = __builtin_bit_cast(double,
-                                           __builtin_amdgcn_raw_buffer_load_b64(rv, (voff[j] + r * rstep) / vdiv, 0, 0));
-        }
+        for (int r0 = 0; r0 < R; r0 += CH) {
+            double vv[CH];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const cx<T> x = v[j * R + r];
-            const double q2 =
-                voff[j] + r * rstep < lim ? (double)x.x * (double)x.x + (double)x.y * (double)x.y : 0.0;
-            s1 += q2;
-            s2 += vv[r] * q2;
+            for (int r = 0; r < CH; ++r) {
+                if constexpr (PV) vv[r] = sv[j * R + r0 + r];
+                else
+                    vv[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                           rv, (voff[j] + (r0 + r) * rstep) / vdiv, 0, 0));
+            }
+#pragma unroll
+            for (int r = 0; r < CH; ++r) {
+                const cx<T> x = v[j * R + r0 + r];
+                const double q2 = voff[j] + (r0 + r) * rstep < lim
+                                      ? (double)x.x * (double)x.x + (double)x.y * (double)x.y
+                                      : 0.0;
+                s1 += q2;
+                s2 += vv[r] * q2;
+            }
+            if constexpr (CH < R) __builtin_amdgcn_sched_barrier(0);
         }
     }
     block_sum2<NT>(s1, s2);
