@@ -127,3 +127,33 @@ def test_step_sums_zero_steps_and_errors(lt):
     assert np.max(np.abs(got[:, 0, 1] - hist[:, 0, 2])) < 1e-12 * np.max(np.abs(v)) / 0.1
     with pytest.raises(Exception):
         lt.strang_run_sums(plan, vv, u, -0.1, 1e-2, 3)
+
+
+@pytest.mark.parametrize("cv", [1, 5])
+def test_step_sums_on_each_column_geometry(lt, cv):
+    """The step sums on a forced column geometry: variant 1 (16 elements per
+    thread, first radix 16 on the 256-point columns of the prime N = 32749's
+    2^16-point convolution, so v is loaded in chunks) and variant 5 (8
+    elements), both precisions, per-state v, against the oracle's history;
+    the state equals strang_run's on the same geometry."""
+    import torch
+    Z, n, H, v, u0 = rank1_case(32749, 4, 3, 2, False, 0)
+    gamma, dt, steps = 0.05, 2e-3, 12
+    plan = lt.lattice_plan(Z, n, H)
+    assert plan.info["L1"] == 256 and plan.info["passes"] == 2
+    _, s, _ = O.index_set(Z, n, H)
+    ref_u, hist = O.strang_run(n, s, v, u0, gamma, dt, steps, history=True)
+    ref = np.stack([hist[:, :, 0], hist[:, :, 2]], axis=-1)
+    for prec, dtype in (("c128", torch.complex128), ("c64", torch.complex64)):
+        lt.lattice_plan_set_kernels(plan, lt.LT_C128 if prec == "c128" else lt.LT_C64, cv, 1)
+        vv = torch.tensor(v, dtype=torch.float64, device="cuda")
+        u = torch.tensor(u0, dtype=dtype, device="cuda")
+        sums = lt.strang_run_sums(plan, vv, u, gamma, dt, steps)
+        u_plain = torch.tensor(u0, dtype=dtype, device="cuda")
+        lt.strang_run(plan, vv, u_plain, gamma, dt, steps)
+        got = sums.cpu().numpy()
+        scale = np.stack([ref[..., 0], ref[..., 0] * np.max(np.abs(v)) / gamma], axis=-1)
+        e = float(np.max(np.abs(got - ref) / scale))
+        print(f"  variant {cv} {prec}: max rel error of the step sums {e:.2e}", flush=True)
+        assert e < TOL[prec], (cv, prec, e)
+        assert torch.equal(u, u_plain), (cv, prec)
